@@ -1,0 +1,124 @@
+"""Homogeneous per-mode spectra (oracle).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Sec. III-C step 1 draws, for every mode i, a unit-variance field whose
+autocovariance is the diagonal slice A_ii of the tensor of Eq. (6); Sec. III-B
+notes each such slice is a function of the displacement s = (x - x')/D only,
+so it has a spectrum and FFT colouring (Sec. III-A) applies.  The paper defers
+the form of A_ii to the multi-aperture model it cites; the reading used here
+is one collapsed Kolmogorov screen seen by apertures displaced by s*D, which
+makes the spectrum of mode j
+
+    S_j(f) = f^{-11/3} |Q_j(f)|^2,   f in cycles per D,
+
+with |Q_j|^2 = (n+1) [2 J_{n+1}(pi f)/(pi f)]^2 Theta_j(phi_f) and
+Theta_j = 2cos^2(m phi), 2sin^2(m phi) or 1.  Its constant (and D/r0) drop
+out after normalising to unit variance.
+"""
+import numpy as np
+from scipy import special
+
+from .zernike import noll_nm, noll_kind, J_FIRST, J_LAST
+
+
+def kolmogorov_c():
+    """Constant c of the phase spectrum Phi(f) = c r0^{-5/3} f^{-11/3} (f in
+    cycles per metre) for which the structure function is Eq. (4)'s
+    6.88 (r/r0)^{5/3}; 6.88 is 2 [(24/5) Gamma(6/5)]^{5/6} rounded.
+
+    D(r) = 2 \\int Phi(f) (1 - cos 2 pi f.r) d^2 f; the integral
+    \\int_0^inf u^{-8/3}(1 - J0(u)) du has a closed form that gives
+    c = Gamma(11/6)^2 / (2 pi^{11/3}) [(24/5) Gamma(6/5)]^{5/6}.
+    Tests check D(r) by quadrature against Eq. (4)."""
+    bracket = (24.0 / 5.0) * special.gamma(6.0 / 5.0)
+    return special.gamma(11.0 / 6.0) ** 2 / (2.0 * np.pi ** (11.0 / 3.0)) * bracket ** (5.0 / 6.0)
+
+
+def kolmogorov_structure_constant():
+    """The Eq. (4) constant before rounding: 2 [(24/5) Gamma(6/5)]^{5/6}."""
+    return 2.0 * ((24.0 / 5.0) * special.gamma(6.0 / 5.0)) ** (5.0 / 6.0)
+
+
+def mode_spectrum(j, fx, fy):
+    """Continuous S_j(f) at frequencies (fx, fy) in cycles per D; 0 at f = 0."""
+    n, m = noll_nm(j)
+    fx = np.asarray(fx, dtype=np.float64)
+    fy = np.asarray(fy, dtype=np.float64)
+    fr = np.hypot(fx, fy)
+    phi = np.arctan2(fy, fx)
+    x = np.pi * fr
+    safe = np.where(fr > 0, fr, 1.0)
+    xs = np.pi * safe
+    radial = (n + 1) * (2.0 * special.jv(n + 1, xs) / xs) ** 2
+    kind = noll_kind(j)
+    if kind == '0':
+        ang = 1.0
+    elif kind == 'c':
+        ang = 2.0 * np.cos(m * phi) ** 2
+    else:
+        ang = 2.0 * np.sin(m * phi) ** 2
+    out = safe ** (-11.0 / 3.0) * radial * ang
+    return np.where(fr > 0, out, 0.0)
+
+
+def signed_index(G):
+    """Signed FFT bin index k' for k = 0..G-1 (k' = k - G for k >= G/2)."""
+    k = np.arange(G)
+    return np.where(k < G // 2, k, k - G)
+
+
+def discrete_spectrum(j, Gh, Gw, ds, fold=2):
+    """Folded, DC-free, unit-mean discrete spectrum Sbar_j on a Gh x Gw grid.
+
+    Bin k sits at f_k = (k'_x/(Gw ds), k'_y/(Gh ds)) cycles per D, where ds is
+    the pixel pitch in units of D (s = (x - x')/D, Sec. III-B footnote).  The
+    lattice spectrum folds the aliases f_k + l/ds for |l_x|, |l_y| <= fold;
+    the DC bin is set to 0; the table is scaled to mean 1 so every field has
+    unit variance (Sec. III-C step 1) and the s = 0 covariance is exactly A_0.
+    Layout [ky][kx] (row = y)."""
+    kx = signed_index(Gw) / (Gw * ds)
+    ky = signed_index(Gh) / (Gh * ds)
+    FX, FY = np.meshgrid(kx, ky)
+    S = np.zeros((Gh, Gw))
+    for lx in range(-fold, fold + 1):
+        for ly in range(-fold, fold + 1):
+            S += mode_spectrum(j, FX + lx / ds, FY + ly / ds)
+    S[0, 0] = 0.0
+    S *= (Gh * Gw) / S.sum()
+    return S
+
+
+def discrete_correlation(Sbar):
+    """rho_bar = Re IFFT(Sbar): the exact lattice autocorrelation of a field
+    coloured by Sbar (Sec. III-A circulant sampling); rho_bar[0,0] = 1."""
+    return np.real(np.fft.ifft2(Sbar))
+
+
+def all_spectra(Gh, Gw, ds, fold=2, j_first=J_FIRST, j_last=J_LAST):
+    return np.stack([discrete_spectrum(j, Gh, Gw, ds, fold) for j in range(j_first, j_last + 1)])
+
+
+def continuous_correlation(j, sx, sy, fmax=200.0, n_r=20000):
+    """Unit-normalised continuous autocorrelation rho_j(s) of mode j at
+    displacement (sx, sy) in units of D, by Hankel-transform quadrature of
+    S_j (independent of the FFT route).  Uses 2cos^2(m phi) = 1 + cos(2 m phi)
+    and the Jacobi-Anger integral over the angle."""
+    n, m = noll_nm(j)
+    kind = noll_kind(j)
+    # radial grid, geometric near 0 (integrable singularity f^{-5/3} for n=1)
+    f = np.concatenate([np.geomspace(1e-7, 1e-2, 4000, endpoint=False),
+                        np.linspace(1e-2, fmax, n_r)])
+    x = np.pi * f
+    Sr = f ** (-11.0 / 3.0) * (n + 1) * (2.0 * special.jv(n + 1, x) / x) ** 2
+    s = np.hypot(sx, sy)
+    psi = np.arctan2(sy, sx)
+    z = 2.0 * np.pi * f * s
+    if kind == '0':
+        ang = special.jv(0, z)
+    else:
+        sgn = 1.0 if kind == 'c' else -1.0
+        ang = special.jv(0, z) + sgn * ((-1) ** m) * special.jv(2 * m, z) * np.cos(2 * m * psi)
+    num = np.trapezoid(f * Sr * ang, f)
+    den = np.trapezoid(f * Sr, f)
+    return num / den

@@ -1,0 +1,198 @@
+"""Pins for the oracle's noise generator, Zernike modes and Noll covariance.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, textbook closed forms, the Kolmogorov constant printed
+in Eq. (4), Noll's published residual table, and numerical quadrature that
+takes a different route from the closed forms.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import philox, zernike, spectra
+
+
+# ---------------------------------------------------------------- Philox ----
+@pytest.mark.parametrize("ctr,key,expect", [
+    # Known-answer vectors published with the Philox4x32-10 definition
+    # (Salmon et al., SC'11, Random123 distribution).
+    ((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff,) * 4, (0xffffffff, 0xffffffff), (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+])
+def test_philox_known_answers(ctr, key, expect):
+    out = philox.philox4x32_10(*ctr, *key)
+    assert tuple(int(v) for v in out) == expect
+
+
+def test_uniform_open_interval_and_binary32_exact():
+    x = np.array([0, 1, 511, 512, 0xFFFFFFFF, 0x80000000], dtype=np.uint64)
+    u = philox.uniform(x)
+    assert np.all(u > 0) and np.all(u < 1)
+    assert np.all(u.astype(np.float32).astype(np.float64) == u)
+
+
+def test_box_muller_moments():
+    n = 1 << 20
+    g = philox.gaussians4(np.arange(n), 0, 0, 0, seed=12345)
+    g = np.concatenate(g)
+    N = g.size
+    assert abs(g.mean()) < 5 / math.sqrt(N)
+    assert abs(g.var() - 1) < 5 * math.sqrt(2.0 / N)
+    kurt = np.mean(g ** 4) / np.mean(g ** 2) ** 2
+    assert abs(kurt - 3) < 5 * math.sqrt(24.0 / N)
+    # independent streams are uncorrelated
+    a, b, c, d = philox.gaussians4(np.arange(n), 0, 0, 0, seed=12345)
+    assert abs(np.mean(a * c)) < 5 / math.sqrt(n)
+
+
+# --------------------------------------------------------------- Zernike ----
+NOLL_TABLE = {  # Noll (1976) Table I ordering: j -> (n, m)
+    1: (0, 0), 2: (1, 1), 3: (1, 1), 4: (2, 0), 5: (2, 2), 6: (2, 2), 7: (3, 1), 8: (3, 1),
+    9: (3, 3), 10: (3, 3), 11: (4, 0), 12: (4, 2), 13: (4, 2), 14: (4, 4), 15: (4, 4),
+    16: (5, 1), 17: (5, 1), 18: (5, 3), 19: (5, 3), 20: (5, 5), 21: (5, 5), 22: (6, 0),
+    29: (7, 1), 36: (7, 7), 37: (8, 0)}
+
+
+def test_noll_index_table():
+    for j, nm in NOLL_TABLE.items():
+        assert zernike.noll_nm(j) == nm, j
+    assert zernike.noll_kind(2) == 'c' and zernike.noll_kind(3) == 's'
+    assert zernike.noll_kind(5) == 's' and zernike.noll_kind(6) == 'c'
+
+
+def test_zernike_textbook_forms():
+    rng = np.random.default_rng(0)
+    rho = rng.random(50)
+    th = rng.random(50) * 2 * np.pi
+    Z = lambda j: zernike.zernike(j, rho, th)
+    s3, s6, s8, s5 = math.sqrt(3), math.sqrt(6), math.sqrt(8), math.sqrt(5)
+    np.testing.assert_allclose(Z(2), 2 * rho * np.cos(th), atol=1e-14)
+    np.testing.assert_allclose(Z(3), 2 * rho * np.sin(th), atol=1e-14)
+    np.testing.assert_allclose(Z(4), s3 * (2 * rho ** 2 - 1), atol=1e-14)
+    np.testing.assert_allclose(Z(5), s6 * rho ** 2 * np.sin(2 * th), atol=1e-14)
+    np.testing.assert_allclose(Z(6), s6 * rho ** 2 * np.cos(2 * th), atol=1e-14)
+    np.testing.assert_allclose(Z(7), s8 * (3 * rho ** 3 - 2 * rho) * np.sin(th), atol=1e-13)
+    np.testing.assert_allclose(Z(8), s8 * (3 * rho ** 3 - 2 * rho) * np.cos(th), atol=1e-13)
+    np.testing.assert_allclose(Z(11), s5 * (6 * rho ** 4 - 6 * rho ** 2 + 1), atol=1e-13)
+
+
+def _disc_quadrature(nr=48, nt=96):
+    x, w = np.polynomial.legendre.leggauss(nr)
+    r = 0.5 * (x + 1)
+    wr = 0.5 * w * r
+    th = np.arange(nt) * 2 * np.pi / nt
+    R, TH = np.meshgrid(r, th, indexing='ij')
+    Wt = wr[:, None] * (2 * np.pi / nt) * np.ones_like(TH)
+    return R, TH, Wt
+
+
+def test_zernike_orthonormal_on_disc():
+    R, TH, Wt = _disc_quadrature()
+    Zs = np.stack([zernike.zernike(j, R, TH) for j in range(1, 37)])
+    G = np.einsum('iab,jab,ab->ij', Zs, Zs, Wt) / np.pi
+    np.testing.assert_allclose(G, np.eye(36), atol=1e-12)
+
+
+@pytest.mark.parametrize("j", [2, 3, 4, 5, 6, 7, 8, 11, 12, 16, 22, 29, 36])
+def test_zernike_fourier_transform_matches_direct_integral(j):
+    R, TH, Wt = _disc_quadrature(64, 128)
+    Z = zernike.zernike(j, R, TH)
+    for f, phi in [(0.3, 0.2), (1.1, 1.9), (2.7, -0.7), (4.2, 3.0)]:
+        # forward kernel exp(-2 pi i f.r) with r in units of D = 2 * radius
+        arg = np.pi * f * R * np.cos(TH - phi)
+        direct = np.sum(Z * np.exp(-1j * arg) * Wt) / np.pi
+        closed = zernike.zernike_ft(j, f, phi)
+        assert abs(direct - closed) < 1e-10, (j, f, phi, direct, closed)
+
+
+# ------------------------------------------------- Kolmogorov and Noll ----
+def test_kolmogorov_constant_reproduces_eq4():
+    """D(r) = 2 int Phi(f) (1 - cos 2 pi f.r) d^2f must be 6.88 (r/r0)^{5/3}
+    (Eq. (4)); computed by quadrature at r = r0 = 1."""
+    c = spectra.kolmogorov_c()
+    g = lambda f: f ** (-8.0 / 3.0) * (1 - special.j0(2 * np.pi * f))
+    i1, _ = integrate.quad(g, 0, 1, limit=400)
+    # on [1, inf): int f^{-8/3} = 3/5 exactly, minus the oscillatory J0 part
+    # summed over unit intervals; the remainder beyond f = 400 is < 1e-8
+    osc = sum(integrate.quad(lambda f: f ** (-8.0 / 3.0) * special.j0(2 * np.pi * f),
+                             a, a + 1.0, limit=100)[0] for a in np.arange(1.0, 400.0))
+    i2 = 0.6 - osc
+    D = 2 * c * 2 * np.pi * (i1 + i2)
+    assert abs(D - 6.88) < 0.005
+    assert abs(D - spectra.kolmogorov_structure_constant()) < 1e-6
+
+
+def _a0_by_quadrature(i, j):
+    """c int f^{-11/3} Q_i Q_j^* d^2f in polar coordinates (f cycles per D)."""
+    c = spectra.kolmogorov_c()
+    nphi = 64
+    phis = np.arange(nphi) * 2 * np.pi / nphi
+
+    def radial(f):
+        q = zernike.zernike_ft(i, f, phis) * np.conj(zernike.zernike_ft(j, f, phis))
+        return f ** (-8.0 / 3.0) * np.real(np.mean(q)) * 2 * np.pi
+
+    pts = np.arange(0.5, 40.0, 0.5)
+    tot = 0.0
+    edges = np.concatenate([[0.0], pts])
+    for a, b in zip(edges[:-1], edges[1:]):
+        v, _ = integrate.quad(radial, a, b, limit=200, epsabs=1e-13)
+        tot += v
+    v, _ = integrate.quad(radial, 40.0, np.inf, limit=400)
+    return c * (tot + v)
+
+
+@pytest.mark.parametrize("i,j", [(2, 2), (4, 4), (36, 36), (2, 8), (3, 7), (4, 11), (8, 16),
+                                 (11, 22), (6, 12), (5, 13), (2, 3), (4, 5), (7, 9)])
+def test_noll_matrix_matches_spectral_quadrature(i, j):
+    A0 = zernike.noll_matrix(1.0)
+    q = _a0_by_quadrature(i, j)
+    closed = A0[i - 2, j - 2]
+    assert abs(q - closed) <= 2e-5 * max(abs(A0[i - 2, i - 2]), 1e-3), (i, j, q, closed)
+
+
+def test_noll_residuals_match_published_table():
+    """Noll (1976), Table IV: residual phase variance after removing the first
+    J modes, in units of (D/r0)^{5/3}.  The published values were computed
+    with a rounded spectrum constant, so agreement within 1% is asserted."""
+    table = {1: 1.0299, 2: 0.582, 3: 0.134, 4: 0.111, 5: 0.0880, 6: 0.0648,
+             10: 0.0401, 11: 0.0377, 21: 0.0208}
+    for J, v in table.items():
+        got = zernike.noll_residual(J)
+        assert abs(got - v) / v < 0.01, (J, got, v)
+
+
+def test_tilt_variance_matches_classical_z_tilt():
+    """One-axis Z-tilt angle variance 0.182 (lambda/D)^2 (D/r0)^{5/3}: the
+    phase 2 a_2 rho cos(theta) has gradient 4 a_2 / D, i.e. an angle of
+    (2/pi) a_2 lambda/D."""
+    A0 = zernike.noll_matrix(1.0)
+    var_angle = (2 / np.pi) ** 2 * A0[0, 0]
+    assert abs(var_angle - 0.182) < 0.0015
+    np.testing.assert_allclose(A0[0, 0], A0[1, 1], rtol=1e-14)
+    for dr in [0.5, 1.0, 2.0, 4.0, 5.0]:
+        np.testing.assert_allclose(zernike.noll_matrix(dr)[0, 0], A0[0, 0] * dr ** (5 / 3), rtol=1e-13)
+
+
+def test_noll_matrix_structure():
+    """Non-zero only within (m, parity) groups: 15 groups, 31 off-diagonal
+    pairs, positive definite (Sec. III-B, Fig. 5)."""
+    A0 = zernike.noll_matrix(1.0)
+    groups = zernike.mixing_groups()
+    assert len(groups) == 15
+    off = [(a, b) for a in range(35) for b in range(a + 1, 35) if A0[a, b] != 0]
+    assert len(off) == 31
+    gid = {}
+    for k, js in groups.items():
+        for j in js:
+            gid[j] = k
+    for a, b in off:
+        assert gid[a + 2] == gid[b + 2]
+    assert np.all(np.linalg.eigvalsh(A0) > 0)
+    L = zernike.cholesky_lower(A0)
+    np.testing.assert_allclose(L @ L.T, A0, atol=1e-15)
+    assert np.count_nonzero(np.abs(L) > 0) == 35 + 31
