@@ -1,0 +1,178 @@
+/*
+ * tsim.h -- C ABI of the MI355X dense-field phase-to-space (DF-P2S)
+ * turbulence renderer (Chimitt, Zhang, Mao, Chan, "Real-Time Dense Field
+ * Phase-to-Space Simulation of Imaging through Atmospheric Turbulence").
+ *
+ * The per-frame hot path is
+ *   (a) tsim_sample_zernike : per-pixel Zernike coefficient fields drawn by
+ *       FFT colouring of independent unit-variance fields followed by
+ *       per-pixel mixing with the Noll matrix factor (Sec. III-C, Eq. (9));
+ *   (b) tsim_p2s            : Zernike vector -> weights on K PSF basis
+ *       functions (Sec. II-C, Eq. (7)), either by exact pupil-FFT PSFs
+ *       (Eq. (2)) and projection, or by a small learned network;
+ *   (c) tsim_render         : the basis-weighted blur of Eq. (8);
+ *   (d) tsim_warp           : the tilt modes (Noll 2, 3) as a bilinear warp.
+ *
+ * Conventions for every call
+ *   - Return codes: TSIM_OK (0) or a negative TSIM_E* code.  No exception
+ *     crosses the ABI.  Arguments are validated before any launch.
+ *   - Device pointers are caller-owned device memory (hipMalloc or torch),
+ *     256-byte aligned, row-major, frame-major.  The plan owns only its own
+ *     tables.  Host pointers are read during the call only.
+ *   - Launches are asynchronous on the given stream (NULL = default stream);
+ *     kernel faults surface at the caller's next synchronisation.
+ *   - A plan is immutable after creation: concurrent calls on different
+ *     streams are safe if each uses its own workspace.
+ */
+#ifndef TSIM_H
+#define TSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tsim_plan tsim_plan;
+typedef void *tsim_stream; /* a hipStream_t */
+
+enum {
+  TSIM_OK = 0,
+  TSIM_EINVAL = -1,      /* bad argument (pointer, size, parameter)        */
+  TSIM_ENOMEM = -2,      /* device or host allocation failed               */
+  TSIM_EDEVICE = -3,     /* no usable gfx950 device or a HIP runtime error */
+  TSIM_EARTEFACT = -4,   /* basis or network weights missing or malformed  */
+  TSIM_EUNSUPPORTED = -5 /* valid request this build does not implement    */
+};
+
+enum { TSIM_P2S_EXACT = 0, TSIM_P2S_LEARNED = 1 };
+enum { TSIM_FP32 = 0, TSIM_BF16 = 1 };
+
+#define TSIM_N_MODES 35  /* Noll j = 2..36 (Sec. II-B keeps N = 36 modes; piston dropped) */
+
+/*
+ * Problem statement (Sec. II and its footnote on s = (x - x')/D).
+ *
+ *   H, W, C        image rows, columns, channels (1 <= H, W <= 4096, 1 <= C <= 4)
+ *   Gh, Gw         zero-padded periodic FFT grid for the sampler; powers of
+ *                  two, 64 <= G <= 4096, Gh >= H, Gw >= W
+ *   n_modes        must be TSIM_N_MODES
+ *   pixel_pitch_over_d
+ *                  one image pixel in units of the aperture diameter D
+ *                  (the displacement unit of the Zernike space).  If <= 0 it
+ *                  is derived from the optics as L*lambda/(2 D^2): the image
+ *                  pixel is the Nyquist angle lambda/(2D) seen over path L.
+ *   aperture_d_m, wavelength_m, path_length_m
+ *                  D, lambda, L in metres (used only when the pitch is <= 0)
+ *   alias_fold     spectral aliases folded per axis (0..4; 2 recommended)
+ *   pupil_n        P, pupil samples per side for exact PSFs (64 or 128); the
+ *                  circular aperture spans P/2 samples, so one PSF sample is
+ *                  one image pixel
+ *   psf_t          T, odd PSF support (3 <= T <= P/2 + 1)
+ *   basis_k        K, number of PSF basis functions (1 <= K <= 128)
+ *   basis          host [K][T*T] float64, orthonormal rows (Eq. (7)); copied.
+ *                  May be NULL for a plan that only samples and warps.
+ *   p2s_mode       TSIM_P2S_EXACT or TSIM_P2S_LEARNED
+ *   precision      TSIM_FP32 (plain form) or TSIM_BF16 (learned form: BF16
+ *                  network and basis contraction, FP32 accumulation)
+ */
+typedef struct tsim_params {
+  int32_t H, W, C;
+  int32_t Gh, Gw;
+  int32_t n_modes;
+  double pixel_pitch_over_d;
+  double aperture_d_m, wavelength_m, path_length_m;
+  int32_t alias_fold;
+  int32_t pupil_n;
+  int32_t psf_t;
+  int32_t basis_k;
+  const double *basis;
+  int32_t p2s_mode;
+  int32_t precision;
+} tsim_params;
+
+/* Build the FP64 plan tables on the host and upload them: the Noll matrix
+ * A_0 and its lower Cholesky factor L (Sec. III-C: L L^T = A_0), the folded
+ * unit-mean per-mode spectra of the autocovariances A_ii (Sec. III-B/III-C),
+ * the Zernike pupil table for exact PSFs (Eq. (2), (5)) and the basis.  Uses
+ * the current HIP device.  On error *out is NULL. */
+int tsim_plan_create(const tsim_params *p, tsim_plan **out);
+
+/* The host half of plan creation without any device: validates `p`, builds
+ * the FP64 tables and copies table `what` (numbering of tsim_plan_table) to
+ * host_out.  For inspection and CPU-side tests of the plan builder. */
+int tsim_host_tables(const tsim_params *p, int what, double *host_out, size_t count);
+
+/* Free the plan's device tables.  NULL is accepted. */
+int tsim_plan_destroy(tsim_plan *plan);
+
+/* Bytes of caller-provided device workspace needed by calls on `frames`
+ * frames: the larger of the sampler's pass-1 intermediate (frames x 18 x
+ * H x Gw complex samples, chunked to about 2 GB) and the exact-P2S PSF
+ * buffer (up to 2^20 pixels x T*T floats).  The same workspace may be reused by consecutive calls on one
+ * stream. */
+int tsim_workspace_bytes(const tsim_plan *plan, int frames, size_t *bytes);
+
+/* Copy a plan table to host memory as float64, for inspection and tests.
+ *   what = 0: A_0 at D/r0 = 1, [35][35]
+ *   what = 1: L, [35][35] lower triangular
+ *   what = 2: sqrt of the quarter spectra, [35][Gw/2+1][Gh/2+1] (ky fastest)
+ *   what = 3: pixel pitch over D, [1]
+ * `count` is the number of doubles `host_out` can hold. */
+int tsim_plan_table(const tsim_plan *plan, int what, double *host_out, size_t count);
+
+/* (a) Zernike fields for `frames` frames (Sec. III-C):
+ *   step 1: for field q = 0..17 (modes 2+2q and 3+2q in its real and
+ *           imaginary parts), Hermitian white noise from Philox4x32-10 with
+ *           key (seed lo, seed hi) and counter (canonical bin, q, frame0+f,
+ *           0) is coloured by the square-root spectra and inverse-FFT'd on
+ *           the Gh x Gw grid (unitary scaling), then cropped to H x W;
+ *   step 2: a_x = (D/r0)^{5/6} L ybar_x at every pixel.
+ *   d_over_r0 : host [frames], each > 0 and finite
+ *   zern      : device [frames][35][H][W] float32, output
+ *   ws        : device workspace of tsim_workspace_bytes(plan, frames) */
+int tsim_sample_zernike(const tsim_plan *plan, int frames, const float *d_over_r0,
+                        uint64_t seed, uint64_t frame0, float *zern, void *ws,
+                        tsim_stream stream);
+
+/* (b) Basis weights beta[f][y][x][k] from Zernike fields (Sec. II-C).
+ *   Exact mode: the per-pixel PSF of Eq. (2) from modes 4..36 on the P x P
+ *   pupil, cropped to T x T around the zero frequency and normalised to unit
+ *   sum, projected on the basis (beta = Psi h).  Output float32.
+ *   Learned mode: the network of tsim_mlp_set_weights; output float32 or
+ *   bfloat16 per the plan's precision.
+ *   zern : device [frames][35][H][W] float32
+ *   beta : device [frames][H][W][K] */
+int tsim_p2s(const tsim_plan *plan, int frames, const float *zern, void *beta, void *ws,
+             tsim_stream stream);
+
+/* (c) Eq. (8): out_c(x) = sum_k beta_k(x) sum_u psi_k(u) img_c(clamp(x - u)),
+ * u in [-(T-1)/2, (T-1)/2]^2, a true convolution with replicated borders.
+ *   img, out : device [frames][C][H][W] float32, img != out
+ *   beta     : device [frames][H][W][K] (float32, or bfloat16 in BF16 plans) */
+int tsim_render(const tsim_plan *plan, int frames, const float *img, const void *beta,
+                float *out, void *ws, tsim_stream stream);
+
+/* (d) Tilt warp: out_c(x) = bilinear(img_c, x - t_x) with the four taps
+ * clamped to the image and t_x = -(4/pi) (a_{x,2}, a_{x,3}) pixels, read
+ * from planes 0 and 1 of zern (a pure tilt a_2 moves the Eq. (2) PSF by
+ * -4 a_2/pi samples).
+ *   img, out : device [frames][C][H][W] float32, img != out
+ *   zern     : device [frames][35][H][W] float32 */
+int tsim_warp(const tsim_plan *plan, int frames, const float *img, const float *zern,
+              float *out, tsim_stream stream);
+
+/* Exact PSFs of Eq. (2) for n Zernike vectors (modes 4..36 used):
+ *   zvec : device [n][35] float32;  psf : device [n][T*T] float32, unit sum. */
+int tsim_psf_exact(const tsim_plan *plan, int n, const float *zvec, float *psf,
+                   tsim_stream stream);
+
+/* Human-readable text for a status code. */
+const char *tsim_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSIM_H */

@@ -16,6 +16,9 @@ with |Q_j|^2 = (n+1) [2 J_{n+1}(pi f)/(pi f)]^2 Theta_j(phi_f) and
 Theta_j = 2cos^2(m phi), 2sin^2(m phi) or 1.  Its constant (and D/r0) drop
 out after normalising to unit variance.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 from scipy import special
 
@@ -96,7 +99,46 @@ def discrete_correlation(Sbar):
 
 
 def all_spectra(Gh, Gw, ds, fold=2, j_first=J_FIRST, j_last=J_LAST):
-    return np.stack([discrete_spectrum(j, Gh, Gw, ds, fold) for j in range(j_first, j_last + 1)])
+    """Stack of ``discrete_spectrum`` for modes j_first..j_last.  Same sums as
+    calling it per mode; the radial factor (one Bessel order per radial order
+    n) is evaluated once per alias and shared by the modes of that order."""
+    js = list(range(j_first, j_last + 1))
+    kx = signed_index(Gw) / (Gw * ds)
+    ky = signed_index(Gh) / (Gh * ds)
+    FX, FY = np.meshgrid(kx, ky)
+    orders = sorted({noll_nm(j)[0] for j in js})
+
+    def alias_term(l):
+        lx, ly = l
+        fx = FX + lx / ds
+        fy = FY + ly / ds
+        fr = np.hypot(fx, fy)
+        phi = np.arctan2(fy, fx)
+        safe = np.where(fr > 0, fr, 1.0)
+        xs = np.pi * safe
+        base = np.where(fr > 0, safe ** (-11.0 / 3.0), 0.0)
+        rad = {n: (n + 1) * (2.0 * special.jv(n + 1, xs) / xs) ** 2 * base for n in orders}
+        part = np.zeros((len(js), Gh, Gw))
+        for t, j in enumerate(js):
+            n, m = noll_nm(j)
+            kind = noll_kind(j)
+            if kind == '0':
+                part[t] = rad[n]
+            elif kind == 'c':
+                part[t] = rad[n] * 2.0 * np.cos(m * phi) ** 2
+            else:
+                part[t] = rad[n] * 2.0 * np.sin(m * phi) ** 2
+        return part
+
+    aliases = [(lx, ly) for lx in range(-fold, fold + 1) for ly in range(-fold, fold + 1)]
+    workers = min(len(aliases), os.cpu_count() or 1, 16)
+    S = np.zeros((len(js), Gh, Gw))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for part in ex.map(alias_term, aliases):   # summed in alias order
+            S += part
+    S[:, 0, 0] = 0.0
+    S *= (Gh * Gw) / S.sum(axis=(1, 2), keepdims=True)
+    return S
 
 
 def continuous_correlation(j, sx, sy, fmax=200.0, n_r=20000):

@@ -1,0 +1,213 @@
+"""MI355X dense-field phase-to-space turbulence renderer: Python binding.
+
+Thin ctypes binding over ``libtsim.so`` (declared in ``include/tsim.h``).
+The functions here only marshal arguments -- torch tensors become device
+pointers, the current torch stream becomes the HIP stream -- and every step
+of the renderer runs in the library's HIP kernels.  There is no CPU fallback:
+importing fails if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # loaded first so the library shares torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsim.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python paper_2210_06713_amd/build.py` "
+        "(the renderer has no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+N_MODES = 35
+OK, EINVAL, ENOMEM, EDEVICE, EARTEFACT, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+P2S_EXACT, P2S_LEARNED = 0, 1
+FP32, BF16 = 0, 1
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32),
+                ("Gh", ctypes.c_int32), ("Gw", ctypes.c_int32), ("n_modes", ctypes.c_int32),
+                ("pixel_pitch_over_d", ctypes.c_double), ("aperture_d_m", ctypes.c_double),
+                ("wavelength_m", ctypes.c_double), ("path_length_m", ctypes.c_double),
+                ("alias_fold", ctypes.c_int32), ("pupil_n", ctypes.c_int32),
+                ("psf_t", ctypes.c_int32), ("basis_k", ctypes.c_int32),
+                ("basis", ctypes.POINTER(ctypes.c_double)), ("p2s_mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_u64 = ctypes.c_uint64
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_lib_plan_create = _sig("tsim_plan_create", _i, [ctypes.POINTER(_Params), ctypes.POINTER(_vp)])
+_lib_plan_destroy = _sig("tsim_plan_destroy", _i, [_vp])
+_lib_ws = _sig("tsim_workspace_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_size_t)])
+_lib_table = _sig("tsim_plan_table", _i, [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
+_lib_sample = _sig("tsim_sample_zernike", _i,
+                   [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64, _vp, _vp, _vp])
+_lib_p2s = _sig("tsim_p2s", _i, [_vp, _i, _vp, _vp, _vp, _vp])
+_lib_render = _sig("tsim_render", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp])
+_lib_warp = _sig("tsim_warp", _i, [_vp, _i, _vp, _vp, _vp, _vp])
+_lib_psf = _sig("tsim_psf_exact", _i, [_vp, _i, _vp, _vp, _vp])
+_lib_status = _sig("tsim_status_string", ctypes.c_char_p, [_i])
+_lib_host_tables = _sig("tsim_host_tables", _i,
+                        [ctypes.POINTER(_Params), _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
+
+EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "tsim_plan_table",
+            "tsim_sample_zernike", "tsim_p2s", "tsim_render", "tsim_warp", "tsim_psf_exact",
+            "tsim_status_string", "tsim_host_tables"]
+
+
+class TsimError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {_lib_status(status).decode()} ({status})")
+        self.status = status
+
+
+def _check(status, what):
+    if status != OK:
+        raise TsimError(status, what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_params(H, W, C=1, Gh=None, Gw=None, pixel_pitch_over_d=0.125, aperture_d_m=0.0,
+                wavelength_m=0.0, path_length_m=0.0, alias_fold=2, pupil_n=64, psf_t=33,
+                basis_k=1, p2s_mode=P2S_EXACT, precision=FP32):
+    if Gh is None:
+        Gh = 1 << int(np.ceil(np.log2(2 * H)))
+    if Gw is None:
+        Gw = 1 << int(np.ceil(np.log2(2 * W)))
+    return _Params(H, W, C, Gh, Gw, N_MODES, pixel_pitch_over_d, aperture_d_m, wavelength_m,
+                   path_length_m, alias_fold, pupil_n, psf_t, basis_k, None, p2s_mode, precision)
+
+
+def host_tables(params, what):
+    """Run the host half of plan creation (no device) and return one table:
+    0 = A_0, 1 = L, 2 = sqrt quarter spectra [35][Gw/2+1][Gh/2+1], 3 = pitch."""
+    sizes = {0: N_MODES * N_MODES, 1: N_MODES * N_MODES,
+             2: N_MODES * (params.Gw // 2 + 1) * (params.Gh // 2 + 1), 3: 1}
+    out = np.zeros(sizes[what], dtype=np.float64)
+    _check(_lib_host_tables(ctypes.byref(params), what,
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size),
+           "tsim_host_tables")
+    if what in (0, 1):
+        return out.reshape(N_MODES, N_MODES)
+    if what == 2:
+        return out.reshape(N_MODES, params.Gw // 2 + 1, params.Gh // 2 + 1)
+    return out[0]
+
+
+class Plan:
+    """A renderer plan (``tsim_plan``): FP64 tables built once, then
+    immutable.  Sizes follow ``tsim_params`` in ``include/tsim.h``."""
+
+    def __init__(self, H, W, C=1, Gh=None, Gw=None, pixel_pitch_over_d=0.125,
+                 aperture_d_m=0.0, wavelength_m=0.0, path_length_m=0.0, alias_fold=2,
+                 pupil_n=64, psf_t=33, basis=None, basis_k=None, p2s_mode=P2S_EXACT,
+                 precision=FP32):
+        if Gh is None:
+            Gh = 1 << int(np.ceil(np.log2(2 * H)))
+        if Gw is None:
+            Gw = 1 << int(np.ceil(np.log2(2 * W)))
+        self._basis = None
+        bptr = None
+        if basis is not None:
+            self._basis = np.ascontiguousarray(basis, dtype=np.float64)
+            basis_k = self._basis.shape[0]
+            bptr = self._basis.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if basis_k is None:
+            basis_k = 1
+        self.params = _Params(H, W, C, Gh, Gw, N_MODES, pixel_pitch_over_d, aperture_d_m,
+                              wavelength_m, path_length_m, alias_fold, pupil_n, psf_t, basis_k,
+                              bptr, p2s_mode, precision)
+        self.H, self.W, self.C, self.Gh, self.Gw = H, W, C, Gh, Gw
+        self.T, self.K, self.P = psf_t, basis_k, pupil_n
+        h = _vp()
+        _check(_lib_plan_create(ctypes.byref(self.params), ctypes.byref(h)), "tsim_plan_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- plan tables -------------------------------------------------
+    def table(self, what):
+        sizes = {0: N_MODES * N_MODES, 1: N_MODES * N_MODES,
+                 2: N_MODES * (self.Gw // 2 + 1) * (self.Gh // 2 + 1), 3: 1}
+        out = np.zeros(sizes[what], dtype=np.float64)
+        _check(_lib_table(self._h, what, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          out.size), "tsim_plan_table")
+        if what in (0, 1):
+            return out.reshape(N_MODES, N_MODES)
+        if what == 2:
+            return out.reshape(N_MODES, self.Gw // 2 + 1, self.Gh // 2 + 1)
+        return out[0]
+
+    def workspace_bytes(self, frames):
+        n = ctypes.c_size_t()
+        _check(_lib_ws(self._h, frames, ctypes.byref(n)), "tsim_workspace_bytes")
+        return n.value
+
+    def workspace(self, frames, device="cuda"):
+        """Allocate a device workspace (plumbing only) for `frames` frames."""
+        n = max(self.workspace_bytes(frames), 256)
+        return torch.empty(n, dtype=torch.uint8, device=device)
+
+    # ---- hot path ----------------------------------------------------
+    def sample_zernike(self, d_over_r0, seed, frame0, zern, ws, stream=None):
+        d = np.ascontiguousarray(np.atleast_1d(d_over_r0), dtype=np.float32)
+        frames = zern.shape[0]
+        if d.size != frames:
+            raise ValueError("one D/r0 per frame expected")
+        _check(_lib_sample(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                           int(seed), int(frame0), _ptr(zern), _ptr(ws), _stream(stream)),
+               "tsim_sample_zernike")
+
+    def p2s(self, zern, beta, ws, stream=None):
+        _check(_lib_p2s(self._h, zern.shape[0], _ptr(zern), _ptr(beta), _ptr(ws), _stream(stream)),
+               "tsim_p2s")
+
+    def render(self, img, beta, out, ws=None, stream=None):
+        _check(_lib_render(self._h, img.shape[0], _ptr(img), _ptr(beta), _ptr(out), _ptr(ws),
+                           _stream(stream)), "tsim_render")
+
+    def warp(self, img, zern, out, stream=None):
+        _check(_lib_warp(self._h, img.shape[0], _ptr(img), _ptr(zern), _ptr(out), _stream(stream)),
+               "tsim_warp")
+
+    def psf_exact(self, zvec, psf, stream=None):
+        _check(_lib_psf(self._h, zvec.shape[0], _ptr(zvec), _ptr(psf), _stream(stream)),
+               "tsim_psf_exact")

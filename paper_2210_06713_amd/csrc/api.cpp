@@ -1,0 +1,79 @@
+// Per-frame entry points of the C ABI: argument validation, then launches.
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+bool frames_ok(const tsim_plan *pl, int frames) {
+  return pl && frames >= 1 && frames <= 65535;  // frames index grid z
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsim_workspace_bytes(const tsim_plan *pl, int frames, size_t *bytes) {
+  if (!bytes || !frames_ok(pl, frames)) return TSIM_EINVAL;
+  size_t a = sampler_ws_bytes(pl, frames);
+  size_t b = p2s_ws_bytes(pl, frames);
+  *bytes = a > b ? a : b;
+  return TSIM_OK;
+}
+
+int tsim_sample_zernike(const tsim_plan *pl, int frames, const float *d_over_r0, uint64_t seed,
+                        uint64_t frame0, float *zern, void *ws, tsim_stream stream) {
+  if (!frames_ok(pl, frames) || !d_over_r0 || !zern || !ws) return TSIM_EINVAL;
+  if (!aligned(zern) || !aligned(ws)) return TSIM_EINVAL;
+  if (frame0 + uint64_t(frames) > (uint64_t(1) << 32)) return TSIM_EINVAL;  // 32-bit frame counter
+  std::vector<float> scale(static_cast<size_t>(frames));
+  for (int f = 0; f < frames; ++f) {
+    double v = d_over_r0[f];
+    if (!(v > 0.0) || !std::isfinite(v)) return TSIM_EINVAL;
+    scale[f] = float(std::pow(v, 5.0 / 6.0));
+  }
+  return launch_sampler(pl, frames, scale.data(), seed, frame0, zern, ws,
+                        static_cast<hipStream_t>(stream));
+}
+
+int tsim_p2s(const tsim_plan *pl, int frames, const float *zern, void *beta, void *ws,
+             tsim_stream stream) {
+  if (!frames_ok(pl, frames) || !zern || !beta || !ws) return TSIM_EINVAL;
+  if (!aligned(zern) || !aligned(beta) || !aligned(ws)) return TSIM_EINVAL;
+  if (!pl->d_basis) return TSIM_EARTEFACT;
+  if (pl->p.p2s_mode != TSIM_P2S_EXACT) return TSIM_EUNSUPPORTED;
+  return launch_p2s_exact(pl, frames, zern, static_cast<float *>(beta), ws,
+                          static_cast<hipStream_t>(stream));
+}
+
+int tsim_render(const tsim_plan *pl, int frames, const float *img, const void *beta, float *out,
+                void *ws, tsim_stream stream) {
+  (void)ws;
+  if (!frames_ok(pl, frames) || !img || !beta || !out) return TSIM_EINVAL;
+  if (img == out) return TSIM_EINVAL;
+  if (!aligned(img) || !aligned(beta) || !aligned(out)) return TSIM_EINVAL;
+  if (!pl->d_basis) return TSIM_EARTEFACT;
+  if (pl->p.precision != TSIM_FP32) return TSIM_EUNSUPPORTED;
+  return launch_render_fp32(pl, frames, img, static_cast<const float *>(beta), out,
+                            static_cast<hipStream_t>(stream));
+}
+
+int tsim_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
+              tsim_stream stream) {
+  if (!frames_ok(pl, frames) || !img || !zern || !out) return TSIM_EINVAL;
+  if (img == out) return TSIM_EINVAL;
+  if (!aligned(img) || !aligned(zern) || !aligned(out)) return TSIM_EINVAL;
+  return launch_warp(pl, frames, img, zern, out, static_cast<hipStream_t>(stream));
+}
+
+int tsim_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, tsim_stream stream) {
+  if (!pl || n < 1 || !zvec || !psf) return TSIM_EINVAL;
+  if (!aligned(zvec) || !aligned(psf)) return TSIM_EINVAL;
+  return launch_psf_exact(pl, n, zvec, psf, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

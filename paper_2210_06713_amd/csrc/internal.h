@@ -1,0 +1,58 @@
+// Internal declarations shared by the host plan builder and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/tsim.h"
+
+#define TSIM_FIELDS 18        // complex fields carrying the 35 real modes
+#define TSIM_PSF_MODE0 2      // first mode index (0-based, Noll 4) inside the PSF
+
+struct tsim_plan {
+  tsim_params p;
+  double ds;                   // pixel pitch over D
+  int Gh, Gw, H, W, C, P, T, K;
+  int KP;                      // K padded to 32, 64, 112 or 128
+  // host FP64 copies (for tsim_plan_table)
+  std::vector<double> A0;      // [35][35] at D/r0 = 1
+  std::vector<double> L;       // [35][35] lower
+  std::vector<double> sqrtS;   // [35][Gw/2+1][Gh/2+1]
+  std::vector<double> basis;   // [K][T*T]
+  // device tables
+  float *d_sqrtS = nullptr;    // [35][Gw/2+1][Gh/2+1] float32
+  float2 *d_tw_h = nullptr;    // twiddles exp(+2 pi i k / Gh), k < Gh/2
+  float2 *d_tw_w = nullptr;    // twiddles exp(+2 pi i k / Gw), k < Gw/2
+  float *d_L = nullptr;        // [35][35] float32 lower
+  float *d_zpupil = nullptr;   // [P/2][P/2][36] Zernike modes 4..36 (zero padded) per window sample
+  int n_pupil = 0;             // NS
+  int pupil_win = 0;           // side of the square window holding the aperture
+  float *d_basis = nullptr;    // [K][T*T] float32
+  float *d_basis_t = nullptr;  // [T*T][KP] float32 (tap-major, zero padded)
+  float2 *d_tw_p = nullptr;    // twiddles exp(-2 pi i k / P), k < P
+};
+
+// ---- launchers (sampler.hip) ----
+int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
+                   uint64_t frame0, float *zern, void *ws, hipStream_t s);
+size_t sampler_ws_bytes(const tsim_plan *pl, int frames);
+
+// ---- launchers (psf.hip) ----
+int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, hipStream_t s);
+int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *beta, void *ws,
+                     hipStream_t s);
+size_t p2s_ws_bytes(const tsim_plan *pl, int frames);
+
+// ---- launchers (render.hip) ----
+int launch_render_fp32(const tsim_plan *pl, int frames, const float *img, const float *beta,
+                       float *out, hipStream_t s);
+int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
+                hipStream_t s);
+
+#define TSIM_HIP_CHECK(expr)                 \
+  do {                                       \
+    if ((expr) != hipSuccess) return TSIM_EDEVICE; \
+  } while (0)

@@ -1,0 +1,429 @@
+// Host-side FP64 plan tables and the plan half of the C ABI.
+//
+// Everything here runs once per plan on the CPU in float64 and is uploaded
+// to the device as float32:
+//   * the Noll covariance A_0 of the Zernike coefficients at one pixel
+//     (Sec. II-B; Sec. III-B: the s = 0 slice of the tensor of Eq. (6)) and
+//     its lower Cholesky factor L (Sec. III-C, Eq. (9): L L^T = A_0);
+//   * per-mode lattice spectra of the homogeneous autocovariances A_ii
+//     (Sec. III-B/III-C), square-rooted, stored as a quarter table;
+//   * the Zernike pupil table for the exact PSFs of Eq. (2);
+//   * the PSF basis of Eq. (7).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <thread>
+
+#include "internal.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- Noll ----
+void noll_nm(int j, int *n_out, int *m_out) {
+  int n = 0;
+  while ((n + 1) * (n + 2) / 2 < j) ++n;
+  int k = j - n * (n + 1) / 2;  // 1..n+1 inside the radial order
+  int m = (n % 2 == 0) ? 2 * (k / 2) : 2 * ((k - 1) / 2) + 1;
+  *n_out = n;
+  *m_out = m;
+}
+
+// Phase-spectrum constant for Phi(f) = c r0^{-5/3} f^{-11/3}, f in cycles per
+// metre, chosen so the structure function is Eq. (4)'s 6.88 (r/r0)^{5/3} with
+// 6.88 = 2[(24/5) Gamma(6/5)]^{5/6}.
+double kolmogorov_c() {
+  double bracket = 4.8 * std::tgamma(1.2);
+  return std::tgamma(11.0 / 6.0) * std::tgamma(11.0 / 6.0) / (2.0 * std::pow(kPi, 11.0 / 3.0)) *
+         std::pow(bracket, 5.0 / 6.0);
+}
+
+// Noll's closed form: the Zernike filters of a Kolmogorov screen integrate to
+// Gamma-function ratios (Weber-Schafheitlin, exponent 14/3).
+double noll_entry(int j, int jp, double kc) {
+  int n, m, np, mp;
+  noll_nm(j, &n, &m);
+  noll_nm(jp, &np, &mp);
+  if (m != mp) return 0.0;
+  if (m != 0 && (j % 2) != (jp % 2)) return 0.0;
+  double sign = (((n + np - 2 * m) / 2) % 2 == 0) ? 1.0 : -1.0;
+  double g = std::tgamma((n + np - 5.0 / 3.0) / 2.0) /
+             (std::tgamma((n - np + 17.0 / 3.0) / 2.0) * std::tgamma((np - n + 17.0 / 3.0) / 2.0) *
+              std::tgamma((n + np + 23.0 / 3.0) / 2.0));
+  return kc * sign * std::sqrt(double((n + 1) * (np + 1))) * g;
+}
+
+bool cholesky(const std::vector<double> &A, std::vector<double> &L, int n) {
+  L.assign(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double s = A[size_t(i) * n + j];
+      for (int k = 0; k < j; ++k) s -= L[size_t(i) * n + k] * L[size_t(j) * n + k];
+      if (i == j) {
+        if (!(s > 0.0)) return false;
+        L[size_t(i) * n + i] = std::sqrt(s);
+      } else {
+        L[size_t(i) * n + j] = s / L[size_t(j) * n + j];
+      }
+    }
+  }
+  return true;
+}
+
+// ------------------------------------------------------------- Bessel ----
+// J_0..J_nmax(x) for x >= 0 by Miller's downward recurrence
+//   J_{k-1} = (2k/x) J_k - J_{k+1},
+// started well above max(x, nmax) and normalised with the Neumann identity
+// J_0 + 2 sum_k J_{2k} = 1.  One pass gives every order needed by a
+// frequency sample.
+void bessel_j_orders(double x, int nmax, double *out) {
+  if (x < 1e-8) {
+    out[0] = 1.0;
+    for (int k = 1; k <= nmax; ++k) out[k] = 0.0;
+    // leading term (x/2)^k / k! keeps tiny-frequency spectra exact
+    double t = 1.0;
+    for (int k = 1; k <= nmax; ++k) {
+      t *= 0.5 * x / k;
+      out[k] = t;
+    }
+    return;
+  }
+  int start = int(std::max(x, double(nmax))) + 30 + int(12.0 * std::cbrt(x));
+  if (start & 1) ++start;
+  double jp1 = 0.0, j = 1e-300, norm = 0.0;
+  for (int k = start; k >= 1; --k) {
+    double jm1 = (2.0 * k / x) * j - jp1;
+    jp1 = j;
+    j = jm1;  // now J_{k-1}
+    int km1 = k - 1;
+    if (km1 <= nmax) out[km1] = j;
+    if (km1 % 2 == 0 && km1 > 0) norm += 2.0 * j;
+    if (std::fabs(j) > 1e250) {  // rescale to stay in range
+      j *= 1e-250;
+      jp1 *= 1e-250;
+      norm *= 1e-250;
+      for (int q = km1; q <= nmax; ++q) out[q] *= 1e-250;
+    }
+  }
+  norm += j;  // J_0
+  double inv = 1.0 / norm;
+  for (int k = 0; k <= nmax; ++k) out[k] *= inv;
+}
+
+// Spectrum of mode j (without its constant): f^{-11/3} |Q_j(f)|^2 with
+// |Q_j|^2 = (n+1) [2 J_{n+1}(pi f)/(pi f)]^2 Theta_j(phi), f in cycles per D.
+// `jb` holds J_0..J_8(pi f).  cos(m phi), sin(m phi) come from the caller.
+inline double mode_spectrum(int n, int m, int kind, double f, const double *jb, double cm,
+                            double sm) {
+  double x = kPi * f;
+  double r = 2.0 * jb[n + 1] / x;
+  double ang = (kind == 0) ? 1.0 : (kind == 1 ? 2.0 * cm * cm : 2.0 * sm * sm);
+  return std::pow(f, -11.0 / 3.0) * (n + 1) * r * r * ang;
+}
+
+struct ModeInfo {
+  int n, m, kind;  // kind 0: m = 0, 1: cosine (even j), 2: sine (odd j)
+};
+
+void build_spectra(tsim_plan *pl) {
+  const int Gh = pl->Gh, Gw = pl->Gw;
+  const int qh = Gh / 2 + 1, qw = Gw / 2 + 1;
+  const int A = pl->p.alias_fold;
+  const double ds = pl->ds;
+  ModeInfo mi[TSIM_N_MODES];
+  for (int t = 0; t < TSIM_N_MODES; ++t) {
+    int j = t + 2, n, m;
+    noll_nm(j, &n, &m);
+    mi[t] = {n, m, m == 0 ? 0 : (j % 2 == 0 ? 1 : 2)};
+  }
+  // quarter table S[mode][kx'][ky'] in float64
+  std::vector<double> S(size_t(TSIM_N_MODES) * qw * qh, 0.0);
+  auto work = [&](int kx0, int kx1) {
+    double jb[9];
+    double cm[8], sm[8];
+    for (int kx = kx0; kx < kx1; ++kx) {
+      for (int ky = 0; ky < qh; ++ky) {
+        if (kx == 0 && ky == 0) continue;  // DC removed
+        double acc[TSIM_N_MODES] = {0};
+        for (int lx = -A; lx <= A; ++lx) {
+          for (int ly = -A; ly <= A; ++ly) {
+            double fx = double(kx) / (Gw * ds) + lx / ds;
+            double fy = double(ky) / (Gh * ds) + ly / ds;
+            double f = std::hypot(fx, fy);
+            if (f == 0.0) continue;
+            bessel_j_orders(kPi * f, 8, jb);
+            double c1 = fx / f, s1 = fy / f;
+            cm[0] = 1.0;
+            sm[0] = 0.0;
+            for (int q = 1; q < 8; ++q) {
+              cm[q] = cm[q - 1] * c1 - sm[q - 1] * s1;
+              sm[q] = sm[q - 1] * c1 + cm[q - 1] * s1;
+            }
+            for (int t = 0; t < TSIM_N_MODES; ++t)
+              acc[t] += mode_spectrum(mi[t].n, mi[t].m, mi[t].kind, f, jb, cm[mi[t].m], sm[mi[t].m]);
+          }
+        }
+        for (int t = 0; t < TSIM_N_MODES; ++t) S[(size_t(t) * qw + kx) * qh + ky] = acc[t];
+      }
+    }
+  };
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  int chunk = (qw + nt - 1) / nt;
+  for (unsigned i = 0; i < nt; ++i) {
+    int a = int(i) * chunk, b = std::min(qw, a + chunk);
+    if (a < b) th.emplace_back(work, a, b);
+  }
+  for (auto &t : th) t.join();
+  // unit mean over the full Gh x Gw grid: interior quarter bins stand for
+  // two mirror bins per axis, the DC and Nyquist rows/columns for one.
+  pl->sqrtS.assign(S.size(), 0.0);
+  for (int t = 0; t < TSIM_N_MODES; ++t) {
+    double tot = 0.0;
+    for (int kx = 0; kx < qw; ++kx) {
+      double wx = (kx == 0 || kx == Gw / 2) ? 1.0 : 2.0;
+      for (int ky = 0; ky < qh; ++ky) {
+        double wy = (ky == 0 || ky == Gh / 2) ? 1.0 : 2.0;
+        tot += wx * wy * S[(size_t(t) * qw + kx) * qh + ky];
+      }
+    }
+    double scale = double(Gh) * Gw / tot;
+    for (size_t i = size_t(t) * qw * qh; i < size_t(t + 1) * qw * qh; ++i)
+      pl->sqrtS[i] = std::sqrt(S[i] * scale);
+  }
+}
+
+// Zernike Z_j(rho, theta), Noll normalisation (mean square 1 on the disc).
+double zernike(int j, double rho, double theta) {
+  int n, m;
+  noll_nm(j, &n, &m);
+  double r = 0.0;
+  for (int s = 0; s <= (n - m) / 2; ++s) {
+    double c = std::tgamma(n - s + 1.0) /
+               (std::tgamma(s + 1.0) * std::tgamma((n + m) / 2 - s + 1.0) *
+                std::tgamma((n - m) / 2 - s + 1.0));
+    r += ((s % 2) ? -c : c) * std::pow(rho, n - 2 * s);
+  }
+  r *= std::sqrt(double(n + 1));
+  if (m == 0) return r;
+  return (j % 2 == 0) ? r * std::sqrt(2.0) * std::cos(m * theta)
+                      : r * std::sqrt(2.0) * std::sin(m * theta);
+}
+
+template <class T>
+int upload(T **dst, const T *src, size_t n) {
+  if (hipMalloc(dst, n * sizeof(T)) != hipSuccess) {
+    *dst = nullptr;
+    return TSIM_ENOMEM;
+  }
+  if (hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return TSIM_EDEVICE;
+  return TSIM_OK;
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int validate(const tsim_params *p) {
+  if (!p) return TSIM_EINVAL;
+  if (p->H < 1 || p->W < 1 || p->H > 4096 || p->W > 4096) return TSIM_EINVAL;
+  if (p->C < 1 || p->C > 4) return TSIM_EINVAL;
+  if (!pow2(p->Gh) || !pow2(p->Gw) || p->Gh < 64 || p->Gw < 64 || p->Gh > 4096 || p->Gw > 4096)
+    return TSIM_EINVAL;
+  if (p->Gh < p->H || p->Gw < p->W) return TSIM_EINVAL;
+  if (p->n_modes != TSIM_N_MODES) return TSIM_EINVAL;
+  if (p->alias_fold < 0 || p->alias_fold > 4) return TSIM_EINVAL;
+  if (!(p->pixel_pitch_over_d > 0.0) || !std::isfinite(p->pixel_pitch_over_d)) {
+    if (!(p->aperture_d_m > 0.0) || !(p->wavelength_m > 0.0) || !(p->path_length_m > 0.0))
+      return TSIM_EINVAL;
+  }
+  if (p->pupil_n != 64 && p->pupil_n != 128) return TSIM_EUNSUPPORTED;
+  if (p->psf_t < 3 || (p->psf_t % 2) == 0 || p->psf_t > p->pupil_n / 2 + 1) return TSIM_EINVAL;
+  if (p->basis_k < 1 || p->basis_k > 128) return TSIM_EINVAL;
+  if (p->p2s_mode != TSIM_P2S_EXACT && p->p2s_mode != TSIM_P2S_LEARNED) return TSIM_EINVAL;
+  if (p->precision != TSIM_FP32 && p->precision != TSIM_BF16) return TSIM_EINVAL;
+  return TSIM_OK;
+}
+
+void free_plan(tsim_plan *pl) {
+  if (!pl) return;
+  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L,
+                  pl->d_zpupil, pl->d_basis, pl->d_basis_t, pl->d_tw_p};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  delete pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tsim_status_string(int s) {
+  switch (s) {
+    case TSIM_OK: return "ok";
+    case TSIM_EINVAL: return "invalid argument";
+    case TSIM_ENOMEM: return "out of memory";
+    case TSIM_EDEVICE: return "device or HIP runtime error";
+    case TSIM_EARTEFACT: return "basis or network weights missing or malformed";
+    case TSIM_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host half of plan creation: validated parameters -> FP64 tables.
+int build_host(const tsim_params *p, tsim_plan *pl) {
+  pl->p = *p;
+  pl->p.basis = nullptr;
+  pl->Gh = p->Gh;
+  pl->Gw = p->Gw;
+  pl->H = p->H;
+  pl->W = p->W;
+  pl->C = p->C;
+  pl->P = p->pupil_n;
+  pl->T = p->psf_t;
+  pl->K = p->basis_k;
+  pl->KP = p->basis_k <= 32 ? 32 : p->basis_k <= 64 ? 64 : p->basis_k <= 112 ? 112 : 128;
+  pl->ds = (p->pixel_pitch_over_d > 0.0)
+               ? p->pixel_pitch_over_d
+               : p->path_length_m * p->wavelength_m / (2.0 * p->aperture_d_m * p->aperture_d_m);
+  // Noll matrix and its Cholesky factor
+  const int N = TSIM_N_MODES;
+  double c = kolmogorov_c();
+  double kc = 8.0 * c * std::pow(kPi, 8.0 / 3.0) * std::tgamma(14.0 / 3.0) / std::pow(2.0, 14.0 / 3.0);
+  pl->A0.assign(size_t(N) * N, 0.0);
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) pl->A0[size_t(a) * N + b] = noll_entry(a + 2, b + 2, kc);
+  if (!cholesky(pl->A0, pl->L, N)) return TSIM_EINVAL;
+  build_spectra(pl);
+  return TSIM_OK;
+}
+
+int copy_table(const tsim_plan *pl, int what, double *host_out, size_t count) {
+  const std::vector<double> *src = nullptr;
+  switch (what) {
+    case 0: src = &pl->A0; break;
+    case 1: src = &pl->L; break;
+    case 2: src = &pl->sqrtS; break;
+    case 3:
+      if (count < 1) return TSIM_EINVAL;
+      host_out[0] = pl->ds;
+      return TSIM_OK;
+    default: return TSIM_EINVAL;
+  }
+  if (count < src->size()) return TSIM_EINVAL;
+  std::memcpy(host_out, src->data(), src->size() * sizeof(double));
+  return TSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsim_host_tables(const tsim_params *p, int what, double *host_out, size_t count) {
+  if (!host_out) return TSIM_EINVAL;
+  int st = validate(p);
+  if (st != TSIM_OK) return st;
+  tsim_plan *pl = new (std::nothrow) tsim_plan();
+  if (!pl) return TSIM_ENOMEM;
+  st = build_host(p, pl);
+  if (st == TSIM_OK) st = copy_table(pl, what, host_out, count);
+  delete pl;
+  return st;
+}
+
+int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
+  if (!out) return TSIM_EINVAL;
+  *out = nullptr;
+  int st = validate(p);
+  if (st != TSIM_OK) return st;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return TSIM_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TSIM_EDEVICE;
+
+  tsim_plan *pl = new (std::nothrow) tsim_plan();
+  if (!pl) return TSIM_ENOMEM;
+  if ((st = build_host(p, pl)) != TSIM_OK) {
+    free_plan(pl);
+    return st;
+  }
+  // device tables
+  std::vector<float> f32(pl->sqrtS.begin(), pl->sqrtS.end());
+  if ((st = upload(&pl->d_sqrtS, f32.data(), f32.size())) != TSIM_OK) goto fail;
+  {
+    std::vector<float2> tw(static_cast<size_t>(pl->Gh / 2));
+    for (int k = 0; k < pl->Gh / 2; ++k)
+      tw[k] = make_float2(float(std::cos(2 * kPi * k / pl->Gh)), float(std::sin(2 * kPi * k / pl->Gh)));
+    if ((st = upload(&pl->d_tw_h, tw.data(), tw.size())) != TSIM_OK) goto fail;
+    std::vector<float2> tw2(static_cast<size_t>(pl->Gw / 2));
+    for (int k = 0; k < pl->Gw / 2; ++k)
+      tw2[k] = make_float2(float(std::cos(2 * kPi * k / pl->Gw)), float(std::sin(2 * kPi * k / pl->Gw)));
+    if ((st = upload(&pl->d_tw_w, tw2.data(), tw2.size())) != TSIM_OK) goto fail;
+    std::vector<float> Lf(pl->L.begin(), pl->L.end());
+    if ((st = upload(&pl->d_L, Lf.data(), Lf.size())) != TSIM_OK) goto fail;
+  }
+  {
+    // Pupil: P x P samples, aperture diameter P/2 centred on sample P/2,
+    // samples strictly inside the unit circle.  The window is the
+    // (P/2) x (P/2) square of offsets [-P/4, P/4) around the centre.
+    const int P = pl->P, R = P / 4, win = P / 2;
+    pl->pupil_win = win;
+    const int NZ = 33, NZP = 36;  // modes 4..36, padded to 36 floats per sample
+    std::vector<float> zt(size_t(win) * win * NZP, 0.0f);  // [row][col][mode], zero outside
+    for (int r = 0; r < win; ++r) {
+      for (int cc = 0; cc < win; ++cc) {
+        int dy = r - R, dx = cc - R;
+        double xr = double(dx) / R, yr = double(dy) / R;
+        double rho = std::hypot(xr, yr);
+        if (!(rho < 1.0)) continue;
+        double th = std::atan2(yr, xr);
+        for (int t = 0; t < NZ; ++t) zt[(size_t(r) * win + cc) * NZP + t] = float(zernike(t + 4, rho, th));
+        pl->n_pupil++;
+      }
+    }
+    if ((st = upload(&pl->d_zpupil, zt.data(), zt.size())) != TSIM_OK) goto fail;
+    std::vector<float2> twp(static_cast<size_t>(P));
+    for (int k = 0; k < P; ++k)
+      twp[k] = make_float2(float(std::cos(2 * kPi * k / P)), float(-std::sin(2 * kPi * k / P)));
+    if ((st = upload(&pl->d_tw_p, twp.data(), twp.size())) != TSIM_OK) goto fail;
+  }
+  if (p->basis) {
+    const int T2 = pl->T * pl->T, K = pl->K, KP = pl->KP;
+    pl->basis.assign(p->basis, p->basis + size_t(K) * T2);
+    for (double v : pl->basis)
+      if (!std::isfinite(v)) {
+        st = TSIM_EARTEFACT;
+        goto fail;
+      }
+    std::vector<float> b(size_t(K) * T2), bt(size_t(KP) * T2, 0.0f);
+    for (int k = 0; k < K; ++k)
+      for (int t = 0; t < T2; ++t) {
+        b[size_t(k) * T2 + t] = float(pl->basis[size_t(k) * T2 + t]);
+        bt[size_t(t) * KP + k] = float(pl->basis[size_t(k) * T2 + t]);
+      }
+    if ((st = upload(&pl->d_basis, b.data(), b.size())) != TSIM_OK) goto fail;
+    if ((st = upload(&pl->d_basis_t, bt.data(), bt.size())) != TSIM_OK) goto fail;
+  }
+  *out = pl;
+  return TSIM_OK;
+fail:
+  free_plan(pl);
+  return st;
+}
+
+int tsim_plan_destroy(tsim_plan *pl) {
+  free_plan(pl);
+  return TSIM_OK;
+}
+
+int tsim_plan_table(const tsim_plan *pl, int what, double *host_out, size_t count) {
+  if (!pl || !host_out) return TSIM_EINVAL;
+  return copy_table(pl, what, host_out, count);
+}
+
+}  // extern "C"

@@ -1,0 +1,308 @@
+// Exact per-pixel PSFs (Eq. (2)) and their projection on the PSF basis
+// (Eq. (7)): the plain form of the phase-to-space step.
+//
+// k_psf64 (pupil P = 64, aperture diameter 32 samples, crop T <= 33):
+// 32 lanes (half a wavefront) own one pixel.  The pupil function
+// P(xi) exp(-i phi(xi)) is non-zero only on the 31 x 31 window around the
+// pupil centre, and only the 33 x 33 lowest frequencies of the 64 x 64 DFT are
+// kept, so the DFT is pruned on both sides: a 64-point DFT of 32 samples at
+// 33 frequencies splits into the 32-point DFTs of x[c] (even frequencies)
+// and x[c] exp(-2 pi i c/64) (odd frequencies).  Stage 1: lane = pupil row,
+// two register FFT-32s along x.  Stage 2 (after an LDS transpose): lane =
+// frequency column, two FFT-32s along y; the 33rd column is a direct
+// 32-term DFT shared by the lanes.  |.|^2, unit-sum normalisation, write.
+//
+// k_project: beta[p][k] = sum_t h[p][t] psi[k][t], an FP32 GEMM tiled through
+// LDS (64 pixels x KP weights per block).
+#include <algorithm>
+
+#include "common.cuh"
+#include "internal.h"
+#include "twiddle64.h"
+
+namespace {
+
+using tsim::cmul;
+
+constexpr int kZPad = 36;  // modes 4..36 padded to 36 floats per pupil sample
+
+constexpr int brev5(int v) {
+  return ((v & 1) << 4) | ((v & 2) << 2) | (v & 4) | ((v & 8) >> 2) | ((v & 16) >> 4);
+}
+
+__device__ __forceinline__ float2 f2add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 f2sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// Forward 32-point DFT in registers, natural order in and out.
+__device__ __forceinline__ void fft32_fwd(float2 (&x)[32]) {
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const int j = brev5(i);
+    if (j > i) {
+      float2 t = x[i];
+      x[i] = x[j];
+      x[j] = t;
+    }
+  }
+#pragma unroll
+  for (int hs = 1; hs < 32; hs <<= 1) {
+#pragma unroll
+    for (int g = 0; g < 32; g += 2 * hs) {
+#pragma unroll
+      for (int j = 0; j < hs; ++j) {
+        float2 a = x[g + j], b = x[g + j + hs];
+        float2 t;
+        if (j == 0) {
+          t = b;
+        } else {
+          const int k = j * (32 / hs);  // omega_{2hs}^j = exp(-2 pi i j/(2 hs)) = W64[j * 32/hs]
+          t = cmul(make_float2(kW64re[k], kW64im[k]), b);
+        }
+        x[g + j] = f2add(a, t);
+        x[g + j + hs] = f2sub(a, t);
+      }
+    }
+  }
+}
+
+// value of the 64-point DFT at signed frequency k in [-16, 16] from the two
+// 32-point DFTs: even k from E, odd k from O
+__device__ __forceinline__ float2 pick(const float2 (&E)[32], const float2 (&O)[32], int k) {
+  return (k & 1) ? O[((k - 1) >> 1) & 31] : E[(k >> 1) & 31];
+}
+
+template <int T>
+__global__ void __launch_bounds__(256)
+k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
+        const float *__restrict__ zt, float *__restrict__ psf) {
+  constexpr int R = (T - 1) / 2;  // crop radius, <= 16
+  constexpr int LS = 33;          // LDS row stride (complex)
+  __shared__ float2 s1[8][32 * LS];
+  const int lane = threadIdx.x & 31;
+  const int slot = threadIdx.x >> 5;  // half-wave within the block
+  float2 *buf = s1[slot];
+  const int p = blockIdx.x * 8 + slot;
+  const bool active = p < n_pix;
+  const int pc = active ? p : 0;
+
+  // Zernike coefficients of modes 4..36 of this pixel
+  float a[33];
+  {
+    const size_t pg = p_base + size_t(pc);  // pixel index into zern
+    const size_t fr = pg / size_t(hw), yx = pg - fr * size_t(hw);
+    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
+#pragma unroll
+    for (int t = 0; t < 33; ++t) a[t] = zp[size_t(t + TSIM_PSF_MODE0) * hw];
+  }
+
+  // ---- stage 1: lane = window row wr, pupil row offset r' = wr - 16 ----
+  float2 E[32], O[32];
+  {
+    const int wr = lane;
+    const int rp = wr - 16;
+#pragma unroll
+    for (int n = 0; n < 32; ++n) {
+      const int cp = (n < 16) ? n : n - 32;  // signed column offset
+      const int wc = cp + 16;
+      float2 v = make_float2(0.f, 0.f);
+      if (rp * rp + cp * cp < 256) {
+        const float4 *zs = reinterpret_cast<const float4 *>(zt + (size_t(wr) * 32 + wc) * kZPad);
+        float phi = 0.f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          float4 z = zs[q];
+          phi = fmaf(a[4 * q + 0], z.x, phi);
+          if (4 * q + 1 < 33) phi = fmaf(a[4 * q + 1], z.y, phi);
+          if (4 * q + 2 < 33) phi = fmaf(a[4 * q + 2], z.z, phi);
+          if (4 * q + 3 < 33) phi = fmaf(a[4 * q + 3], z.w, phi);
+        }
+        float sn, cs;
+        sincosf(phi, &sn, &cs);
+        v = make_float2(cs, -sn);  // exp(-i phi)
+      }
+      E[n] = v;
+      const int k = (cp + 64) & 63;  // exp(-2 pi i c'/64)
+      O[n] = cmul(make_float2(kW64re[k], kW64im[k]), v);
+    }
+    fft32_fwd(E);
+    fft32_fwd(O);
+    // X1[r'][kx] for kx in [-16, 16] -> buf[wr][kx + 16]
+#pragma unroll
+    for (int kx = -16; kx <= 16; ++kx) buf[wr * LS + kx + 16] = pick(E, O, kx);
+  }
+  __syncthreads();
+
+  // ---- stage 2: lane = frequency column kx = lane - 16 ----
+  float h[T];
+  float hx[2] = {0.f, 0.f};  // column kx = +16: rows ky = lane - 16 and (lane 0) ky = +16
+  float total = 0.f;
+  {
+    const int col = lane;
+#pragma unroll
+    for (int n = 0; n < 32; ++n) {
+      const int rp = (n < 16) ? n : n - 32;
+      float2 v = buf[(rp + 16) * LS + col];
+      E[n] = v;
+      const int k = (rp + 64) & 63;
+      O[n] = cmul(make_float2(kW64re[k], kW64im[k]), v);
+    }
+    fft32_fwd(E);
+    fft32_fwd(O);
+    const int kx = lane - 16;
+#pragma unroll
+    for (int ky = -R; ky <= R; ++ky) {
+      float2 v = pick(E, O, ky);
+      float m = v.x * v.x + v.y * v.y;
+      h[ky + R] = m;
+      if (kx >= -R && kx <= R) total += m;
+    }
+    if (R == 16) {
+      // direct DFT of the column kx = +16 over rows r' in [-16, 15]
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int ky = (s == 0) ? lane - 16 : 16;
+        if (s == 1 && lane != 0) break;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int wr = 0; wr < 32; ++wr) {
+          const int rp = wr - 16;
+          const int k = (ky * rp + 64 * 64) & 63;
+          acc = f2add(acc, cmul(make_float2(kW64re[k], kW64im[k]), buf[wr * LS + 32]));
+        }
+        float m = acc.x * acc.x + acc.y * acc.y;
+        hx[s] = m;
+        total += m;
+      }
+    }
+  }
+  // unit-sum normalisation over the T x T crop (32-lane reduction)
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) total += __shfl_xor(total, off, 32);
+  const float inv = 1.0f / total;
+  if (active) {
+    float *out = psf + size_t(p) * T * T;
+    const int kx = lane - 16;
+    if (kx >= -R && kx <= R) {
+#pragma unroll
+      for (int ky = -R; ky <= R; ++ky) out[(ky + R) * T + (kx + R)] = h[ky + R] * inv;
+    }
+    if (R == 16) {
+      out[(lane - 16 + R) * T + (16 + R)] = hx[0] * inv;
+      if (lane == 0) out[(16 + R) * T + (16 + R)] = hx[1] * inv;
+    }
+  }
+}
+
+template <int KP>
+__global__ void __launch_bounds__(256)
+k_project(const float *__restrict__ h, const float *__restrict__ psi_t, float *__restrict__ beta,
+          int n, int T2, int K) {
+  __shared__ float As[32][64 + 4];
+  __shared__ float Bs[32][KP];
+  constexpr int NB = KP / 16;
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  const int p0 = blockIdx.x * 64;
+  float acc[4][NB];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = 0.f;
+  for (int t0 = 0; t0 < T2; t0 += 32) {
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      const int px = e >> 5, tt = e & 31;
+      const int gp = p0 + px, gt = t0 + tt;
+      As[tt][px] = (gp < n && gt < T2) ? h[size_t(gp) * T2 + gt] : 0.f;
+    }
+    for (int e = threadIdx.x; e < 32 * KP; e += 256) {
+      const int tt = e / KP, kk = e - tt * KP;
+      const int gt = t0 + tt;
+      Bs[tt][kk] = (gt < T2) ? psi_t[size_t(gt) * KP + kk] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int tt = 0; tt < 32; ++tt) {
+      float4 av = *reinterpret_cast<const float4 *>(&As[tt][tr * 4]);
+      float b[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) b[j] = Bs[tt][tc + 16 * j];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        acc[0][j] = fmaf(av.x, b[j], acc[0][j]);
+        acc[1][j] = fmaf(av.y, b[j], acc[1][j]);
+        acc[2][j] = fmaf(av.z, b[j], acc[2][j]);
+        acc[3][j] = fmaf(av.w, b[j], acc[3][j]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gp = p0 + tr * 4 + i;
+    if (gp >= n) continue;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int k = tc + 16 * j;
+      if (k < K) beta[size_t(gp) * K + k] = acc[i][j];
+    }
+  }
+}
+
+int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_base, int n, float *psf,
+                    hipStream_t s) {
+  if (pl->P != 64) return TSIM_EUNSUPPORTED;
+  dim3 grid((n + 7) / 8);
+  const float *zt = pl->d_zpupil;
+  switch (pl->T) {
+    case 33: hipLaunchKernelGGL(k_psf64<33>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
+    case 31: hipLaunchKernelGGL(k_psf64<31>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
+    case 21: hipLaunchKernelGGL(k_psf64<21>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
+    case 15: hipLaunchKernelGGL(k_psf64<15>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
+    case 9: hipLaunchKernelGGL(k_psf64<9>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
+    default: return TSIM_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s) {
+  const int T2 = pl->T * pl->T;
+  dim3 grid((n + 63) / 64);
+  switch (pl->KP) {
+    case 32: hipLaunchKernelGGL(k_project<32>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
+    case 64: hipLaunchKernelGGL(k_project<64>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
+    case 112: hipLaunchKernelGGL(k_project<112>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
+    default: hipLaunchKernelGGL(k_project<128>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
+  }
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+// pixels per P2S chunk: bounds the PSF workspace
+size_t p2s_chunk(const tsim_plan *pl, size_t total) {
+  size_t cap = size_t(1) << 20;
+  return std::min(total, cap);
+}
+
+}  // namespace
+
+size_t p2s_ws_bytes(const tsim_plan *pl, int frames) {
+  size_t total = size_t(frames) * pl->H * pl->W;
+  return p2s_chunk(pl, total) * size_t(pl->T) * pl->T * sizeof(float);
+}
+
+int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, hipStream_t s) {
+  return launch_psf_impl(pl, zvec, 1, 0, n, psf, s);
+}
+
+int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *beta, void *ws,
+                     hipStream_t s) {
+  const int hw = pl->H * pl->W;
+  const size_t total = size_t(frames) * hw;
+  const size_t chunk = p2s_chunk(pl, total);
+  float *h = static_cast<float *>(ws);
+  for (size_t p0 = 0; p0 < total; p0 += chunk) {
+    const int n = int(std::min(chunk, total - p0));
+    int st = launch_psf_impl(pl, zern, hw, p0, n, h, s);
+    if (st != TSIM_OK) return st;
+    st = launch_project(pl, h, n, beta + p0 * pl->K, s);
+    if (st != TSIM_OK) return st;
+  }
+  return TSIM_OK;
+}

@@ -1,0 +1,127 @@
+// Image formation: the basis-weighted blur of Eq. (8) and the tilt warp.
+//
+// k_render_fp32: one thread per output pixel of a 16 x 16 tile.  The image
+// tile with its (T-1)/2 halo (borders replicated) sits in LDS for every
+// channel; the pixel's K weights sit in registers.  For each tap u the
+// reconstructed PSF value h(u) = sum_k beta_k psi_k(u) is formed once and
+// applied to all channels, so the sum of Eq. (8) is evaluated in the
+// reconstruct-first order, sum_u (sum_k beta_k psi_k(u)) I(x - u), which is
+// the same quantity with about C times fewer multiply-adds.
+//
+// k_warp: out(x) = bilinear(img, x - t_x), t_x = -(4/pi)(a_2, a_3).
+#include <algorithm>
+
+#include "common.cuh"
+#include "internal.h"
+
+namespace {
+
+constexpr int kTile = 16;
+
+template <int KP>
+__global__ void __launch_bounds__(256)
+k_render_fp32(const float *__restrict__ img, const float *__restrict__ beta,
+              const float *__restrict__ psi_t /*[T*T][KP]*/, float *__restrict__ out, int H, int W,
+              int C, int T, int K) {
+  extern __shared__ float tile[];  // [C][S][S], S = kTile + T - 1
+  const int r = (T - 1) / 2;
+  const int S = kTile + T - 1;
+  const int f = blockIdx.z;
+  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
+  const float *imf = img + size_t(f) * C * H * W;
+  for (int e = threadIdx.x; e < C * S * S; e += blockDim.x) {
+    int c = e / (S * S);
+    int rem = e - c * S * S;
+    int sy = rem / S, sx = rem - sy * S;
+    int gy = min(max(ty0 + sy - r, 0), H - 1);
+    int gx = min(max(tx0 + sx - r, 0), W - 1);
+    tile[e] = imf[(size_t(c) * H + gy) * W + gx];
+  }
+  const int ly = threadIdx.x / kTile, lx = threadIdx.x % kTile;
+  const int y = ty0 + ly, x = tx0 + lx;
+  const bool valid = (y < H) && (x < W);
+  float b[KP];
+  const float *bp = beta + ((size_t(f) * H + (valid ? y : 0)) * W + (valid ? x : 0)) * K;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) b[k] = (k < K) ? bp[k] : 0.f;
+  __syncthreads();
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int uy = -r; uy <= r; ++uy) {
+    // offset u = (ux, uy) reads img(x - u): tile index (ly + r - uy, lx + r - ux)
+    const int rowb = (ly + r - uy) * S + lx + r;
+    const float *pt = psi_t + size_t((uy + r) * T) * KP;
+    for (int ux = -r; ux <= r; ++ux, pt += KP) {
+      float h = 0.f;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) h = fmaf(b[k], pt[k], h);
+      const int idx = rowb - ux;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < C) acc[c] = fmaf(h, tile[c * S * S + idx], acc[c]);
+    }
+  }
+  if (valid) {
+    float *o = out + size_t(f) * C * H * W;
+    for (int c = 0; c < C; ++c) o[(size_t(c) * H + y) * W + x] = acc[c];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_warp(const float *__restrict__ img, const float *__restrict__ zern, float *__restrict__ out,
+       int H, int W, int C) {
+  const int f = blockIdx.z;
+  const int y = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= W) return;
+  const size_t plane = size_t(H) * W;
+  const float *zf = zern + size_t(f) * TSIM_N_MODES * plane;
+  const float k = -1.27323954473516268f;  // -4/pi pixels per radian of tilt
+  const float tx = k * zf[size_t(y) * W + x];
+  const float ty = k * zf[plane + size_t(y) * W + x];
+  const float px = float(x) - tx, py = float(y) - ty;
+  const float fx0 = floorf(px), fy0 = floorf(py);
+  const float fx = px - fx0, fy = py - fy0;
+  // clamp in float first so huge displacements cannot overflow the int cast
+  const int x0 = int(fminf(fmaxf(fx0, -1.f), float(W)));
+  const int y0 = int(fminf(fmaxf(fy0, -1.f), float(H)));
+  const int x0c = min(max(x0, 0), W - 1), x1c = min(max(x0 + 1, 0), W - 1);
+  const int y0c = min(max(y0, 0), H - 1), y1c = min(max(y0 + 1, 0), H - 1);
+  const float *imf = img + size_t(f) * C * plane;
+  float *of = out + size_t(f) * C * plane;
+  for (int c = 0; c < C; ++c) {
+    const float *p = imf + size_t(c) * plane;
+    float v00 = p[size_t(y0c) * W + x0c], v01 = p[size_t(y0c) * W + x1c];
+    float v10 = p[size_t(y1c) * W + x0c], v11 = p[size_t(y1c) * W + x1c];
+    float top = fmaf(fx, v01 - v00, v00);
+    float bot = fmaf(fx, v11 - v10, v10);
+    of[size_t(c) * plane + size_t(y) * W + x] = fmaf(fy, bot - top, top);
+  }
+}
+
+}  // namespace
+
+int launch_render_fp32(const tsim_plan *pl, int frames, const float *img, const float *beta,
+                       float *out, hipStream_t s) {
+  const int H = pl->H, W = pl->W, C = pl->C, T = pl->T, K = pl->K;
+  const int S = kTile + T - 1;
+  size_t lds = size_t(C) * S * S * sizeof(float);
+  if (lds > 64 * 1024) return TSIM_EUNSUPPORTED;
+  dim3 grid((W + kTile - 1) / kTile, (H + kTile - 1) / kTile, frames);
+  const int KP = pl->KP;
+  if (KP == 32)
+    hipLaunchKernelGGL(k_render_fp32<32>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
+  else if (KP == 64)
+    hipLaunchKernelGGL(k_render_fp32<64>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
+  else if (KP == 112)
+    hipLaunchKernelGGL(k_render_fp32<112>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
+  else
+    hipLaunchKernelGGL(k_render_fp32<128>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
+                hipStream_t s) {
+  dim3 grid((pl->W + 255) / 256, pl->H, frames);
+  hipLaunchKernelGGL(k_warp, grid, dim3(256), 0, s, img, zern, out, pl->H, pl->W, pl->C);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}

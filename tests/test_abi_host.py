@@ -1,0 +1,82 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol that
+include/tsim.h declares, validates arguments, and its host plan builder
+(FP64 Noll matrix, Cholesky factor, folded lattice spectra) agrees with the
+independent oracle.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import spectra as ospec
+from oracle import zernike as ozern
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def t():
+    import paper_2210_06713_amd as t
+    return t
+
+
+def test_library_exports_every_declared_symbol(t):
+    hdr = open(os.path.join(ROOT, "include", "tsim.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|const char \*)\s*(tsim_\w+)\s*\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    lib = ctypes.CDLL(t.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared <= set(t.EXPORTED)
+
+
+def test_status_strings(t):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert t._lib_status(code)
+    assert t._lib_status(-99) == b"unknown status"
+
+
+@pytest.mark.parametrize("field,value", [
+    ("H", 0), ("Gh", 96), ("Gw", 32), ("n_modes", 36), ("psf_t", 32), ("psf_t", 1),
+    ("basis_k", 0), ("basis_k", 200), ("alias_fold", 7), ("C", 0), ("precision", 5)])
+def test_invalid_parameters_rejected(t, field, value):
+    p = t.make_params(64, 64, 1, 128, 128)
+    setattr(p, field, value)
+    with pytest.raises(t.TsimError) as e:
+        t.host_tables(p, 0)
+    assert e.value.status == t.EINVAL
+
+
+def test_grid_smaller_than_image_rejected(t):
+    p = t.make_params(200, 64, 1, 128, 128)
+    with pytest.raises(t.TsimError):
+        t.host_tables(p, 0)
+
+
+def test_pitch_from_optics(t):
+    p = t.make_params(64, 64, 1, 128, 128, pixel_pitch_over_d=0.0, aperture_d_m=0.1,
+                      wavelength_m=0.5e-6, path_length_m=5000.0)
+    assert abs(t.host_tables(p, 3) - 0.125) < 1e-15
+    p = t.make_params(64, 64, 1, 128, 128, pixel_pitch_over_d=0.0)
+    with pytest.raises(t.TsimError):
+        t.host_tables(p, 0)
+
+
+def test_noll_and_cholesky_match_oracle(t):
+    p = t.make_params(64, 64, 1, 128, 128)
+    A0 = t.host_tables(p, 0)
+    L = t.host_tables(p, 1)
+    ref = ozern.noll_matrix(1.0)
+    np.testing.assert_allclose(A0, ref, rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(L, ozern.cholesky_lower(ref), rtol=1e-11, atol=1e-15)
+
+
+@pytest.mark.parametrize("Gh,Gw,ds,fold", [(128, 128, 0.125, 2), (64, 256, 0.25, 1), (256, 128, 0.125, 3)])
+def test_spectra_match_oracle(t, Gh, Gw, ds, fold):
+    p = t.make_params(32, 32, 1, Gh, Gw, pixel_pitch_over_d=ds, alias_fold=fold)
+    sq = t.host_tables(p, 2)                 # [35][Gw/2+1][Gh/2+1]
+    for j in [2, 3, 4, 7, 12, 20, 36]:
+        S = ospec.discrete_spectrum(j, Gh, Gw, ds, fold)   # [ky][kx]
+        quarter = np.sqrt(S[:Gh // 2 + 1, :Gw // 2 + 1]).T  # [kx][ky]
+        np.testing.assert_allclose(sq[j - 2], quarter, rtol=1e-11, atol=1e-14)

@@ -1,0 +1,231 @@
+"""GPU parity: every hot-path call through the C ABI against the FP64 oracle
+on the same seeded inputs.
+
+Bar (FP32 paths): relative L2 error ||gpu - oracle|| / ||oracle|| <= 1e-5 per
+coefficient plane, per PSF batch, per weight array and per image; the FP32
+kernels accumulate a few dozen rounding steps (two FFT passes, a 33-term
+phase sum, 1089-term projections), each ~6e-8 relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import psf as opsf  # noqa: E402
+from oracle import render as orender  # noqa: E402
+from oracle import sampler as osamp  # noqa: E402
+from oracle import spectra as ospec  # noqa: E402
+from oracle import zernike as ozern  # noqa: E402
+import synthetic  # noqa: E402
+
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def t():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2210_06713_amd as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def basis33():
+    A, _ = opsf.basis_draws(1500, seed=2024)
+    H = opsf.psf_batch(A, 64, 33)
+    Psi, _ = opsf.pca_basis(H, 100)
+    return Psi
+
+
+def _sample(t, plan, d_over_r0, seed, frame0, frames):
+    dev = torch.device("cuda")
+    zern = torch.empty((frames, 35, plan.H, plan.W), dtype=torch.float32, device=dev)
+    ws = plan.workspace(frames)
+    plan.sample_zernike(d_over_r0, seed, frame0, zern, ws)
+    torch.cuda.synchronize()
+    return zern
+
+
+@pytest.mark.parametrize("H,W,Gh,Gw,seed,frame0,dr", [
+    (64, 64, 128, 128, 0, 0, 2.0),             # 64 x 64 workload, G = 128
+    (48, 80, 128, 256, 2 ** 40 + 77, 5, 3.3),  # ragged, non-square, 64-bit seed
+    (64, 64, 64, 64, 11, 0, 1.0),              # grid equal to the image
+])
+def test_sampler_matches_oracle(t, H, W, Gh, Gw, seed, frame0, dr):
+    say(f"sampler H={H} W={W} G={Gh}x{Gw} seed={seed} frame0={frame0}")
+    plan = t.Plan(H, W, 1, Gh, Gw, pixel_pitch_over_d=0.125)
+    frames = 2
+    zern = _sample(t, plan, [dr, 0.5 * dr], seed, frame0, frames).cpu().numpy()
+    S = ospec.all_spectra(Gh, Gw, 0.125, 2)
+    L = ozern.cholesky_lower(ozern.noll_matrix(1.0))
+    for f in range(frames):
+        ref = osamp.sample_zernike(H, W, Gh, Gw, 0.125, [dr, 0.5 * dr][f], seed, frame0 + f,
+                                   spectra=S, L=L)
+        errs = [rel(zern[f, j], ref[j]) for j in range(35)]
+        assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
+
+
+@pytest.mark.slow
+def test_sampler_full_size_frame(t):
+    """512 x 512 frame on the 1024 x 1024 grid, the benchmark's launch shape."""
+    say("sampler full size 512x512 G=1024")
+    H = W = 512
+    plan = t.Plan(H, W, 3, 1024, 1024, pixel_pitch_over_d=0.125)
+    zern = _sample(t, plan, [2.0, 4.0], 0, 0, 2).cpu().numpy()
+    ref = osamp.sample_zernike(H, W, 1024, 1024, 0.125, 4.0, 0, 1)
+    errs = [rel(zern[1, j], ref[j]) for j in range(35)]
+    assert max(errs) < TOL, max(errs)
+
+
+def test_plan_tables_match_oracle(t):
+    plan = t.Plan(64, 64, 1, 128, 128)
+    np.testing.assert_allclose(plan.table(0), ozern.noll_matrix(1.0), rtol=1e-12, atol=1e-16)
+
+
+def test_psf_exact_matches_oracle(t):
+    say("psf exact, 300 vectors, P=64 T=33")
+    plan = t.Plan(64, 64, 1, 128, 128, psf_t=33)
+    A, _ = opsf.basis_draws(300, seed=77)
+    A[:5] *= 0.0                     # diffraction-limited
+    A[5:10] *= 3.0                   # strong turbulence (D/r0 up to ~10)
+    z = torch.tensor(A, dtype=torch.float32, device="cuda")
+    out = torch.empty((300, 33 * 33), dtype=torch.float32, device="cuda")
+    plan.psf_exact(z, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(300, 33, 33)
+    ref = opsf.psf_batch(A.astype(np.float32).astype(np.float64), 64, 33)
+    errs = [rel(got[i], ref[i]) for i in range(300)]
+    assert max(errs) < TOL, (int(np.argmax(errs)), max(errs))
+    np.testing.assert_allclose(got.sum(axis=(1, 2)), 1.0, atol=1e-5)
+
+
+@pytest.mark.parametrize("T", [15, 21])
+def test_psf_exact_smaller_crops(t, T):
+    plan = t.Plan(64, 64, 1, 128, 128, psf_t=T)
+    A, _ = opsf.basis_draws(40, seed=5)
+    z = torch.tensor(A, dtype=torch.float32, device="cuda")
+    out = torch.empty((40, T * T), dtype=torch.float32, device="cuda")
+    plan.psf_exact(z, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(40, T, T)
+    ref = opsf.psf_batch(A.astype(np.float32).astype(np.float64), 64, T)
+    assert max(rel(got[i], ref[i]) for i in range(40)) < TOL
+
+
+def test_p2s_exact_matches_oracle(t, basis33):
+    say("p2s exact 64x64x2 frames K=100")
+    H = W = 64
+    plan = t.Plan(H, W, 1, 128, 128, basis=basis33, psf_t=33)
+    zern = _sample(t, plan, [2.0, 5.0], 3, 0, 2)
+    beta = torch.empty((2, H, W, 100), dtype=torch.float32, device="cuda")
+    plan.p2s(zern, beta, plan.workspace(2))
+    torch.cuda.synchronize()
+    z = zern.cpu().numpy().astype(np.float64)
+    got = beta.cpu().numpy()
+    for f in range(2):
+        ref = opsf.psf_field(z[f], 64, 33, basis33)
+        assert rel(got[f], ref) < TOL, f
+
+
+def test_render_matches_oracle(t, basis33):
+    say("render fp32 C=3 40x72")
+    H, W, C = 40, 72, 3
+    plan = t.Plan(H, W, C, 128, 128, basis=basis33, psf_t=33)
+    img = synthetic.test_image(C, H, W, 8, seed=1)[None]
+    rng = np.random.default_rng(3)
+    beta = (rng.standard_normal((1, H, W, 100)) * 0.05).astype(np.float32)
+    beta[..., 0] += 1.0
+    out = torch.empty((1, C, H, W), dtype=torch.float32, device="cuda")
+    plan.render(torch.tensor(img, device="cuda"), torch.tensor(beta, device="cuda"), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0]
+    for c in range(C):
+        ref = orender.render_basis(img[0, c].astype(np.float64), beta[0].astype(np.float64),
+                                   basis33, 33)
+        assert rel(got[c], ref) < TOL, c
+
+
+def test_warp_matches_oracle(t):
+    say("warp C=2 50x70")
+    H, W, C = 50, 70, 2
+    plan = t.Plan(H, W, C, 128, 128)
+    img = synthetic.test_image(C, H, W, 4, seed=2)[None]
+    rng = np.random.default_rng(9)
+    zern = np.zeros((1, 35, H, W), dtype=np.float32)
+    zern[0, 0] = rng.standard_normal((H, W)) * 3.0
+    zern[0, 1] = rng.standard_normal((H, W)) * 3.0
+    out = torch.empty((1, C, H, W), dtype=torch.float32, device="cuda")
+    plan.warp(torch.tensor(img, device="cuda"), torch.tensor(zern, device="cuda"), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0]
+    tx, ty = orender.tilt_shift(zern[0].astype(np.float64))
+    for c in range(C):
+        ref = orender.warp(img[0, c].astype(np.float64), tx, ty)
+        assert rel(got[c], ref) < TOL, c
+
+
+def test_end_to_end_small_workload(t, basis33):
+    """64 x 64 grayscale, D/r0 = 2, G = 128, seed 0: sample -> exact P2S ->
+    render -> warp, against the oracle chain on the same inputs."""
+    say("end-to-end 64x64")
+    H = W = 64
+    plan = t.Plan(H, W, 1, 128, 128, basis=basis33, psf_t=33)
+    img = synthetic.test_image(1, H, W, 8, seed=0)[None]
+    zern = _sample(t, plan, [2.0], 0, 0, 1)
+    beta = torch.empty((1, H, W, 100), dtype=torch.float32, device="cuda")
+    ws = plan.workspace(1)
+    plan.p2s(zern, beta, ws)
+    blur = torch.empty((1, 1, H, W), dtype=torch.float32, device="cuda")
+    out = torch.empty_like(blur)
+    plan.render(torch.tensor(img, device="cuda"), beta, blur)
+    plan.warp(blur, zern, out)
+    torch.cuda.synchronize()
+    zr = osamp.sample_zernike(H, W, 128, 128, 0.125, 2.0, 0, 0)
+    br = opsf.psf_field(zr, 64, 33, basis33)
+    ref = orender.render_frame(img[0].astype(np.float64), zr, br, basis33, 33)
+    assert rel(zern.cpu().numpy()[0], zr) < TOL
+    assert rel(out.cpu().numpy()[0], ref) < TOL
+
+
+def test_argument_errors(t, basis33):
+    plan = t.Plan(32, 32, 1, 64, 64, basis=basis33, psf_t=33)
+    x = torch.zeros((1, 1, 32, 32), dtype=torch.float32, device="cuda")
+    z = torch.zeros((1, 35, 32, 32), dtype=torch.float32, device="cuda")
+    with pytest.raises(t.TsimError) as e:
+        plan.warp(x, z, x)              # in place
+    assert e.value.status == t.EINVAL
+    with pytest.raises(t.TsimError):
+        plan.sample_zernike([float("nan")], 0, 0, z, plan.workspace(1))
+    with pytest.raises(t.TsimError):
+        plan.sample_zernike([-1.0], 0, 0, z, plan.workspace(1))
+    big = torch.zeros(1024 + 64, dtype=torch.float32, device="cuda")
+    mis = big[1:1 + 32 * 32].view(1, 1, 32, 32)   # 4-byte offset: misaligned
+    with pytest.raises(t.TsimError):
+        plan.warp(mis, z, x)
+    nobasis = t.Plan(32, 32, 1, 64, 64)
+    with pytest.raises(t.TsimError) as e:
+        nobasis.render(x, torch.zeros((1, 32, 32, 1), device="cuda"), torch.empty_like(x))
+    assert e.value.status == t.EARTEFACT
+
+
+def test_repeat_run_is_bit_identical(t):
+    plan = t.Plan(64, 64, 1, 128, 128)
+    a = _sample(t, plan, [2.0], 9, 3, 1)
+    b = _sample(t, plan, [2.0], 9, 3, 1)
+    assert torch.equal(a, b)
