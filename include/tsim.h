@@ -168,6 +168,31 @@ int tsim_warp(const tsim_plan *plan, int frames, const float *img, const float *
 int tsim_psf_exact(const tsim_plan *plan, int n, const float *zvec, float *psf,
                    tsim_stream stream);
 
+/* PSF basis of Eq. (7) by PCA over a database of exact PSFs (Sec. II-C).
+ * Draws n_psf Zernike vectors a = (D/r0)^{5/6} L g (g ~ N(0, I) from Philox
+ * counters (i, w, 0, 1), D/r0 uniform in [dr_lo, dr_hi] from word 0 of
+ * (i, 9, 0, 1)), computes their exact T x T PSFs (modes 4..36) on the device,
+ * forms the FP64 Gram matrix of the PSF matrix, and returns its top-K
+ * eigenvectors (the uncentred principal components), each signed so its sum
+ * is non-negative (ties: largest-magnitude entry positive).  K, T and P come
+ * from the plan, which need not hold a basis.  Synchronous; allocates and
+ * frees its own device buffers.
+ *   basis_out : host [K][T*T] float64, output (orthonormal rows)
+ *   eig_out   : host [K] float64 eigenvalues, descending (may be NULL)
+ * Returns TSIM_EARTEFACT if the eigen-solver does not converge. */
+int tsim_basis_build(const tsim_plan *plan, int n_psf, uint64_t seed, double dr_lo, double dr_hi,
+                     double *basis_out, double *eig_out);
+
+/* Kernel tracing.  tsim_trace_enable(1) clears the counters and brackets
+ * every later kernel launch of the library with two HIP events recorded on
+ * the launch's stream; tsim_trace_enable(0) stops.  tsim_trace_count and
+ * tsim_trace_get wait for the recorded events, then report per kernel name
+ * the number of launches and their summed duration in milliseconds.  Not
+ * for use while a stream is being captured into a graph. */
+int tsim_trace_enable(int on);
+int tsim_trace_count(int *n_kernels);
+int tsim_trace_get(int index, char *name, size_t name_len, double *total_ms, int *launches);
+
 /* Human-readable text for a status code. */
 const char *tsim_status_string(int status);
 

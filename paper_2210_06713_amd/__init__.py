@@ -62,12 +62,38 @@ _lib_render = _sig("tsim_render", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp])
 _lib_warp = _sig("tsim_warp", _i, [_vp, _i, _vp, _vp, _vp, _vp])
 _lib_psf = _sig("tsim_psf_exact", _i, [_vp, _i, _vp, _vp, _vp])
 _lib_status = _sig("tsim_status_string", ctypes.c_char_p, [_i])
+_lib_basis = _sig("tsim_basis_build", _i, [_vp, _i, _u64, ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)])
+_lib_trace_enable = _sig("tsim_trace_enable", _i, [_i])
+_lib_trace_count = _sig("tsim_trace_count", _i, [ctypes.POINTER(_i)])
+_lib_trace_get = _sig("tsim_trace_get", _i, [_i, ctypes.c_char_p, ctypes.c_size_t,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i)])
 _lib_host_tables = _sig("tsim_host_tables", _i,
                         [ctypes.POINTER(_Params), _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
 
 EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "tsim_plan_table",
             "tsim_sample_zernike", "tsim_p2s", "tsim_render", "tsim_warp", "tsim_psf_exact",
-            "tsim_status_string", "tsim_host_tables"]
+            "tsim_status_string", "tsim_host_tables", "tsim_basis_build", "tsim_trace_enable",
+            "tsim_trace_count", "tsim_trace_get"]
+
+
+def trace_enable(on=True):
+    """Start (clearing old counts) or stop per-kernel event timing."""
+    _check(_lib_trace_enable(1 if on else 0), "tsim_trace_enable")
+
+
+def trace_report():
+    """{kernel name: (launches, total ms)} for launches since trace_enable()."""
+    n = _i()
+    _check(_lib_trace_count(ctypes.byref(n)), "tsim_trace_count")
+    out = {}
+    for i in range(n.value):
+        buf = ctypes.create_string_buffer(128)
+        ms = ctypes.c_double()
+        cnt = _i()
+        _check(_lib_trace_get(i, buf, 128, ctypes.byref(ms), ctypes.byref(cnt)), "tsim_trace_get")
+        out[buf.value.decode()] = (cnt.value, ms.value)
+    return out
 
 
 class TsimError(RuntimeError):
@@ -207,6 +233,16 @@ class Plan:
     def warp(self, img, zern, out, stream=None):
         _check(_lib_warp(self._h, img.shape[0], _ptr(img), _ptr(zern), _ptr(out), _stream(stream)),
                "tsim_warp")
+
+    def basis_build(self, n_psf=20000, seed=0, dr_lo=0.5, dr_hi=5.0):
+        """PCA PSF basis (K x T*T float64) and its eigenvalues, computed by
+        the library (device PSFs and Gram matrix, host eigen-solver)."""
+        out = np.zeros((self.K, self.T * self.T), dtype=np.float64)
+        eig = np.zeros(self.K, dtype=np.float64)
+        _check(_lib_basis(self._h, int(n_psf), int(seed), float(dr_lo), float(dr_hi),
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          eig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "tsim_basis_build")
+        return out, eig
 
     def psf_exact(self, zvec, psf, stream=None):
         _check(_lib_psf(self._h, zvec.shape[0], _ptr(zvec), _ptr(psf), _stream(stream)),

@@ -35,6 +35,19 @@ struct tsim_plan {
   float2 *d_tw_p = nullptr;    // twiddles exp(-2 pi i k / P), k < P
 };
 
+// Brackets one kernel launch with timing events when tracing is enabled.
+class TraceScope {
+ public:
+  TraceScope(const char *name, hipStream_t s);
+  ~TraceScope();
+  TraceScope(const TraceScope &) = delete;
+  TraceScope &operator=(const TraceScope &) = delete;
+
+ private:
+  hipStream_t s_;
+  int slot_;
+};
+
 // ---- launchers (sampler.hip) ----
 int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
                    uint64_t frame0, float *zern, void *ws, hipStream_t s);

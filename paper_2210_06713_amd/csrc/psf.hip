@@ -251,6 +251,7 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
   if (pl->P != 64) return TSIM_EUNSUPPORTED;
   dim3 grid((n + 7) / 8);
   const float *zt = pl->d_zpupil;
+  TraceScope tr("k_psf64", s);
   switch (pl->T) {
     case 33: hipLaunchKernelGGL(k_psf64<33>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
     case 31: hipLaunchKernelGGL(k_psf64<31>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
@@ -265,6 +266,7 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
 int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s) {
   const int T2 = pl->T * pl->T;
   dim3 grid((n + 63) / 64);
+  TraceScope tr("k_project", s);
   switch (pl->KP) {
     case 32: hipLaunchKernelGGL(k_project<32>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
     case 64: hipLaunchKernelGGL(k_project<64>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;

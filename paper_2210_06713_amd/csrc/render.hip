@@ -108,6 +108,7 @@ int launch_render_fp32(const tsim_plan *pl, int frames, const float *img, const 
   if (lds > 64 * 1024) return TSIM_EUNSUPPORTED;
   dim3 grid((W + kTile - 1) / kTile, (H + kTile - 1) / kTile, frames);
   const int KP = pl->KP;
+  TraceScope tr("k_render_fp32", s);
   if (KP == 32)
     hipLaunchKernelGGL(k_render_fp32<32>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
   else if (KP == 64)
@@ -122,6 +123,7 @@ int launch_render_fp32(const tsim_plan *pl, int frames, const float *img, const 
 int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
                 hipStream_t s) {
   dim3 grid((pl->W + 255) / 256, pl->H, frames);
+  TraceScope tr("k_warp", s);
   hipLaunchKernelGGL(k_warp, grid, dim3(256), 0, s, img, zern, out, pl->H, pl->W, pl->C);
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }

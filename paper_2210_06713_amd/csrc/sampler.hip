@@ -170,15 +170,19 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
   for (int f0 = 0; f0 < frames; f0 += chunk) {
     const int nf = std::min(chunk, frames - f0);
     dim3 g1(Gw / NC, TSIM_FIELDS, nf);
-    hipLaunchKernelGGL(k_sampler_cols, g1, dim3(256), size_t(NC) * Gh * sizeof(float2), s, pl->d_sqrtS,
+    {
+      TraceScope tr("k_sampler_cols", s);
+      hipLaunchKernelGGL(k_sampler_cols, g1, dim3(256), size_t(NC) * Gh * sizeof(float2), s, pl->d_sqrtS,
                        pl->d_tw_h, V, Gh, Gw, log2h, H, NC, key0, key1,
                        uint32_t(frame0 + uint64_t(f0)));
+    }
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
     FrameScales sc;
     for (int i = 0; i < kMaxFramesPerLaunch; ++i) sc.s[i] = 0.f;
     for (int i = 0; i < nf; ++i) sc.s[i] = scale_host[f0 + i];
     dim3 g2(H, nf);
     size_t lds = size_t(Gw) * sizeof(float2);
+    TraceScope tr("k_sampler_rows_mix", s);
     if (W <= 256)
       hipLaunchKernelGGL((k_sampler_rows_mix<1, 256>), g2, dim3(256), lds, s, V, pl->d_tw_w, pl->d_L,
                          zern, Gw, log2w, H, W, sc, f0);
