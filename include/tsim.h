@@ -183,6 +183,60 @@ int tsim_psf_exact(const tsim_plan *plan, int n, const float *zvec, float *psf,
 int tsim_basis_build(const tsim_plan *plan, int n_psf, uint64_t seed, double dr_lo, double dr_hi,
                      double *basis_out, double *eig_out);
 
+/* ---- The learned P2S map (Sec. II-C: a small neural network maps each
+ * pixel's Zernike vector to its PSF-basis weights) ----
+ *
+ * Network: 35 -> 256 -> 256 -> 256 -> K, exact (erf) GELU after the hidden
+ * layers.  Input x_j = a_j * inv_s_j (the tilt slots Noll 2, 3 carry
+ * inv_s = 0: tilt is applied by tsim_warp); output beta = s_out * y + mu.
+ * Products run on BF16 matrix cores with FP32 accumulation; master weights,
+ * biases, Adam moments and the loss are FP32.  Parameters are one flat FP32
+ * array: for layer l = 0..3, W_l [out][in] at off_w[l] and b_l [out] at
+ * off_b[l] (tsim_mlp_layout).  A tsim_mlp is not thread-safe. */
+typedef struct tsim_mlp tsim_mlp;
+
+/* Allocate a network for the plan's K with training batch `batch`;
+ * weights ~ N(0, 1/fan_in) from Philox counters (i, 0, layer, 3) under key
+ * `seed`, biases 0; inv_s_j = 1/sqrt(A_0[j][j] 2.75^{5/3}), mu = 0, s_out = 1. */
+int tsim_mlp_create(const tsim_plan *plan, int batch, uint64_t seed, tsim_mlp **out);
+int tsim_mlp_destroy(tsim_mlp *net);
+int tsim_mlp_param_count(const tsim_mlp *net, size_t *count);
+int tsim_mlp_layout(const tsim_mlp *net, size_t *off_w /*[4]*/, size_t *off_b /*[4]*/);
+
+/* Copy out / in (host float32): what = 0 parameters [param_count],
+ * 1 gradients of the last tsim_mlp_grad/train step [param_count] (get only),
+ * 2 inv_s [35], 3 mu [K], 4 s_out [1].  Synchronises the device. */
+int tsim_mlp_get(const tsim_mlp *net, int what, float *host, size_t count);
+int tsim_mlp_set(tsim_mlp *net, int what, const float *host, size_t count);
+
+/* Training pairs from the exact path: n_pairs Zernike vectors a = (D/r0)^{5/6}
+ * L g (Philox counters (i, w, 0, 2), D/r0 uniform in [dr_lo, dr_hi] from word
+ * 0 of (i, 9, 0, 2)) and their exact projected weights (Eq. (2) + Eq. (7)).
+ *   zvec : device [n_pairs][35] f32;  beta : device [n_pairs][K] f32
+ *   ws   : device, min(n_pairs, 2^20) * T*T floats */
+int tsim_mlp_make_data(const tsim_plan *plan, int n_pairs, uint64_t seed, float dr_lo, float dr_hi,
+                       float *zvec, float *beta, void *ws, tsim_stream stream);
+
+/* Loss (mean over batch and outputs of (y - (target - mu)/s_out)^2) and its
+ * gradients for one batch, without updating.  zvec [batch][35], target
+ * [batch][K] device f32; loss_host may be NULL. */
+int tsim_mlp_grad(tsim_mlp *net, int batch, const float *zvec, const float *target,
+                  float *loss_host, tsim_stream stream);
+
+/* `steps` AdamW steps (beta1 0.9, beta2 0.999, eps 1e-8, no weight decay,
+ * cosine learning rate lr_max -> lr_min) on consecutive batches of the
+ * pairs (wrapping around).  loss_host [steps] may be NULL. */
+int tsim_mlp_train(tsim_mlp *net, const float *zvec, const float *target, int n_pairs, int steps,
+                   float lr_max, float lr_min, float *loss_host, tsim_stream stream);
+
+/* Copy the network into the plan for tsim_p2s in TSIM_P2S_LEARNED mode
+ * (BF16 weights padded to the inference layout).  Must not run
+ * concurrently with tsim_p2s on the plan.  In learned mode tsim_p2s writes
+ * beta as float32 [F][H][W][K] in TSIM_FP32 plans and as bfloat16
+ * [F][H][W][KP] (KP = K rounded up to 32, 64, 112 or 128, zero padded) in
+ * TSIM_BF16 plans, the layout tsim_render then reads. */
+int tsim_plan_set_mlp(tsim_plan *plan, const tsim_mlp *net);
+
 /* Kernel tracing.  tsim_trace_enable(1) clears the counters and brackets
  * every later kernel launch of the library with two HIP events recorded on
  * the launch's stream; tsim_trace_enable(0) stops.  tsim_trace_count and

@@ -77,13 +77,14 @@ def psf_batch(A, P, T, modes=range(4, 37)):
     return np.stack([psf_exact(a, P, T, modes, zstack) for a in A])
 
 
-def basis_draws(n, seed, dr_lo=0.5, dr_hi=5.0):
+def basis_draws(n, seed, dr_lo=0.5, dr_hi=5.0, tag=philox.TAG_BASIS):
     """Zernike vectors for the PSF database: a = (D/r0)^{5/6} L g with
-    g ~ N(0, I_35) from Philox counters (i, w, 0, tag 1), w = 0..8, and
-    D/r0 = lo + (hi - lo) u with u from word 0 of call (i, 9, 0, tag 1)."""
+    g ~ N(0, I_35) from Philox counters (i, w, 0, tag), w = 0..8, and
+    D/r0 = lo + (hi - lo) u with u from word 0 of call (i, 9, 0, tag); tag 1
+    for the basis database, tag 2 for network training pairs."""
     L = cholesky_lower(noll_matrix(1.0))
-    g = philox.gaussian_vectors(n, 35, 0, philox.TAG_BASIS, seed)
-    u = philox.uniforms_extra(n, 9, 0, philox.TAG_BASIS, seed)
+    g = philox.gaussian_vectors(n, 35, 0, tag, seed)
+    u = philox.uniforms_extra(n, 9, 0, tag, seed)
     dr = dr_lo + (dr_hi - dr_lo) * u
     return (g @ L.T) * (dr ** (5.0 / 6.0))[:, None], dr
 

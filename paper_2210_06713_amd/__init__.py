@@ -68,13 +68,28 @@ _lib_trace_enable = _sig("tsim_trace_enable", _i, [_i])
 _lib_trace_count = _sig("tsim_trace_count", _i, [ctypes.POINTER(_i)])
 _lib_trace_get = _sig("tsim_trace_get", _i, [_i, ctypes.c_char_p, ctypes.c_size_t,
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i)])
+_f = ctypes.c_float
+_fp = ctypes.POINTER(ctypes.c_float)
+_lib_mlp_create = _sig("tsim_mlp_create", _i, [_vp, _i, _u64, ctypes.POINTER(_vp)])
+_lib_mlp_destroy = _sig("tsim_mlp_destroy", _i, [_vp])
+_lib_mlp_count = _sig("tsim_mlp_param_count", _i, [_vp, ctypes.POINTER(ctypes.c_size_t)])
+_lib_mlp_layout = _sig("tsim_mlp_layout", _i, [_vp, ctypes.POINTER(ctypes.c_size_t),
+                                              ctypes.POINTER(ctypes.c_size_t)])
+_lib_mlp_get = _sig("tsim_mlp_get", _i, [_vp, _i, _fp, ctypes.c_size_t])
+_lib_mlp_set = _sig("tsim_mlp_set", _i, [_vp, _i, _fp, ctypes.c_size_t])
+_lib_mlp_data = _sig("tsim_mlp_make_data", _i, [_vp, _i, _u64, _f, _f, _vp, _vp, _vp, _vp])
+_lib_mlp_grad = _sig("tsim_mlp_grad", _i, [_vp, _i, _vp, _vp, _fp, _vp])
+_lib_mlp_train = _sig("tsim_mlp_train", _i, [_vp, _vp, _vp, _i, _i, _f, _f, _fp, _vp])
+_lib_set_mlp = _sig("tsim_plan_set_mlp", _i, [_vp, _vp])
 _lib_host_tables = _sig("tsim_host_tables", _i,
                         [ctypes.POINTER(_Params), _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
 
 EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "tsim_plan_table",
             "tsim_sample_zernike", "tsim_p2s", "tsim_render", "tsim_warp", "tsim_psf_exact",
             "tsim_status_string", "tsim_host_tables", "tsim_basis_build", "tsim_trace_enable",
-            "tsim_trace_count", "tsim_trace_get"]
+            "tsim_trace_count", "tsim_trace_get", "tsim_mlp_create", "tsim_mlp_destroy",
+            "tsim_mlp_param_count", "tsim_mlp_layout", "tsim_mlp_get", "tsim_mlp_set",
+            "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp"]
 
 
 def trace_enable(on=True):
@@ -247,3 +262,90 @@ class Plan:
     def psf_exact(self, zvec, psf, stream=None):
         _check(_lib_psf(self._h, zvec.shape[0], _ptr(zvec), _ptr(psf), _stream(stream)),
                "tsim_psf_exact")
+
+
+class Mlp:
+    """The learned P2S network (``tsim_mlp``): 35 -> 256 -> 256 -> 256 -> K."""
+
+    def __init__(self, plan, batch=8192, seed=0):
+        h = _vp()
+        _check(_lib_mlp_create(plan._h, int(batch), int(seed), ctypes.byref(h)), "tsim_mlp_create")
+        self._h = h
+        self.K = plan.K
+        self.batch = batch
+        n = ctypes.c_size_t()
+        _check(_lib_mlp_count(self._h, ctypes.byref(n)), "tsim_mlp_param_count")
+        self.n_params = n.value
+        ow = (ctypes.c_size_t * 4)()
+        ob = (ctypes.c_size_t * 4)()
+        _check(_lib_mlp_layout(self._h, ow, ob), "tsim_mlp_layout")
+        self.off_w = list(ow)
+        self.off_b = list(ob)
+        self.dims = [N_MODES, 256, 256, 256, self.K]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    _SIZES = {0: None, 1: None, 2: N_MODES, 3: None, 4: 1}
+
+    def get(self, what):
+        n = {0: self.n_params, 1: self.n_params, 2: N_MODES, 3: self.K, 4: 1}[what]
+        out = np.zeros(n, dtype=np.float32)
+        _check(_lib_mlp_get(self._h, what, out.ctypes.data_as(_fp), n), "tsim_mlp_get")
+        return out
+
+    def set(self, what, values):
+        v = np.ascontiguousarray(values, dtype=np.float32).ravel()
+        _check(_lib_mlp_set(self._h, what, v.ctypes.data_as(_fp), v.size), "tsim_mlp_set")
+
+    def unpack(self, flat):
+        """[(W [out][in], b [out])] views of a flat parameter array."""
+        out = []
+        for l in range(4):
+            i, o = self.dims[l], self.dims[l + 1]
+            out.append((flat[self.off_w[l]:self.off_w[l] + o * i].reshape(o, i),
+                        flat[self.off_b[l]:self.off_b[l] + o]))
+        return out
+
+    def pack(self, layers):
+        flat = np.zeros(self.n_params, dtype=np.float32)
+        for l, (W, b) in enumerate(layers):
+            flat[self.off_w[l]:self.off_w[l] + W.size] = np.asarray(W, dtype=np.float32).ravel()
+            flat[self.off_b[l]:self.off_b[l] + b.size] = b
+        return flat
+
+    def grad(self, zvec, target, stream=None):
+        loss = ctypes.c_float()
+        _check(_lib_mlp_grad(self._h, zvec.shape[0], _ptr(zvec), _ptr(target), ctypes.byref(loss),
+                             _stream(stream)), "tsim_mlp_grad")
+        return loss.value
+
+    def train(self, zvec, target, steps, lr_max=1e-3, lr_min=1e-5, stream=None):
+        losses = np.zeros(steps, dtype=np.float32)
+        _check(_lib_mlp_train(self._h, _ptr(zvec), _ptr(target), zvec.shape[0], int(steps),
+                              float(lr_max), float(lr_min), losses.ctypes.data_as(_fp),
+                              _stream(stream)), "tsim_mlp_train")
+        return losses
+
+
+def make_training_data(plan, n_pairs, seed=0, dr_lo=0.5, dr_hi=5.0, stream=None):
+    """(zvec [n][35], beta [n][K]) device tensors from the exact path."""
+    z = torch.empty((n_pairs, N_MODES), dtype=torch.float32, device="cuda")
+    b = torch.empty((n_pairs, plan.K), dtype=torch.float32, device="cuda")
+    ws = torch.empty(max(min(n_pairs, 1 << 20) * plan.T * plan.T * 4, 256), dtype=torch.uint8,
+                     device="cuda")
+    _check(_lib_mlp_data(plan._h, int(n_pairs), int(seed), float(dr_lo), float(dr_hi), _ptr(z),
+                         _ptr(b), _ptr(ws), _stream(stream)), "tsim_mlp_make_data")
+    return z, b
+
+
+def plan_set_mlp(plan, mlp):
+    _check(_lib_set_mlp(plan._h, mlp._h), "tsim_plan_set_mlp")

@@ -45,9 +45,15 @@ int tsim_p2s(const tsim_plan *pl, int frames, const float *zern, void *beta, voi
   if (!frames_ok(pl, frames) || !zern || !beta || !ws) return TSIM_EINVAL;
   if (!aligned(zern) || !aligned(beta) || !aligned(ws)) return TSIM_EINVAL;
   if (!pl->d_basis) return TSIM_EARTEFACT;
-  if (pl->p.p2s_mode != TSIM_P2S_EXACT) return TSIM_EUNSUPPORTED;
-  return launch_p2s_exact(pl, frames, zern, static_cast<float *>(beta), ws,
-                          static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->p.p2s_mode == TSIM_P2S_LEARNED) {
+    if (!pl->d_mlp_w) return TSIM_EARTEFACT;
+    const bool bf = pl->p.precision == TSIM_BF16;
+    return launch_mlp_infer(pl, zern, pl->H * pl->W, size_t(frames) * pl->H * pl->W, beta, bf ? 1 : 0,
+                            bf ? pl->KP : pl->K, s);
+  }
+  if (pl->p.precision != TSIM_FP32) return TSIM_EUNSUPPORTED;
+  return launch_p2s_exact(pl, frames, zern, static_cast<float *>(beta), ws, s);
 }
 
 int tsim_render(const tsim_plan *pl, int frames, const float *img, const void *beta, float *out,
@@ -57,7 +63,9 @@ int tsim_render(const tsim_plan *pl, int frames, const float *img, const void *b
   if (img == out) return TSIM_EINVAL;
   if (!aligned(img) || !aligned(beta) || !aligned(out)) return TSIM_EINVAL;
   if (!pl->d_basis) return TSIM_EARTEFACT;
-  if (pl->p.precision != TSIM_FP32) return TSIM_EUNSUPPORTED;
+  if (pl->p.precision == TSIM_BF16)
+    return launch_render_bf16(pl, frames, img, static_cast<const uint16_t *>(beta), out,
+                              static_cast<hipStream_t>(stream));
   return launch_render_fp32(pl, frames, img, static_cast<const float *>(beta), out,
                             static_cast<hipStream_t>(stream));
 }
@@ -68,6 +76,11 @@ int tsim_warp(const tsim_plan *pl, int frames, const float *img, const float *ze
   if (img == out) return TSIM_EINVAL;
   if (!aligned(img) || !aligned(zern) || !aligned(out)) return TSIM_EINVAL;
   return launch_warp(pl, frames, img, zern, out, static_cast<hipStream_t>(stream));
+}
+
+int tsim_plan_set_mlp(tsim_plan *pl, const tsim_mlp *net) {
+  if (!pl || !net) return TSIM_EINVAL;
+  return plan_set_mlp_impl(pl, net);
 }
 
 int tsim_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, tsim_stream stream) {

@@ -33,7 +33,13 @@ struct tsim_plan {
   float *d_basis = nullptr;    // [K][T*T] float32
   float *d_basis_t = nullptr;  // [T*T][KP] float32 (tap-major, zero padded)
   float2 *d_tw_p = nullptr;    // twiddles exp(-2 pi i k / P), k < P
+  uint16_t *d_basis_bf = nullptr;  // [roundup(T*T, 32)][KP] bfloat16, zero padded (tap-major)
+  uint16_t *d_mlp_w = nullptr;     // packed BF16 network weights (inference layout)
+  float *d_mlp_f = nullptr;        // biases, input scales, output means (FP32)
+  float mlp_s_out = 1.f;
 };
+
+struct tsim_mlp;
 
 // Brackets one kernel launch with timing events when tracing is enabled.
 class TraceScope {
@@ -58,9 +64,17 @@ int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, 
 int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *beta, void *ws,
                      hipStream_t s);
 size_t p2s_ws_bytes(const tsim_plan *pl, int frames);
+int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s);
+
+// ---- launchers (mlp.hip) ----
+int plan_set_mlp_impl(tsim_plan *pl, const tsim_mlp *n);
+int launch_mlp_infer(const tsim_plan *pl, const float *zern, int hw, size_t n_pix, void *beta,
+                     int out_bf16, int kb, hipStream_t s);
 
 // ---- launchers (render.hip) ----
 int launch_render_fp32(const tsim_plan *pl, int frames, const float *img, const float *beta,
+                       float *out, hipStream_t s);
+int launch_render_bf16(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta,
                        float *out, hipStream_t s);
 int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
                 hipStream_t s);

@@ -1,0 +1,658 @@
+// The learned phase-to-space map (Sec. II-C: a small network turns each
+// pixel's Zernike vector into its PSF-basis weights): a 35 -> 256 -> 256 ->
+// 256 -> K perceptron with exact (erf) GELU, trained and evaluated with BF16
+// matrix-core (MFMA) products and FP32 accumulation, FP32 master weights and
+// AdamW.
+//
+// Kernels
+//   k_gemm_bf16<EPI>   C = A B over an LDS-staged 64 x 64 tile (4 waves, one
+//                      32x32x16 BF16 MFMA tile each), any operand strides, so
+//                      the forward (X W^T), input-gradient (dZ W) and weight-
+//                      gradient (dZ^T X) products share it; fused epilogues
+//                      add the bias and apply GELU or its derivative.
+//   k_mlp_infer        fused per-pixel inference for the P2S step: each wave
+//                      carries 32 pixels through all four layers, the
+//                      activations staying in LDS, weights streamed from L2.
+//   k_prep, k_mse_grad, k_colsum, k_adamw, k_init_normal, k_draws: data
+//                      preparation, loss, bias gradients, optimiser, seeded
+//                      initialisation and training-pair draws.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.cuh"
+#include "internal.h"
+
+namespace {
+
+using namespace tsim;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t b = __float_as_uint(f);
+  uint32_t lsb = (b >> 16) & 1u;
+  return uint16_t((b + 0x7FFFu + lsb) >> 16);  // nearest, ties to even (finite inputs)
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+__device__ __forceinline__ float gelu(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
+  uint4 u = *reinterpret_cast<const uint4 *>(p);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_GELU_GRAD = 3 };
+
+constexpr int GT = 64, GK = 32, GKP = GK + 8;
+
+// C[m][n] = sum_k A(m,k) B(k,n); A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn]
+template <int EPI>
+__global__ void __launch_bounds__(256)
+k_gemm_bf16(const uint16_t *__restrict__ A, long sam, long sak, const uint16_t *__restrict__ B,
+            long sbk, long sbn, int M, int N, int Kd, const float *__restrict__ bias,
+            float *__restrict__ Z, float *__restrict__ outf, uint16_t *__restrict__ outb, int ldc) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GT][GKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GKP];
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  f32x16 acc = {};
+  for (int k0 = 0; k0 < Kd; k0 += GK) {
+    for (int e = threadIdx.x; e < GT * GK; e += 256) {
+      int m, k;
+      if (sak == 1) { m = e / GK; k = e % GK; } else { m = e % GT; k = e / GT; }
+      const int gm = m0 + m, gk = k0 + k;
+      As[m][k] = (gm < M && gk < Kd) ? A[gm * sam + gk * sak] : uint16_t(0);
+      int n, kb;
+      if (sbk == 1) { n = e / GK; kb = e % GK; } else { n = e % GT; kb = e / GT; }
+      const int gn = n0 + n, gkb = k0 + kb;
+      Bs[n][kb] = (gn < N && gkb < Kd) ? B[gkb * sbk + gn * sbn] : uint16_t(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 16) {
+      bf16x8 a = load8(&As[wm * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+      bf16x8 b = load8(&Bs[wn * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int n = n0 + wn * 32 + (lane & 31);
+    if (m >= M || n >= N) continue;
+    const size_t o = size_t(m) * ldc + n;
+    const float v = acc[r];
+    if (EPI == EPI_F32) {
+      outf[o] = v;
+    } else if (EPI == EPI_BIAS_F32) {
+      outf[o] = v + bias[n];
+    } else if (EPI == EPI_BIAS_GELU) {
+      const float z = v + bias[n];
+      Z[o] = z;
+      outb[o] = f2bf(gelu(z));
+    } else {
+      const float dz = v * gelu_grad(Z[o]);
+      outf[o] = dz;
+      outb[o] = f2bf(dz);
+    }
+  }
+}
+
+// network input: x = a * inv_s (tilt slots carry inv_s = 0), bf16; targets
+// standardised (beta - mu) / s_out
+__global__ void k_prep(const float *__restrict__ a, const float *__restrict__ beta, int n_total,
+                       int start, int B, const float *__restrict__ inv_s, const float *__restrict__ mu,
+                       float inv_sout, int K, uint16_t *__restrict__ x, float *__restrict__ t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const int src = (start + i) % n_total;
+  for (int j = 0; j < TSIM_N_MODES; ++j)
+    x[size_t(i) * TSIM_N_MODES + j] = f2bf(a[size_t(src) * TSIM_N_MODES + j] * inv_s[j]);
+  if (beta)
+    for (int k = 0; k < K; ++k) t[size_t(i) * K + k] = (beta[size_t(src) * K + k] - mu[k]) * inv_sout;
+}
+
+// dY = 2 (Y - T) / (B K); loss += mean square
+__global__ void k_mse_grad(const float *__restrict__ Y, const float *__restrict__ T, int n,
+                           float scale, float *__restrict__ dzf, uint16_t *__restrict__ dzb,
+                           float *__restrict__ loss) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float d = Y[i] - T[i];
+    const float g = 2.f * d * scale;
+    dzf[i] = g;
+    dzb[i] = f2bf(g);
+    s += d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, red[0] * scale);
+}
+
+// db[n] = sum_m dZ[m][n]
+__global__ void k_colsum(const float *__restrict__ dz, int M, int N, float *__restrict__ db) {
+  const int n = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  __shared__ float red[4][64];
+  float s = 0.f;
+  if (n < N)
+    for (int m = g; m < M; m += 4) s += dz[size_t(m) * N + n];
+  red[g][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (g == 0 && n < N) db[n] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ void k_adamw(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                        float *__restrict__ v, uint16_t *__restrict__ wb, int n, float lr, float b1,
+                        float b2, float c1, float c2, float eps, float wd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / c1, vh = vi / c2;
+  const float wi = w[i] - lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+  w[i] = wi;
+  wb[i] = f2bf(wi);
+}
+
+__global__ void k_init_normal(float *__restrict__ w, uint16_t *__restrict__ wb, int n, float std,
+                              uint32_t key0, uint32_t key1, uint32_t stream) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  u32x4 r = philox4x32_10(u32x4{uint32_t(i), 0u, stream, 3u}, key0, key1);
+  const float v = box_muller(r.x, r.y).x * std;
+  w[i] = v;
+  wb[i] = f2bf(v);
+}
+
+// training pairs: a = (D/r0)^{5/6} L g, g from Philox (i, w, 0, 2), D/r0 from (i, 9, 0, 2)
+__global__ void k_draws(const float *__restrict__ Lmat, float *__restrict__ zvec, int n,
+                        uint32_t key0, uint32_t key1, float lo, float hi, uint32_t tag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float g[36];
+#pragma unroll
+  for (int w = 0; w < 9; ++w) {
+    u32x4 r = philox4x32_10(u32x4{uint32_t(i), uint32_t(w), 0u, tag}, key0, key1);
+    float2 a = box_muller(r.x, r.y), b = box_muller(r.z, r.w);
+    g[4 * w] = a.x; g[4 * w + 1] = a.y; g[4 * w + 2] = b.x; g[4 * w + 3] = b.y;
+  }
+  u32x4 r = philox4x32_10(u32x4{uint32_t(i), 9u, 0u, tag}, key0, key1);
+  const float sc = powf(lo + (hi - lo) * u01(r.x), 5.0f / 6.0f);
+  for (int j = 0; j < TSIM_N_MODES; ++j) {
+    float s = 0.f;
+    for (int k = 0; k <= j; ++k) s = fmaf(Lmat[j * TSIM_N_MODES + k], g[k], s);
+    zvec[size_t(i) * TSIM_N_MODES + j] = s * sc;
+  }
+}
+
+// ----------------------------------------------------------- inference ----
+constexpr int HID = 256;
+constexpr int IN_PAD = 48;   // 35 inputs padded to three 16-wide k-steps
+constexpr int ACT_LD = HID + 8;
+
+// One 32-row tile: out[32][NT*32] = act[32][KSTEPS*16] * W[n][k]^T, acc in regs.
+template <int NT, int KSTEPS>
+__device__ __forceinline__ void mlp_layer(const uint16_t *act, const uint16_t *__restrict__ W, int ldw,
+                                          f32x16 (&acc)[8], int lane) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+#pragma unroll 4
+  for (int s = 0; s < KSTEPS; ++s) {
+    const bf16x8 a = load8(act + (lane & 31) * ACT_LD + s * 16 + 8 * (lane >> 5));
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bf16x8 b = load8(W + size_t(t * 32 + (lane & 31)) * ldw + s * 16 + 8 * (lane >> 5));
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void mlp_store_gelu(uint16_t *act, const f32x16 (&acc)[8],
+                                               const float *__restrict__ bias, int lane) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int n = t * 32 + (lane & 31);
+      act[m * ACT_LD + n] = f2bf(gelu(acc[t][r] + bias[n]));
+    }
+}
+
+struct InferParams {
+  const uint16_t *W1, *W2, *W3, *W4;  // [256][48], [256][256], [256][256], [128][256] bf16
+  const float *b1, *b2, *b3, *b4;     // [256] x3, [128]
+  const float *inv_s;                 // [35]
+  const float *mu;                    // [128] output means (0 beyond K)
+  float s_out;
+  int K, KB;                          // outputs, row stride of beta
+  int out_bf16;
+};
+
+__global__ void __launch_bounds__(256)
+k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip, void *__restrict__ beta) {
+  __shared__ __attribute__((aligned(16))) uint16_t act_all[4][32 * ACT_LD];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint16_t *act = act_all[w];
+  const size_t p0 = (size_t(blockIdx.x) * 4 + w) * 32;
+  // input rows: lanes 0..31 each load one pixel's 35 coefficients
+  if (lane < 32) {
+    const size_t p = p0 + lane;
+    const bool ok = p < n_pix;
+    const size_t pc = ok ? p : 0;
+    const size_t fr = pc / size_t(hw), yx = pc - fr * size_t(hw);
+    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
+    for (int j = 0; j < IN_PAD; ++j) {
+      float v = (ok && j < TSIM_N_MODES) ? zp[size_t(j) * hw] * ip.inv_s[j] : 0.f;
+      act[lane * ACT_LD + j] = f2bf(v);
+    }
+  }
+  __syncthreads();
+  f32x16 acc[8];
+  mlp_layer<8, IN_PAD / 16>(act, ip.W1, IN_PAD, acc, lane);
+  __syncthreads();
+  mlp_store_gelu<8>(act, acc, ip.b1, lane);
+  __syncthreads();
+  mlp_layer<8, HID / 16>(act, ip.W2, HID, acc, lane);
+  __syncthreads();
+  mlp_store_gelu<8>(act, acc, ip.b2, lane);
+  __syncthreads();
+  mlp_layer<8, HID / 16>(act, ip.W3, HID, acc, lane);
+  __syncthreads();
+  mlp_store_gelu<8>(act, acc, ip.b3, lane);
+  __syncthreads();
+  mlp_layer<4, HID / 16>(act, ip.W4, HID, acc, lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int n = t * 32 + (lane & 31);
+      const size_t p = p0 + m;
+      if (p >= n_pix || n >= ip.KB) continue;
+      const float y = (n < ip.K) ? (acc[t][r] + ip.b4[n]) * ip.s_out + ip.mu[n] : 0.f;
+      if (ip.out_bf16)
+        static_cast<uint16_t *>(beta)[p * ip.KB + n] = f2bf(y);
+      else
+        static_cast<float *>(beta)[p * ip.KB + n] = y;
+    }
+}
+
+template <int EPI>
+int gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const uint16_t *B, long sbk, long sbn,
+         int M, int N, int Kd, const float *bias, float *Z, float *outf, uint16_t *outb, int ldc) {
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  hipLaunchKernelGGL(k_gemm_bf16<EPI>, grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, M, N, Kd,
+                     bias, Z, outf, outb, ldc);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host --
+struct tsim_mlp {
+  int K = 0, B = 0;
+  size_t n_par = 0;
+  size_t off_w[4], off_b[4];
+  int din[4], dout[4];
+  float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // flat FP32
+  uint16_t *wb = nullptr;                                         // flat BF16 copy
+  float *inv_s = nullptr, *mu = nullptr;                          // [35], [K]
+  float s_out = 1.f;
+  uint16_t *x = nullptr, *act[3] = {nullptr, nullptr, nullptr}, *dzb = nullptr;
+  float *z[3] = {nullptr, nullptr, nullptr}, *y = nullptr, *t = nullptr, *dzf = nullptr;
+  float *loss = nullptr;
+  int step = 0;
+  std::vector<double> A0diag;
+};
+
+namespace {
+
+void mlp_free(tsim_mlp *n) {
+  if (!n) return;
+  void *ptrs[] = {n->w, n->g, n->m, n->v, n->wb, n->inv_s, n->mu, n->x, n->act[0], n->act[1],
+                  n->act[2], n->dzb, n->z[0], n->z[1], n->z[2], n->y, n->t, n->dzf, n->loss};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete n;
+}
+
+template <class T>
+bool dalloc(T **p, size_t n) {
+  return hipMalloc(p, std::max<size_t>(n, 1) * sizeof(T)) == hipSuccess;
+}
+
+// forward + backward for the current batch (x, t already prepared)
+int mlp_fwd_bwd(tsim_mlp *n, int Bsz, hipStream_t s) {
+  const int H = HID, K = n->K;
+  int st;
+  const uint16_t *Wb[4];
+  for (int l = 0; l < 4; ++l) Wb[l] = n->wb + n->off_w[l];
+  const float *bf[4];
+  for (int l = 0; l < 4; ++l) bf[l] = n->w + n->off_b[l];
+  // forward
+  if ((st = gemm<EPI_BIAS_GELU>(s, n->x, TSIM_N_MODES, 1, Wb[0], 1, TSIM_N_MODES, Bsz, H, TSIM_N_MODES,
+                                 bf[0], n->z[0], nullptr, n->act[0], H)) != TSIM_OK) return st;
+  for (int l = 1; l < 3; ++l)
+    if ((st = gemm<EPI_BIAS_GELU>(s, n->act[l - 1], H, 1, Wb[l], 1, H, Bsz, H, H, bf[l], n->z[l],
+                                   nullptr, n->act[l], H)) != TSIM_OK) return st;
+  if ((st = gemm<EPI_BIAS_F32>(s, n->act[2], H, 1, Wb[3], 1, H, Bsz, K, H, bf[3], nullptr, n->y,
+                                nullptr, K)) != TSIM_OK) return st;
+  // loss gradient
+  const int nel = Bsz * K;
+  hipLaunchKernelGGL(k_mse_grad, dim3(std::min(1024, (nel + 255) / 256)), dim3(256), 0, s, n->y, n->t,
+                     nel, 1.0f / float(nel), n->dzf, n->dzb, n->loss + n->step);
+  // backward: layer l has input act[l-1] (x for l = 0), output gradient dZ (dzf/dzb, width dout)
+  for (int l = 3; l >= 0; --l) {
+    const int dout = n->dout[l], din = n->din[l];
+    const uint16_t *in = (l == 0) ? n->x : n->act[l - 1];
+    // dW = dZ^T X: M = dout, N = din, reduction over the batch
+    if ((st = gemm<EPI_F32>(s, n->dzb, 1, dout, in, din, 1, dout, din, Bsz, nullptr, nullptr,
+                            n->g + n->off_w[l], nullptr, din)) != TSIM_OK) return st;
+    hipLaunchKernelGGL(k_colsum, dim3((dout + 63) / 64), dim3(256), 0, s, n->dzf, Bsz, dout,
+                       n->g + n->off_b[l]);
+    if (l > 0) {
+      // dA = dZ W (M = batch, N = din, reduction over dout), then dZ_prev = dA * GELU'(Z_prev).
+      // dZ of width din is written after the product has consumed dZ of width dout,
+      // so the two share buffers only across separate launches (stream order).
+      if ((st = gemm<EPI_GELU_GRAD>(s, n->dzb, dout, 1, Wb[l], din, 1, Bsz, din, dout, nullptr,
+                                    n->z[l - 1], n->dzf + size_t(Bsz) * 256, n->dzb + size_t(Bsz) * 256,
+                                    din)) != TSIM_OK) return st;
+      // move the new dZ to the front of the buffers
+      if (hipMemcpyAsync(n->dzf, n->dzf + size_t(Bsz) * 256, size_t(Bsz) * din * sizeof(float),
+                         hipMemcpyDeviceToDevice, s) != hipSuccess) return TSIM_EDEVICE;
+      if (hipMemcpyAsync(n->dzb, n->dzb + size_t(Bsz) * 256, size_t(Bsz) * din * sizeof(uint16_t),
+                         hipMemcpyDeviceToDevice, s) != hipSuccess) return TSIM_EDEVICE;
+    }
+  }
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsim_mlp_create(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **out) {
+  if (!pl || !out || batch < 1 || batch > (1 << 20)) return TSIM_EINVAL;
+  *out = nullptr;
+  if (pl->K > 128) return TSIM_EUNSUPPORTED;
+  tsim_mlp *n = new (std::nothrow) tsim_mlp();
+  if (!n) return TSIM_ENOMEM;
+  n->K = pl->K;
+  n->B = batch;
+  const int dims[5] = {TSIM_N_MODES, HID, HID, HID, pl->K};
+  size_t off = 0;
+  for (int l = 0; l < 4; ++l) {
+    n->din[l] = dims[l];
+    n->dout[l] = dims[l + 1];
+    n->off_w[l] = off;
+    off += size_t(dims[l]) * dims[l + 1];
+    off = (off + 63) & ~size_t(63);
+    n->off_b[l] = off;
+    off += dims[l + 1];
+    off = (off + 63) & ~size_t(63);
+  }
+  n->n_par = off;
+  const size_t B = batch;
+  bool ok = dalloc(&n->w, off) && dalloc(&n->g, off) && dalloc(&n->m, off) && dalloc(&n->v, off) &&
+            dalloc(&n->wb, off) && dalloc(&n->inv_s, TSIM_N_MODES) && dalloc(&n->mu, 128) &&
+            dalloc(&n->x, B * TSIM_N_MODES) && dalloc(&n->y, B * pl->K) && dalloc(&n->t, B * pl->K) &&
+            dalloc(&n->dzf, 2 * B * 256) && dalloc(&n->dzb, 2 * B * 256) && dalloc(&n->loss, 1 << 20);
+  for (int l = 0; l < 3 && ok; ++l) ok = dalloc(&n->act[l], B * HID) && dalloc(&n->z[l], B * HID);
+  if (!ok) {
+    mlp_free(n);
+    return TSIM_ENOMEM;
+  }
+  if (hipMemset(n->w, 0, off * 4) != hipSuccess || hipMemset(n->m, 0, off * 4) != hipSuccess ||
+      hipMemset(n->v, 0, off * 4) != hipSuccess || hipMemset(n->wb, 0, off * 2) != hipSuccess ||
+      hipMemset(n->mu, 0, 128 * 4) != hipSuccess || hipMemset(n->loss, 0, (1 << 20) * 4) != hipSuccess) {
+    mlp_free(n);
+    return TSIM_EDEVICE;
+  }
+  // seeded initialisation: W ~ N(0, 1/fan_in), biases 0 (Philox counters (i, 0, layer, 3))
+  for (int l = 0; l < 4; ++l) {
+    const int cnt = n->din[l] * n->dout[l];
+    const float sd = 1.0f / std::sqrt(float(n->din[l]));
+    hipLaunchKernelGGL(k_init_normal, dim3((cnt + 255) / 256), dim3(256), 0, 0, n->w + n->off_w[l],
+                       n->wb + n->off_w[l], cnt, sd, uint32_t(seed), uint32_t(seed >> 32), uint32_t(l));
+  }
+  // input scales: 1 / sqrt(A0[j][j] (D/r0)^{5/3}) at D/r0 = 2.75, tilt slots 0
+  std::vector<float> inv(TSIM_N_MODES, 0.f);
+  for (int j = 2; j < TSIM_N_MODES; ++j)
+    inv[j] = float(1.0 / std::sqrt(pl->A0[size_t(j) * TSIM_N_MODES + j] * std::pow(2.75, 5.0 / 3.0)));
+  if (hipMemcpy(n->inv_s, inv.data(), inv.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    mlp_free(n);
+    return TSIM_EDEVICE;
+  }
+  *out = n;
+  return TSIM_OK;
+}
+
+int tsim_mlp_destroy(tsim_mlp *n) {
+  mlp_free(n);
+  return TSIM_OK;
+}
+
+int tsim_mlp_param_count(const tsim_mlp *n, size_t *count) {
+  if (!n || !count) return TSIM_EINVAL;
+  *count = n->n_par;
+  return TSIM_OK;
+}
+
+int tsim_mlp_layout(const tsim_mlp *n, size_t *off_w, size_t *off_b) {
+  if (!n || !off_w || !off_b) return TSIM_EINVAL;
+  for (int l = 0; l < 4; ++l) {
+    off_w[l] = n->off_w[l];
+    off_b[l] = n->off_b[l];
+  }
+  return TSIM_OK;
+}
+
+int tsim_mlp_get(const tsim_mlp *n, int what, float *host, size_t count) {
+  if (!n || !host) return TSIM_EINVAL;
+  const float *src = nullptr;
+  size_t cnt = n->n_par;
+  switch (what) {
+    case 0: src = n->w; break;
+    case 1: src = n->g; break;
+    case 2: src = n->inv_s; cnt = TSIM_N_MODES; break;
+    case 3: src = n->mu; cnt = size_t(n->K); break;
+    case 4:
+      if (count < 1) return TSIM_EINVAL;
+      host[0] = n->s_out;
+      return TSIM_OK;
+    default: return TSIM_EINVAL;
+  }
+  if (count < cnt) return TSIM_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return TSIM_EDEVICE;
+  return hipMemcpy(host, src, cnt * 4, hipMemcpyDeviceToHost) == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+int tsim_mlp_set(tsim_mlp *n, int what, const float *host, size_t count) {
+  if (!n || !host) return TSIM_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return TSIM_EDEVICE;
+  switch (what) {
+    case 0: {
+      if (count != n->n_par) return TSIM_EINVAL;
+      std::vector<uint16_t> b(n->n_par);
+      for (size_t i = 0; i < n->n_par; ++i) {
+        uint32_t u;
+        std::memcpy(&u, &host[i], 4);
+        b[i] = uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+      }
+      if (hipMemcpy(n->w, host, n->n_par * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(n->wb, b.data(), n->n_par * 2, hipMemcpyHostToDevice) != hipSuccess)
+        return TSIM_EDEVICE;
+      return TSIM_OK;
+    }
+    case 2:
+      if (count != TSIM_N_MODES) return TSIM_EINVAL;
+      return hipMemcpy(n->inv_s, host, count * 4, hipMemcpyHostToDevice) == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+    case 3:
+      if (count != size_t(n->K)) return TSIM_EINVAL;
+      return hipMemcpy(n->mu, host, count * 4, hipMemcpyHostToDevice) == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+    case 4:
+      if (count != 1 || !(host[0] > 0.f)) return TSIM_EINVAL;
+      n->s_out = host[0];
+      return TSIM_OK;
+    default: return TSIM_EINVAL;
+  }
+}
+
+int tsim_mlp_make_data(const tsim_plan *pl, int n_pairs, uint64_t seed, float dr_lo, float dr_hi,
+                       float *zvec, float *beta, void *ws, tsim_stream stream) {
+  if (!pl || n_pairs < 1 || !zvec || !beta || !ws) return TSIM_EINVAL;
+  if (!pl->d_basis) return TSIM_EARTEFACT;
+  if (!(dr_lo > 0.f) || !(dr_hi >= dr_lo)) return TSIM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_draws, dim3((n_pairs + 255) / 256), dim3(256), 0, s, pl->d_L, zvec, n_pairs,
+                     uint32_t(seed), uint32_t(seed >> 32), dr_lo, dr_hi, 2u);
+  if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+  const size_t chunk = size_t(1) << 20;
+  for (size_t p0 = 0; p0 < size_t(n_pairs); p0 += chunk) {
+    const int cnt = int(std::min(chunk, size_t(n_pairs) - p0));
+    int st = launch_psf_exact(pl, cnt, zvec + p0 * TSIM_N_MODES, static_cast<float *>(ws), s);
+    if (st != TSIM_OK) return st;
+    st = launch_project(pl, static_cast<float *>(ws), cnt, beta + p0 * pl->K, s);
+    if (st != TSIM_OK) return st;
+  }
+  return TSIM_OK;
+}
+
+int tsim_mlp_grad(tsim_mlp *n, int batch, const float *zvec, const float *target, float *loss_host,
+                  tsim_stream stream) {
+  if (!n || batch < 1 || batch > n->B || !zvec || !target) return TSIM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_prep, dim3((batch + 255) / 256), dim3(256), 0, s, zvec, target, batch, 0, batch,
+                     n->inv_s, n->mu, 1.0f / n->s_out, n->K, n->x, n->t);
+  if (hipMemsetAsync(n->loss + n->step, 0, 4, s) != hipSuccess) return TSIM_EDEVICE;
+  int st = mlp_fwd_bwd(n, batch, s);
+  if (st != TSIM_OK) return st;
+  if (loss_host) {
+    if (hipStreamSynchronize(s) != hipSuccess) return TSIM_EDEVICE;
+    if (hipMemcpy(loss_host, n->loss + n->step, 4, hipMemcpyDeviceToHost) != hipSuccess) return TSIM_EDEVICE;
+  }
+  return TSIM_OK;
+}
+
+int tsim_mlp_train(tsim_mlp *n, const float *zvec, const float *target, int n_pairs, int steps,
+                   float lr_max, float lr_min, float *loss_host, tsim_stream stream) {
+  if (!n || !zvec || !target || n_pairs < n->B || steps < 1 || steps > (1 << 20)) return TSIM_EINVAL;
+  if (!(lr_max > 0.f) || !(lr_min >= 0.f)) return TSIM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipMemsetAsync(n->loss, 0, size_t(steps) * 4, s) != hipSuccess) return TSIM_EDEVICE;
+  const int B = n->B;
+  const double b1 = 0.9, b2 = 0.999;
+  for (int it = 0; it < steps; ++it) {
+    n->step = it;
+    const int start = int((size_t(it) * B) % size_t(n_pairs));
+    hipLaunchKernelGGL(k_prep, dim3((B + 255) / 256), dim3(256), 0, s, zvec, target, n_pairs, start, B,
+                       n->inv_s, n->mu, 1.0f / n->s_out, n->K, n->x, n->t);
+    int st = mlp_fwd_bwd(n, B, s);
+    if (st != TSIM_OK) return st;
+    const double prog = steps > 1 ? double(it) / double(steps - 1) : 1.0;
+    const float lr = float(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + std::cos(3.14159265358979 * prog)));
+    const int t = it + 1;
+    hipLaunchKernelGGL(k_adamw, dim3(int((n->n_par + 255) / 256)), dim3(256), 0, s, n->w, n->g, n->m,
+                       n->v, n->wb, int(n->n_par), lr, float(b1), float(b2),
+                       float(1.0 - std::pow(b1, t)), float(1.0 - std::pow(b2, t)), 1e-8f, 0.0f);
+    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+  }
+  n->step = 0;
+  if (loss_host) {
+    if (hipStreamSynchronize(s) != hipSuccess) return TSIM_EDEVICE;
+    if (hipMemcpy(loss_host, n->loss, size_t(steps) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return TSIM_EDEVICE;
+  }
+  return TSIM_OK;
+}
+
+}  // extern "C"
+
+// Pack the network into the plan's inference layout (padded BF16 weights).
+int plan_set_mlp_impl(tsim_plan *pl, const tsim_mlp *n) {
+  if (!pl || !n || n->K != pl->K) return TSIM_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return TSIM_EDEVICE;
+  std::vector<float> w(n->n_par), inv(TSIM_N_MODES), mu(n->K);
+  if (hipMemcpy(w.data(), n->w, w.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(inv.data(), n->inv_s, inv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(mu.data(), n->mu, mu.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return TSIM_EDEVICE;
+  auto bf = [](float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  };
+  // packed: W1 [256][48] | W2 [256][256] | W3 [256][256] | W4 [128][256]
+  const size_t s1 = size_t(HID) * IN_PAD, s2 = size_t(HID) * HID, s4 = size_t(128) * HID;
+  std::vector<uint16_t> pk(s1 + 2 * s2 + s4, 0);
+  for (int o = 0; o < HID; ++o)
+    for (int i = 0; i < TSIM_N_MODES; ++i) pk[size_t(o) * IN_PAD + i] = bf(w[n->off_w[0] + size_t(o) * TSIM_N_MODES + i]);
+  for (int l = 1; l < 3; ++l)
+    for (size_t e = 0; e < s2; ++e) pk[s1 + (l - 1) * s2 + e] = bf(w[n->off_w[l] + e]);
+  for (int o = 0; o < n->K; ++o)
+    for (int i = 0; i < HID; ++i) pk[s1 + 2 * s2 + size_t(o) * HID + i] = bf(w[n->off_w[3] + size_t(o) * HID + i]);
+  // FP32: b1 | b2 | b3 | b4[128] | inv_s[35] (pad 64) | mu[128]
+  std::vector<float> fb(3 * HID + 128 + 64 + 128, 0.f);
+  for (int l = 0; l < 3; ++l)
+    for (int o = 0; o < HID; ++o) fb[l * HID + o] = w[n->off_b[l] + o];
+  for (int o = 0; o < n->K; ++o) fb[3 * HID + o] = w[n->off_b[3] + o];
+  for (int j = 0; j < TSIM_N_MODES; ++j) fb[3 * HID + 128 + j] = inv[j];
+  for (int o = 0; o < n->K; ++o) fb[3 * HID + 128 + 64 + o] = mu[o];
+  if (!pl->d_mlp_w && hipMalloc(&pl->d_mlp_w, pk.size() * 2) != hipSuccess) return TSIM_ENOMEM;
+  if (!pl->d_mlp_f && hipMalloc(&pl->d_mlp_f, fb.size() * 4) != hipSuccess) return TSIM_ENOMEM;
+  if (hipMemcpy(pl->d_mlp_w, pk.data(), pk.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pl->d_mlp_f, fb.data(), fb.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return TSIM_EDEVICE;
+  pl->mlp_s_out = n->s_out;
+  return TSIM_OK;
+}
+
+int launch_mlp_infer(const tsim_plan *pl, const float *zern, int hw, size_t n_pix, void *beta,
+                     int out_bf16, int kb, hipStream_t s) {
+  if (!pl->d_mlp_w) return TSIM_EARTEFACT;
+  InferParams ip;
+  const size_t s1 = size_t(HID) * IN_PAD, s2 = size_t(HID) * HID;
+  ip.W1 = pl->d_mlp_w;
+  ip.W2 = pl->d_mlp_w + s1;
+  ip.W3 = pl->d_mlp_w + s1 + s2;
+  ip.W4 = pl->d_mlp_w + s1 + 2 * s2;
+  ip.b1 = pl->d_mlp_f;
+  ip.b2 = pl->d_mlp_f + HID;
+  ip.b3 = pl->d_mlp_f + 2 * HID;
+  ip.b4 = pl->d_mlp_f + 3 * HID;
+  ip.inv_s = pl->d_mlp_f + 3 * HID + 128;
+  ip.mu = pl->d_mlp_f + 3 * HID + 128 + 64;
+  ip.s_out = pl->mlp_s_out;
+  ip.K = pl->K;
+  ip.KB = kb;
+  ip.out_bf16 = out_bf16;
+  const size_t blocks = (n_pix + 127) / 128;
+  TraceScope tr("k_mlp_infer", s);
+  hipLaunchKernelGGL(k_mlp_infer, dim3(unsigned(blocks)), dim3(256), 0, s, zern, hw, n_pix, ip, beta);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}

@@ -247,8 +247,8 @@ int validate(const tsim_params *p) {
 
 void free_plan(tsim_plan *pl) {
   if (!pl) return;
-  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L,
-                  pl->d_zpupil, pl->d_basis, pl->d_basis_t, pl->d_tw_p};
+  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L,       pl->d_zpupil, pl->d_basis,
+                  pl->d_basis_t, pl->d_tw_p, pl->d_basis_bf, pl->d_mlp_w, pl->d_mlp_f};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   delete pl;
@@ -408,6 +408,17 @@ int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
       }
     if ((st = upload(&pl->d_basis, b.data(), b.size())) != TSIM_OK) goto fail;
     if ((st = upload(&pl->d_basis_t, bt.data(), bt.size())) != TSIM_OK) goto fail;
+    // BF16 tap-major copy for the matrix-core blur, taps padded to 32
+    const int TTP = (T2 + 31) / 32 * 32;
+    std::vector<uint16_t> bb(size_t(TTP) * KP, 0);
+    for (int t = 0; t < T2; ++t)
+      for (int k = 0; k < K; ++k) {
+        float f = float(pl->basis[size_t(k) * T2 + t]);
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        bb[size_t(t) * KP + k] = uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+      }
+    if ((st = upload(&pl->d_basis_bf, bb.data(), bb.size())) != TSIM_OK) goto fail;
   }
   *out = pl;
   return TSIM_OK;

@@ -263,6 +263,14 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
 
+// pixels per P2S chunk: bounds the PSF workspace
+size_t p2s_chunk(const tsim_plan *pl, size_t total) {
+  size_t cap = size_t(1) << 20;
+  return std::min(total, cap);
+}
+
+}  // namespace
+
 int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s) {
   const int T2 = pl->T * pl->T;
   dim3 grid((n + 63) / 64);
@@ -275,14 +283,6 @@ int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipS
   }
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
-
-// pixels per P2S chunk: bounds the PSF workspace
-size_t p2s_chunk(const tsim_plan *pl, size_t total) {
-  size_t cap = size_t(1) << 20;
-  return std::min(total, cap);
-}
-
-}  // namespace
 
 size_t p2s_ws_bytes(const tsim_plan *pl, int frames) {
   size_t total = size_t(frames) * pl->H * pl->W;
