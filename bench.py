@@ -23,6 +23,10 @@ sys.path.insert(0, ROOT)
 METRIC = "dense-field Mpixel/s @512² & 4K: plain FP32 vs BF16+learned P2S at fixed err"
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+N_TRAIN = 2_000_000
+N_HELDOUT = 100_000
+TRAIN_BATCH = 8192
 
 H = W = 512
 C = 3
@@ -59,7 +63,41 @@ def kernel_work(name, frames):
         return "alu", px * (2 * K * T * T + 2 * C * T * T), "flop"
     if name == "k_warp":
         return "hbm", px * (8 + 4 * C + 4 * C), "B"
+    if name == "k_mlp_infer":
+        return "mfma", px * 2 * (35 * 256 + 2 * 256 * 256 + 256 * K), "flop"
+    if name == "k_render_bf16":
+        return "mfma", px * (2 * K * T * T + 2 * C * T * T), "flop"
     return None
+
+
+def summarize(rep, steps, frames, traffic=True):
+    """Per-kernel roofline entries from the tracer's {name: (launches, ms)}."""
+    kernels = {}
+    for name, (n, tot) in rep.items():
+        w = kernel_work(name, frames)
+        per_step = n / steps
+        avg_ms = tot / n
+        ent = {"launches_per_step": per_step, "avg_ms": round(avg_ms, 4),
+               "ms_per_step": round(tot / steps, 4)}
+        if w:
+            bound, amount, unit = w
+            per_launch = amount / per_step
+            if bound == "hbm":
+                ach = per_launch / (avg_ms * 1e-3) / 1e9
+                ent.update(bound="hbm", achieved=round(ach, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                           frac=round(ach / PEAK_HBM_GBS, 4))
+            else:
+                peak = PEAK_BF16_TFLOPS if bound == "mfma" else PEAK_FP32_TFLOPS
+                ach = per_launch / (avg_ms * 1e-3) / 1e12
+                ent.update(bound=bound, achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
+                           frac=round(ach / peak, 4))
+        kernels[name] = ent
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    d = kernels[dom]
+    roof = {"kernel": dom, "bound": d.get("bound"), "achieved": d.get("achieved"),
+            "peak": d.get("peak"), "unit": d.get("unit"), "frac": d.get("frac"),
+            "traffic": measured_traffic(dom, d["launches_per_step"]) if traffic else None}
+    return kernels, roof
 
 
 def source_hash(kernel):
@@ -130,6 +168,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); frames shard "
@@ -153,62 +193,90 @@ def main():
 
     img = torch.tensor(np.repeat(synthetic.test_image(C, H, W, 16, 0)[None], FRAMES, 0), device=dev)
     zern = torch.empty((FRAMES, 35, H, W), dtype=torch.float32, device=dev)
-    beta = torch.empty((FRAMES, H, W, K), dtype=torch.float32, device=dev)
-    blur = torch.empty((FRAMES, C, H, W), dtype=torch.float32, device=dev)
-    out = torch.empty_like(blur)
-    ws = plan.workspace(FRAMES)
     drs = [DR_CYCLE[i % 3] for i in range(FRAMES)]
 
-    def step(i):
-        plan.sample_zernike(drs, 0, i * FRAMES, zern, ws)
-        plan.p2s(zern, beta, ws)
-        plan.render(img, beta, blur)
-        plan.warp(blur, zern, out)
+    def run(pl, beta, steps, warmup):
+        """Time `steps` whole-path steps after `warmup`; returns (ms/step,
+        tracer report, output of the last step)."""
+        blur = torch.empty((FRAMES, C, H, W), dtype=torch.float32, device=dev)
+        out = torch.empty_like(blur)
+        ws = pl.workspace(FRAMES)
 
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    tsim.trace_enable(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for i in range(args.steps):
-        step(args.warmup + i)
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
-    rep = tsim.trace_report()
-    tsim.trace_enable(False)
-    if not torch.isfinite(out).all():
-        raise RuntimeError("non-finite output")
+        def step(i):
+            pl.sample_zernike(drs, 0, i * FRAMES, zern, ws)
+            pl.p2s(zern, beta, ws)
+            pl.render(img, beta, blur)
+            pl.warp(blur, zern, out)
 
-    kernels = {}
-    for name, (n, tot) in rep.items():
-        w = kernel_work(name, FRAMES)
-        per_step = n / args.steps
-        avg_ms = tot / n
-        ent = {"launches_per_step": per_step, "avg_ms": round(avg_ms, 4),
-               "ms_per_step": round(tot / args.steps, 4)}
-        if w:
-            bound, amount, unit = w
-            per_launch = amount / per_step
-            if bound == "hbm":
-                ach = per_launch / (avg_ms * 1e-3) / 1e9
-                ent.update(bound="hbm", achieved=round(ach, 2), peak=PEAK_HBM_GBS, unit="GB/s",
-                           frac=round(ach / PEAK_HBM_GBS, 4))
-            else:
-                ach = per_launch / (avg_ms * 1e-3) / 1e12
-                ent.update(bound="alu", achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS,
-                           unit="TFLOP/s", frac=round(ach / PEAK_FP32_TFLOPS, 4))
-        kernels[name] = ent
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    d = kernels[dom]
-    roofline = {"kernel": dom, "bound": d.get("bound"), "achieved": d.get("achieved"),
-                "peak": d.get("peak"), "unit": d.get("unit"), "frac": d.get("frac"),
-                "traffic": measured_traffic(dom, d["launches_per_step"])}
+        for i in range(warmup):
+            step(i)
+        torch.cuda.synchronize()
+        tsim.trace_enable(True)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for i in range(steps):
+            step(warmup + i)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / steps
+        rep = tsim.trace_report()
+        tsim.trace_enable(False)
+        if not torch.isfinite(out).all():
+            raise RuntimeError("non-finite output")
+        # the last step rendered frames (warmup + steps - 1) * FRAMES ...; rerun step 0 for a
+        # fixed comparison frame set
+        step(0)
+        torch.cuda.synchronize()
+        return ms, rep, out.clone()
 
+    # ---- plain FP32 form (exact P2S) ----
+    beta32 = torch.empty((FRAMES, H, W, K), dtype=torch.float32, device=dev)
+    ms, rep, out_plain = run(plan, beta32, args.steps, args.warmup)
+    kernels, roofline = summarize(rep, args.steps, FRAMES)
     value = FRAMES * H * W / (ms * 1e-3) / 1e6
+
+    # ---- BF16 + learned form ----
+    learned = None
+    if not args.no_learned:
+        t0 = time.perf_counter()
+        plan_l = tsim.Plan(H, W, C, G, G, pixel_pitch_over_d=PITCH, psf_t=T, pupil_n=P, basis=basis,
+                           p2s_mode=tsim.P2S_LEARNED, precision=tsim.BF16)
+        z_tr, b_tr = tsim.make_training_data(plan_l, N_TRAIN, seed=1)
+        net = tsim.Mlp(plan_l, batch=TRAIN_BATCH, seed=0)
+        net.fit_output(b_tr)
+        t1 = time.perf_counter()
+        losses = net.train(z_tr, b_tr, args.train_steps, lr_max=1e-3, lr_min=1e-5)
+        train_s = time.perf_counter() - t1
+        tsim.plan_set_mlp(plan_l, net)
+        del z_tr, b_tr
+        z_te, b_te = tsim.make_training_data(plan_l, N_HELDOUT, seed=2)
+        pred = tsim.mlp_predict(plan_l, z_te)
+        torch.cuda.synchronize()
+        err = (torch.linalg.vector_norm(pred - b_te, dim=1)
+               / torch.linalg.vector_norm(b_te, dim=1)).cpu().numpy()
+        setup_l = time.perf_counter() - t0
+        kp = 32 if K <= 32 else 64 if K <= 64 else 112 if K <= 112 else 128
+        beta16 = torch.empty((FRAMES, H, W, kp), dtype=torch.bfloat16, device=dev)
+        ms_l, rep_l, out_l = run(plan_l, beta16, args.steps, args.warmup)
+        kern_l, roof_l = summarize(rep_l, args.steps, FRAMES, traffic=False)
+        mse = float(torch.mean((out_l - out_plain) ** 2))
+        learned = {"value": round(FRAMES * H * W / (ms_l * 1e-3) / 1e6, 3), "unit": "Mpixel/s",
+                   "ms_per_step": round(ms_l, 3), "dtype": "bf16 MFMA, fp32 accumulate",
+                   "speedup_vs_plain_fp32": round(ms / ms_l, 2),
+                   "psf_rel_err_mean": round(float(err.mean()), 5),
+                   "psf_rel_err_median": round(float(np.median(err)), 5),
+                   "psf_rel_err_p95": round(float(np.percentile(err, 95)), 5),
+                   "psf_err_definition": "||beta_net - beta_exact|| / ||beta_exact|| on 1e5 held-out "
+                                         "pairs (= relative L2 error of the projected PSF)",
+                   "image_psnr_db_vs_plain_fp32": round(10 * math.log10(1.0 / mse), 2) if mse > 0 else None,
+                   "train": {"pairs": N_TRAIN, "batch": TRAIN_BATCH, "steps": args.train_steps,
+                             "seconds": round(train_s, 2),
+                             "loss_first": float(losses[:10].mean()),
+                             "loss_last": float(losses[-10:].mean())},
+                   "setup_s": round(setup_l, 2), "roofline": roof_l, "kernels": kern_l}
+
     line = {"metric": METRIC, "value": round(value, 3), "unit": "Mpixel/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -218,7 +286,7 @@ def main():
                                    "basis, FP32 basis blur + bilinear tilt warp (plain FP32 form)",
                        "frames_per_step": FRAMES, "H": H, "W": W, "C": C, "grid": G, "K": K,
                        "T": T, "pupil": P},
-            "roofline": roofline, "kernels": kernels,
+            "roofline": roofline, "kernels": kernels, "learned_bf16": learned,
             "setup_s": round(setup_s, 2)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

@@ -223,6 +223,15 @@ int tsim_mlp_make_data(const tsim_plan *plan, int n_pairs, uint64_t seed, float 
 int tsim_mlp_grad(tsim_mlp *net, int batch, const float *zvec, const float *target,
                   float *loss_host, tsim_stream stream);
 
+/* Set the output normalisation from training targets [n_pairs][K] (device):
+ * mu = per-output mean, s_out = RMS deviation from mu over all outputs. */
+int tsim_mlp_fit_output(tsim_mlp *net, const float *target, int n_pairs, tsim_stream stream);
+
+/* The plan's network on n_vec Zernike vectors: zvec [n_vec][35] device f32
+ * -> beta [n_vec][K] device f32 (BF16 products, FP32 accumulation). */
+int tsim_mlp_predict(const tsim_plan *plan, int n_vec, const float *zvec, float *beta,
+                     tsim_stream stream);
+
 /* `steps` AdamW steps (beta1 0.9, beta2 0.999, eps 1e-8, no weight decay,
  * cosine learning rate lr_max -> lr_min) on consecutive batches of the
  * pairs (wrapping around).  loss_host [steps] may be NULL. */

@@ -81,6 +81,8 @@ _lib_mlp_data = _sig("tsim_mlp_make_data", _i, [_vp, _i, _u64, _f, _f, _vp, _vp,
 _lib_mlp_grad = _sig("tsim_mlp_grad", _i, [_vp, _i, _vp, _vp, _fp, _vp])
 _lib_mlp_train = _sig("tsim_mlp_train", _i, [_vp, _vp, _vp, _i, _i, _f, _f, _fp, _vp])
 _lib_set_mlp = _sig("tsim_plan_set_mlp", _i, [_vp, _vp])
+_lib_mlp_fit = _sig("tsim_mlp_fit_output", _i, [_vp, _vp, _i, _vp])
+_lib_mlp_predict = _sig("tsim_mlp_predict", _i, [_vp, _i, _vp, _vp, _vp])
 _lib_host_tables = _sig("tsim_host_tables", _i,
                         [ctypes.POINTER(_Params), _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
 
@@ -89,7 +91,8 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_status_string", "tsim_host_tables", "tsim_basis_build", "tsim_trace_enable",
             "tsim_trace_count", "tsim_trace_get", "tsim_mlp_create", "tsim_mlp_destroy",
             "tsim_mlp_param_count", "tsim_mlp_layout", "tsim_mlp_get", "tsim_mlp_set",
-            "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp"]
+            "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp",
+            "tsim_mlp_fit_output", "tsim_mlp_predict"]
 
 
 def trace_enable(on=True):
@@ -328,6 +331,10 @@ class Mlp:
                              _stream(stream)), "tsim_mlp_grad")
         return loss.value
 
+    def fit_output(self, target, stream=None):
+        _check(_lib_mlp_fit(self._h, _ptr(target), target.shape[0], _stream(stream)),
+               "tsim_mlp_fit_output")
+
     def train(self, zvec, target, steps, lr_max=1e-3, lr_min=1e-5, stream=None):
         losses = np.zeros(steps, dtype=np.float32)
         _check(_lib_mlp_train(self._h, _ptr(zvec), _ptr(target), zvec.shape[0], int(steps),
@@ -345,6 +352,14 @@ def make_training_data(plan, n_pairs, seed=0, dr_lo=0.5, dr_hi=5.0, stream=None)
     _check(_lib_mlp_data(plan._h, int(n_pairs), int(seed), float(dr_lo), float(dr_hi), _ptr(z),
                          _ptr(b), _ptr(ws), _stream(stream)), "tsim_mlp_make_data")
     return z, b
+
+
+def mlp_predict(plan, zvec, stream=None):
+    """The plan's network on Zernike vectors [n][35] -> beta [n][K] (float32)."""
+    out = torch.empty((zvec.shape[0], plan.K), dtype=torch.float32, device="cuda")
+    _check(_lib_mlp_predict(plan._h, zvec.shape[0], _ptr(zvec), _ptr(out), _stream(stream)),
+           "tsim_mlp_predict")
+    return out
 
 
 def plan_set_mlp(plan, mlp):

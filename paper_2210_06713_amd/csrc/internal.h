@@ -28,6 +28,7 @@ struct tsim_plan {
   float2 *d_tw_w = nullptr;    // twiddles exp(+2 pi i k / Gw), k < Gw/2
   float *d_L = nullptr;        // [35][35] float32 lower
   float *d_zpupil = nullptr;   // [P/2][P/2][36] Zernike modes 4..36 (zero padded) per window sample
+  float *d_zrow = nullptr;     // [8][33][P/2] per-row Chebyshev coefficients of modes 4..36
   int n_pupil = 0;             // NS
   int pupil_win = 0;           // side of the square window holding the aperture
   float *d_basis = nullptr;    // [K][T*T] float32

@@ -160,6 +160,29 @@ __global__ void k_colsum(const float *__restrict__ dz, int M, int N, float *__re
   if (g == 0 && n < N) db[n] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
+// sum of squared deviations from mu over [n][K] (output scale of the network)
+__global__ void k_sqdev(const float *__restrict__ beta, const float *__restrict__ mu, size_t nel, int K,
+                        float *__restrict__ acc) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nel; i += size_t(gridDim.x) * blockDim.x) {
+    const float d = beta[i] - mu[i % K];
+    s += d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(acc, red[0]);
+}
+
+__global__ void k_scale(float *__restrict__ v, int n, float s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] *= s;
+}
+
 __global__ void k_adamw(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                         float *__restrict__ v, uint16_t *__restrict__ wb, int n, float lr, float b1,
                         float b2, float c1, float c2, float eps, float wd) {
@@ -557,6 +580,30 @@ int tsim_mlp_grad(tsim_mlp *n, int batch, const float *zvec, const float *target
     if (hipMemcpy(loss_host, n->loss + n->step, 4, hipMemcpyDeviceToHost) != hipSuccess) return TSIM_EDEVICE;
   }
   return TSIM_OK;
+}
+
+int tsim_mlp_fit_output(tsim_mlp *n, const float *target, int n_pairs, tsim_stream stream) {
+  if (!n || !target || n_pairs < 1) return TSIM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_colsum, dim3((n->K + 63) / 64), dim3(256), 0, s, target, n_pairs, n->K, n->mu);
+  hipLaunchKernelGGL(k_scale, dim3(1), dim3(128), 0, s, n->mu, n->K, 1.0f / float(n_pairs));
+  if (hipMemsetAsync(n->loss, 0, 4, s) != hipSuccess) return TSIM_EDEVICE;
+  const size_t nel = size_t(n_pairs) * n->K;
+  hipLaunchKernelGGL(k_sqdev, dim3(1024), dim3(256), 0, s, target, n->mu, nel, n->K, n->loss);
+  float sq = 0.f;
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(&sq, n->loss, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return TSIM_EDEVICE;
+  const float rms = std::sqrt(sq / float(nel));
+  if (!(rms > 0.f) || !std::isfinite(rms)) return TSIM_EINVAL;
+  n->s_out = rms;
+  return TSIM_OK;
+}
+
+int tsim_mlp_predict(const tsim_plan *pl, int n_vec, const float *zvec, float *beta, tsim_stream stream) {
+  if (!pl || n_vec < 1 || !zvec || !beta) return TSIM_EINVAL;
+  if (!pl->d_mlp_w) return TSIM_EARTEFACT;
+  return launch_mlp_infer(pl, zvec, 1, size_t(n_vec), beta, 0, pl->K, static_cast<hipStream_t>(stream));
 }
 
 int tsim_mlp_train(tsim_mlp *n, const float *zvec, const float *target, int n_pairs, int steps,

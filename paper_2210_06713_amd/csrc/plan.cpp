@@ -247,7 +247,7 @@ int validate(const tsim_params *p) {
 
 void free_plan(tsim_plan *pl) {
   if (!pl) return;
-  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L,       pl->d_zpupil, pl->d_basis,
+  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zpupil, pl->d_zrow, pl->d_basis,
                   pl->d_basis_t, pl->d_tw_p, pl->d_basis_bf, pl->d_mlp_w, pl->d_mlp_f};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -387,6 +387,29 @@ int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
       }
     }
     if ((st = upload(&pl->d_zpupil, zt.data(), zt.size())) != TSIM_OK) goto fail;
+    // Per-row Chebyshev form of the phase: for window row r (y = (r - R)/R),
+    // Z_j(x, y) = sum_p e_{j,p}(y) T_p(x) exactly (degree <= 7 in x), with
+    // e obtained by interpolation at the 8 Chebyshev nodes.  Stored
+    // [p][j][r] so the 32 lanes of a pixel (one row each) read contiguously.
+    const int NP = 8;
+    std::vector<float> zr(size_t(NP) * NZ * win, 0.0f);
+    for (int r = 0; r < win; ++r) {
+      const double y = double(r - R) / R;
+      for (int t = 0; t < NZ; ++t) {
+        double fk[NP];
+        for (int k = 0; k < NP; ++k) {
+          const double x = std::cos(kPi * (k + 0.5) / NP);
+          fk[k] = zernike(t + 4, std::hypot(x, y), std::atan2(y, x));
+        }
+        for (int p = 0; p < NP; ++p) {
+          double c = 0.0;
+          for (int k = 0; k < NP; ++k) c += fk[k] * std::cos(p * kPi * (k + 0.5) / NP);
+          c *= (p == 0 ? 1.0 : 2.0) / NP;
+          zr[(size_t(p) * NZ + t) * win + r] = float(c);
+        }
+      }
+    }
+    if ((st = upload(&pl->d_zrow, zr.data(), zr.size())) != TSIM_OK) goto fail;
     std::vector<float2> twp(static_cast<size_t>(P));
     for (int k = 0; k < P; ++k)
       twp[k] = make_float2(float(std::cos(2 * kPi * k / P)), float(-std::sin(2 * kPi * k / P)));

@@ -18,6 +18,7 @@
 
 #include "common.cuh"
 #include "internal.h"
+#include "cheb32.h"
 #include "twiddle64.h"
 
 namespace {
@@ -74,7 +75,7 @@ __device__ __forceinline__ float2 pick(const float2 (&E)[32], const float2 (&O)[
 template <int T>
 __global__ void __launch_bounds__(256)
 k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
-        const float *__restrict__ zt, float *__restrict__ psf) {
+        const float *__restrict__ zrow, float *__restrict__ psf) {
   constexpr int R = (T - 1) / 2;  // crop radius, <= 16
   constexpr int LS = 33;          // LDS row stride (complex)
   __shared__ float2 s1[8][32 * LS];
@@ -100,25 +101,27 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
   {
     const int wr = lane;
     const int rp = wr - 16;
+    // this row's phase as a Chebyshev series in x: phi(x) = sum_p d_p T_p(x),
+    // d_p = sum_j a_j e_{j,p}(y) from the per-row table [p][j][row]
+    float d[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      float s = 0.f;
+#pragma unroll
+      for (int j = 0; j < 33; ++j) s = fmaf(a[j], zrow[(p * 33 + j) * 32 + wr], s);
+      d[p] = s;
+    }
 #pragma unroll
     for (int n = 0; n < 32; ++n) {
       const int cp = (n < 16) ? n : n - 32;  // signed column offset
-      const int wc = cp + 16;
       float2 v = make_float2(0.f, 0.f);
       if (rp * rp + cp * cp < 256) {
-        const float4 *zs = reinterpret_cast<const float4 *>(zt + (size_t(wr) * 32 + wc) * kZPad);
         float phi = 0.f;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          float4 z = zs[q];
-          phi = fmaf(a[4 * q + 0], z.x, phi);
-          if (4 * q + 1 < 33) phi = fmaf(a[4 * q + 1], z.y, phi);
-          if (4 * q + 2 < 33) phi = fmaf(a[4 * q + 2], z.z, phi);
-          if (4 * q + 3 < 33) phi = fmaf(a[4 * q + 3], z.w, phi);
-        }
-        float sn, cs;
-        sincosf(phi, &sn, &cs);
-        v = make_float2(cs, -sn);  // exp(-i phi)
+        for (int p = 0; p < 8; ++p) phi = fmaf(d[p], kChebCol[n][p], phi);
+        // exp(-i phi) with the hardware sine/cosine (input in revolutions)
+        const float rev = phi * 0.15915494309189535f;
+        v = make_float2(__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev));
       }
       E[n] = v;
       const int k = (cp + 64) & 63;  // exp(-2 pi i c'/64)
@@ -163,10 +166,13 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
         const int ky = (s == 0) ? lane - 16 : 16;
         if (s == 1 && lane != 0) break;
         float2 acc = make_float2(0.f, 0.f);
+        // twiddle exp(-2 pi i ky r'/64) for r' = -16, -15, ... by recurrence
+        const int k0 = (-16 * ky + 64 * 64) & 63, k1 = (ky + 64) & 63;
+        float2 tw = make_float2(kW64re[k0], kW64im[k0]);
+        const float2 step = make_float2(kW64re[k1], kW64im[k1]);
         for (int wr = 0; wr < 32; ++wr) {
-          const int rp = wr - 16;
-          const int k = (ky * rp + 64 * 64) & 63;
-          acc = f2add(acc, cmul(make_float2(kW64re[k], kW64im[k]), buf[wr * LS + 32]));
+          acc = f2add(acc, cmul(tw, buf[wr * LS + 32]));
+          tw = cmul(tw, step);
         }
         float m = acc.x * acc.x + acc.y * acc.y;
         hx[s] = m;
@@ -250,7 +256,7 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
                     hipStream_t s) {
   if (pl->P != 64) return TSIM_EUNSUPPORTED;
   dim3 grid((n + 7) / 8);
-  const float *zt = pl->d_zpupil;
+  const float *zt = pl->d_zrow;
   TraceScope tr("k_psf64", s);
   switch (pl->T) {
     case 33: hipLaunchKernelGGL(k_psf64<33>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
