@@ -234,35 +234,61 @@ __global__ void k_draws(const float *__restrict__ Lmat, float *__restrict__ zvec
 constexpr int HID = 256;
 constexpr int IN_PAD = 48;   // 35 inputs padded to three 16-wide k-steps
 constexpr int ACT_LD = HID + 8;
+constexpr int IPX = 64;      // pixels per inference block (two 32-row tiles)
 
-// One 32-row tile: out[32][NT*32] = act[32][KSTEPS*16] * W[n][k]^T, acc in regs.
+// erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7): the inference GELU
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  const float poly = fmaf(fmaf(fmaf(fmaf(1.061405429f, t, -1.453152027f), t, 1.421413741f), t,
+                              -0.284496736f), t, 0.254829592f) * t;
+  const float y = 1.0f - poly * __expf(-ax * ax);
+  return copysignf(y, x);
+}
+__device__ __forceinline__ float gelu_fast(float z) {
+  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
+}
+
+// acc[t] (t < NT) = act[32 rows of tile mt][KSTEPS*16] x W[n0 + 32t + .][.]^T
 template <int NT, int KSTEPS>
-__device__ __forceinline__ void mlp_layer(const uint16_t *act, const uint16_t *__restrict__ W, int ldw,
-                                          f32x16 (&acc)[8], int lane) {
+__device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__restrict__ W, int ldw,
+                                         int n0, f32x16 (&acc)[NT], int lane) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
-#pragma unroll 4
-  for (int s = 0; s < KSTEPS; ++s) {
-    const bf16x8 a = load8(act + (lane & 31) * ACT_LD + s * 16 + 8 * (lane >> 5));
+  const uint16_t *wrow = W + size_t(n0 + (lane & 31)) * ldw + 8 * (lane >> 5);
+  const uint16_t *arow = act + (lane & 31) * ACT_LD + 8 * (lane >> 5);
+  bf16x8 b[NT], bn[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const bf16x8 b = load8(W + size_t(t * 32 + (lane & 31)) * ldw + s * 16 + 8 * (lane >> 5));
-      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+  for (int t = 0; t < NT; ++t) b[t] = load8(wrow + size_t(t) * 32 * ldw);
+#pragma unroll
+  for (int s = 0; s < KSTEPS; ++s) {
+    if (s + 1 < KSTEPS) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bn[t] = load8(wrow + size_t(t) * 32 * ldw + (s + 1) * 16);
+    }
+    const bf16x8 a = load8(arow + s * 16);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t], acc[t], 0, 0, 0);
+    if (s + 1 < KSTEPS) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b[t] = bn[t];
     }
   }
 }
 
 template <int NT>
-__device__ __forceinline__ void mlp_store_gelu(uint16_t *act, const f32x16 (&acc)[8],
-                                               const float *__restrict__ bias, int lane) {
+__device__ __forceinline__ void mlp_store_gelu(uint16_t *act, const f32x16 (&acc)[NT],
+                                               const float *__restrict__ bias, int n0, int lane) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int t = 0; t < NT; ++t) {
+    const int n = n0 + t * 32 + (lane & 31);
+    const float bn = bias[n];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      const int n = t * 32 + (lane & 31);
-      act[m * ACT_LD + n] = f2bf(gelu(acc[t][r] + bias[n]));
+      act[m * ACT_LD + n] = f2bf(gelu_fast(acc[t][r] + bn));
     }
+  }
 }
 
 struct InferParams {
@@ -275,53 +301,64 @@ struct InferParams {
   int out_bf16;
 };
 
+// Block: 64 pixels, 4 waves.  Wave w computes rows of tile (w & 1) and the
+// output columns [128 (w >> 1), +128) of each hidden layer (64 for the last).
 __global__ void __launch_bounds__(256)
 k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip, void *__restrict__ beta) {
-  __shared__ __attribute__((aligned(16))) uint16_t act_all[4][32 * ACT_LD];
+  __shared__ __attribute__((aligned(16))) uint16_t act_all[IPX * ACT_LD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint16_t *act = act_all[w];
-  const size_t p0 = (size_t(blockIdx.x) * 4 + w) * 32;
-  // input rows: lanes 0..31 each load one pixel's 35 coefficients
-  if (lane < 32) {
-    const size_t p = p0 + lane;
+  const int mt = w & 1, nh = w >> 1;
+  uint16_t *act = act_all + mt * 32 * ACT_LD;
+  const size_t pb = size_t(blockIdx.x) * IPX;
+  {
+    // inputs: thread -> pixel (tid % 64), modes [12 (tid / 64), +12)
+    const int px = threadIdx.x & 63, j0 = (threadIdx.x >> 6) * 12;
+    const size_t p = pb + px;
     const bool ok = p < n_pix;
     const size_t pc = ok ? p : 0;
     const size_t fr = pc / size_t(hw), yx = pc - fr * size_t(hw);
     const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
-    for (int j = 0; j < IN_PAD; ++j) {
-      float v = (ok && j < TSIM_N_MODES) ? zp[size_t(j) * hw] * ip.inv_s[j] : 0.f;
-      act[lane * ACT_LD + j] = f2bf(v);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      const int j = j0 + q;
+      const float v = (ok && j < TSIM_N_MODES) ? zp[size_t(j) * hw] * ip.inv_s[j] : 0.f;
+      act_all[px * ACT_LD + j] = f2bf(v);
     }
   }
   __syncthreads();
-  f32x16 acc[8];
-  mlp_layer<8, IN_PAD / 16>(act, ip.W1, IN_PAD, acc, lane);
+  f32x16 acc[4];
+  mlp_tile<4, IN_PAD / 16>(act, ip.W1, IN_PAD, nh * 128, acc, lane);
   __syncthreads();
-  mlp_store_gelu<8>(act, acc, ip.b1, lane);
+  mlp_store_gelu<4>(act, acc, ip.b1, nh * 128, lane);
   __syncthreads();
-  mlp_layer<8, HID / 16>(act, ip.W2, HID, acc, lane);
+  mlp_tile<4, HID / 16>(act, ip.W2, HID, nh * 128, acc, lane);
   __syncthreads();
-  mlp_store_gelu<8>(act, acc, ip.b2, lane);
+  mlp_store_gelu<4>(act, acc, ip.b2, nh * 128, lane);
   __syncthreads();
-  mlp_layer<8, HID / 16>(act, ip.W3, HID, acc, lane);
+  mlp_tile<4, HID / 16>(act, ip.W3, HID, nh * 128, acc, lane);
   __syncthreads();
-  mlp_store_gelu<8>(act, acc, ip.b3, lane);
+  mlp_store_gelu<4>(act, acc, ip.b3, nh * 128, lane);
   __syncthreads();
-  mlp_layer<4, HID / 16>(act, ip.W4, HID, acc, lane);
+  f32x16 acc2[2];
+  mlp_tile<2, HID / 16>(act, ip.W4, HID, nh * 64, acc2, lane);
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 2; ++t) {
+    const int n = nh * 64 + t * 32 + (lane & 31);
+    if (n >= ip.KB) continue;
+    const bool real = n < ip.K;
+    const float bn = real ? ip.b4[n] : 0.f, mun = real ? ip.mu[n] : 0.f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      const int n = t * 32 + (lane & 31);
-      const size_t p = p0 + m;
-      if (p >= n_pix || n >= ip.KB) continue;
-      const float y = (n < ip.K) ? (acc[t][r] + ip.b4[n]) * ip.s_out + ip.mu[n] : 0.f;
+      const size_t p = pb + mt * 32 + m;
+      if (p >= n_pix) continue;
+      const float y = real ? (acc2[t][r] + bn) * ip.s_out + mun : 0.f;
       if (ip.out_bf16)
         static_cast<uint16_t *>(beta)[p * ip.KB + n] = f2bf(y);
       else
         static_cast<float *>(beta)[p * ip.KB + n] = y;
     }
+  }
 }
 
 template <int EPI>
@@ -698,7 +735,7 @@ int launch_mlp_infer(const tsim_plan *pl, const float *zern, int hw, size_t n_pi
   ip.K = pl->K;
   ip.KB = kb;
   ip.out_bf16 = out_bf16;
-  const size_t blocks = (n_pix + 127) / 128;
+  const size_t blocks = (n_pix + IPX - 1) / IPX;
   TraceScope tr("k_mlp_infer", s);
   hipLaunchKernelGGL(k_mlp_infer, dim3(unsigned(blocks)), dim3(256), 0, s, zern, hw, n_pix, ip, beta);
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;

@@ -110,13 +110,15 @@ __device__ __forceinline__ bf16x8 ld_bf8(const uint16_t *p) {
 // block of 32 taps the matrix cores form htilde[32 px][32 taps] = beta (BF16)
 // x psi (BF16) with FP32 accumulation; each lane then multiplies its 16
 // (pixel, tap) values by the image samples I(x - u) from LDS and keeps
-// per-pixel partial sums; a 32-lane reduction finishes the tap sum.
+// per-pixel partial sums; a 32-lane reduction finishes the tap sum.  The psi
+// tap tiles are staged through double-buffered LDS shared by the 4 waves.
 template <int KS>
 __global__ void __launch_bounds__(256)
 k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
               const uint16_t *__restrict__ psi /*[ntiles*32][KS*16]*/, float *__restrict__ out,
               int H, int W, int C, int T, int ntiles) {
-  constexpr int TH = 8, TW = 16, KB = KS * 16;
+  constexpr int TH = 8, TW = 16, KB = KS * 16, PLD = KB + 8;  // padded psi rows (bank spread)
+  __shared__ __attribute__((aligned(16))) uint16_t ps[2][32 * PLD];
   extern __shared__ float tile[];
   const int R = (T - 1) / 2;
   const int SH = TH + T - 1, SW = TW + T - 1;
@@ -131,8 +133,16 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
     const int gx = min(max(tx0 + sx - R, 0), W - 1);
     tile[e] = imf[(size_t(c) * H + gy) * W + gx];
   }
+  // stage psi tile 0: 32 rows x KB bf16 = 32 * KS * 2 chunks of 16 B
+  auto stage = [&](int t, int buf) {
+    for (int e = threadIdx.x; e < 32 * KS * 2; e += 256) {
+      const int row = e / (KS * 2), ch = e - row * (KS * 2);
+      *reinterpret_cast<uint4 *>(&ps[buf][row * PLD + ch * 8]) =
+          *reinterpret_cast<const uint4 *>(psi + size_t(32 * t + row) * KB + ch * 8);
+    }
+  };
+  stage(0, 0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // A operand: this lane's pixel row of beta
   bf16x8 a[KS];
   {
     const int m = lane & 31;
@@ -156,11 +166,13 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
   __syncthreads();
   const int plane = SH * SW;
   for (int t = 0; t < ntiles; ++t) {
-    const int n = 32 * t + (lane & 31);
+    const int cur = t & 1;
+    if (t + 1 < ntiles) stage(t + 1, cur ^ 1);
     f32x16 acc = {};
-    const uint16_t *pp = psi + size_t(n) * KB + 8 * (lane >> 5);
+    const uint16_t *pp = &ps[cur][(lane & 31) * PLD + 8 * (lane >> 5)];
 #pragma unroll
     for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], ld_bf8(pp + 16 * s), acc, 0, 0, 0);
+    const int n = 32 * t + (lane & 31);
     const int nn = n < T * T ? n : 0;  // padded taps carry psi = 0
     const int uy = nn / T - R, ux = nn - (nn / T) * T - R;
     const int off = uy * SW + ux;
@@ -171,6 +183,7 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
       for (int c = 0; c < 4; ++c)
         if (c < C) sum[r][c] = fmaf(acc[r], tile[c * plane + idx], sum[r][c]);
     }
+    __syncthreads();  // tile t+1 staged; everyone done with tile t's buffer
   }
   // reduce over the 32 lanes that hold the same pixel rows
 #pragma unroll
