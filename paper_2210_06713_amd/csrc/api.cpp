@@ -66,6 +66,10 @@ int tsim_render(const tsim_plan *pl, int frames, const float *img, const void *b
   if (pl->p.precision == TSIM_BF16)
     return launch_render_bf16(pl, frames, img, static_cast<const uint16_t *>(beta), out,
                               static_cast<hipStream_t>(stream));
+  // FP32 matrix cores for the instantiated shape (K = 100, T = 33), else the vector-ALU kernel
+  const int st = launch_render_f32_mfma(pl, frames, img, static_cast<const float *>(beta), out,
+                                        static_cast<hipStream_t>(stream));
+  if (st != TSIM_EUNSUPPORTED) return st;
   return launch_render_fp32(pl, frames, img, static_cast<const float *>(beta), out,
                             static_cast<hipStream_t>(stream));
 }

@@ -35,6 +35,8 @@ struct tsim_plan {
   float *d_basis_t = nullptr;  // [T*T][KP] float32 (tap-major, zero padded)
   float2 *d_tw_p = nullptr;    // twiddles exp(-2 pi i k / P), k < P
   uint16_t *d_basis_bf = nullptr;  // [roundup(T*T, 32)][KP] bfloat16, zero padded (tap-major)
+  float *d_basis_t128 = nullptr;   // [T*T][128] float32, zero padded (projection on matrix cores)
+  float *d_basis_k2 = nullptr;     // [roundup(T*T,32)][2][K2P] float32: psi[2s+g][tap] (FP32 matrix-core blur)
   uint16_t *d_mlp_w = nullptr;     // packed BF16 network weights (inference layout)
   float *d_mlp_f = nullptr;        // biases, input scales, output means (FP32)
   float mlp_s_out = 1.f;
@@ -77,6 +79,8 @@ int launch_render_fp32(const tsim_plan *pl, int frames, const float *img, const 
                        float *out, hipStream_t s);
 int launch_render_bf16(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta,
                        float *out, hipStream_t s);
+int launch_render_f32_mfma(const tsim_plan *pl, int frames, const float *img, const float *beta,
+                           float *out, hipStream_t s);
 int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
                 hipStream_t s);
 

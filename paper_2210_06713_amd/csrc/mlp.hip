@@ -52,7 +52,7 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
-enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_GELU_GRAD = 3 };
+enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_GELU_GRAD = 3, EPI_F32_ADD = 4 };
 
 constexpr int GT = 64, GK = 32, GKP = GK + 8;
 
@@ -68,7 +68,10 @@ k_gemm_bf16(const uint16_t *__restrict__ A, long sam, long sak, const uint16_t *
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   f32x16 acc = {};
-  for (int k0 = 0; k0 < Kd; k0 += GK) {
+  // split-K: block z reduces over k in [z * kchunk, (z + 1) * kchunk)
+  const int kchunk = ((Kd + int(gridDim.z) - 1) / int(gridDim.z) + GK - 1) / GK * GK;
+  const int kbeg = blockIdx.z * kchunk, kend = min(Kd, kbeg + kchunk);
+  for (int k0 = kbeg; k0 < kend; k0 += GK) {
     for (int e = threadIdx.x; e < GT * GK; e += 256) {
       int m, k;
       if (sak == 1) { m = e / GK; k = e % GK; } else { m = e % GT; k = e / GT; }
@@ -97,6 +100,8 @@ k_gemm_bf16(const uint16_t *__restrict__ A, long sam, long sak, const uint16_t *
     const float v = acc[r];
     if (EPI == EPI_F32) {
       outf[o] = v;
+    } else if (EPI == EPI_F32_ADD) {
+      atomicAdd(&outf[o], v);
     } else if (EPI == EPI_BIAS_F32) {
       outf[o] = v + bias[n];
     } else if (EPI == EPI_BIAS_GELU) {
@@ -363,8 +368,9 @@ k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip
 
 template <int EPI>
 int gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const uint16_t *B, long sbk, long sbn,
-         int M, int N, int Kd, const float *bias, float *Z, float *outf, uint16_t *outb, int ldc) {
-  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+         int M, int N, int Kd, const float *bias, float *Z, float *outf, uint16_t *outb, int ldc,
+         int splits = 1) {
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, splits);
   hipLaunchKernelGGL(k_gemm_bf16<EPI>, grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, M, N, Kd,
                      bias, Z, outf, outb, ldc);
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
@@ -429,9 +435,14 @@ int mlp_fwd_bwd(tsim_mlp *n, int Bsz, hipStream_t s) {
   for (int l = 3; l >= 0; --l) {
     const int dout = n->dout[l], din = n->din[l];
     const uint16_t *in = (l == 0) ? n->x : n->act[l - 1];
-    // dW = dZ^T X: M = dout, N = din, reduction over the batch
-    if ((st = gemm<EPI_F32>(s, n->dzb, 1, dout, in, din, 1, dout, din, Bsz, nullptr, nullptr,
-                            n->g + n->off_w[l], nullptr, din)) != TSIM_OK) return st;
+    // dW = dZ^T X: M = dout, N = din, reduction over the batch, split over
+    // the batch so that ~512 blocks run, partial sums added atomically
+    const int tiles = ((dout + GT - 1) / GT) * ((din + GT - 1) / GT);
+    const int splits = std::max(1, std::min(Bsz / 256, 512 / tiles));
+    if (hipMemsetAsync(n->g + n->off_w[l], 0, size_t(dout) * din * sizeof(float), s) != hipSuccess)
+      return TSIM_EDEVICE;
+    if ((st = gemm<EPI_F32_ADD>(s, n->dzb, 1, dout, in, din, 1, dout, din, Bsz, nullptr, nullptr,
+                                n->g + n->off_w[l], nullptr, din, splits)) != TSIM_OK) return st;
     hipLaunchKernelGGL(k_colsum, dim3((dout + 63) / 64), dim3(256), 0, s, n->dzf, Bsz, dout,
                        n->g + n->off_b[l]);
     if (l > 0) {

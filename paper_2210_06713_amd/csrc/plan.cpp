@@ -247,7 +247,7 @@ int validate(const tsim_params *p) {
 
 void free_plan(tsim_plan *pl) {
   if (!pl) return;
-  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zpupil, pl->d_zrow, pl->d_basis,
+  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zpupil, pl->d_zrow, pl->d_basis, pl->d_basis_t128, pl->d_basis_k2,
                   pl->d_basis_t, pl->d_tw_p, pl->d_basis_bf, pl->d_mlp_w, pl->d_mlp_f};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -442,6 +442,20 @@ int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
         bb[size_t(t) * KP + k] = uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
       }
     if ((st = upload(&pl->d_basis_bf, bb.data(), bb.size())) != TSIM_OK) goto fail;
+    std::vector<float> b128(size_t(T2) * 128, 0.0f);
+    for (int t = 0; t < T2; ++t)
+      for (int k = 0; k < K; ++k) b128[size_t(t) * 128 + k] = float(pl->basis[size_t(k) * T2 + t]);
+    if ((st = upload(&pl->d_basis_t128, b128.data(), b128.size())) != TSIM_OK) goto fail;
+    // lane-contiguous layout for the FP32 matrix-core blur: [tap][g][s] = psi[2s + g][tap]
+    const int K2 = (K + 1) / 2, K2P = (K2 + 3) / 4 * 4;
+    std::vector<float> bk2(size_t(TTP) * 2 * K2P, 0.0f);
+    for (int t = 0; t < T2; ++t)
+      for (int g = 0; g < 2; ++g)
+        for (int s2 = 0; s2 < K2; ++s2) {
+          const int k = 2 * s2 + g;
+          if (k < K) bk2[(size_t(t) * 2 + g) * K2P + s2] = float(pl->basis[size_t(k) * T2 + t]);
+        }
+    if ((st = upload(&pl->d_basis_k2, bk2.data(), bk2.size())) != TSIM_OK) goto fail;
   }
   *out = pl;
   return TSIM_OK;

@@ -12,8 +12,8 @@
 // frequency column, two FFT-32s along y; the 33rd column is a direct
 // 32-term DFT shared by the lanes.  |.|^2, unit-sum normalisation, write.
 //
-// k_project: beta[p][k] = sum_t h[p][t] psi[k][t], an FP32 GEMM tiled through
-// LDS (64 pixels x KP weights per block).
+// k_project_mfma: beta[p][k] = sum_t h[p][t] psi[k][t] on the FP32 matrix
+// cores, h and psi^T staged through LDS in 32-tap chunks.
 #include <algorithm>
 
 #include "common.cuh"
@@ -198,56 +198,58 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
   }
 }
 
-template <int KP>
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// beta[p][k] = sum_t h[p][t] psi[k][t] on the FP32 matrix cores
+// (v_mfma_f32_32x32x2f32).  Block: 128 pixels x 128 outputs, 4 waves, wave
+// w owns pixel tile w and all four 32-wide output tiles; 32-tap chunks of h
+// and psi^T are staged through LDS (h rows padded against bank conflicts).
+constexpr int PJ_PX = 128, PJ_TK = 32, PJ_N = 128;
+
 __global__ void __launch_bounds__(256)
-k_project(const float *__restrict__ h, const float *__restrict__ psi_t, float *__restrict__ beta,
-          int n, int T2, int K) {
-  __shared__ float As[32][64 + 4];
-  __shared__ float Bs[32][KP];
-  constexpr int NB = KP / 16;
-  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-  const int p0 = blockIdx.x * 64;
-  float acc[4][NB];
+k_project_mfma(const float *__restrict__ h, const float *__restrict__ psi_t128 /*[T2][128]*/,
+               float *__restrict__ beta, int n, int T2, int K) {
+  __shared__ float As[PJ_PX][PJ_TK + 1];
+  __shared__ __attribute__((aligned(16))) float Bs[PJ_TK][PJ_N];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p0 = blockIdx.x * PJ_PX;
+  f32x16 acc[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = 0.f;
-  for (int t0 = 0; t0 < T2; t0 += 32) {
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-      const int px = e >> 5, tt = e & 31;
+  for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
+  for (int t0 = 0; t0 < T2; t0 += PJ_TK) {
+    for (int e = threadIdx.x; e < PJ_PX * PJ_TK; e += 256) {
+      const int px = e / PJ_TK, tt = e % PJ_TK;
       const int gp = p0 + px, gt = t0 + tt;
-      As[tt][px] = (gp < n && gt < T2) ? h[size_t(gp) * T2 + gt] : 0.f;
+      As[px][tt] = (gp < n && gt < T2) ? h[size_t(gp) * T2 + gt] : 0.f;
     }
-    for (int e = threadIdx.x; e < 32 * KP; e += 256) {
-      const int tt = e / KP, kk = e - tt * KP;
+    for (int e = threadIdx.x; e < PJ_TK * PJ_N / 4; e += 256) {
+      const int tt = e / (PJ_N / 4), c4 = e % (PJ_N / 4);
       const int gt = t0 + tt;
-      Bs[tt][kk] = (gt < T2) ? psi_t[size_t(gt) * KP + kk] : 0.f;
+      float4 v = (gt < T2) ? *reinterpret_cast<const float4 *>(psi_t128 + size_t(gt) * PJ_N + 4 * c4)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4 *>(&Bs[tt][4 * c4]) = v;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int tt = 0; tt < 32; ++tt) {
-      float4 av = *reinterpret_cast<const float4 *>(&As[tt][tr * 4]);
-      float b[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) b[j] = Bs[tt][tc + 16 * j];
+    for (int s = 0; s < PJ_TK / 2; ++s) {
+      const float a = As[w * 32 + (lane & 31)][2 * s + (lane >> 5)];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        acc[0][j] = fmaf(av.x, b[j], acc[0][j]);
-        acc[1][j] = fmaf(av.y, b[j], acc[1][j]);
-        acc[2][j] = fmaf(av.z, b[j], acc[2][j]);
-        acc[3][j] = fmaf(av.w, b[j], acc[3][j]);
+      for (int t = 0; t < 4; ++t) {
+        const float b = Bs[2 * s + (lane >> 5)][t * 32 + (lane & 31)];
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gp = p0 + tr * 4 + i;
-    if (gp >= n) continue;
+  for (int t = 0; t < 4; ++t) {
+    const int k = t * 32 + (lane & 31);
+    if (k >= K) continue;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int k = tc + 16 * j;
-      if (k < K) beta[size_t(gp) * K + k] = acc[i][j];
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int gp = p0 + w * 32 + m;
+      if (gp < n) beta[size_t(gp) * K + k] = acc[t][r];
     }
   }
 }
@@ -279,14 +281,9 @@ size_t p2s_chunk(const tsim_plan *pl, size_t total) {
 
 int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s) {
   const int T2 = pl->T * pl->T;
-  dim3 grid((n + 63) / 64);
+  dim3 grid((n + PJ_PX - 1) / PJ_PX);
   TraceScope tr("k_project", s);
-  switch (pl->KP) {
-    case 32: hipLaunchKernelGGL(k_project<32>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
-    case 64: hipLaunchKernelGGL(k_project<64>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
-    case 112: hipLaunchKernelGGL(k_project<112>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
-    default: hipLaunchKernelGGL(k_project<128>, grid, dim3(256), 0, s, h, pl->d_basis_t, beta, n, T2, pl->K); break;
-  }
+  hipLaunchKernelGGL(k_project_mfma, grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K);
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
 
