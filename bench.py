@@ -162,6 +162,62 @@ def cpu_baseline():
                        f"{t_block:.2f} s, extrapolated to the frame ({t_frame:.1f} s/frame)")}
 
 
+BATCH_SIZES = ((24, 256, 256, 512, 512), (24, 512, 512, 1024, 1024), (16, 768, 1024, 2048, 2048))
+
+
+def batched_graph(tsim, basis, net, steps):
+    """Mixed-size batch (24 x 256^2, 24 x 512^2, 16 x 768x1024, 3 channels,
+    per-frame D/r0 ~ U[1, 4]) in the learned BF16 form, captured once into a
+    HIP graph and replayed: whole-batch Mpixel/s."""
+    import numpy as np
+    import torch
+    import synthetic
+    dev = torch.device("cuda:0")
+    kp = 32 if K <= 32 else 64 if K <= 64 else 112 if K <= 112 else 128
+    work = []
+    for i, (F, Hb, Wb, Gh, Gw) in enumerate(BATCH_SIZES):
+        pl = tsim.Plan(Hb, Wb, C, Gh, Gw, pixel_pitch_over_d=PITCH, psf_t=T, pupil_n=P, basis=basis,
+                       p2s_mode=tsim.P2S_LEARNED, precision=tsim.BF16)
+        tsim.plan_set_mlp(pl, net)
+        img = torch.tensor(np.repeat(synthetic.test_image(C, Hb, Wb, 16, i)[None], F, 0), device=dev)
+        work.append(dict(pl=pl, F=F, img=img, dr=list(synthetic.d_over_r0_uniform(F, 1.0, 4.0, i)),
+                         zern=torch.empty((F, 35, Hb, Wb), device=dev),
+                         beta=torch.empty((F, Hb, Wb, kp), dtype=torch.bfloat16, device=dev),
+                         blur=torch.empty((F, C, Hb, Wb), device=dev),
+                         out=torch.empty((F, C, Hb, Wb), device=dev), ws=pl.workspace(F)))
+
+    def run_all():
+        for w in work:
+            w["pl"].sample_zernike(w["dr"], 3, 0, w["zern"], w["ws"])
+            w["pl"].p2s(w["zern"], w["beta"], w["ws"])
+            w["pl"].render(w["img"], w["beta"], w["blur"])
+            w["pl"].warp(w["blur"], w["zern"], w["out"])
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run_all()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run_all()
+    g.replay()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        g.replay()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    px = sum(F * Hb * Wb for (F, Hb, Wb, _, _) in BATCH_SIZES)
+    return {"workload": "64 frames: 24x256^2 (G=512), 24x512^2 (G=1024), 16x768x1024 (G=2048), "
+                        "3 channels, D/r0 ~ U[1,4], learned BF16 form, one HIP graph",
+            "value": round(px / (ms * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_batch": round(ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,7 +225,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-steps", type=int, default=12000)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); frames shard "
@@ -276,6 +333,9 @@ def main():
                              "loss_first": float(losses[:10].mean()),
                              "loss_last": float(losses[-10:].mean())},
                    "setup_s": round(setup_l, 2), "roofline": roof_l, "kernels": kern_l}
+
+        if not args.no_batched:
+            learned["batched_graph"] = batched_graph(tsim, basis, net, args.steps)
 
     line = {"metric": METRIC, "value": round(value, 3), "unit": "Mpixel/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
