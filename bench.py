@@ -39,42 +39,57 @@ PITCH = 0.125
 DR_CYCLE = (1.0, 2.0, 4.0)
 N_BASIS_PSF = 20000
 
+# the two single-frame-size workloads; `chunk` frames go through each call
+S512 = dict(H=H, W=W, C=C, G=G, T=T, P=P, K=K, frames=FRAMES, chunk=FRAMES, drs=DR_CYCLE,
+            square=16)
+S4K = dict(H=2160, W=3840, C=3, G=4096, T=65, P=128, K=100, frames=30, chunk=6, drs=(3.0,),
+           square=64)
 
-def kernel_work(name, frames):
-    """Algorithmic work of one launch-set of `name` for `frames` frames:
-    (bound, amount, unit).  Bytes are compulsory HBM traffic; flops count the
-    arithmetic of the algorithm as specified (not instructions issued)."""
-    px = frames * H * W
+
+def n_aperture(P):
+    """Pupil samples strictly inside the aperture (diameter P/2 samples)."""
+    r = P // 4
+    return sum(1 for y in range(-r, r) for x in range(-r, r) if x * x + y * y < r * r)
+
+
+def kernel_work(name, frames, s):
+    """Algorithmic work of one launch-set of `name` for `frames` frames of
+    shape `s`: (bound, amount, unit).  Bytes are compulsory HBM traffic;
+    flops count the arithmetic of the algorithm as specified (not
+    instructions issued)."""
+    h, w, c, g, t, k = s["H"], s["W"], s["C"], s["G"], s["T"], s["K"]
+    px = frames * h * w
     if name == "k_sampler_cols":
         # write the row-cropped column-IFFT intermediate, 18 complex fields
-        return "hbm", frames * 18 * H * G * 8, "B"
+        return "hbm", frames * 18 * h * g * 8, "B"
     if name == "k_sampler_rows_mix":
         # read the intermediate, write 35 coefficient planes
-        return "hbm", frames * (18 * H * G * 8 + 35 * H * W * 4), "B"
-    if name == "k_psf64":
-        n_ap = 797  # pupil samples strictly inside the aperture (P = 64)
-        phase = 2 * 33 * n_ap
-        fft32 = 80 * 10 + 32 * 6          # radix-2 butterflies + pre-twiddle
-        dft = 31 * 2 * fft32 + 33 * 2 * fft32 + 2 * 32 * 8
-        return "alu", px * (phase + dft + 3 * T * T), "flop"
+        return "hbm", frames * (18 * h * g * 8 + 35 * h * w * 4), "B"
+    if name in ("k_psf64", "k_psf128"):
+        n = 32 if name == "k_psf64" else 64      # register FFT length
+        rows = n - 1                              # window rows inside the aperture
+        fft = (n // 2) * int(math.log2(n)) * 10 + n * 6   # butterflies + pre-twiddle
+        phase = 2 * 33 * n_aperture(2 * n)
+        dft = rows * 2 * fft + n * 2 * fft + (n + 1) * n * 8   # + the direct edge column
+        return "alu", px * (phase + dft + 3 * t * t), "flop"
     if name == "k_project":
-        return "alu", px * 2 * T * T * K, "flop"
+        return "alu", px * 2 * t * t * k, "flop"
     if name == "k_render_fp32":
-        return "alu", px * (2 * K * T * T + 2 * C * T * T), "flop"
+        return "alu", px * (2 * k * t * t + 2 * c * t * t), "flop"
     if name == "k_warp":
-        return "hbm", px * (8 + 4 * C + 4 * C), "B"
+        return "hbm", px * (8 + 4 * c + 4 * c), "B"
     if name == "k_mlp_infer":
-        return "mfma", px * 2 * (35 * 256 + 2 * 256 * 256 + 256 * K), "flop"
+        return "mfma", px * 2 * (35 * 256 + 2 * 256 * 256 + 256 * k), "flop"
     if name == "k_render_bf16":
-        return "mfma", px * (2 * K * T * T + 2 * C * T * T), "flop"
+        return "mfma", px * (2 * k * t * t + 2 * c * t * t), "flop"
     return None
 
 
-def summarize(rep, steps, frames, traffic=True):
+def summarize(rep, steps, frames, s, traffic=True):
     """Per-kernel roofline entries from the tracer's {name: (launches, ms)}."""
     kernels = {}
     for name, (n, tot) in rep.items():
-        w = kernel_work(name, frames)
+        w = kernel_work(name, frames, s)
         per_step = n / steps
         avg_ms = tot / n
         ent = {"launches_per_step": per_step, "avg_ms": round(avg_ms, 4),
@@ -102,8 +117,9 @@ def summarize(rep, steps, frames, traffic=True):
 
 def source_hash(kernel):
     files = {"k_sampler_cols": "sampler.hip", "k_sampler_rows_mix": "sampler.hip",
-             "k_psf64": "psf.hip", "k_project": "psf.hip", "k_render_fp32": "render.hip",
-             "k_warp": "render.hip"}
+             "k_psf64": "psf.hip", "k_psf128": "psf.hip", "k_project": "psf.hip",
+             "k_render_fp32": "render_bf16.hip", "k_render_bf16": "render_bf16.hip",
+             "k_mlp_infer": "mlp.hip", "k_warp": "render.hip"}
     f = files.get(kernel)
     if f is None:
         return None
@@ -218,52 +234,40 @@ def batched_graph(tsim, basis, net, steps):
             "value": round(px / (ms * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_batch": round(ms, 3)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=12000)
-    ap.add_argument("--no-batched", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); frames shard "
-              "independently across GPUs, so the per-GPU figure is the one reported",
-              file=sys.stderr)
-        sys.exit(2)
+class Workload:
+    """Frames of one shape: a repeated synthetic scene, per-frame D/r0, and
+    `chunk`-frame buffers that each call works on."""
 
-    import numpy as np
-    import torch
-    import paper_2210_06713_amd as tsim
-    import synthetic
+    def __init__(self, torch, synthetic, s, dev):
+        import numpy as np
+        self.torch, self.s, self.dev = torch, s, dev
+        n = s["chunk"]
+        self.img = torch.tensor(np.repeat(synthetic.test_image(s["C"], s["H"], s["W"], s["square"], 0)[None],
+                                          n, 0), device=dev)
+        self.zern = torch.empty((n, 35, s["H"], s["W"]), dtype=torch.float32, device=dev)
+        self.blur = torch.empty((n, s["C"], s["H"], s["W"]), dtype=torch.float32, device=dev)
+        self.out = torch.empty_like(self.blur)
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    t_setup = time.perf_counter()
-    probe = tsim.Plan(H, W, C, G, G, pixel_pitch_over_d=PITCH, psf_t=T, pupil_n=P, basis_k=K)
-    basis, eig = probe.basis_build(N_BASIS_PSF, seed=0, dr_lo=0.5, dr_hi=5.0)
-    probe.close()
-    plan = tsim.Plan(H, W, C, G, G, pixel_pitch_over_d=PITCH, psf_t=T, pupil_n=P, basis=basis)
-    setup_s = time.perf_counter() - t_setup
+    def run(self, tsim, pl, beta, steps, warmup, frames):
+        """Time `steps` whole-path steps of `frames` frames after `warmup`;
+        returns (ms/step, tracer report, output of the first chunk of step 0)."""
+        torch, s = self.torch, self.s
+        n = s["chunk"]
+        ws = pl.workspace(n)
+        drs = s["drs"]
 
-    img = torch.tensor(np.repeat(synthetic.test_image(C, H, W, 16, 0)[None], FRAMES, 0), device=dev)
-    zern = torch.empty((FRAMES, 35, H, W), dtype=torch.float32, device=dev)
-    drs = [DR_CYCLE[i % 3] for i in range(FRAMES)]
-
-    def run(pl, beta, steps, warmup):
-        """Time `steps` whole-path steps after `warmup`; returns (ms/step,
-        tracer report, output of the last step)."""
-        blur = torch.empty((FRAMES, C, H, W), dtype=torch.float32, device=dev)
-        out = torch.empty_like(blur)
-        ws = pl.workspace(FRAMES)
+        def chunk(i, c0):
+            m = min(n, frames - c0)
+            f0 = i * frames + c0
+            z, b, bl, o = self.zern[:m], beta[:m], self.blur[:m], self.out[:m]
+            pl.sample_zernike([drs[(c0 + f) % len(drs)] for f in range(m)], 0, f0, z, ws)
+            pl.p2s(z, b, ws)
+            pl.render(self.img[:m], b, bl)
+            pl.warp(bl, z, o)
 
         def step(i):
-            pl.sample_zernike(drs, 0, i * FRAMES, zern, ws)
-            pl.p2s(zern, beta, ws)
-            pl.render(img, beta, blur)
-            pl.warp(blur, zern, out)
+            for c0 in range(0, frames, n):
+                chunk(i, c0)
 
         for i in range(warmup):
             step(i)
@@ -280,62 +284,171 @@ def main():
         ms = start.elapsed_time(stop) / steps
         rep = tsim.trace_report()
         tsim.trace_enable(False)
-        if not torch.isfinite(out).all():
+        if not torch.isfinite(self.out).all():
             raise RuntimeError("non-finite output")
-        # the last step rendered frames (warmup + steps - 1) * FRAMES ...; rerun step 0 for a
-        # fixed comparison frame set
-        step(0)
+        chunk(0, 0)              # fixed frames (the first chunk of step 0) for comparing forms
         torch.cuda.synchronize()
-        return ms, rep, out.clone()
+        return ms, rep, self.out[:min(n, frames)].clone()
+
+
+def train_network(tsim, torch, np, plan_l, train_steps):
+    """The learned form's network: 2M exact (Zernike, weight) pairs from the
+    plan's own PSF path, MSE training on the GPU, held-out PSF error."""
+    t0 = time.perf_counter()
+    z_tr, b_tr = tsim.make_training_data(plan_l, N_TRAIN, seed=1)
+    net = tsim.Mlp(plan_l, batch=TRAIN_BATCH, seed=0)
+    net.fit_output(b_tr)
+    t1 = time.perf_counter()
+    losses = net.train(z_tr, b_tr, train_steps, lr_max=1e-3, lr_min=1e-5)
+    train_s = time.perf_counter() - t1
+    tsim.plan_set_mlp(plan_l, net)
+    del z_tr, b_tr
+    z_te, b_te = tsim.make_training_data(plan_l, N_HELDOUT, seed=2)
+    pred = tsim.mlp_predict(plan_l, z_te)
+    torch.cuda.synchronize()
+    err = (torch.linalg.vector_norm(pred - b_te, dim=1)
+           / torch.linalg.vector_norm(b_te, dim=1)).cpu().numpy()
+    info = {"psf_rel_err_mean": round(float(err.mean()), 5),
+            "psf_rel_err_median": round(float(np.median(err)), 5),
+            "psf_rel_err_p95": round(float(np.percentile(err, 95)), 5),
+            "psf_err_definition": "||beta_net - beta_exact|| / ||beta_exact|| on 1e5 held-out "
+                                  "pairs (= relative L2 error of the projected PSF)",
+            "train": {"pairs": N_TRAIN, "batch": TRAIN_BATCH, "steps": train_steps,
+                      "seconds": round(train_s, 2),
+                      "loss_first": float(losses[:10].mean()),
+                      "loss_last": float(losses[-10:].mean())},
+            "setup_s": round(time.perf_counter() - t0, 2)}
+    return net, info
+
+
+def kpad(k):
+    return 32 if k <= 32 else 64 if k <= 64 else 112 if k <= 112 else 128
+
+
+def psnr(a, b):
+    mse = float(((a - b) ** 2).mean())
+    return round(10 * math.log10(1.0 / mse), 2) if mse > 0 else None
+
+
+def large_frame(tsim, torch, np, synthetic, dev, args):
+    """3840 x 2160 x 3 frames, D/r0 = 3, 4096^2 grid, 128 x 128 pupil, K = 100
+    basis of 65 x 65 kernels: a 30-frame sequence of independent draws per
+    step in the learned BF16 form; the plain FP32 form on 6 frames per step
+    (its exact PSFs cost about a second per frame)."""
+    s = S4K
+    t0 = time.perf_counter()
+    probe = tsim.Plan(s["H"], s["W"], s["C"], s["G"], s["G"], pixel_pitch_over_d=PITCH, psf_t=s["T"],
+                      pupil_n=s["P"], basis_k=s["K"])
+    basis, _ = probe.basis_build(N_BASIS_PSF, seed=0, dr_lo=0.5, dr_hi=5.0)
+    probe.close()
+    basis_s = time.perf_counter() - t0
+    wl = Workload(torch, synthetic, s, dev)
+    n = s["chunk"]
+    plan = tsim.Plan(s["H"], s["W"], s["C"], s["G"], s["G"], pixel_pitch_over_d=PITCH, psf_t=s["T"],
+                     pupil_n=s["P"], basis=basis)
+    beta32 = torch.empty((n, s["H"], s["W"], s["K"]), dtype=torch.float32, device=dev)
+    f_plain = n
+    st_plain = max(1, min(args.steps, 2))
+    ms_p, rep_p, out_p = wl.run(tsim, plan, beta32, st_plain, 1, f_plain)
+    kern_p, roof_p = summarize(rep_p, st_plain, f_plain, s, traffic=False)
+    del beta32
+    plan.close()
+    px = s["H"] * s["W"]
+    plain = {"value": round(f_plain * px / (ms_p * 1e-3) / 1e6, 3), "unit": "Mpixel/s",
+             "ms_per_step": round(ms_p, 3), "frames_per_step": f_plain, "steps": st_plain,
+             "warmup": 1, "dtype": "f32", "roofline": roof_p, "kernels": kern_p}
+    out = {"workload": "3840x2160x3 float32, D/r0 = 3, Noll 2..36 on a 4096x4096 grid, "
+                       "128x128-pupil PSFs, K=100 65x65 PCA basis, blur + bilinear tilt warp",
+           "basis_build_s": round(basis_s, 2), "plain_fp32": plain}
+    if not args.no_learned:
+        plan_l = tsim.Plan(s["H"], s["W"], s["C"], s["G"], s["G"], pixel_pitch_over_d=PITCH,
+                           psf_t=s["T"], pupil_n=s["P"], basis=basis, p2s_mode=tsim.P2S_LEARNED,
+                           precision=tsim.BF16)
+        net, info = train_network(tsim, torch, np, plan_l, args.train_steps)
+        beta16 = torch.empty((n, s["H"], s["W"], kpad(s["K"])), dtype=torch.bfloat16, device=dev)
+        ms_l, rep_l, out_l = wl.run(tsim, plan_l, beta16, args.steps, args.warmup, s["frames"])
+        kern_l, roof_l = summarize(rep_l, args.steps, s["frames"], s, traffic=False)
+        learned = {"value": round(s["frames"] * px / (ms_l * 1e-3) / 1e6, 3), "unit": "Mpixel/s",
+                   "ms_per_step": round(ms_l, 3), "frames_per_step": s["frames"],
+                   "steps": args.steps, "warmup": args.warmup,
+                   "dtype": "bf16 MFMA, fp32 accumulate",
+                   "speedup_vs_plain_fp32": round((ms_p / f_plain) / (ms_l / s["frames"]), 2),
+                   "image_psnr_db_vs_plain_fp32": psnr(out_l, out_p)}
+        learned.update(info)
+        learned.update(roofline=roof_l, kernels=kern_l)
+        out["learned_bf16"] = learned
+        del beta16, net
+        plan_l.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=12000)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-4k", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); frames shard "
+              "independently across GPUs, so the per-GPU figure is the one reported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2210_06713_amd as tsim
+    import synthetic
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = S512
+    t_setup = time.perf_counter()
+    probe = tsim.Plan(H, W, C, G, G, pixel_pitch_over_d=PITCH, psf_t=T, pupil_n=P, basis_k=K)
+    basis, eig = probe.basis_build(N_BASIS_PSF, seed=0, dr_lo=0.5, dr_hi=5.0)
+    probe.close()
+    plan = tsim.Plan(H, W, C, G, G, pixel_pitch_over_d=PITCH, psf_t=T, pupil_n=P, basis=basis)
+    setup_s = time.perf_counter() - t_setup
+    wl = Workload(torch, synthetic, s, dev)
 
     # ---- plain FP32 form (exact P2S) ----
     beta32 = torch.empty((FRAMES, H, W, K), dtype=torch.float32, device=dev)
-    ms, rep, out_plain = run(plan, beta32, args.steps, args.warmup)
-    kernels, roofline = summarize(rep, args.steps, FRAMES)
+    ms, rep, out_plain = wl.run(tsim, plan, beta32, args.steps, args.warmup, FRAMES)
+    kernels, roofline = summarize(rep, args.steps, FRAMES, s)
     value = FRAMES * H * W / (ms * 1e-3) / 1e6
+    del beta32
 
     # ---- BF16 + learned form ----
     learned = None
     if not args.no_learned:
-        t0 = time.perf_counter()
         plan_l = tsim.Plan(H, W, C, G, G, pixel_pitch_over_d=PITCH, psf_t=T, pupil_n=P, basis=basis,
                            p2s_mode=tsim.P2S_LEARNED, precision=tsim.BF16)
-        z_tr, b_tr = tsim.make_training_data(plan_l, N_TRAIN, seed=1)
-        net = tsim.Mlp(plan_l, batch=TRAIN_BATCH, seed=0)
-        net.fit_output(b_tr)
-        t1 = time.perf_counter()
-        losses = net.train(z_tr, b_tr, args.train_steps, lr_max=1e-3, lr_min=1e-5)
-        train_s = time.perf_counter() - t1
-        tsim.plan_set_mlp(plan_l, net)
-        del z_tr, b_tr
-        z_te, b_te = tsim.make_training_data(plan_l, N_HELDOUT, seed=2)
-        pred = tsim.mlp_predict(plan_l, z_te)
-        torch.cuda.synchronize()
-        err = (torch.linalg.vector_norm(pred - b_te, dim=1)
-               / torch.linalg.vector_norm(b_te, dim=1)).cpu().numpy()
-        setup_l = time.perf_counter() - t0
-        kp = 32 if K <= 32 else 64 if K <= 64 else 112 if K <= 112 else 128
-        beta16 = torch.empty((FRAMES, H, W, kp), dtype=torch.bfloat16, device=dev)
-        ms_l, rep_l, out_l = run(plan_l, beta16, args.steps, args.warmup)
-        kern_l, roof_l = summarize(rep_l, args.steps, FRAMES, traffic=False)
-        mse = float(torch.mean((out_l - out_plain) ** 2))
+        net, info = train_network(tsim, torch, np, plan_l, args.train_steps)
+        beta16 = torch.empty((FRAMES, H, W, kpad(K)), dtype=torch.bfloat16, device=dev)
+        ms_l, rep_l, out_l = wl.run(tsim, plan_l, beta16, args.steps, args.warmup, FRAMES)
+        kern_l, roof_l = summarize(rep_l, args.steps, FRAMES, s, traffic=False)
         learned = {"value": round(FRAMES * H * W / (ms_l * 1e-3) / 1e6, 3), "unit": "Mpixel/s",
                    "ms_per_step": round(ms_l, 3), "dtype": "bf16 MFMA, fp32 accumulate",
                    "speedup_vs_plain_fp32": round(ms / ms_l, 2),
-                   "psf_rel_err_mean": round(float(err.mean()), 5),
-                   "psf_rel_err_median": round(float(np.median(err)), 5),
-                   "psf_rel_err_p95": round(float(np.percentile(err, 95)), 5),
-                   "psf_err_definition": "||beta_net - beta_exact|| / ||beta_exact|| on 1e5 held-out "
-                                         "pairs (= relative L2 error of the projected PSF)",
-                   "image_psnr_db_vs_plain_fp32": round(10 * math.log10(1.0 / mse), 2) if mse > 0 else None,
-                   "train": {"pairs": N_TRAIN, "batch": TRAIN_BATCH, "steps": args.train_steps,
-                             "seconds": round(train_s, 2),
-                             "loss_first": float(losses[:10].mean()),
-                             "loss_last": float(losses[-10:].mean())},
-                   "setup_s": round(setup_l, 2), "roofline": roof_l, "kernels": kern_l}
-
+                   "image_psnr_db_vs_plain_fp32": psnr(out_l, out_plain)}
+        learned.update(info)
+        learned.update(roofline=roof_l, kernels=kern_l)
+        del beta16
         if not args.no_batched:
             learned["batched_graph"] = batched_graph(tsim, basis, net, args.steps)
+        del net
+        plan_l.close()
+    plan.close()
+    del wl
+    torch.cuda.empty_cache()
+
+    large = None
+    if not args.no_4k:
+        large = large_frame(tsim, torch, np, synthetic, dev, args)
 
     line = {"metric": METRIC, "value": round(value, 3), "unit": "Mpixel/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -347,7 +460,7 @@ def main():
                        "frames_per_step": FRAMES, "H": H, "W": W, "C": C, "grid": G, "K": K,
                        "T": T, "pupil": P},
             "roofline": roofline, "kernels": kernels, "learned_bf16": learned,
-            "setup_s": round(setup_s, 2)}
+            "large_4k": large, "setup_s": round(setup_s, 2)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -213,7 +213,9 @@ int tsim_mlp_set(tsim_mlp *net, int what, const float *host, size_t count);
  * L g (Philox counters (i, w, 0, 2), D/r0 uniform in [dr_lo, dr_hi] from word
  * 0 of (i, 9, 0, 2)) and their exact projected weights (Eq. (2) + Eq. (7)).
  *   zvec : device [n_pairs][35] f32;  beta : device [n_pairs][K] f32
- *   ws   : device, min(n_pairs, 2^20) * T*T floats */
+ *   ws   : device, tsim_mlp_data_ws_bytes(plan, n_pairs) bytes (PSFs of one
+ *          chunk: at most 2^20 pairs and about 5 GB) */
+int tsim_mlp_data_ws_bytes(const tsim_plan *plan, int n_pairs, size_t *bytes);
 int tsim_mlp_make_data(const tsim_plan *plan, int n_pairs, uint64_t seed, float dr_lo, float dr_hi,
                        float *zvec, float *beta, void *ws, tsim_stream stream);
 

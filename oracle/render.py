@@ -76,6 +76,43 @@ def warp(img, tx, ty):
             + fy * ((1 - fx) * img[y1c, x0c] + fx * img[y1c, x1c]))
 
 
+def render_at(img, beta_px, Psi, T, ys, xs):
+    """Eq. (8) at the listed pixels only, for frames too large to blur whole:
+    I(x) = sum_m beta_{x,m} sum_u varphi_m(u) I_g(clamp(x - u)).
+    img (H, W); beta_px (n, K) holds the weights of pixel (ys[i], xs[i])."""
+    H, W = img.shape
+    r = (T - 1) // 2
+    u = np.arange(-r, r + 1)
+    out = np.empty(len(ys))
+    for i, (y, x) in enumerate(zip(ys, xs)):
+        yy = np.clip(y - u, 0, H - 1)[:, None]
+        xx = np.clip(x - u, 0, W - 1)[None, :]
+        patch = img[yy, xx].reshape(-1)          # I(x - u), u row-major like varphi_m
+        conv = Psi @ patch                        # (varphi_m conv I)(x) for every m
+        out[i] = float(np.dot(beta_px[i], conv))
+    return out
+
+
+def warp_at(img, tx_px, ty_px, ys, xs):
+    """The bilinear backward warp at the listed pixels; tx_px, ty_px are the
+    displacements of those pixels."""
+    H, W = img.shape
+    px = np.asarray(xs, np.float64) - tx_px
+    py = np.asarray(ys, np.float64) - ty_px
+    x0 = np.floor(px)
+    y0 = np.floor(py)
+    fx = px - x0
+    fy = py - y0
+    x0 = x0.astype(np.int64)
+    y0 = y0.astype(np.int64)
+    x0c = np.clip(x0, 0, W - 1)
+    x1c = np.clip(x0 + 1, 0, W - 1)
+    y0c = np.clip(y0, 0, H - 1)
+    y1c = np.clip(y0 + 1, 0, H - 1)
+    return ((1 - fy) * ((1 - fx) * img[y0c, x0c] + fx * img[y0c, x1c])
+            + fy * ((1 - fx) * img[y1c, x0c] + fx * img[y1c, x1c]))
+
+
 def render_frame(img, zern, beta, Psi, T):
     """Blur then warp for a multi-channel frame: img (C, H, W)."""
     tx, ty = tilt_shift(zern)

@@ -78,6 +78,7 @@ _lib_mlp_layout = _sig("tsim_mlp_layout", _i, [_vp, ctypes.POINTER(ctypes.c_size
 _lib_mlp_get = _sig("tsim_mlp_get", _i, [_vp, _i, _fp, ctypes.c_size_t])
 _lib_mlp_set = _sig("tsim_mlp_set", _i, [_vp, _i, _fp, ctypes.c_size_t])
 _lib_mlp_data = _sig("tsim_mlp_make_data", _i, [_vp, _i, _u64, _f, _f, _vp, _vp, _vp, _vp])
+_lib_mlp_data_ws = _sig("tsim_mlp_data_ws_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_size_t)])
 _lib_mlp_grad = _sig("tsim_mlp_grad", _i, [_vp, _i, _vp, _vp, _fp, _vp])
 _lib_mlp_train = _sig("tsim_mlp_train", _i, [_vp, _vp, _vp, _i, _i, _f, _f, _fp, _vp])
 _lib_set_mlp = _sig("tsim_plan_set_mlp", _i, [_vp, _vp])
@@ -91,7 +92,7 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_status_string", "tsim_host_tables", "tsim_basis_build", "tsim_trace_enable",
             "tsim_trace_count", "tsim_trace_get", "tsim_mlp_create", "tsim_mlp_destroy",
             "tsim_mlp_param_count", "tsim_mlp_layout", "tsim_mlp_get", "tsim_mlp_set",
-            "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp",
+            "tsim_mlp_data_ws_bytes", "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp",
             "tsim_mlp_fit_output", "tsim_mlp_predict"]
 
 
@@ -347,8 +348,9 @@ def make_training_data(plan, n_pairs, seed=0, dr_lo=0.5, dr_hi=5.0, stream=None)
     """(zvec [n][35], beta [n][K]) device tensors from the exact path."""
     z = torch.empty((n_pairs, N_MODES), dtype=torch.float32, device="cuda")
     b = torch.empty((n_pairs, plan.K), dtype=torch.float32, device="cuda")
-    ws = torch.empty(max(min(n_pairs, 1 << 20) * plan.T * plan.T * 4, 256), dtype=torch.uint8,
-                     device="cuda")
+    nb = ctypes.c_size_t(0)
+    _check(_lib_mlp_data_ws(plan._h, int(n_pairs), ctypes.byref(nb)), "tsim_mlp_data_ws_bytes")
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
     _check(_lib_mlp_data(plan._h, int(n_pairs), int(seed), float(dr_lo), float(dr_hi), _ptr(z),
                          _ptr(b), _ptr(ws), _stream(stream)), "tsim_mlp_make_data")
     return z, b

@@ -66,12 +66,12 @@ __device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int 
   while (h < n) {
     if (2 * h < n) {
       // stages of span h and 2h on quadruples (i, i+h, i+2h, i+3h)
-      const int groups = ncol * (n >> 2);
+      const int groups = ncol << (log2n - 2);
       const int tstep1 = n / (2 * h);   // omega_{2h}^j = tw[j * n/(2h)]
       const int tstep2 = n / (4 * h);   // omega_{4h}^j = tw[j * n/(4h)]
       for (int g = tid; g < groups; g += nthr) {
-        int line = g / (n >> 2);
-        int gg = g - line * (n >> 2);
+        int line = g >> (log2n - 2);
+        int gg = g & ((n >> 2) - 1);
         int j = gg & (h - 1);
         int i = ((gg >> lh) << (lh + 2)) + j;
         float2 *b = buf + line * stride;
@@ -95,11 +95,11 @@ __device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int 
       h <<= 2;
       lh += 2;
     } else {
-      const int groups = ncol * (n >> 1);
+      const int groups = ncol << (log2n - 1);
       const int tstep1 = n / (2 * h);
       for (int g = tid; g < groups; g += nthr) {
-        int line = g / (n >> 1);
-        int gg = g - line * (n >> 1);
+        int line = g >> (log2n - 1);
+        int gg = g & ((n >> 1) - 1);
         int j = gg & (h - 1);
         int i = ((gg >> lh) << (lh + 1)) + j;
         float2 *b = buf + line * stride;

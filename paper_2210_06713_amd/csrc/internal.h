@@ -67,6 +67,7 @@ int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, 
 int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *beta, void *ws,
                      hipStream_t s);
 size_t p2s_ws_bytes(const tsim_plan *pl, int frames);
+size_t p2s_chunk_pixels(const tsim_plan *pl, size_t total);
 int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s);
 
 // ---- launchers (mlp.hip) ----

@@ -594,6 +594,12 @@ int tsim_mlp_set(tsim_mlp *n, int what, const float *host, size_t count) {
   }
 }
 
+int tsim_mlp_data_ws_bytes(const tsim_plan *pl, int n_pairs, size_t *bytes) {
+  if (!pl || n_pairs < 1 || !bytes) return TSIM_EINVAL;
+  *bytes = p2s_chunk_pixels(pl, size_t(n_pairs)) * size_t(pl->T) * pl->T * sizeof(float);
+  return TSIM_OK;
+}
+
 int tsim_mlp_make_data(const tsim_plan *pl, int n_pairs, uint64_t seed, float dr_lo, float dr_hi,
                        float *zvec, float *beta, void *ws, tsim_stream stream) {
   if (!pl || n_pairs < 1 || !zvec || !beta || !ws) return TSIM_EINVAL;
@@ -603,7 +609,7 @@ int tsim_mlp_make_data(const tsim_plan *pl, int n_pairs, uint64_t seed, float dr
   hipLaunchKernelGGL(k_draws, dim3((n_pairs + 255) / 256), dim3(256), 0, s, pl->d_L, zvec, n_pairs,
                      uint32_t(seed), uint32_t(seed >> 32), dr_lo, dr_hi, 2u);
   if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
-  const size_t chunk = size_t(1) << 20;
+  const size_t chunk = p2s_chunk_pixels(pl, size_t(n_pairs));
   for (size_t p0 = 0; p0 < size_t(n_pairs); p0 += chunk) {
     const int cnt = int(std::min(chunk, size_t(n_pairs) - p0));
     int st = launch_psf_exact(pl, cnt, zvec + p0 * TSIM_N_MODES, static_cast<float *>(ws), s);

@@ -12,6 +12,9 @@
 // frequency column, two FFT-32s along y; the 33rd column is a direct
 // 32-term DFT shared by the lanes.  |.|^2, unit-sum normalisation, write.
 //
+// k_psf128 (pupil P = 128, crop T <= 65): the same pruned DFT with one
+// wavefront per pixel and register FFT-64s; see the kernel.
+//
 // k_project_mfma: beta[p][k] = sum_t h[p][t] psi[k][t] on the FP32 matrix
 // cores, h and psi^T staged through LDS in 32-tap chunks.
 #include <algorithm>
@@ -19,6 +22,8 @@
 #include "common.cuh"
 #include "internal.h"
 #include "cheb32.h"
+#include "cheb64.h"
+#include "twiddle128.h"
 #include "twiddle64.h"
 
 namespace {
@@ -27,18 +32,25 @@ using tsim::cmul;
 
 constexpr int kZPad = 36;  // modes 4..36 padded to 36 floats per pupil sample
 
-constexpr int brev5(int v) {
-  return ((v & 1) << 4) | ((v & 2) << 2) | (v & 4) | ((v & 8) >> 2) | ((v & 16) >> 4);
+template <int LOG>
+constexpr int brev(int v) {
+  int r = 0;
+  for (int b = 0; b < LOG; ++b) r |= ((v >> b) & 1) << (LOG - 1 - b);
+  return r;
 }
 
 __device__ __forceinline__ float2 f2add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 f2sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// Forward 32-point DFT in registers, natural order in and out.
-__device__ __forceinline__ void fft32_fwd(float2 (&x)[32]) {
+// Forward N-point DFT in registers (N = 32 or 64), natural order in and out:
+// radix-2 decimation in time; the stage twiddle exp(-2 pi i j / (2 hs)) is
+// W64[j * 32 / hs], with the factor -i applied as a swap.
+template <int N>
+__device__ __forceinline__ void fft_fwd(float2 (&x)[N]) {
+  constexpr int LOG = N == 32 ? 5 : 6;
 #pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    const int j = brev5(i);
+  for (int i = 0; i < N; ++i) {
+    const int j = brev<LOG>(i);
     if (j > i) {
       float2 t = x[i];
       x[i] = x[j];
@@ -46,17 +58,19 @@ __device__ __forceinline__ void fft32_fwd(float2 (&x)[32]) {
     }
   }
 #pragma unroll
-  for (int hs = 1; hs < 32; hs <<= 1) {
+  for (int hs = 1; hs < N; hs <<= 1) {
 #pragma unroll
-    for (int g = 0; g < 32; g += 2 * hs) {
+    for (int g = 0; g < N; g += 2 * hs) {
 #pragma unroll
       for (int j = 0; j < hs; ++j) {
         float2 a = x[g + j], b = x[g + j + hs];
+        const int k = j * (32 / hs);
         float2 t;
-        if (j == 0) {
+        if (k == 0) {
           t = b;
+        } else if (k == 16) {
+          t = make_float2(b.y, -b.x);
         } else {
-          const int k = j * (32 / hs);  // omega_{2hs}^j = exp(-2 pi i j/(2 hs)) = W64[j * 32/hs]
           t = cmul(make_float2(kW64re[k], kW64im[k]), b);
         }
         x[g + j] = f2add(a, t);
@@ -127,8 +141,8 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
       const int k = (cp + 64) & 63;  // exp(-2 pi i c'/64)
       O[n] = cmul(make_float2(kW64re[k], kW64im[k]), v);
     }
-    fft32_fwd(E);
-    fft32_fwd(O);
+    fft_fwd<32>(E);
+    fft_fwd<32>(O);
     // X1[r'][kx] for kx in [-16, 16] -> buf[wr][kx + 16]
 #pragma unroll
     for (int kx = -16; kx <= 16; ++kx) buf[wr * LS + kx + 16] = pick(E, O, kx);
@@ -149,8 +163,8 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
       const int k = (rp + 64) & 63;
       O[n] = cmul(make_float2(kW64re[k], kW64im[k]), v);
     }
-    fft32_fwd(E);
-    fft32_fwd(O);
+    fft_fwd<32>(E);
+    fft_fwd<32>(O);
     const int kx = lane - 16;
 #pragma unroll
     for (int ky = -R; ky <= R; ++ky) {
@@ -198,12 +212,158 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
   }
 }
 
+// k_psf128 (pupil P = 128, aperture diameter 64 samples, crop T <= 65):
+// one wavefront owns one pixel.  The aperture fits the 64 x 64 window of
+// offsets [-32, 32) and the 65 x 65 lowest frequencies of the 128 x 128 DFT
+// are kept; a 128-point DFT of 64 samples at frequencies [-32, 32] splits
+// into the 64-point DFTs of x[c] (even) and x[c] exp(-2 pi i c/128) (odd).
+// Stage 1: lane = pupil row; the row is kept in LDS while its two register
+// FFT-64s run one after the other, then its 65 outputs overwrite it.
+// Stage 2: lane = frequency column kx in [-32, 32); the column kx = +32 is a
+// direct 64-term DFT (row ky = +32 of it: twiddles (-i)^r', a wave sum).
+template <int T>
+__global__ void __launch_bounds__(64)
+k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__restrict__ zrow,
+         float *__restrict__ psf) {
+  constexpr int R = (T - 1) / 2;  // crop radius, <= 32
+  constexpr int LS = 65;          // LDS row stride (complex)
+  __shared__ float2 buf[64 * LS];
+  const int lane = threadIdx.x;
+  const size_t p = blockIdx.x;
+
+  float a[33];
+  {
+    const size_t pg = p_base + p;
+    const size_t fr = pg / size_t(hw), yx = pg - fr * size_t(hw);
+    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
+#pragma unroll
+    for (int t = 0; t < 33; ++t) a[t] = zp[size_t(t + TSIM_PSF_MODE0) * hw];
+  }
+
+  float2 X[64];
+  // ---- stage 1: lane = window row wr, pupil row offset r' = wr - 32 ----
+  {
+    const int wr = lane, rp = wr - 32;
+    float2 *row = buf + wr * LS;
+    float d[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float s = 0.f;
+#pragma unroll
+      for (int j = 0; j < 33; ++j) s = fmaf(a[j], zrow[(q * 33 + j) * 64 + wr], s);
+      d[q] = s;
+    }
+#pragma unroll
+    for (int n = 0; n < 64; ++n) {
+      const int cp = (n < 32) ? n : n - 64;
+      float2 v = make_float2(0.f, 0.f);
+      if (rp * rp + cp * cp < 1024) {
+        float phi = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) phi = fmaf(d[q], kChebCol64[n][q], phi);
+        const float rev = phi * 0.15915494309189535f;
+        v = make_float2(__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev));
+      }
+      X[n] = v;
+      row[n] = v;
+    }
+    fft_fwd<64>(X);
+    float2 ev[33];  // even kx = 2m, m in [-16, 16]
+#pragma unroll
+    for (int m = -16; m <= 16; ++m) ev[m + 16] = X[m & 63];
+#pragma unroll
+    for (int n = 0; n < 64; ++n) {
+      const int k = ((n < 32) ? n : n - 64) & 127;  // exp(-2 pi i c'/128)
+      X[n] = cmul(make_float2(kW128re[k], kW128im[k]), row[n]);
+    }
+    fft_fwd<64>(X);
+    // X1[r'][kx] for kx in [-32, 32] -> row[kx + 32]
+#pragma unroll
+    for (int kx = -32; kx <= 32; ++kx)
+      row[kx + 32] = (kx & 1) ? X[((kx - 1) >> 1) & 63] : ev[(kx >> 1) + 16];
+  }
+  __syncthreads();
+
+  // ---- stage 2: lane = frequency column kx = lane - 32 ----
+  const int kx = lane - 32;
+  float he[33], ho[32];  // |X|^2 at even ky = 2m (m in [-16, 16]) and odd ky = 2m + 1
+  float hx = 0.f, hx32 = 0.f;  // column kx = +32: row ky = lane - 32, and row ky = +32
+  float total = 0.f;
+  if (R == 32) {
+    float2 acc = make_float2(0.f, 0.f);
+    const int ky = lane - 32;
+    for (int wr = 0; wr < 64; ++wr) {
+      const float rev = float((ky * (wr - 32)) & 127) * (1.0f / 128.0f);
+      const float2 w = make_float2(__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev));
+      acc = f2add(acc, cmul(w, buf[wr * LS + 64]));
+    }
+    hx = acc.x * acc.x + acc.y * acc.y;
+    // ky = +32: exp(-2 pi i 32 r'/128) = (-i)^r'; lane = row
+    const float2 v = buf[lane * LS + 64];
+    const int q = (lane - 32) & 3;
+    float2 t = q == 0 ? v : q == 1 ? make_float2(v.y, -v.x) : q == 2 ? make_float2(-v.x, -v.y)
+                                                                      : make_float2(-v.y, v.x);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      t.x += __shfl_xor(t.x, off, 64);
+      t.y += __shfl_xor(t.y, off, 64);
+    }
+    hx32 = t.x * t.x + t.y * t.y;
+    total = hx + (lane == 0 ? hx32 : 0.f);
+  }
+  {
+    const int col = lane;
+#pragma unroll
+    for (int n = 0; n < 64; ++n) {
+      const int rp = (n < 32) ? n : n - 64;
+      X[n] = buf[(rp + 32) * LS + col];
+    }
+    fft_fwd<64>(X);
+#pragma unroll
+    for (int m = -16; m <= 16; ++m) {
+      const float2 v = X[m & 63];
+      he[m + 16] = v.x * v.x + v.y * v.y;
+    }
+#pragma unroll
+    for (int n = 0; n < 64; ++n) {
+      const int rp = (n < 32) ? n : n - 64;
+      const int k = rp & 127;
+      X[n] = cmul(make_float2(kW128re[k], kW128im[k]), buf[(rp + 32) * LS + col]);
+    }
+    fft_fwd<64>(X);
+#pragma unroll
+    for (int m = -16; m <= 15; ++m) {
+      const float2 v = X[m & 63];
+      ho[m + 16] = v.x * v.x + v.y * v.y;
+    }
+  }
+  auto hval = [&](int ky) { return (ky & 1) ? ho[((ky - 1) >> 1) + 16] : he[(ky >> 1) + 16]; };
+  if (kx >= -R && kx <= R) {
+#pragma unroll
+    for (int ky = -R; ky <= R; ++ky) total += hval(ky);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) total += __shfl_xor(total, off, 64);
+  const float inv = 1.0f / total;
+  float *out = psf + p * T * T;
+  if (kx >= -R && kx <= R) {
+#pragma unroll
+    for (int ky = -R; ky <= R; ++ky) out[(ky + R) * T + (kx + R)] = hval(ky) * inv;
+  }
+  if (R == 32) {
+    out[(lane - 32 + R) * T + (32 + R)] = hx * inv;
+    if (lane == 0) out[(32 + R) * T + (32 + R)] = hx32 * inv;
+  }
+}
+
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // beta[p][k] = sum_t h[p][t] psi[k][t] on the FP32 matrix cores
 // (v_mfma_f32_32x32x2f32).  Block: 128 pixels x 128 outputs, 4 waves, wave
 // w owns pixel tile w and all four 32-wide output tiles; 32-tap chunks of h
-// and psi^T are staged through LDS (h rows padded against bank conflicts).
+// and psi^T are staged through LDS (h rows padded against bank conflicts),
+// and the global loads of chunk c + 1 are in flight in registers while the
+// matrix cores work on chunk c.
 constexpr int PJ_PX = 128, PJ_TK = 32, PJ_N = 128;
 
 __global__ void __launch_bounds__(256)
@@ -213,23 +373,43 @@ k_project_mfma(const float *__restrict__ h, const float *__restrict__ psi_t128 /
   __shared__ __attribute__((aligned(16))) float Bs[PJ_TK][PJ_N];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int p0 = blockIdx.x * PJ_PX;
+  constexpr int NA = PJ_PX * PJ_TK / 256, NB = PJ_TK * PJ_N / 4 / 256;
+  float ra[NA];
+  float4 rb[NB];
+  auto gload = [&](int t0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = threadIdx.x + i * 256;
+      const int px = e >> 5, tt = e & 31;
+      const int gp = p0 + px, gt = t0 + tt;
+      ra[i] = (gp < n && gt < T2) ? h[size_t(gp) * T2 + gt] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = threadIdx.x + i * 256;
+      const int tt = e >> 5, c4 = e & 31;
+      const int gt = t0 + tt;
+      rb[i] = (gt < T2) ? *reinterpret_cast<const float4 *>(psi_t128 + size_t(gt) * PJ_N + 4 * c4)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
   f32x16 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
+  gload(0);
   for (int t0 = 0; t0 < T2; t0 += PJ_TK) {
-    for (int e = threadIdx.x; e < PJ_PX * PJ_TK; e += 256) {
-      const int px = e / PJ_TK, tt = e % PJ_TK;
-      const int gp = p0 + px, gt = t0 + tt;
-      As[px][tt] = (gp < n && gt < T2) ? h[size_t(gp) * T2 + gt] : 0.f;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = threadIdx.x + i * 256;
+      As[e >> 5][e & 31] = ra[i];
     }
-    for (int e = threadIdx.x; e < PJ_TK * PJ_N / 4; e += 256) {
-      const int tt = e / (PJ_N / 4), c4 = e % (PJ_N / 4);
-      const int gt = t0 + tt;
-      float4 v = (gt < T2) ? *reinterpret_cast<const float4 *>(psi_t128 + size_t(gt) * PJ_N + 4 * c4)
-                           : make_float4(0.f, 0.f, 0.f, 0.f);
-      *reinterpret_cast<float4 *>(&Bs[tt][4 * c4]) = v;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = threadIdx.x + i * 256;
+      *reinterpret_cast<float4 *>(&Bs[e >> 5][4 * (e & 31)]) = rb[i];
     }
     __syncthreads();
+    if (t0 + PJ_TK < T2) gload(t0 + PJ_TK);
 #pragma unroll
     for (int s = 0; s < PJ_TK / 2; ++s) {
       const float a = As[w * 32 + (lane & 31)][2 * s + (lane >> 5)];
@@ -256,9 +436,18 @@ k_project_mfma(const float *__restrict__ h, const float *__restrict__ psi_t128 /
 
 int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_base, int n, float *psf,
                     hipStream_t s) {
+  const float *zt = pl->d_zrow;
+  if (pl->P == 128) {
+    TraceScope tr("k_psf128", s);
+    switch (pl->T) {
+      case 65: hipLaunchKernelGGL(k_psf128<65>, dim3(n), dim3(64), 0, s, zern, hw, p_base, zt, psf); break;
+      case 33: hipLaunchKernelGGL(k_psf128<33>, dim3(n), dim3(64), 0, s, zern, hw, p_base, zt, psf); break;
+      default: return TSIM_EUNSUPPORTED;
+    }
+    return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+  }
   if (pl->P != 64) return TSIM_EUNSUPPORTED;
   dim3 grid((n + 7) / 8);
-  const float *zt = pl->d_zrow;
   TraceScope tr("k_psf64", s);
   switch (pl->T) {
     case 33: hipLaunchKernelGGL(k_psf64<33>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
@@ -271,13 +460,15 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
 
-// pixels per P2S chunk: bounds the PSF workspace
-size_t p2s_chunk(const tsim_plan *pl, size_t total) {
-  size_t cap = size_t(1) << 20;
-  return std::min(total, cap);
-}
-
 }  // namespace
+
+// pixels per P2S chunk: at most 2^20 pixels and about 5 GB of PSFs, in whole
+// projection tiles (bounds the PSF workspace)
+size_t p2s_chunk_pixels(const tsim_plan *pl, size_t total) {
+  const size_t per = size_t(pl->T) * pl->T * sizeof(float);
+  size_t cap = std::min(size_t(1) << 20, (size_t(5) << 30) / per / PJ_PX * PJ_PX);
+  return std::min(total, std::max(cap, size_t(PJ_PX)));
+}
 
 int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s) {
   const int T2 = pl->T * pl->T;
@@ -289,7 +480,7 @@ int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipS
 
 size_t p2s_ws_bytes(const tsim_plan *pl, int frames) {
   size_t total = size_t(frames) * pl->H * pl->W;
-  return p2s_chunk(pl, total) * size_t(pl->T) * pl->T * sizeof(float);
+  return p2s_chunk_pixels(pl, total) * size_t(pl->T) * pl->T * sizeof(float);
 }
 
 int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, hipStream_t s) {
@@ -300,7 +491,7 @@ int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *
                      hipStream_t s) {
   const int hw = pl->H * pl->W;
   const size_t total = size_t(frames) * hw;
-  const size_t chunk = p2s_chunk(pl, total);
+  const size_t chunk = p2s_chunk_pixels(pl, total);
   float *h = static_cast<float *>(ws);
   for (size_t p0 = 0; p0 < total; p0 += chunk) {
     const int n = int(std::min(chunk, total - p0));

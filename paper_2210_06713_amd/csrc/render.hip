@@ -78,12 +78,23 @@ k_warp(const float *__restrict__ img, const float *__restrict__ zern, float *__r
   const float k = -1.27323954473516268f;  // -4/pi pixels per radian of tilt
   const float tx = k * zf[size_t(y) * W + x];
   const float ty = k * zf[plane + size_t(y) * W + x];
-  const float px = float(x) - tx, py = float(y) - ty;
-  const float fx0 = floorf(px), fy0 = floorf(py);
-  const float fx = px - fx0, fy = py - fy0;
-  // clamp in float first so huge displacements cannot overflow the int cast
-  const int x0 = int(fminf(fmaxf(fx0, -1.f), float(W)));
-  const int y0 = int(fminf(fmaxf(fy0, -1.f), float(H)));
+  // sample point x - t = (x - floor(t) - 1) + (1 - frac(t)): the integer part
+  // is exact and the fraction keeps the precision of t itself, which
+  // float(x) - t would lose at large x (ulp 2^-12 at x ~ 4000)
+  const float tix = floorf(tx), tiy = floorf(ty);
+  float fx = 1.f - (tx - tix), fy = 1.f - (ty - tiy);  // in (0, 1]
+  // clamp in float first so huge displacements cannot overflow the int cast;
+  // beyond +-(size + 2) both taps sit on the border whatever the fraction
+  int x0 = x - int(fminf(fmaxf(tix, -float(W) - 2.f), float(W) + 2.f)) - 1;
+  int y0 = y - int(fminf(fmaxf(tiy, -float(H) - 2.f), float(H) + 2.f)) - 1;
+  if (fx >= 1.f) {
+    fx -= 1.f;
+    x0 += 1;
+  }
+  if (fy >= 1.f) {
+    fy -= 1.f;
+    y0 += 1;
+  }
   const int x0c = min(max(x0, 0), W - 1), x1c = min(max(x0 + 1, 0), W - 1);
   const int y0c = min(max(y0, 0), H - 1), y1c = min(max(y0 + 1, 0), H - 1);
   const float *imf = img + size_t(f) * C * plane;

@@ -33,7 +33,7 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
   constexpr int SH = TH + T - 1, SW = TW + T - 1, PLANE = SH * SW;
   constexpr int NT = (T * T + 31) / 32;
   extern __shared__ float tile[];             // [C][SH][SW]
-  __shared__ int offtab[NT * 32];             // tap -> uy * SW + ux (0 for padded taps)
+  __shared__ short offtab[NT * 32];           // tap -> uy * SW + ux (0 for padded taps)
   const int f = blockIdx.z;
   const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
   const float *imf = img + size_t(f) * C * H * W;
@@ -68,7 +68,7 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
 
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   auto epilogue = [&](const f32x16 &acc, int t) {
-    const int *ot = offtab + 32 * t + mrow;
+    const short *ot = offtab + 32 * t + mrow;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int idx = pbase - ot[8 * (r >> 2) + (r & 3)];
@@ -145,7 +145,7 @@ k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
   constexpr int SH = TH + T - 1, SW = TW + T - 1, PLANE = SH * SW;
   constexpr int NT = (T * T + 31) / 32;
   extern __shared__ float tile[];
-  __shared__ int offtab[NT * 32];
+  __shared__ short offtab[NT * 32];
   const int f = blockIdx.z;
   const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
   const float *imf = img + size_t(f) * C * H * W;
@@ -190,7 +190,7 @@ k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
       if (4 * q + 2 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b[4 * q + 2], acc0, 0, 0, 0);
       if (4 * q + 3 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b[4 * q + 3], acc0, 0, 0, 0);
     }
-    const int *ot = offtab + 32 * t + mrow;
+    const short *ot = offtab + 32 * t + mrow;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int idx = pbase - ot[8 * (r >> 2) + (r & 3)];
@@ -215,19 +215,45 @@ k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
   }
 }
 
+// Dynamic LDS of the image tile; tiles above 64 KB (T = 65) need the
+// device's larger workgroup limit, checked here and raised on the kernel.
+template <typename Kern>
+int prepare_lds(Kern kern, size_t lds, int T) {
+  const size_t stat = sizeof(short) * size_t((T * T + 31) / 32 * 32);
+  int dev = 0, max_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return TSIM_EDEVICE;
+  if (lds + stat > size_t(max_lds)) return TSIM_EUNSUPPORTED;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          int(lds)) != hipSuccess)
+    return TSIM_EDEVICE;
+  return TSIM_OK;
+}
+
+template <int KS, int T>
+int launch_ks_t(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta, float *out,
+                hipStream_t s) {
+  const int H = pl->H, W = pl->W, C = pl->C;
+  dim3 grid((W + 15) / 16, (H + 7) / 8, frames);
+  const size_t lds = size_t(C) * (8 + T - 1) * (16 + T - 1) * sizeof(float);
+  const int st = prepare_lds(k_render_bf16<KS, T>, lds, T);
+  if (st != TSIM_OK) return st;
+  hipLaunchKernelGGL((k_render_bf16<KS, T>), grid, dim3(256), lds, s, img, beta, pl->d_basis_bf, out, H, W, C);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
 template <int KS>
 int launch_ks(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta, float *out,
               hipStream_t s) {
-  const int H = pl->H, W = pl->W, C = pl->C, T = pl->T;
-  dim3 grid((W + 15) / 16, (H + 7) / 8, frames);
-  const size_t lds = size_t(C) * (8 + T - 1) * (16 + T - 1) * sizeof(float);
-  switch (T) {
-    case 33: hipLaunchKernelGGL((k_render_bf16<KS, 33>), grid, dim3(256), lds, s, img, beta, pl->d_basis_bf, out, H, W, C); break;
-    case 21: hipLaunchKernelGGL((k_render_bf16<KS, 21>), grid, dim3(256), lds, s, img, beta, pl->d_basis_bf, out, H, W, C); break;
-    case 15: hipLaunchKernelGGL((k_render_bf16<KS, 15>), grid, dim3(256), lds, s, img, beta, pl->d_basis_bf, out, H, W, C); break;
+  switch (pl->T) {
+    case 65: return launch_ks_t<KS, 65>(pl, frames, img, beta, out, s);
+    case 33: return launch_ks_t<KS, 33>(pl, frames, img, beta, out, s);
+    case 21: return launch_ks_t<KS, 21>(pl, frames, img, beta, out, s);
+    case 15: return launch_ks_t<KS, 15>(pl, frames, img, beta, out, s);
     default: return TSIM_EUNSUPPORTED;
   }
-  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
 
 }  // namespace
@@ -235,12 +261,18 @@ int launch_ks(const tsim_plan *pl, int frames, const float *img, const uint16_t 
 int launch_render_f32_mfma(const tsim_plan *pl, int frames, const float *img, const float *beta,
                            float *out, hipStream_t s) {
   const int H = pl->H, W = pl->W, C = pl->C, T = pl->T;
-  if (!pl->d_basis_k2 || pl->K != 100 || T != 33) return TSIM_EUNSUPPORTED;
+  if (!pl->d_basis_k2 || pl->K != 100 || (T != 33 && T != 65)) return TSIM_EUNSUPPORTED;
   dim3 grid((W + 15) / 16, (H + 7) / 8, frames);
   const size_t lds = size_t(C) * (8 + T - 1) * (16 + T - 1) * sizeof(float);
+  const int st = T == 33 ? prepare_lds(k_render_f32m<50, 33>, lds, T) : prepare_lds(k_render_f32m<50, 65>, lds, T);
+  if (st != TSIM_OK) return st;
   TraceScope tr("k_render_fp32", s);
-  hipLaunchKernelGGL((k_render_f32m<50, 33>), grid, dim3(256), lds, s, img, beta, pl->d_basis_k2, out,
-                     H, W, C, pl->K);
+  if (T == 33)
+    hipLaunchKernelGGL((k_render_f32m<50, 33>), grid, dim3(256), lds, s, img, beta, pl->d_basis_k2, out,
+                       H, W, C, pl->K);
+  else
+    hipLaunchKernelGGL((k_render_f32m<50, 65>), grid, dim3(256), lds, s, img, beta, pl->d_basis_k2, out,
+                       H, W, C, pl->K);
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
 

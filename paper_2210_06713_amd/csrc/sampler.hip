@@ -2,14 +2,16 @@
 // two-step generation, Eq. (9)).
 //
 // Pass 1 (k_sampler_cols): for field q (Noll modes 2+2q, 3+2q in its real
-// and imaginary parts) and a strip of NC adjacent frequency columns kx, the
-// Hermitian white noise of every bin is drawn in registers from Philox,
-// coloured by the square-root spectra, and inverse-transformed along ky in
-// LDS; rows y < H of the result are written to the workspace V[f][q][y][kx].
+// and imaginary parts) and NC/2 pairs of Hermitian-mirror frequency columns
+// (kx, Gw - kx), the white noise is drawn in registers from Philox once per
+// bin pair, coloured by the square-root spectra at both bins, and
+// inverse-transformed along ky in LDS; rows y < H of the result are written
+// to the workspace V[f][q][y][slot], columns in mirror-pair slot order.
 // Pass 2 (k_sampler_rows_mix): one block per output row y inverse-transforms
 // V[f][q][y][:] along kx for every field, keeps columns x < W, and mixes the
 // 35 unit-variance fields at each pixel with (D/r0)^{5/6} L before writing
-// the 35 coefficient planes.  Only rows y < H survive pass 1 and only columns
+// the 35 coefficient planes (only L's structurally non-zero entries, each
+// output plane written once its last field is in).  Only rows y < H survive pass 1 and only columns
 // x < W pass 2 (crop of the top-left corner of the periodic grid).
 #include <algorithm>
 
@@ -27,63 +29,223 @@ struct FrameScales {
   float s[kMaxFramesPerLaunch];
 };
 
-__global__ void __launch_bounds__(256)
+// Column slots of the intermediate: slots 2p and 2p + 1 hold the Hermitian
+// mirror columns kx = p and Gw - p (1 <= p < Gw/2); slots 0 and 1 hold the
+// self-mirror columns 0 and Gw/2.  A pass-1 block owns whole slot pairs, so
+// every noise draw serves a bin and its mirror, and writes NC adjacent slots.
+__device__ __forceinline__ int slot_col(int c, int Gw) {
+  const int p = c >> 1;
+  if (p == 0) return (c & 1) ? (Gw >> 1) : 0;
+  return (c & 1) ? Gw - p : p;
+}
+
+__global__ void __launch_bounds__(512)
 k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, float2 *__restrict__ V,
                int Gh, int Gw, int log2h, int H, int NC, uint32_t key0, uint32_t key1,
                uint32_t frame_base) {
-  extern __shared__ float2 lds[];
+  extern __shared__ float2 lds[];  // [NC][Gh], slot-major
   const int q = blockIdx.y;
   const int fl = blockIdx.z;  // frame within this launch
   const uint32_t frame = frame_base + uint32_t(fl);
-  const int c0 = blockIdx.x * NC;
-  const int qh = Gh / 2 + 1, qw = Gw / 2 + 1;
+  // XCD-aware order: consecutive blocks go to different XCDs (round robin over
+  // 8), so give the blocks of one XCD adjacent slot groups; their row
+  // segments then share 128-byte lines in that XCD's L2.
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int grp = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int s0 = grp * NC;          // first slot of this block
+  const int qh = Gh / 2 + 1;
   const int ma = 2 * q, mb = 2 * q + 1;  // 0-based mode indices (Noll 2+2q, 3+2q)
   const bool has_b = mb < TSIM_N_MODES;
   const float rs2 = 0.70710678118654752f;
+  const bool zero_pair = s0 == 0;
+  // work items: one per noise draw; the self-mirror pair (columns 0, Gw/2)
+  // has Gh/2 + 1 draws per column, the others Gh per pair
+  const int items = (NC / 2) * Gh + (zero_pair ? 2 : 0);
 
-  for (int e = threadIdx.x; e < NC * Gh; e += blockDim.x) {
-    const int col = e >> log2h;
-    const int ky = e & (Gh - 1);
-    const int kx = c0 + col;
-    const int mky = (Gh - ky) & (Gh - 1);
-    const int mkx = (Gw - kx) & (Gw - 1);
-    const uint32_t lin = uint32_t(ky) * Gw + kx;
-    const uint32_t lin_m = uint32_t(mky) * Gw + mkx;
-    const uint32_t canon = lin < lin_m ? lin : lin_m;
-    u32x4 r = philox4x32_10(u32x4{canon, uint32_t(q), frame, 0u}, key0, key1);
-    float2 g01 = box_muller(r.x, r.y);
-    float2 g23 = box_muller(r.z, r.w);
-    float2 wa, wb;
-    if (lin == lin_m) {
-      wa = make_float2(g01.x, 0.f);
-      wb = make_float2(g23.x, 0.f);
+  for (int e = threadIdx.x; e < items; e += blockDim.x) {
+    int slotA, slotB, kyA, kyB, kx;
+    bool self_conj = false;
+    if (zero_pair && e < Gh + 2) {
+      const int half = Gh / 2 + 1;
+      const int c = e < half ? 0 : 1;
+      kyA = e < half ? e : e - half;   // 0..Gh/2
+      kx = c ? (Gw >> 1) : 0;
+      kyB = (Gh - kyA) & (Gh - 1);
+      slotA = slotB = c;
+      self_conj = kyA == kyB;
     } else {
-      wa = make_float2(g01.x * rs2, g01.y * rs2);
-      wb = make_float2(g23.x * rs2, g23.y * rs2);
-      if (lin > lin_m) {
-        wa.y = -wa.y;
-        wb.y = -wb.y;
-      }
+      const int e2 = zero_pair ? e - 2 : e;
+      const int pp = e2 >> log2h;     // pair within the block
+      kyA = e2 & (Gh - 1);
+      kx = (s0 >> 1) + pp;            // >= 1 here
+      kyB = (Gh - kyA) & (Gh - 1);
+      slotA = 2 * pp;
+      slotB = 2 * pp + 1;
     }
-    const int kxq = kx < qw ? kx : Gw - kx;
-    const int kyq = ky < qh ? ky : Gh - ky;
+    // bin A = (kyA, kx); its mirror B = (kyB, -kx mod Gw); canonical = smaller linear index
+    const uint32_t linA = uint32_t(kyA) * Gw + kx;
+    const uint32_t linB = uint32_t(kyB) * Gw + ((Gw - kx) & (Gw - 1));
+    const bool a_canon = linA <= linB;
+    const uint32_t canon = a_canon ? linA : linB;
+    u32x4 r = philox4x32_10(u32x4{canon, uint32_t(q), frame, 0u}, key0, key1);
+    const float2 g01 = box_muller(r.x, r.y);
+    const float2 g23 = box_muller(r.z, r.w);
+    const int kxq = kx;                // kx <= Gw/2 for every bin A
+    const int kyq = kyA < qh ? kyA : Gh - kyA;
+    const int qw = Gw / 2 + 1;
     const float sa = sqrtS[(size_t(ma) * qw + kxq) * qh + kyq];
     const float sb = has_b ? sqrtS[(size_t(mb) * qw + kxq) * qh + kyq] : 0.f;
-    // U = sa Wa + i sb Wb
-    float2 u = make_float2(sa * wa.x - sb * wb.y, sa * wa.y + sb * wb.x);
-    lds[col * Gh + bitrev(uint32_t(ky), log2h)] = u;
+    if (self_conj) {
+      // U = sa g0 + i sb g2 (real noise at self-conjugate bins)
+      lds[slotA * Gh + bitrev(uint32_t(kyA), log2h)] = make_float2(sa * g01.x, sb * g23.x);
+    } else {
+      // noise of A: W (canonical) or conj(W); B takes the conjugate
+      const float sg = a_canon ? 1.f : -1.f;
+      const float2 wa = make_float2(g01.x * rs2, sg * g01.y * rs2);
+      const float2 wb = make_float2(g23.x * rs2, sg * g23.y * rs2);
+      // U = sa Wa + i sb Wb at A, and sa conj(Wa) + i sb conj(Wb) at B
+      lds[slotA * Gh + bitrev(uint32_t(kyA), log2h)] =
+          make_float2(sa * wa.x - sb * wb.y, sa * wa.y + sb * wb.x);
+      lds[slotB * Gh + bitrev(uint32_t(kyB), log2h)] =
+          make_float2(sa * wa.x + sb * wb.y, -sa * wa.y + sb * wb.x);
+    }
   }
   __syncthreads();
   lds_fft_dit(lds, Gh, log2h, NC, Gh, tw);
   const float norm = rsqrtf(float(Gh) * float(Gw));
-  float2 *Vout = V + (size_t(fl) * TSIM_FIELDS + q) * size_t(H) * Gw;
+  float2 *Vout = V + (size_t(fl) * TSIM_FIELDS + q) * size_t(H) * Gw + s0;
+  const int log2nc = __builtin_ctz(NC);
   for (int e = threadIdx.x; e < H * NC; e += blockDim.x) {
-    const int y = e / NC;
-    const int col = e - y * NC;
-    float2 v = lds[col * Gh + y];
-    Vout[size_t(y) * Gw + c0 + col] = make_float2(v.x * norm, v.y * norm);
+    const int y = e >> log2nc;
+    const int c = e & (NC - 1);
+    const float2 v = lds[c * Gh + y];
+    Vout[size_t(y) * Gw + c] = make_float2(v.x * norm, v.y * norm);
   }
 }
+
+// Structure of the mixing matrix.  L (lower Cholesky factor of the Noll
+// matrix in Noll order) is non-zero only inside the (|m|, parity) groups of
+// modes: mode k feeds output t iff both have the same |m| (and, for m != 0,
+// the same parity of the Noll index) and k <= t.  Field q carries modes
+// 2q and 2q + 1 (0-based, Noll 2 + 2q and 3 + 2q); fields are transformed in
+// the order below, chosen so that at most 9 outputs have received some but
+// not all of their terms at any point, and each output is written as soon as
+// its last field is mixed in: few accumulators stay live per pixel.
+struct MixPlan {
+  bool nz[TSIM_N_MODES][TSIM_N_MODES];  // L[t][k] structurally non-zero
+  int first[TSIM_N_MODES];               // position in kFieldOrder of output t's first term
+  int first_k[TSIM_N_MODES];             // mode of that first term
+  int last[TSIM_N_MODES];                // position in kFieldOrder of output t's last field
+};
+
+constexpr int kFieldOrder[TSIM_FIELDS] = {10, 4, 16, 8, 15, 9, 1, 17, 14, 3, 7, 5, 2, 11, 0, 6, 13, 12};
+
+constexpr int noll_abs_m(int j) {
+  int n = 0;
+  while ((n + 1) * (n + 2) / 2 < j) ++n;
+  const int p = j - (n * (n + 1) / 2 + 1);
+  return (n % 2 == 0) ? 2 * ((p + 1) / 2) : 2 * (p / 2) + 1;
+}
+
+constexpr int mix_group(int t) {  // t = 0-based mode index (Noll t + 2)
+  const int j = t + 2, m = noll_abs_m(j);
+  return m == 0 ? 0 : 2 * m - 1 + (j & 1);
+}
+
+constexpr MixPlan make_mix_plan() {
+  MixPlan mp{};
+  for (int t = 0; t < TSIM_N_MODES; ++t) {
+    mp.first[t] = mp.first_k[t] = mp.last[t] = -1;
+    for (int k = 0; k < TSIM_N_MODES; ++k) mp.nz[t][k] = k <= t && mix_group(k) == mix_group(t);
+  }
+  for (int i = 0; i < TSIM_FIELDS; ++i) {
+    const int q = kFieldOrder[i];
+    for (int t = 0; t < TSIM_N_MODES; ++t) {
+      const bool a = mp.nz[t][2 * q];
+      const bool b = 2 * q + 1 < TSIM_N_MODES && mp.nz[t][2 * q + 1];
+      if ((a || b) && mp.first[t] < 0) {
+        mp.first[t] = i;
+        mp.first_k[t] = a ? 2 * q : 2 * q + 1;
+      }
+      if (a || b) mp.last[t] = i;
+    }
+  }
+  return mp;
+}
+
+constexpr MixPlan kMix = make_mix_plan();
+
+struct RowArgs {
+  float2 *lds;
+  const float2 *V;  // this frame's rows: V[q][y][:] at V + (q * H + y) * Gw
+  const float2 *tw;
+  const float *Lmat;
+  float *out;       // this frame and row: plane t at out + t * H * W
+  int Gw, log2w, H, W, y;
+  float sc;
+};
+
+// Field at position I of kFieldOrder: inverse transform of its row, then its
+// terms of the mix; outputs whose last field this is are written.
+template <int I, int PX, int NT>
+__device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_MODES][PX]) {
+  constexpr int q = kFieldOrder[I];
+  constexpr int ta = 2 * q, tb = 2 * q + 1;
+  const float2 *row = a.V + (size_t(q) * a.H + a.y) * size_t(a.Gw);
+  for (int c = threadIdx.x; c < a.Gw; c += NT) a.lds[bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w)] = row[c];
+  __syncthreads();
+  lds_fft_dit(a.lds, a.Gw, a.log2w, 1, a.Gw, a.tw);
+  float ya[PX], yb[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const int x = threadIdx.x + k * NT;
+    const float2 z = (x < a.W) ? a.lds[x] : make_float2(0.f, 0.f);
+    ya[k] = z.x;
+    yb[k] = z.y;
+  }
+  __syncthreads();  // lds is overwritten by the next field
+#pragma unroll
+  for (int t = 0; t < TSIM_N_MODES; ++t) {
+    if (kMix.nz[t][ta]) {
+      const float la = a.Lmat[t * TSIM_N_MODES + ta];
+      const bool init = kMix.first[t] == I && kMix.first_k[t] == ta;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) acc[t][k] = init ? la * ya[k] : fmaf(la, ya[k], acc[t][k]);
+    }
+    if (tb < TSIM_N_MODES && kMix.nz[t][tb]) {
+      const float lb = a.Lmat[t * TSIM_N_MODES + tb];
+      const bool init = kMix.first[t] == I && kMix.first_k[t] == tb;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) acc[t][k] = init ? lb * yb[k] : fmaf(lb, yb[k], acc[t][k]);
+    }
+    if (kMix.last[t] == I) {
+      // opaque plane size: keeps the compiler from forming all 35 plane
+      // addresses at kernel entry and holding them in registers
+      size_t plane = size_t(a.H) * a.W;
+      asm volatile("" : "+s"(plane));
+      float *po = a.out + size_t(t) * plane;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        const int x = threadIdx.x + k * NT;
+        if (x < a.W) po[x] = acc[t][k] * a.sc;
+      }
+    }
+  }
+}
+
+template <int I, int PX, int NT>
+struct FieldSteps {
+  __device__ __forceinline__ static void run(const RowArgs &a, float (&acc)[TSIM_N_MODES][PX]) {
+    mix_field<I, PX, NT>(a, acc);
+    FieldSteps<I + 1, PX, NT>::run(a, acc);
+  }
+};
+
+template <int PX, int NT>
+struct FieldSteps<TSIM_FIELDS, PX, NT> {
+  __device__ __forceinline__ static void run(const RowArgs &, float (&)[TSIM_N_MODES][PX]) {}
+};
 
 template <int PX, int NT>
 __global__ void __launch_bounds__(NT)
@@ -93,46 +255,20 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
   extern __shared__ float2 lds[];
   const int y = blockIdx.x;
   const int fl = blockIdx.y;
-  const int nthr = NT;
-  float acc[TSIM_N_MODES][PX];
-#pragma unroll
-  for (int j = 0; j < TSIM_N_MODES; ++j)
-#pragma unroll
-    for (int k = 0; k < PX; ++k) acc[j][k] = 0.f;
-
-  for (int q = 0; q < TSIM_FIELDS; ++q) {
-    const float2 *row = V + ((size_t(fl) * TSIM_FIELDS + q) * H + y) * size_t(Gw);
-    for (int kx = threadIdx.x; kx < Gw; kx += nthr) lds[bitrev(uint32_t(kx), log2w)] = row[kx];
-    __syncthreads();
-    lds_fft_dit(lds, Gw, log2w, 1, Gw, tw);
-    float ya[PX], yb[PX];
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      int x = threadIdx.x + k * nthr;
-      float2 z = (x < W) ? lds[x] : make_float2(0.f, 0.f);
-      ya[k] = z.x;
-      yb[k] = z.y;
-    }
-    __syncthreads();  // lds is overwritten by the next field
-    // a_j += L[j][2q] ybar_{2q} + L[j][2q+1] ybar_{2q+1} (L lower triangular)
-    const int ta = 2 * q, tb = 2 * q + 1;
-#pragma unroll
-    for (int j = 0; j < TSIM_N_MODES; ++j) {
-      const float la = Lmat[j * TSIM_N_MODES + ta];
-      const float lb = (tb < TSIM_N_MODES) ? Lmat[j * TSIM_N_MODES + tb] : 0.f;
-#pragma unroll
-      for (int k = 0; k < PX; ++k) acc[j][k] = fmaf(la, ya[k], fmaf(lb, yb[k], acc[j][k]));
-    }
-  }
-  const float sc = scales.s[fl];
-  float *out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * size_t(H) * W + size_t(y) * W;
-#pragma unroll
-  for (int j = 0; j < TSIM_N_MODES; ++j)
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      int x = threadIdx.x + k * nthr;
-      if (x < W) out[size_t(j) * H * W + x] = acc[j][k] * sc;
-    }
+  RowArgs a;
+  a.lds = lds;
+  a.V = V + size_t(fl) * TSIM_FIELDS * H * size_t(Gw);
+  a.tw = tw;
+  a.Lmat = Lmat;
+  a.out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * size_t(H) * W + size_t(y) * W;
+  a.Gw = Gw;
+  a.log2w = log2w;
+  a.H = H;
+  a.W = W;
+  a.y = y;
+  a.sc = scales.s[fl];
+  float acc[TSIM_N_MODES][PX];  // each output starts at its first term
+  FieldSteps<0, PX, NT>::run(a, acc);
 }
 
 int ilog2(int v) {
@@ -172,7 +308,7 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     dim3 g1(Gw / NC, TSIM_FIELDS, nf);
     {
       TraceScope tr("k_sampler_cols", s);
-      hipLaunchKernelGGL(k_sampler_cols, g1, dim3(256), size_t(NC) * Gh * sizeof(float2), s, pl->d_sqrtS,
+      hipLaunchKernelGGL(k_sampler_cols, g1, dim3(512), size_t(NC) * Gh * sizeof(float2), s, pl->d_sqrtS,
                        pl->d_tw_h, V, Gh, Gw, log2h, H, NC, key0, key1,
                        uint32_t(frame0 + uint64_t(f0)));
     }

@@ -33,3 +33,11 @@ def random_coefficients(n, scale, seed):
     """Generic N(0, scale^2) float32 array of shape n (weights, test betas)."""
     rng = np.random.default_rng(seed + 104729)
     return (scale * rng.standard_normal(n)).astype(np.float32)
+
+
+def index_map(H, W, n, seed):
+    """Seeded int64 map (H, W) of row indices into an n-row table: gives a
+    full-size frame of per-pixel inputs (weights, coefficient vectors) from a
+    small random table."""
+    rng = np.random.default_rng(seed + 15485863)
+    return rng.integers(0, n, size=(H, W))

@@ -131,7 +131,7 @@ def test_render_bf16_matches_eq8_on_rounded_operands(t, basis):
     plan.render(torch.tensor(img, device="cuda"), bt, out)
     torch.cuda.synchronize()
     got = out.cpu().numpy()[0]
-    br = bt.float().cpu().numpy()[0, :, :, :100].astype(np.float64)
+    br = omlp.to_bf16(b[0].astype(np.float64))
     Pr = omlp.to_bf16(basis)
     for c in range(C):
         ref = orender.render_basis(img[0, c].astype(np.float64), br, Pr, 33)
@@ -145,7 +145,7 @@ def test_training_pairs_match_oracle(t, basis):
     torch.cuda.synchronize()
     A, _ = opsf.basis_draws(2000, seed=5, tag=philox.TAG_MLP_DATA)
     assert rel(z.cpu().numpy(), A) < 1e-6
-    ref = opsf.project(opsf.psf_batch(z.cpu().numpy().astype(np.float64), 64, 33), basis)
+    ref = opsf.project(opsf.psf_batch(A.astype(np.float32).astype(np.float64), 64, 33), basis)
     assert rel(b.cpu().numpy(), ref) < 1e-5
 
 

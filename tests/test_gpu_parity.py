@@ -132,11 +132,13 @@ def test_p2s_exact_matches_oracle(t, basis33):
     say("p2s exact 64x64x2 frames K=100")
     H = W = 64
     plan = t.Plan(H, W, 1, 128, 128, basis=basis33, psf_t=33)
-    zern = _sample(t, plan, [2.0, 5.0], 3, 0, 2)
+    # the oracle's own fields (D/r0 = 2 and 5) are the common input
+    z32 = np.stack([osamp.sample_zernike(H, W, 128, 128, 0.125, dr, 3, f)
+                    for f, dr in enumerate([2.0, 5.0])]).astype(np.float32)
+    z = z32.astype(np.float64)
     beta = torch.empty((2, H, W, 100), dtype=torch.float32, device="cuda")
-    plan.p2s(zern, beta, plan.workspace(2))
+    plan.p2s(torch.tensor(z32, device="cuda"), beta, plan.workspace(2))
     torch.cuda.synchronize()
-    z = zern.cpu().numpy().astype(np.float64)
     got = beta.cpu().numpy()
     for f in range(2):
         ref = opsf.psf_field(z[f], 64, 33, basis33)

@@ -198,3 +198,51 @@ def test_warp_sign_matches_psf_tilt():
     h = psf.crop(psf.psf_full(a, P, modes=range(2, 37)), T)
     peak = np.unravel_index(np.argmax(h), h.shape)
     assert peak == (T // 2, T // 2 - k)
+
+
+def test_render_at_constant_beta_and_delta():
+    """Eq. (8) at listed pixels: with beta constant it is one spatially
+    invariant convolution (scipy.ndimage.convolve, nearest), clamped borders
+    included; a delta image at p returns B(p + u) = h(u)."""
+    Tt, K = 9, 12
+    Psi = _basis(K, Tt, 7)
+    rng = np.random.default_rng(8)
+    img = rng.random((20, 23))
+    b = rng.standard_normal(K)
+    ys, xs = np.meshgrid(np.arange(20), np.arange(23), indexing='ij')
+    ys, xs = ys.ravel(), xs.ravel()
+    got = render.render_at(img, np.broadcast_to(b, (len(ys), K)), Psi, Tt, ys, xs)
+    ref = ndimage.convolve(img, (b @ Psi).reshape(Tt, Tt), mode='nearest')
+    np.testing.assert_allclose(got, ref.ravel(), atol=1e-12)
+    d = np.zeros((21, 21))
+    d[10, 10] = 1.0
+    py, px = np.meshgrid(np.arange(6, 15), np.arange(6, 15), indexing='ij')
+    got = render.render_at(d, np.broadcast_to(b, (81, K)), Psi, Tt, py.ravel(), px.ravel())
+    np.testing.assert_allclose(got.reshape(9, 9), (b @ Psi).reshape(Tt, Tt), atol=1e-12)
+
+
+def test_render_at_per_pixel_weights_match_gather():
+    """With per-pixel weights, each listed pixel equals the gather form
+    Eq. (1) with the projected PSF sum_m beta_m psi_m (linearity)."""
+    Tt, K = 7, 10
+    Psi = _basis(K, Tt, 9)
+    rng = np.random.default_rng(10)
+    img = rng.random((15, 11))
+    beta = rng.standard_normal((15, 11, K))
+    ref = render.render_gather(img, (beta @ Psi).reshape(15, 11, Tt, Tt), Tt)
+    ys = np.array([0, 0, 14, 14, 7, 3])
+    xs = np.array([0, 10, 0, 10, 5, 9])
+    got = render.render_at(img, beta[ys, xs], Psi, Tt, ys, xs)
+    np.testing.assert_allclose(got, ref[ys, xs], atol=1e-12)
+
+
+def test_warp_at_matches_library_shift():
+    """The bilinear warp at listed pixels against scipy.ndimage.shift
+    (order 1, nearest) for a constant displacement, borders included."""
+    rng = np.random.default_rng(11)
+    img = rng.random((17, 19))
+    ys, xs = np.meshgrid(np.arange(17), np.arange(19), indexing='ij')
+    for tx, ty in [(0.3, -0.7), (-1.25, 2.5), (3.0, -2.0)]:
+        got = render.warp_at(img, np.full(ys.size, tx), np.full(ys.size, ty), ys.ravel(), xs.ravel())
+        ref = ndimage.shift(img, (ty, tx), order=1, mode='nearest')
+        np.testing.assert_allclose(got, ref.ravel(), atol=1e-12)
