@@ -239,7 +239,7 @@ __global__ void k_draws(const float *__restrict__ Lmat, float *__restrict__ zvec
 constexpr int HID = 256;
 constexpr int IN_PAD = 48;   // 35 inputs padded to three 16-wide k-steps
 constexpr int ACT_LD = HID + 8;
-constexpr int IPX = 64;      // pixels per inference block (two 32-row tiles)
+constexpr int IPX = 128;     // pixels per inference block (four 32-row tiles)
 
 // erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7): the inference GELU
 __device__ __forceinline__ float erf_as(float x) {
@@ -254,12 +254,13 @@ __device__ __forceinline__ float gelu_fast(float z) {
   return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
 }
 
-// acc[t] (t < NT) = act[32 rows of tile mt][KSTEPS*16] x W[n0 + 32t + .][.]^T
+// acc[i][t] (i < 2, t < NT) = act[32 rows of tile i][KSTEPS*16] x W[n0 + 32t + .][.]^T:
+// each weight fragment feeds the two row tiles
 template <int NT, int KSTEPS>
 __device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__restrict__ W, int ldw,
-                                         int n0, f32x16 (&acc)[NT], int lane) {
+                                         int n0, f32x16 (&acc)[2][NT], int lane) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+  for (int t = 0; t < NT; ++t) acc[0][t] = acc[1][t] = f32x16{};
   const uint16_t *wrow = W + size_t(n0 + (lane & 31)) * ldw + 8 * (lane >> 5);
   const uint16_t *arow = act + (lane & 31) * ACT_LD + 8 * (lane >> 5);
   bf16x8 b[NT], bn[NT];
@@ -271,9 +272,13 @@ __device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__
 #pragma unroll
       for (int t = 0; t < NT; ++t) bn[t] = load8(wrow + size_t(t) * 32 * ldw + (s + 1) * 16);
     }
-    const bf16x8 a = load8(arow + s * 16);
+    const bf16x8 a0 = load8(arow + s * 16);
+    const bf16x8 a1 = load8(arow + 32 * ACT_LD + s * 16);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t], acc[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) {
+      acc[0][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b[t], acc[0][t], 0, 0, 0);
+      acc[1][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b[t], acc[1][t], 0, 0, 0);
+    }
     if (s + 1 < KSTEPS) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) b[t] = bn[t];
@@ -282,17 +287,19 @@ __device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__
 }
 
 template <int NT>
-__device__ __forceinline__ void mlp_store_gelu(uint16_t *act, const f32x16 (&acc)[NT],
+__device__ __forceinline__ void mlp_store_gelu(uint16_t *act, const f32x16 (&acc)[2][NT],
                                                const float *__restrict__ bias, int n0, int lane) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int n = n0 + t * 32 + (lane & 31);
     const float bn = bias[n];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      act[m * ACT_LD + n] = f2bf(gelu_fast(acc[t][r] + bn));
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        act[m * ACT_LD + n] = f2bf(gelu_fast(acc[i][t][r] + bn));
+      }
   }
 }
 
@@ -306,32 +313,33 @@ struct InferParams {
   int out_bf16;
 };
 
-// Block: 64 pixels, 4 waves.  Wave w computes rows of tile (w & 1) and the
-// output columns [128 (w >> 1), +128) of each hidden layer (64 for the last).
+// Block: 128 pixels, 4 waves.  Wave w computes rows 64 (w >> 1) .. +63 (two
+// 32-row tiles) and the output columns [128 (w & 1), +128) of each hidden
+// layer (64 for the last), activations in place in LDS between layers.
 __global__ void __launch_bounds__(256)
 k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip, void *__restrict__ beta) {
   __shared__ __attribute__((aligned(16))) uint16_t act_all[IPX * ACT_LD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int mt = w & 1, nh = w >> 1;
-  uint16_t *act = act_all + mt * 32 * ACT_LD;
+  const int mp = w >> 1, nh = w & 1;
+  uint16_t *act = act_all + mp * 64 * ACT_LD;
   const size_t pb = size_t(blockIdx.x) * IPX;
   {
-    // inputs: thread -> pixel (tid % 64), modes [12 (tid / 64), +12)
-    const int px = threadIdx.x & 63, j0 = (threadIdx.x >> 6) * 12;
+    // inputs: thread -> pixel (tid % 128), modes [24 (tid / 128), +24)
+    const int px = threadIdx.x & 127, j0 = (threadIdx.x >> 7) * 24;
     const size_t p = pb + px;
     const bool ok = p < n_pix;
     const size_t pc = ok ? p : 0;
     const size_t fr = pc / size_t(hw), yx = pc - fr * size_t(hw);
     const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
+    for (int q = 0; q < 24; ++q) {
       const int j = j0 + q;
       const float v = (ok && j < TSIM_N_MODES) ? zp[size_t(j) * hw] * ip.inv_s[j] : 0.f;
       act_all[px * ACT_LD + j] = f2bf(v);
     }
   }
   __syncthreads();
-  f32x16 acc[4];
+  f32x16 acc[2][4];
   mlp_tile<4, IN_PAD / 16>(act, ip.W1, IN_PAD, nh * 128, acc, lane);
   __syncthreads();
   mlp_store_gelu<4>(act, acc, ip.b1, nh * 128, lane);
@@ -344,7 +352,7 @@ k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip
   __syncthreads();
   mlp_store_gelu<4>(act, acc, ip.b3, nh * 128, lane);
   __syncthreads();
-  f32x16 acc2[2];
+  f32x16 acc2[2][2];
   mlp_tile<2, HID / 16>(act, ip.W4, HID, nh * 64, acc2, lane);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -353,16 +361,18 @@ k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip
     const bool real = n < ip.K;
     const float bn = real ? ip.b4[n] : 0.f, mun = real ? ip.mu[n] : 0.f;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      const size_t p = pb + mt * 32 + m;
-      if (p >= n_pix) continue;
-      const float y = real ? (acc2[t][r] + bn) * ip.s_out + mun : 0.f;
-      if (ip.out_bf16)
-        static_cast<uint16_t *>(beta)[p * ip.KB + n] = f2bf(y);
-      else
-        static_cast<float *>(beta)[p * ip.KB + n] = y;
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const size_t p = pb + mp * 64 + m;
+        if (p >= n_pix) continue;
+        const float y = real ? (acc2[i][t][r] + bn) * ip.s_out + mun : 0.f;
+        if (ip.out_bf16)
+          static_cast<uint16_t *>(beta)[p * ip.KB + n] = f2bf(y);
+        else
+          static_cast<float *>(beta)[p * ip.KB + n] = y;
+      }
   }
 }
 

@@ -3,12 +3,13 @@
 //
 // Block = 8 x 16 output pixels, 4 waves; wave w owns the 32 pixels of rows
 // 2w, 2w+1.  For each block of 32 taps the matrix cores form
-// htilde^T[32 taps][32 px] = psi (BF16, rows = taps) x beta^T (BF16), FP32
-// accumulation, so every lane owns ONE pixel (column) and 16 of the 32 taps
-// (rows): it multiplies them by the image samples I(x - u) read from the LDS
-// tile and keeps just C running sums.  Tap blocks are software-pipelined:
-// the psi fragments of block t+2 are in flight and the products of block
-// t+1 are issued while the epilogue of block t runs.
+// htilde[32 px][32 taps] = beta (BF16, rows = pixels) x psi^T (BF16), FP32
+// accumulation, so every lane owns ONE tap (column) for 16 of the 32 pixels:
+// it multiplies them by the image samples I(x - u) read from the LDS tile at
+// compile-time offsets from a per-lane base and keeps C x 16 running sums,
+// summed over the lanes once at the end.  Tap blocks are software-
+// pipelined: the psi fragments of block t+2 are in flight and the products
+// of block t+1 are issued while the epilogue of block t runs.
 #include <algorithm>
 
 #include "common.cuh"
@@ -23,17 +24,16 @@ __device__ __forceinline__ bf16x8 ld_bf8g(const uint16_t *p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
 }
 
-template <int KS, int T>
+template <int KS, int T, int C>
 __global__ void __launch_bounds__(256)
 k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
               const uint16_t *__restrict__ psi /*[ntiles*32][KS*16]*/, float *__restrict__ out,
-              int H, int W, int C) {
+              int H, int W) {
   constexpr int TH = 8, TW = 16, KB = KS * 16;
   constexpr int R = (T - 1) / 2;
   constexpr int SH = TH + T - 1, SW = TW + T - 1, PLANE = SH * SW;
   constexpr int NT = (T * T + 31) / 32;
   extern __shared__ float tile[];             // [C][SH][SW]
-  __shared__ short offtab[NT * 32];           // tap -> uy * SW + ux (0 for padded taps)
   const int f = blockIdx.z;
   const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
   const float *imf = img + size_t(f) * C * H * W;
@@ -45,56 +45,61 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
     const int gx = min(max(tx0 + sx - R, 0), W - 1);
     tile[e] = imf[(size_t(c) * H + gy) * W + gx];
   }
-  for (int e = threadIdx.x; e < NT * 32; e += 256) {
-    const int uy = e / T - R, ux = e % T - R;
-    offtab[e] = (e < T * T) ? uy * SW + ux : 0;
-  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int pn = lane & 31;                   // this lane's pixel within the wave
-  const int py = 2 * w + (pn >> 4), px = pn & 15;
-  const int y = ty0 + py, x = tx0 + px;
-  const bool ok = (y < H) && (x < W);
+  const int pn = lane & 31, g = lane >> 5;
+  // A operand: beta of pixel pn of the wave (rows 2w, 2w+1 of the block)
   bf16x8 b[KS];
   {
-    const uint16_t *bp = beta + ((size_t(f) * H + (ok ? y : 0)) * W + (ok ? x : 0)) * KB + 8 * (lane >> 5);
+    const int py = 2 * w + (pn >> 4), px = pn & 15;
+    const int y = ty0 + py, x = tx0 + px;
+    const bool ok = (y < H) && (x < W);
+    const uint16_t *bp = beta + ((size_t(f) * H + (ok ? y : 0)) * W + (ok ? x : 0)) * KB + 8 * g;
 #pragma unroll
     for (int s = 0; s < KS; ++s) b[s] = ok ? ld_bf8g(bp + 16 * s) : bf16x8{};
   }
-  const int pbase = (py + R) * SW + px + R;
-  const uint16_t *prow = psi + size_t(pn) * KB + 8 * (lane >> 5);  // + t*32*KB
-  // tap rows of the accumulator owned by this lane: m_r = 8(r/4) + 4(lane/32) + r%4
-  const int mrow = 4 * (lane >> 5);
+  // B operand: psi^T column = tap pn of the 32-tap block, k-slice 8g..8g+7
+  const uint16_t *prow = psi + size_t(pn) * KB + 8 * g;  // + t*32*KB
+  // the lane's accumulator rows are pixels m_r + 4g, m_r = 8(r/4) + r%4: all in
+  // one tile row, so pixel position = wave base + 4g + (compile-time part)
+  const int pbase = (2 * w + R) * SW + R + 4 * g;
   __syncthreads();
 
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  float sum[C][16];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sum[c][r] = 0.f;
   auto epilogue = [&](const f32x16 &acc, int t) {
-    const short *ot = offtab + 32 * t + mrow;
+    // this lane's tap u = 32t + pn, offset (uy - R) SW + (ux - R); padded taps carry 0
+    const int u = 32 * t + pn;
+    const int uy = u / T, ux = u - uy * T;
+    const int lb = pbase - ((u < T * T) ? (uy - R) * SW + (ux - R) : 0);
+    const float *tl = tile + lb;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int idx = pbase - ot[8 * (r >> 2) + (r & 3)];
+      const int m = 8 * (r >> 2) + (r & 3);
+      const int o = (m >> 4) * SW + (m & 15);
       const float v = acc[r];
-      s0 = fmaf(v, tile[idx], s0);
-      if (C > 1) s1 = fmaf(v, tile[PLANE + idx], s1);
-      if (C > 2) s2 = fmaf(v, tile[2 * PLANE + idx], s2);
-      if (C > 3) s3 = fmaf(v, tile[3 * PLANE + idx], s3);
+#pragma unroll
+      for (int c = 0; c < C; ++c) sum[c][r] = fmaf(v, tl[c * PLANE + o], sum[c][r]);
     }
   };
-  bf16x8 pa[KS], pb[KS];
+  bf16x8 pa[KS], pq[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) pa[s] = ld_bf8g(prow + 16 * s);
   f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
-  for (int s = 0; s < KS; ++s) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pa[s], b[s], acc0, 0, 0, 0);
+  for (int s = 0; s < KS; ++s) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[s], pa[s], acc0, 0, 0, 0);
   if (NT > 1) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) pb[s] = ld_bf8g(prow + size_t(32) * KB + 16 * s);
+    for (int s = 0; s < KS; ++s) pq[s] = ld_bf8g(prow + size_t(32) * KB + 16 * s);
   }
   for (int t = 0; t < NT; t += 2) {
     // block t+1: products (its psi was loaded an iteration earlier); block t+2: loads
     if (t + 1 < NT) {
       acc1 = f32x16{};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pb[s], b[s], acc1, 0, 0, 0);
+      for (int s = 0; s < KS; ++s) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[s], pq[s], acc1, 0, 0, 0);
     }
     if (t + 2 < NT) {
 #pragma unroll
@@ -105,27 +110,38 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
       if (t + 2 < NT) {
         acc0 = f32x16{};
 #pragma unroll
-        for (int s = 0; s < KS; ++s) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pa[s], b[s], acc0, 0, 0, 0);
+        for (int s = 0; s < KS; ++s) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[s], pa[s], acc0, 0, 0, 0);
       }
       if (t + 3 < NT) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) pb[s] = ld_bf8g(prow + size_t(32 * (t + 3)) * KB + 16 * s);
+        for (int s = 0; s < KS; ++s) pq[s] = ld_bf8g(prow + size_t(32 * (t + 3)) * KB + 16 * s);
       }
       epilogue(acc1, t + 1);
     }
   }
-  // lanes l and l + 32 hold the same pixel (different taps)
-  s0 += __shfl_xor(s0, 32);
-  s1 += __shfl_xor(s1, 32);
-  s2 += __shfl_xor(s2, 32);
-  s3 += __shfl_xor(s3, 32);
-  if (lane < 32 && ok) {
-    float *of = out + size_t(f) * C * H * W + size_t(y) * W + x;
-    const size_t pl = size_t(H) * W;
-    of[0] = s0;
-    if (C > 1) of[pl] = s1;
-    if (C > 2) of[2 * pl] = s2;
-    if (C > 3) of[3 * pl] = s3;
+  // the 32 lanes of a half hold the 32 taps-columns of the same 16 pixels: sum them
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      float v = sum[c][r];
+#pragma unroll
+      for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+      sum[c][r] = v;
+    }
+  }
+  // lane pn < 16 of each half writes pixel m_pn + 4g
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (pn != r) continue;
+    const int m = 8 * (r >> 2) + (r & 3) + 4 * g;
+    const int y = ty0 + 2 * w + (m >> 4), x = tx0 + (m & 15);
+    if (y < H && x < W) {
+      float *of = out + size_t(f) * C * H * W + size_t(y) * W + x;
+      const size_t pl = size_t(H) * W;
+#pragma unroll
+      for (int c = 0; c < C; ++c) of[c * pl] = sum[c][r];
+    }
   }
 }
 
@@ -232,16 +248,28 @@ int prepare_lds(Kern kern, size_t lds, int T) {
   return TSIM_OK;
 }
 
+template <int KS, int T, int C>
+int launch_ks_tc(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta, float *out,
+                 hipStream_t s) {
+  const int H = pl->H, W = pl->W;
+  dim3 grid((W + 15) / 16, (H + 7) / 8, frames);
+  const size_t lds = size_t(C) * (8 + T - 1) * (16 + T - 1) * sizeof(float);
+  const int st = prepare_lds(k_render_bf16<KS, T, C>, lds, T);
+  if (st != TSIM_OK) return st;
+  hipLaunchKernelGGL((k_render_bf16<KS, T, C>), grid, dim3(256), lds, s, img, beta, pl->d_basis_bf, out, H, W);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
 template <int KS, int T>
 int launch_ks_t(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta, float *out,
                 hipStream_t s) {
-  const int H = pl->H, W = pl->W, C = pl->C;
-  dim3 grid((W + 15) / 16, (H + 7) / 8, frames);
-  const size_t lds = size_t(C) * (8 + T - 1) * (16 + T - 1) * sizeof(float);
-  const int st = prepare_lds(k_render_bf16<KS, T>, lds, T);
-  if (st != TSIM_OK) return st;
-  hipLaunchKernelGGL((k_render_bf16<KS, T>), grid, dim3(256), lds, s, img, beta, pl->d_basis_bf, out, H, W, C);
-  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+  switch (pl->C) {
+    case 1: return launch_ks_tc<KS, T, 1>(pl, frames, img, beta, out, s);
+    case 2: return launch_ks_tc<KS, T, 2>(pl, frames, img, beta, out, s);
+    case 3: return launch_ks_tc<KS, T, 3>(pl, frames, img, beta, out, s);
+    case 4: return launch_ks_tc<KS, T, 4>(pl, frames, img, beta, out, s);
+    default: return TSIM_EUNSUPPORTED;
+  }
 }
 
 template <int KS>
