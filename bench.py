@@ -78,6 +78,9 @@ def kernel_work(name, frames, s):
         return "alu", px * (2 * k * t * t + 2 * c * t * t), "flop"
     if name == "k_warp":
         return "hbm", px * (8 + 4 * c + 4 * c), "B"
+    if name == "k_ar_scan":
+        # read each fresh frame and write the correlated one, 35 planes
+        return "hbm", px * 2 * 35 * 4, "B"
     if name == "k_mlp_infer":
         return "mfma", px * 2 * (35 * 256 + 2 * 256 * 256 + 256 * k), "flop"
     if name == "k_render_bf16":
@@ -330,6 +333,40 @@ def psnr(a, b):
     return round(10 * math.log10(1.0 / mse), 2) if mse > 0 else None
 
 
+def ar_sequence(tsim, torch, wl, s, steps):
+    """Temporally correlated frames (auto-regression, alpha = 0.95) in
+    6-frame chunks, each chunk continuing from the previous one's last frame:
+    sampler + scan per chunk."""
+    pl = tsim.Plan(s["H"], s["W"], s["C"], s["G"], s["G"], pixel_pitch_over_d=PITCH)
+    n = s["chunk"]
+    ws = pl.workspace(n)
+    prev = torch.zeros_like(wl.zern[0])
+    drs = [s["drs"][0]] * n
+
+    def chunk(i):
+        pl.sample_zernike_ar(drs, 0, i * n, 0.95, wl.zern, ws, zern_prev=prev, d_over_r0_prev=drs[0])
+        prev.copy_(wl.zern[n - 1])
+
+    chunk(0)
+    torch.cuda.synchronize()
+    tsim.trace_enable(True)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(steps):
+        chunk(1 + i)
+    b.record()
+    torch.cuda.synchronize()
+    rep = tsim.trace_report()
+    tsim.trace_enable(False)
+    kern, roof = summarize(rep, steps, n, s, traffic=False)
+    ms = a.elapsed_time(b) / steps
+    pl.close()
+    return {"workload": f"{n} frames per chunk, alpha 0.95, continuing chunk to chunk",
+            "value": round(n * s["H"] * s["W"] / (ms * 1e-3) / 1e6, 3), "unit": "Mpixel/s",
+            "ms_per_chunk": round(ms, 3), "kernels": kern}
+
+
 def large_frame(tsim, torch, np, synthetic, dev, args):
     """3840 x 2160 x 3 frames, D/r0 = 3, 4096^2 grid, 128 x 128 pupil, K = 100
     basis of 65 x 65 kernels: a 30-frame sequence of independent draws per
@@ -379,6 +416,7 @@ def large_frame(tsim, torch, np, synthetic, dev, args):
         out["learned_bf16"] = learned
         del beta16, net
         plan_l.close()
+        out["ar_sequence"] = ar_sequence(tsim, torch, wl, s, args.steps)
     return out
 
 

@@ -136,6 +136,27 @@ int tsim_sample_zernike(const tsim_plan *plan, int frames, const float *d_over_r
                         uint64_t seed, uint64_t frame0, float *zern, void *ws,
                         tsim_stream stream);
 
+/* (a') Temporally correlated Zernike fields by an auto-regressive process,
+ * the low-order workaround the paper gives for spatio-temporal correlation
+ * (Sec. IV-A): the unit-variance fields of frame t follow
+ *   ybar_t = alpha ybar_{t-1} + sqrt(1 - alpha^2) w_t,
+ * with w_t the independent fields tsim_sample_zernike draws for frame
+ * frame0 + t, and frame t is mixed with its own (D/r0_t)^{5/6} L.  Each
+ * field keeps its spatial statistics; frames t and t + k correlate by
+ * alpha^k.  Computed on the mixed fields as
+ *   a_t = alpha (s_t / s_{t-1}) a_{t-1} + sqrt(1 - alpha^2) a_t^new,
+ * s = (D/r0)^{5/6}, which is the same recursion.
+ *   alpha          : in [0, 1]
+ *   zern_prev      : device [35][H][W] float32, the coefficients of the frame
+ *                    before frame0, or NULL to start the sequence from
+ *                    frame0's own (already stationary) draw; must not
+ *                    overlap zern
+ *   d_over_r0_prev : that frame's D/r0 (> 0; ignored when zern_prev is NULL)
+ *   other arguments as tsim_sample_zernike (same workspace size). */
+int tsim_sample_zernike_ar(const tsim_plan *plan, int frames, const float *d_over_r0,
+                           uint64_t seed, uint64_t frame0, float alpha, const float *zern_prev,
+                           float d_over_r0_prev, float *zern, void *ws, tsim_stream stream);
+
 /* (b) Basis weights beta[f][y][x][k] from Zernike fields (Sec. II-C).
  *   Exact mode: the per-pixel PSF of Eq. (2) from modes 4..36 on the P x P
  *   pupil, cropped to T x T around the zero frequency and normalised to unit

@@ -95,6 +95,32 @@ def sample_zernike(H, W, Gh, Gw, ds, d_over_r0, seed, frame, fold=2, spectra=Non
     return mix(y, L, d_over_r0)
 
 
+def sample_sequence_ar(H, W, Gh, Gw, ds, d_over_r0s, seed, frame0, alpha, y_prev=None, fold=2,
+                       spectra=None, L=None):
+    """Temporally correlated frames by an auto-regressive process (the
+    workaround the paper gives for spatio-temporal correlation, Sec. IV-A):
+    the unit-variance fields follow ybar_t = alpha ybar_{t-1} +
+    sqrt(1 - alpha^2) w_t, where w_t are frame (frame0 + t)'s own independent
+    unit fields, and frame t is mixed with its own (D/r0)^{5/6} L.  Each field
+    keeps its spatial correlation and unit variance, and fields of frames
+    t and t + k correlate by alpha^k.  ``y_prev`` holds the unit fields of the
+    frame before the first (None: the sequence starts from its first draw,
+    which is already stationary).  Returns (frames (F, 35, H, W), the last
+    frame's unit fields)."""
+    if spectra is None:
+        spectra = all_spectra(Gh, Gw, ds, fold)
+    if L is None:
+        L = cholesky_lower(noll_matrix(1.0))
+    c = np.sqrt(1.0 - alpha * alpha)
+    y = y_prev
+    out = []
+    for t, dr in enumerate(d_over_r0s):
+        w = unit_fields(spectra, H, W, frame0 + t, seed)
+        y = w if y is None else alpha * y + c * w
+        out.append(mix(y, L, dr))
+    return np.stack(out), y
+
+
 # ----------------------------------------------------------------------------
 # Exact covariance of the sampler (Eq. (9)) and the full tensor on tiny grids
 # ----------------------------------------------------------------------------

@@ -57,6 +57,8 @@ _lib_ws = _sig("tsim_workspace_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_siz
 _lib_table = _sig("tsim_plan_table", _i, [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
 _lib_sample = _sig("tsim_sample_zernike", _i,
                    [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64, _vp, _vp, _vp])
+_lib_sample_ar = _sig("tsim_sample_zernike_ar", _i, [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64,
+                                                     ctypes.c_float, _vp, ctypes.c_float, _vp, _vp, _vp])
 _lib_p2s = _sig("tsim_p2s", _i, [_vp, _i, _vp, _vp, _vp, _vp])
 _lib_render = _sig("tsim_render", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp])
 _lib_warp = _sig("tsim_warp", _i, [_vp, _i, _vp, _vp, _vp, _vp])
@@ -88,7 +90,7 @@ _lib_host_tables = _sig("tsim_host_tables", _i,
                         [ctypes.POINTER(_Params), _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
 
 EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "tsim_plan_table",
-            "tsim_sample_zernike", "tsim_p2s", "tsim_render", "tsim_warp", "tsim_psf_exact",
+            "tsim_sample_zernike", "tsim_sample_zernike_ar", "tsim_p2s", "tsim_render", "tsim_warp", "tsim_psf_exact",
             "tsim_status_string", "tsim_host_tables", "tsim_basis_build", "tsim_trace_enable",
             "tsim_trace_count", "tsim_trace_get", "tsim_mlp_create", "tsim_mlp_destroy",
             "tsim_mlp_param_count", "tsim_mlp_layout", "tsim_mlp_get", "tsim_mlp_set",
@@ -240,6 +242,18 @@ class Plan:
         _check(_lib_sample(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                            int(seed), int(frame0), _ptr(zern), _ptr(ws), _stream(stream)),
                "tsim_sample_zernike")
+
+    def sample_zernike_ar(self, d_over_r0, seed, frame0, alpha, zern, ws, zern_prev=None,
+                          d_over_r0_prev=0.0, stream=None):
+        """Auto-regressively correlated frames (tsim_sample_zernike_ar)."""
+        d = np.ascontiguousarray(np.atleast_1d(d_over_r0), dtype=np.float32)
+        frames = zern.shape[0]
+        if d.size != frames:
+            raise ValueError("one D/r0 per frame expected")
+        _check(_lib_sample_ar(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                              int(seed), int(frame0), float(alpha), _ptr(zern_prev),
+                              float(d_over_r0_prev), _ptr(zern), _ptr(ws), _stream(stream)),
+               "tsim_sample_zernike_ar")
 
     def p2s(self, zern, beta, ws, stream=None):
         _check(_lib_p2s(self._h, zern.shape[0], _ptr(zern), _ptr(beta), _ptr(ws), _stream(stream)),

@@ -40,6 +40,33 @@ int tsim_sample_zernike(const tsim_plan *pl, int frames, const float *d_over_r0,
                         static_cast<hipStream_t>(stream));
 }
 
+int tsim_sample_zernike_ar(const tsim_plan *pl, int frames, const float *d_over_r0, uint64_t seed,
+                           uint64_t frame0, float alpha, const float *zern_prev, float d_over_r0_prev,
+                           float *zern, void *ws, tsim_stream stream) {
+  if (!frames_ok(pl, frames) || !d_over_r0 || !zern || !ws) return TSIM_EINVAL;
+  if (!aligned(zern) || !aligned(ws)) return TSIM_EINVAL;
+  if (!(alpha >= 0.f && alpha <= 1.f)) return TSIM_EINVAL;
+  if (frame0 + uint64_t(frames) > (uint64_t(1) << 32)) return TSIM_EINVAL;
+  float sprev = 1.f;
+  if (zern_prev) {
+    if (!aligned(zern_prev)) return TSIM_EINVAL;
+    if (!(d_over_r0_prev > 0.f) || !std::isfinite(d_over_r0_prev)) return TSIM_EINVAL;
+    const size_t plane = size_t(TSIM_N_MODES) * pl->H * pl->W * sizeof(float);
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(zern), a1 = a0 + plane * size_t(frames);
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(zern_prev), b1 = b0 + plane;
+    if (b0 < a1 && a0 < b1) return TSIM_EINVAL;  // overlap
+    sprev = float(std::pow(double(d_over_r0_prev), 5.0 / 6.0));
+  }
+  std::vector<float> scale(static_cast<size_t>(frames));
+  for (int f = 0; f < frames; ++f) {
+    double v = d_over_r0[f];
+    if (!(v > 0.0) || !std::isfinite(v)) return TSIM_EINVAL;
+    scale[f] = float(std::pow(v, 5.0 / 6.0));
+  }
+  return launch_sampler_ar(pl, frames, scale.data(), alpha, zern_prev, sprev, seed, frame0, zern, ws,
+                           static_cast<hipStream_t>(stream));
+}
+
 int tsim_p2s(const tsim_plan *pl, int frames, const float *zern, void *beta, void *ws,
              tsim_stream stream) {
   if (!frames_ok(pl, frames) || !zern || !beta || !ws) return TSIM_EINVAL;

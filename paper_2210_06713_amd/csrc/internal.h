@@ -61,6 +61,9 @@ class TraceScope {
 int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
                    uint64_t frame0, float *zern, void *ws, hipStream_t s);
 size_t sampler_ws_bytes(const tsim_plan *pl, int frames);
+int launch_sampler_ar(const tsim_plan *pl, int frames, const float *scale_host, float alpha,
+                      const float *zern_prev, float scale_prev, uint64_t seed, uint64_t frame0,
+                      float *zern, void *ws, hipStream_t s);
 
 // ---- launchers (psf.hip) ----
 int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, hipStream_t s);

@@ -47,9 +47,13 @@ __device__ __forceinline__ float gelu_grad(float z) {
          z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-__device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
-  uint4 u = *reinterpret_cast<const uint4 *>(p);
-  return __builtin_bit_cast(bf16x8, u);
+// Fragments stay four 32-bit words until the matrix-core call: copies of
+// 8 x bf16 vectors otherwise get split into 16-bit lanes and re-packed.
+__device__ __forceinline__ uint4 load8(const uint16_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+__device__ __forceinline__ f32x16 mfma_bf16(const uint4 &a, const uint4 &b, const f32x16 &c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                 c, 0, 0, 0);
 }
 
 enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_GELU_GRAD = 3, EPI_F32_ADD = 4 };
@@ -85,9 +89,9 @@ k_gemm_bf16(const uint16_t *__restrict__ A, long sam, long sak, const uint16_t *
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 16) {
-      bf16x8 a = load8(&As[wm * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
-      bf16x8 b = load8(&Bs[wn * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      const uint4 a = load8(&As[wm * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+      const uint4 b = load8(&Bs[wn * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+      acc = mfma_bf16(a, b, acc);
     }
     __syncthreads();
   }
@@ -263,7 +267,7 @@ __device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__
   for (int t = 0; t < NT; ++t) acc[0][t] = acc[1][t] = f32x16{};
   const uint16_t *wrow = W + size_t(n0 + (lane & 31)) * ldw + 8 * (lane >> 5);
   const uint16_t *arow = act + (lane & 31) * ACT_LD + 8 * (lane >> 5);
-  bf16x8 b[NT], bn[NT];
+  uint4 b[NT], bn[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) b[t] = load8(wrow + size_t(t) * 32 * ldw);
 #pragma unroll
@@ -272,12 +276,12 @@ __device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__
 #pragma unroll
       for (int t = 0; t < NT; ++t) bn[t] = load8(wrow + size_t(t) * 32 * ldw + (s + 1) * 16);
     }
-    const bf16x8 a0 = load8(arow + s * 16);
-    const bf16x8 a1 = load8(arow + 32 * ACT_LD + s * 16);
+    const uint4 a0 = load8(arow + s * 16);
+    const uint4 a1 = load8(arow + 32 * ACT_LD + s * 16);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      acc[0][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b[t], acc[0][t], 0, 0, 0);
-      acc[1][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b[t], acc[1][t], 0, 0, 0);
+      acc[0][t] = mfma_bf16(a0, b[t], acc[0][t]);
+      acc[1][t] = mfma_bf16(a1, b[t], acc[1][t]);
     }
     if (s + 1 < KSTEPS) {
 #pragma unroll

@@ -20,8 +20,14 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ bf16x8 ld_bf8g(const uint16_t *p) {
-  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
+// Fragments are kept as four 32-bit words and reinterpreted only at the
+// matrix-core call: copies of 8 x bf16 vectors between pipeline stages
+// otherwise get split into 16-bit lanes and re-packed with byte permutes.
+__device__ __forceinline__ uint4 ld_frag(const uint16_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+__device__ __forceinline__ f32x16 mfma_bf16(const uint4 &a, const uint4 &b, const f32x16 &c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                 c, 0, 0, 0);
 }
 
 template <int KS, int T, int C>
@@ -48,14 +54,14 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pn = lane & 31, g = lane >> 5;
   // A operand: beta of pixel pn of the wave (rows 2w, 2w+1 of the block)
-  bf16x8 b[KS];
+  uint4 b[KS];
   {
     const int py = 2 * w + (pn >> 4), px = pn & 15;
     const int y = ty0 + py, x = tx0 + px;
     const bool ok = (y < H) && (x < W);
     const uint16_t *bp = beta + ((size_t(f) * H + (ok ? y : 0)) * W + (ok ? x : 0)) * KB + 8 * g;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) b[s] = ok ? ld_bf8g(bp + 16 * s) : bf16x8{};
+    for (int s = 0; s < KS; ++s) b[s] = ok ? ld_frag(bp + 16 * s) : make_uint4(0u, 0u, 0u, 0u);
   }
   // B operand: psi^T column = tap pn of the 32-tap block, k-slice 8g..8g+7
   const uint16_t *prow = psi + size_t(pn) * KB + 8 * g;  // + t*32*KB
@@ -84,37 +90,37 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
       for (int c = 0; c < C; ++c) sum[c][r] = fmaf(v, tl[c * PLANE + o], sum[c][r]);
     }
   };
-  bf16x8 pa[KS], pq[KS];
+  uint4 pa[KS], pq[KS];
 #pragma unroll
-  for (int s = 0; s < KS; ++s) pa[s] = ld_bf8g(prow + 16 * s);
+  for (int s = 0; s < KS; ++s) pa[s] = ld_frag(prow + 16 * s);
   f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
-  for (int s = 0; s < KS; ++s) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[s], pa[s], acc0, 0, 0, 0);
+  for (int s = 0; s < KS; ++s) acc0 = mfma_bf16(b[s], pa[s], acc0);
   if (NT > 1) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) pq[s] = ld_bf8g(prow + size_t(32) * KB + 16 * s);
+    for (int s = 0; s < KS; ++s) pq[s] = ld_frag(prow + size_t(32) * KB + 16 * s);
   }
   for (int t = 0; t < NT; t += 2) {
     // block t+1: products (its psi was loaded an iteration earlier); block t+2: loads
     if (t + 1 < NT) {
       acc1 = f32x16{};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[s], pq[s], acc1, 0, 0, 0);
+      for (int s = 0; s < KS; ++s) acc1 = mfma_bf16(b[s], pq[s], acc1);
     }
     if (t + 2 < NT) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s) pa[s] = ld_bf8g(prow + size_t(32 * (t + 2)) * KB + 16 * s);
+      for (int s = 0; s < KS; ++s) pa[s] = ld_frag(prow + size_t(32 * (t + 2)) * KB + 16 * s);
     }
     epilogue(acc0, t);
     if (t + 1 < NT) {
       if (t + 2 < NT) {
         acc0 = f32x16{};
 #pragma unroll
-        for (int s = 0; s < KS; ++s) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[s], pa[s], acc0, 0, 0, 0);
+        for (int s = 0; s < KS; ++s) acc0 = mfma_bf16(b[s], pa[s], acc0);
       }
       if (t + 3 < NT) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) pq[s] = ld_bf8g(prow + size_t(32 * (t + 3)) * KB + 16 * s);
+        for (int s = 0; s < KS; ++s) pq[s] = ld_frag(prow + size_t(32 * (t + 3)) * KB + 16 * s);
       }
       epilogue(acc1, t + 1);
     }

@@ -271,6 +271,31 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
   FieldSteps<0, PX, NT>::run(a, acc);
 }
 
+// Temporal auto-regression on the mixed fields, in place over a chunk of
+// frames: a_f = mul_f a_{f-1} + c a_f^new (mul_f = alpha s_f / s_{f-1}); the
+// frame before the chunk comes from `prev` (NULL at the start of a sequence:
+// frame 0 keeps its own draw).  One thread per (mode, pixel) element, frames
+// in order; every access is a coalesced stream over the planes.
+struct ArCoefs {
+  float mul[kMaxFramesPerLaunch];
+};
+
+__global__ void __launch_bounds__(256)
+k_ar_scan(float *__restrict__ zern, const float *__restrict__ prev, size_t plane, int nf, ArCoefs co,
+          float c) {
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < plane;
+       e += size_t(gridDim.x) * blockDim.x) {
+    float a = prev ? prev[e] : 0.f;
+    for (int f = 0; f < nf; ++f) {
+      float *p = zern + size_t(f) * plane + e;
+      const float nw = *p;
+      const float v = (f == 0 && !prev) ? nw : fmaf(co.mul[f], a, c * nw);
+      *p = v;
+      a = v;
+    }
+  }
+}
+
 int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -331,6 +356,32 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     else
       hipLaunchKernelGGL((k_sampler_rows_mix<4, 1024>), g2, dim3(1024), lds, s, V, pl->d_tw_w, pl->d_L,
                          zern, Gw, log2w, H, W, sc, f0);
+    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+  }
+  return TSIM_OK;
+}
+
+int launch_sampler_ar(const tsim_plan *pl, int frames, const float *scale_host, float alpha,
+                      const float *zern_prev, float scale_prev, uint64_t seed, uint64_t frame0,
+                      float *zern, void *ws, hipStream_t s) {
+  int st = launch_sampler(pl, frames, scale_host, seed, frame0, zern, ws, s);
+  if (st != TSIM_OK) return st;
+  const size_t plane = size_t(TSIM_N_MODES) * pl->H * pl->W;
+  const float c = sqrtf(fmaxf(0.f, 1.f - alpha * alpha));
+  const unsigned blocks = unsigned(std::min<size_t>((plane + 255) / 256, size_t(1) << 20));
+  for (int f0 = 0; f0 < frames; f0 += kMaxFramesPerLaunch) {
+    const int nf = std::min(kMaxFramesPerLaunch, frames - f0);
+    ArCoefs co;
+    for (int i = 0; i < kMaxFramesPerLaunch; ++i) co.mul[i] = 0.f;
+    for (int i = 0; i < nf; ++i) {
+      const int g = f0 + i;
+      const float sp = g > 0 ? scale_host[g - 1] : scale_prev;
+      co.mul[i] = (g > 0 || zern_prev) ? alpha * scale_host[g] / sp : 0.f;
+    }
+    const float *prev = f0 > 0 ? zern + size_t(f0 - 1) * plane : zern_prev;
+    TraceScope tr("k_ar_scan", s);
+    hipLaunchKernelGGL(k_ar_scan, dim3(blocks), dim3(256), 0, s, zern + size_t(f0) * plane, prev, plane, nf,
+                       co, c);
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
   }
   return TSIM_OK;

@@ -260,3 +260,40 @@ def test_basis_build_matches_oracle_pca(t):
     cap_g = np.linalg.norm(X @ Psi_g.T) ** 2
     cap_o = np.linalg.norm(X @ Psi_o.T) ** 2
     assert abs(cap_g - cap_o) / cap_o < 1e-8
+
+
+def test_sampler_ar_matches_oracle(t):
+    """Auto-regressive sequence (alpha = 0.9, per-frame D/r0): five frames from
+    a fresh start, then three more continuing from the oracle's own last
+    frame, against the oracle's recursion on the unit fields."""
+    say("sampler AR 40x56 G=128")
+    H, W, G = 40, 56, 128
+    plan = t.Plan(H, W, 1, G, G, pixel_pitch_over_d=0.125)
+    S = ospec.all_spectra(G, G, 0.125, 2)
+    L = ozern.cholesky_lower(ozern.noll_matrix(1.0))
+    drs = [1.0, 2.0, 3.5, 2.5, 4.0]
+    ref, ylast = osamp.sample_sequence_ar(H, W, G, G, 0.125, drs, 7, 20, 0.9, spectra=S, L=L)
+    zern = torch.empty((5, 35, H, W), dtype=torch.float32, device="cuda")
+    ws = plan.workspace(5)
+    plan.sample_zernike_ar(drs, 7, 20, 0.9, zern, ws)
+    torch.cuda.synchronize()
+    got = zern.cpu().numpy()
+    for f in range(5):
+        errs = [rel(got[f, j], ref[f, j]) for j in range(35)]
+        assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
+    drs2 = [1.5, 3.0, 2.0]
+    ref2, _ = osamp.sample_sequence_ar(H, W, G, G, 0.125, drs2, 7, 25, 0.9, y_prev=ylast, spectra=S, L=L)
+    prev = torch.tensor(ref[-1].astype(np.float32), device="cuda")
+    zern2 = torch.empty((3, 35, H, W), dtype=torch.float32, device="cuda")
+    plan.sample_zernike_ar(drs2, 7, 25, 0.9, zern2, ws, zern_prev=prev, d_over_r0_prev=drs[-1])
+    torch.cuda.synchronize()
+    got2 = zern2.cpu().numpy()
+    for f in range(3):
+        errs = [rel(got2[f, j], ref2[f, j]) for j in range(35)]
+        assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
+    with pytest.raises(t.TsimError) as e:
+        plan.sample_zernike_ar(drs2, 7, 25, 1.5, zern2, ws)
+    assert e.value.status == t.EINVAL
+    with pytest.raises(t.TsimError) as e:   # previous frame inside the output range
+        plan.sample_zernike_ar(drs2[:2], 7, 25, 0.9, zern2[1:], ws, zern_prev=zern2[1], d_over_r0_prev=1.0)
+    assert e.value.status == t.EINVAL

@@ -200,3 +200,48 @@ def test_full_tensor_and_energy_claims():
     emp = smp.T @ smp / smp.shape[0]
     d = np.sqrt(np.outer(np.diag(A), np.diag(A)))
     assert np.max(np.abs(emp - A) / d) < 0.04
+
+
+# --------------------------------------------- temporal auto-regression --
+def test_ar_sequence_limits():
+    """alpha = 0: every frame is the frame's own independent draw; alpha = 1:
+    the unit fields freeze, so frame t is frame 0 rescaled by its own
+    (D/r0)^{5/6} (exact, both)."""
+    S = spectra.all_spectra(16, 16, 0.5)
+    L = zernike.cholesky_lower(zernike.noll_matrix(1.0))
+    drs = [1.0, 2.5, 4.0]
+    f0, _ = sampler.sample_sequence_ar(8, 8, 16, 16, 0.5, drs, 3, 10, 0.0, spectra=S, L=L)
+    for t, dr in enumerate(drs):
+        ref = sampler.sample_zernike(8, 8, 16, 16, 0.5, dr, 3, 10 + t, spectra=S, L=L)
+        np.testing.assert_allclose(f0[t], ref, rtol=0, atol=1e-13)
+    f1, _ = sampler.sample_sequence_ar(8, 8, 16, 16, 0.5, drs, 3, 10, 1.0, spectra=S, L=L)
+    for t, dr in enumerate(drs):
+        np.testing.assert_allclose(f1[t], f1[0] * (dr / drs[0]) ** (5.0 / 6.0), rtol=0, atol=1e-13)
+
+
+def test_ar_sequence_covariance():
+    """Monte Carlo over 400 independent two-frame sequences: the same-pixel
+    covariance between consecutive frames is alpha (s0 s1) A_0 and each frame
+    keeps the stationary covariance s^2 A_0, s = (D/r0)^{5/6} (5.5 standard
+    errors per entry; the test rejects alpha = 0)."""
+    S = spectra.all_spectra(16, 16, 0.5)
+    L = zernike.cholesky_lower(zernike.noll_matrix(1.0))
+    alpha, drs = 0.8, [1.5, 3.0]
+    pairs = []
+    for k in range(400):
+        fr, _ = sampler.sample_sequence_ar(8, 8, 16, 16, 0.5, drs, 11, 2 * k, alpha, spectra=S, L=L)
+        pairs.append(fr)
+    F = np.array(pairs)                                  # (n, 2, 35, 8, 8)
+    a0 = F[:, 0].reshape(400, 35, -1)
+    a1 = F[:, 1].reshape(400, 35, -1)
+    cross = np.einsum('nip,njp->nij', a0, a1) / a0.shape[-1]
+    var1 = np.einsum('nip,njp->nij', a1, a1) / a1.shape[-1]
+    A0 = zernike.noll_matrix(1.0)
+    s0, s1 = (drs[0] ** (5 / 6)), (drs[1] ** (5 / 6))
+    for per, expect in [(cross, alpha * s0 * s1 * A0), (var1, s1 * s1 * A0)]:
+        emp = per.mean(0)
+        se = per.std(0, ddof=1) / np.sqrt(per.shape[0])
+        assert np.max(np.abs(emp - expect) / (se + 1e-12)) < 5.5
+    emp = cross.mean(0)
+    se = cross.std(0, ddof=1) / np.sqrt(400)
+    assert np.max(np.abs(emp) / (se + 1e-12)) > 20          # not independent frames
