@@ -51,8 +51,12 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t v, int log2n) {
   return __builtin_bitreverse32(v) >> (32 - log2n);
 }
 
+// LDS element index with one padding slot per 32 complex samples: strided
+// and bit-reversed access patterns then spread over all banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+
 // In-place decimation-in-time FFT over `ncol` independent lines of length n
-// (power of two) stored line-major in LDS (`buf[line * stride + i]`), input
+// (power of two) stored line-major in LDS (`buf[line * stride + lpad(i)]`), input
 // in bit-reversed order, output natural.  `tw[k] = exp(sign 2 pi i k / n)`
 // for k < n/2 sets the direction.  Two radix-2 stages are fused per pass
 // (radix 2^2), so a length-1024 transform takes five barriers.  All threads
@@ -75,7 +79,7 @@ __device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int 
         int j = gg & (h - 1);
         int i = ((gg >> lh) << (lh + 2)) + j;
         float2 *b = buf + line * stride;
-        float2 x0 = b[i], x1 = b[i + h], x2 = b[i + 2 * h], x3 = b[i + 3 * h];
+        float2 x0 = b[lpad(i)], x1 = b[lpad(i + h)], x2 = b[lpad(i + 2 * h)], x3 = b[lpad(i + 3 * h)];
         float2 w1 = tw[j * tstep1];
         float2 w2 = tw[j * tstep2];
         // omega_{4h}^{j+h} = omega_{4h}^j * omega_4, omega_4 = (0, sign)
@@ -87,10 +91,10 @@ __device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int 
         float2 u2 = cmul(w2, a2);
         float2 w3 = cmul(w2, tw[n >> 2]);  // tw[n/4] = omega_4
         float2 u3 = cmul(w3, a3);
-        b[i] = make_float2(a0.x + u2.x, a0.y + u2.y);
-        b[i + 2 * h] = make_float2(a0.x - u2.x, a0.y - u2.y);
-        b[i + h] = make_float2(a1.x + u3.x, a1.y + u3.y);
-        b[i + 3 * h] = make_float2(a1.x - u3.x, a1.y - u3.y);
+        b[lpad(i)] = make_float2(a0.x + u2.x, a0.y + u2.y);
+        b[lpad(i + 2 * h)] = make_float2(a0.x - u2.x, a0.y - u2.y);
+        b[lpad(i + h)] = make_float2(a1.x + u3.x, a1.y + u3.y);
+        b[lpad(i + 3 * h)] = make_float2(a1.x - u3.x, a1.y - u3.y);
       }
       h <<= 2;
       lh += 2;
@@ -103,10 +107,10 @@ __device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int 
         int j = gg & (h - 1);
         int i = ((gg >> lh) << (lh + 1)) + j;
         float2 *b = buf + line * stride;
-        float2 x0 = b[i], x1 = b[i + h];
+        float2 x0 = b[lpad(i)], x1 = b[lpad(i + h)];
         float2 t1 = cmul(tw[j * tstep1], x1);
-        b[i] = make_float2(x0.x + t1.x, x0.y + t1.y);
-        b[i + h] = make_float2(x0.x - t1.x, x0.y - t1.y);
+        b[lpad(i)] = make_float2(x0.x + t1.x, x0.y + t1.y);
+        b[lpad(i + h)] = make_float2(x0.x - t1.x, x0.y - t1.y);
       }
       h <<= 1;
       lh += 1;

@@ -32,11 +32,8 @@ using namespace tsim;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t b = __float_as_uint(f);
-  uint32_t lsb = (b >> 16) & 1u;
-  return uint16_t((b + 0x7FFFu + lsb) >> 16);  // nearest, ties to even (finite inputs)
-}
+// float -> bfloat16, nearest with ties to even (the hardware conversion)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, __bf16(f)); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
 __device__ __forceinline__ float gelu(float z) {
@@ -245,17 +242,17 @@ constexpr int IN_PAD = 48;   // 35 inputs padded to three 16-wide k-steps
 constexpr int ACT_LD = HID + 8;
 constexpr int IPX = 128;     // pixels per inference block (four 32-row tiles)
 
-// erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7): the inference GELU
-__device__ __forceinline__ float erf_as(float x) {
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
-  const float poly = fmaf(fmaf(fmaf(fmaf(1.061405429f, t, -1.453152027f), t, 1.421413741f), t,
-                              -0.284496736f), t, 0.254829592f) * t;
-  const float y = 1.0f - poly * __expf(-ax * ax);
-  return copysignf(y, x);
-}
+// The inference GELU, z Phi(z) = max(z, 0) - |z| erfc(|z| / sqrt 2) / 2 (one
+// expression for both signs), with erfc by Abramowitz & Stegun 7.1.26:
+// erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x),
+// |error| <= 1.5e-7; the coefficients below are a_i / 2 and p / sqrt 2.
 __device__ __forceinline__ float gelu_fast(float z) {
-  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
+  const float a = fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.231641888f, a, 1.0f));
+  const float q = fmaf(fmaf(fmaf(fmaf(0.5307027145f, t, -0.7265760135f), t, 0.7107068705f), t,
+                            -0.142248368f), t, 0.127414796f) * t;
+  const float e = __expf(-0.5f * a * a);
+  return fmaf(-q, e * a, fmaxf(z, 0.f));
 }
 
 // acc[i][t] (i < 2, t < NT) = act[32 rows of tile i][KSTEPS*16] x W[n0 + 32t + .][.]^T:

@@ -201,17 +201,30 @@ k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
   __syncthreads();
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   f32x16 acc0 = {};
+  // psi of tap block t + 1 is loaded while block t goes through the matrix cores
+  float4 cur[K2P / 4], nxt[K2P / 4];
+  {
+    const float4 *pp = reinterpret_cast<const float4 *>(prow);
+#pragma unroll
+    for (int q = 0; q < K2P / 4; ++q) cur[q] = pp[q];
+  }
   for (int t = 0; t < NT; ++t) {
-    const float4 *pp = reinterpret_cast<const float4 *>(prow + size_t(t) * tstride);
+    if (t + 1 < NT) {
+      const float4 *pp = reinterpret_cast<const float4 *>(prow + size_t(t + 1) * tstride);
+#pragma unroll
+      for (int q = 0; q < K2P / 4; ++q) nxt[q] = pp[q];
+    }
     acc0 = f32x16{};
 #pragma unroll
     for (int q = 0; q < K2P / 4; ++q) {
-      const float4 a = pp[q];
+      const float4 a = cur[q];
       if (4 * q + 0 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b[4 * q + 0], acc0, 0, 0, 0);
       if (4 * q + 1 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b[4 * q + 1], acc0, 0, 0, 0);
       if (4 * q + 2 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b[4 * q + 2], acc0, 0, 0, 0);
       if (4 * q + 3 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b[4 * q + 3], acc0, 0, 0, 0);
     }
+#pragma unroll
+    for (int q = 0; q < K2P / 4; ++q) cur[q] = nxt[q];
     const short *ot = offtab + 32 * t + mrow;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {

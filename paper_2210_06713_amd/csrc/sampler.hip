@@ -43,7 +43,8 @@ __global__ void __launch_bounds__(512)
 k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, float2 *__restrict__ V,
                int Gh, int Gw, int log2h, int H, int NC, uint32_t key0, uint32_t key1,
                uint32_t frame_base) {
-  extern __shared__ float2 lds[];  // [NC][Gh], slot-major
+  extern __shared__ float2 lds[];  // [NC][Gh + Gh/32] (padded), slot-major
+  const int ghp = Gh + (Gh >> 5);
   const int q = blockIdx.y;
   const int fl = blockIdx.z;  // frame within this launch
   const uint32_t frame = frame_base + uint32_t(fl);
@@ -98,28 +99,28 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
     const float sb = has_b ? sqrtS[(size_t(mb) * qw + kxq) * qh + kyq] : 0.f;
     if (self_conj) {
       // U = sa g0 + i sb g2 (real noise at self-conjugate bins)
-      lds[slotA * Gh + bitrev(uint32_t(kyA), log2h)] = make_float2(sa * g01.x, sb * g23.x);
+      lds[slotA * ghp + lpad(bitrev(uint32_t(kyA), log2h))] = make_float2(sa * g01.x, sb * g23.x);
     } else {
       // noise of A: W (canonical) or conj(W); B takes the conjugate
       const float sg = a_canon ? 1.f : -1.f;
       const float2 wa = make_float2(g01.x * rs2, sg * g01.y * rs2);
       const float2 wb = make_float2(g23.x * rs2, sg * g23.y * rs2);
       // U = sa Wa + i sb Wb at A, and sa conj(Wa) + i sb conj(Wb) at B
-      lds[slotA * Gh + bitrev(uint32_t(kyA), log2h)] =
+      lds[slotA * ghp + lpad(bitrev(uint32_t(kyA), log2h))] =
           make_float2(sa * wa.x - sb * wb.y, sa * wa.y + sb * wb.x);
-      lds[slotB * Gh + bitrev(uint32_t(kyB), log2h)] =
+      lds[slotB * ghp + lpad(bitrev(uint32_t(kyB), log2h))] =
           make_float2(sa * wa.x + sb * wb.y, -sa * wa.y + sb * wb.x);
     }
   }
   __syncthreads();
-  lds_fft_dit(lds, Gh, log2h, NC, Gh, tw);
+  lds_fft_dit(lds, Gh, log2h, NC, ghp, tw);
   const float norm = rsqrtf(float(Gh) * float(Gw));
   float2 *Vout = V + (size_t(fl) * TSIM_FIELDS + q) * size_t(H) * Gw + s0;
   const int log2nc = __builtin_ctz(NC);
   for (int e = threadIdx.x; e < H * NC; e += blockDim.x) {
     const int y = e >> log2nc;
     const int c = e & (NC - 1);
-    const float2 v = lds[c * Gh + y];
+    const float2 v = lds[c * ghp + lpad(y)];
     Vout[size_t(y) * Gw + c] = make_float2(v.x * norm, v.y * norm);
   }
 }
@@ -193,14 +194,14 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
   constexpr int q = kFieldOrder[I];
   constexpr int ta = 2 * q, tb = 2 * q + 1;
   const float2 *row = a.V + (size_t(q) * a.H + a.y) * size_t(a.Gw);
-  for (int c = threadIdx.x; c < a.Gw; c += NT) a.lds[bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w)] = row[c];
+  for (int c = threadIdx.x; c < a.Gw; c += NT) a.lds[lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = row[c];
   __syncthreads();
   lds_fft_dit(a.lds, a.Gw, a.log2w, 1, a.Gw, a.tw);
   float ya[PX], yb[PX];
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     const int x = threadIdx.x + k * NT;
-    const float2 z = (x < a.W) ? a.lds[x] : make_float2(0.f, 0.f);
+    const float2 z = (x < a.W) ? a.lds[lpad(x)] : make_float2(0.f, 0.f);
     ya[k] = z.x;
     yb[k] = z.y;
   }
@@ -328,12 +329,29 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
   const uint32_t key0 = uint32_t(seed & 0xffffffffu), key1 = uint32_t(seed >> 32);
   float2 *V = static_cast<float2 *>(ws);
   const int chunk = frames_per_chunk(pl, frames);
+  // NC padded columns: 8 x 1056 samples (66 KB) at Gh = 1024, above the
+  // default 64 KB of dynamic LDS; the device limit is checked and raised once
+  const size_t lds1 = size_t(NC) * (Gh + (Gh >> 5)) * sizeof(float2);
+  if (lds1 > 64 * 1024) {
+    static size_t raised = 0;
+    if (lds1 > raised) {
+      int dev = 0, max_lds = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return TSIM_EDEVICE;
+      if (lds1 > size_t(max_lds)) return TSIM_EUNSUPPORTED;
+      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_sampler_cols),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds1)) != hipSuccess)
+        return TSIM_EDEVICE;
+      raised = lds1;
+    }
+  }
   for (int f0 = 0; f0 < frames; f0 += chunk) {
     const int nf = std::min(chunk, frames - f0);
     dim3 g1(Gw / NC, TSIM_FIELDS, nf);
     {
       TraceScope tr("k_sampler_cols", s);
-      hipLaunchKernelGGL(k_sampler_cols, g1, dim3(512), size_t(NC) * Gh * sizeof(float2), s, pl->d_sqrtS,
+      hipLaunchKernelGGL(k_sampler_cols, g1, dim3(512), lds1, s, pl->d_sqrtS,
                        pl->d_tw_h, V, Gh, Gw, log2h, H, NC, key0, key1,
                        uint32_t(frame0 + uint64_t(f0)));
     }
@@ -342,7 +360,7 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     for (int i = 0; i < kMaxFramesPerLaunch; ++i) sc.s[i] = 0.f;
     for (int i = 0; i < nf; ++i) sc.s[i] = scale_host[f0 + i];
     dim3 g2(H, nf);
-    size_t lds = size_t(Gw) * sizeof(float2);
+    size_t lds = size_t(Gw + (Gw >> 5)) * sizeof(float2);
     TraceScope tr("k_sampler_rows_mix", s);
     if (W <= 256)
       hipLaunchKernelGGL((k_sampler_rows_mix<1, 256>), g2, dim3(256), lds, s, V, pl->d_tw_w, pl->d_L,
