@@ -120,7 +120,7 @@ def summarize(rep, steps, frames, s, traffic=True):
 
 def source_hash(kernel):
     files = {"k_sampler_cols": "sampler.hip", "k_sampler_rows_mix": "sampler.hip",
-             "k_psf64": "psf.hip", "k_psf128": "psf.hip", "k_project": "psf.hip",
+             "k_psf64": "psf.hip", "k_psf128": "psf.hip", "k_project": "project.hip",
              "k_render_fp32": "render_bf16.hip", "k_render_bf16": "render_bf16.hip",
              "k_mlp_infer": "mlp.hip", "k_warp": "render.hip"}
     f = files.get(kernel)

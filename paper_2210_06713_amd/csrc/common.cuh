@@ -55,24 +55,40 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t v, int log2n) {
 // and bit-reversed access patterns then spread over all banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
 
+// Twiddle exp(sign 2 pi i k / n) for k < n/2 from the quarter table
+// twq[k] (k < n/4): the second quarter is the first times exp(sign i pi/2).
+__device__ __forceinline__ float2 twiddle(const float2 *twq, int k, int quarter, float sign) {
+  const bool hi = k >= quarter;
+  const float2 t = twq[hi ? k - quarter : k];
+  return hi ? make_float2(-sign * t.y, sign * t.x) : t;
+}
+
+// Copy the quarter twiddle table (n/4 entries of `tw`, which holds
+// exp(sign 2 pi i k / n) for k < n/2) into LDS; the caller synchronises.
+__device__ __forceinline__ void load_twiddles(float2 *twq, const float2 *__restrict__ tw, int n) {
+  for (int k = threadIdx.x; k < (n >> 2); k += blockDim.x) twq[k] = tw[k];
+}
+
 // In-place decimation-in-time FFT over `ncol` independent lines of length n
-// (power of two) stored line-major in LDS (`buf[line * stride + lpad(i)]`), input
-// in bit-reversed order, output natural.  `tw[k] = exp(sign 2 pi i k / n)`
-// for k < n/2 sets the direction.  Two radix-2 stages are fused per pass
-// (radix 2^2), so a length-1024 transform takes five barriers.  All threads
-// of the block take part; the caller synchronises before and after.
-__device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int stride,
-                                   const float2 *__restrict__ tw) {
+// (power of two, >= 4) stored line-major in LDS (`buf[line * stride +
+// lpad(i)]`), input in bit-reversed order, output natural.  The twiddles
+// come from the LDS quarter table `twq` of exp(sign 2 pi i k / n), which
+// also sets the direction.  Two radix-2 stages are fused per pass (radix
+// 2^2), so a length-1024 transform takes five barriers.  All threads of the
+// block take part; the caller synchronises before and after.
+__device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int stride, const float2 *twq,
+                                   float sign) {
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
+  const int quarter = n >> 2;
   int h = 1;
   int lh = 0;
   while (h < n) {
     if (2 * h < n) {
       // stages of span h and 2h on quadruples (i, i+h, i+2h, i+3h)
       const int groups = ncol << (log2n - 2);
-      const int tstep1 = n / (2 * h);   // omega_{2h}^j = tw[j * n/(2h)]
-      const int tstep2 = n / (4 * h);   // omega_{4h}^j = tw[j * n/(4h)]
+      const int tstep1 = n / (2 * h);   // omega_{2h}^j = w[j * n/(2h)]
+      const int tstep2 = n / (4 * h);   // omega_{4h}^j = w[j * n/(4h)], index < n/4
       for (int g = tid; g < groups; g += nthr) {
         int line = g >> (log2n - 2);
         int gg = g & ((n >> 2) - 1);
@@ -80,16 +96,16 @@ __device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int 
         int i = ((gg >> lh) << (lh + 2)) + j;
         float2 *b = buf + line * stride;
         float2 x0 = b[lpad(i)], x1 = b[lpad(i + h)], x2 = b[lpad(i + 2 * h)], x3 = b[lpad(i + 3 * h)];
-        float2 w1 = tw[j * tstep1];
-        float2 w2 = tw[j * tstep2];
-        // omega_{4h}^{j+h} = omega_{4h}^j * omega_4, omega_4 = (0, sign)
+        float2 w1 = twiddle(twq, j * tstep1, quarter, sign);
+        float2 w2 = twq[j * tstep2];
         float2 t1 = cmul(w1, x1), t3 = cmul(w1, x3);
         float2 a0 = make_float2(x0.x + t1.x, x0.y + t1.y);
         float2 a1 = make_float2(x0.x - t1.x, x0.y - t1.y);
         float2 a2 = make_float2(x2.x + t3.x, x2.y + t3.y);
         float2 a3 = make_float2(x2.x - t3.x, x2.y - t3.y);
         float2 u2 = cmul(w2, a2);
-        float2 w3 = cmul(w2, tw[n >> 2]);  // tw[n/4] = omega_4
+        // omega_{4h}^{j+h} = omega_{4h}^j * omega_4, omega_4 = (0, sign)
+        float2 w3 = make_float2(-sign * w2.y, sign * w2.x);
         float2 u3 = cmul(w3, a3);
         b[lpad(i)] = make_float2(a0.x + u2.x, a0.y + u2.y);
         b[lpad(i + 2 * h)] = make_float2(a0.x - u2.x, a0.y - u2.y);
@@ -108,7 +124,7 @@ __device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int 
         int i = ((gg >> lh) << (lh + 1)) + j;
         float2 *b = buf + line * stride;
         float2 x0 = b[lpad(i)], x1 = b[lpad(i + h)];
-        float2 t1 = cmul(tw[j * tstep1], x1);
+        float2 t1 = cmul(twiddle(twq, j * tstep1, quarter, sign), x1);
         b[lpad(i)] = make_float2(x0.x + t1.x, x0.y + t1.y);
         b[lpad(i + h)] = make_float2(x0.x - t1.x, x0.y - t1.y);
       }

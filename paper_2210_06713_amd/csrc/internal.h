@@ -12,6 +12,8 @@
 #define TSIM_FIELDS 18        // complex fields carrying the 35 real modes
 #define TSIM_PSF_MODE0 2      // first mode index (0-based, Noll 4) inside the PSF
 
+constexpr int kProjectTile = 128;  // pixels per projection block (P2S chunks are multiples)
+
 struct tsim_plan {
   tsim_params p;
   double ds;                   // pixel pitch over D
@@ -27,13 +29,9 @@ struct tsim_plan {
   float2 *d_tw_h = nullptr;    // twiddles exp(+2 pi i k / Gh), k < Gh/2
   float2 *d_tw_w = nullptr;    // twiddles exp(+2 pi i k / Gw), k < Gw/2
   float *d_L = nullptr;        // [35][35] float32 lower
-  float *d_zpupil = nullptr;   // [P/2][P/2][36] Zernike modes 4..36 (zero padded) per window sample
-  float *d_zrow = nullptr;     // [8][33][P/2] per-row Chebyshev coefficients of modes 4..36
-  int n_pupil = 0;             // NS
-  int pupil_win = 0;           // side of the square window holding the aperture
+  float *d_zcheb = nullptr;    // [33][8][8] 2D Chebyshev coefficients of modes 4..36 over the aperture
   float *d_basis = nullptr;    // [K][T*T] float32
   float *d_basis_t = nullptr;  // [T*T][KP] float32 (tap-major, zero padded)
-  float2 *d_tw_p = nullptr;    // twiddles exp(-2 pi i k / P), k < P
   uint16_t *d_basis_bf = nullptr;  // [roundup(T*T, 32)][KP] bfloat16, zero padded (tap-major)
   float *d_basis_t128 = nullptr;   // [T*T][128] float32, zero padded (projection on matrix cores)
   float *d_basis_k2 = nullptr;     // [roundup(T*T,32)][2][K2P] float32: psi[2s+g][tap] (FP32 matrix-core blur)
@@ -71,6 +69,8 @@ int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *
                      hipStream_t s);
 size_t p2s_ws_bytes(const tsim_plan *pl, int frames);
 size_t p2s_chunk_pixels(const tsim_plan *pl, size_t total);
+
+// ---- launchers (project.hip) ----
 int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s);
 
 // ---- launchers (mlp.hip) ----

@@ -247,8 +247,8 @@ int validate(const tsim_params *p) {
 
 void free_plan(tsim_plan *pl) {
   if (!pl) return;
-  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zpupil, pl->d_zrow, pl->d_basis, pl->d_basis_t128, pl->d_basis_k2,
-                  pl->d_basis_t, pl->d_tw_p, pl->d_basis_bf, pl->d_mlp_w, pl->d_mlp_f};
+  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zcheb, pl->d_basis, pl->d_basis_t128, pl->d_basis_k2,
+                  pl->d_basis_t, pl->d_basis_bf, pl->d_mlp_w, pl->d_mlp_f};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   delete pl;
@@ -368,52 +368,32 @@ int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
     if ((st = upload(&pl->d_L, Lf.data(), Lf.size())) != TSIM_OK) goto fail;
   }
   {
-    // Pupil: P x P samples, aperture diameter P/2 centred on sample P/2,
-    // samples strictly inside the unit circle.  The window is the
-    // (P/2) x (P/2) square of offsets [-P/4, P/4) around the centre.
-    const int P = pl->P, R = P / 4, win = P / 2;
-    pl->pupil_win = win;
-    const int NZ = 33, NZP = 36;  // modes 4..36, padded to 36 floats per sample
-    std::vector<float> zt(size_t(win) * win * NZP, 0.0f);  // [row][col][mode], zero outside
-    for (int r = 0; r < win; ++r) {
-      for (int cc = 0; cc < win; ++cc) {
-        int dy = r - R, dx = cc - R;
-        double xr = double(dx) / R, yr = double(dy) / R;
-        double rho = std::hypot(xr, yr);
-        if (!(rho < 1.0)) continue;
-        double th = std::atan2(yr, xr);
-        for (int t = 0; t < NZ; ++t) zt[(size_t(r) * win + cc) * NZP + t] = float(zernike(t + 4, rho, th));
-        pl->n_pupil++;
-      }
-    }
-    if ((st = upload(&pl->d_zpupil, zt.data(), zt.size())) != TSIM_OK) goto fail;
-    // Per-row Chebyshev form of the phase: for window row r (y = (r - R)/R),
-    // Z_j(x, y) = sum_p e_{j,p}(y) T_p(x) exactly (degree <= 7 in x), with
-    // e obtained by interpolation at the 8 Chebyshev nodes.  Stored
-    // [p][j][r] so the 32 lanes of a pixel (one row each) read contiguously.
-    const int NP = 8;
-    std::vector<float> zr(size_t(NP) * NZ * win, 0.0f);
-    for (int r = 0; r < win; ++r) {
-      const double y = double(r - R) / R;
-      for (int t = 0; t < NZ; ++t) {
-        double fk[NP];
-        for (int k = 0; k < NP; ++k) {
-          const double x = std::cos(kPi * (k + 0.5) / NP);
-          fk[k] = zernike(t + 4, std::hypot(x, y), std::atan2(y, x));
+    // Phase of modes 4..36 as 2D Chebyshev series over the aperture square:
+    // Z_j(x, y) = sum_{p,q < 8} E[j][p][q] T_p(x) T_q(y) exactly (each mode up
+    // to radial order 7 is a polynomial of degree <= 7 in x and in y), with E
+    // by interpolation at the 8 x 8 Chebyshev nodes.  Coordinates are
+    // normalised to the aperture radius (P/4 samples), so the table does not
+    // depend on P.  Stored [j][p][q].
+    const int NZ = 33, NP = 8;
+    std::vector<float> zc(size_t(NZ) * NP * NP, 0.0f);
+    for (int t = 0; t < NZ; ++t) {
+      double f[NP][NP];
+      for (int k = 0; k < NP; ++k)
+        for (int l = 0; l < NP; ++l) {
+          const double x = std::cos(kPi * (k + 0.5) / NP), y = std::cos(kPi * (l + 0.5) / NP);
+          f[k][l] = zernike(t + 4, std::hypot(x, y), std::atan2(y, x));
         }
-        for (int p = 0; p < NP; ++p) {
+      for (int p = 0; p < NP; ++p)
+        for (int q = 0; q < NP; ++q) {
           double c = 0.0;
-          for (int k = 0; k < NP; ++k) c += fk[k] * std::cos(p * kPi * (k + 0.5) / NP);
-          c *= (p == 0 ? 1.0 : 2.0) / NP;
-          zr[(size_t(p) * NZ + t) * win + r] = float(c);
+          for (int k = 0; k < NP; ++k)
+            for (int l = 0; l < NP; ++l)
+              c += f[k][l] * std::cos(p * kPi * (k + 0.5) / NP) * std::cos(q * kPi * (l + 0.5) / NP);
+          c *= (p == 0 ? 1.0 : 2.0) * (q == 0 ? 1.0 : 2.0) / (NP * NP);
+          zc[(size_t(t) * NP + p) * NP + q] = float(c);
         }
-      }
     }
-    if ((st = upload(&pl->d_zrow, zr.data(), zr.size())) != TSIM_OK) goto fail;
-    std::vector<float2> twp(static_cast<size_t>(P));
-    for (int k = 0; k < P; ++k)
-      twp[k] = make_float2(float(std::cos(2 * kPi * k / P)), float(-std::sin(2 * kPi * k / P)));
-    if ((st = upload(&pl->d_tw_p, twp.data(), twp.size())) != TSIM_OK) goto fail;
+    if ((st = upload(&pl->d_zcheb, zc.data(), zc.size())) != TSIM_OK) goto fail;
   }
   if (p->basis) {
     const int T2 = pl->T * pl->T, K = pl->K, KP = pl->KP;

@@ -15,8 +15,7 @@
 // k_psf128 (pupil P = 128, crop T <= 65): the same pruned DFT with one
 // wavefront per pixel and register FFT-64s; see the kernel.
 //
-// k_project_mfma: beta[p][k] = sum_t h[p][t] psi[k][t] on the FP32 matrix
-// cores, h and psi^T staged through LDS in 32-tap chunks.
+// The projection of these PSFs on the basis (Eq. (7)) is in project.hip.
 #include <algorithm>
 
 #include "common.cuh"
@@ -86,13 +85,31 @@ __device__ __forceinline__ float2 pick(const float2 (&E)[32], const float2 (&O)[
   return (k & 1) ? O[((k - 1) >> 1) & 31] : E[(k >> 1) & 31];
 }
 
+// This lane's row coefficients d_p = sum_q C[p][q] T_q(y) of the pixel's 2D
+// Chebyshev phase series C (from LDS), y the row's normalised coordinate.
+__device__ __forceinline__ void row_series(const float *cb, float y, float (&d)[8]) {
+  float ty[8];
+  ty[0] = 1.f;
+  ty[1] = y;
+#pragma unroll
+  for (int q = 2; q < 8; ++q) ty[q] = fmaf(2.f * y, ty[q - 1], -ty[q - 2]);
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s = fmaf(cb[8 * p + q], ty[q], s);
+    d[p] = s;
+  }
+}
+
 template <int T>
 __global__ void __launch_bounds__(256)
 k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
-        const float *__restrict__ zrow, float *__restrict__ psf) {
+        const float *__restrict__ zc, float *__restrict__ psf) {
   constexpr int R = (T - 1) / 2;  // crop radius, <= 16
   constexpr int LS = 33;          // LDS row stride (complex)
   __shared__ float2 s1[8][32 * LS];
+  __shared__ float cbuf[8][64];   // per pixel: 2D Chebyshev coefficients of the phase
   const int lane = threadIdx.x & 31;
   const int slot = threadIdx.x >> 5;  // half-wave within the block
   float2 *buf = s1[slot];
@@ -110,21 +127,28 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
     for (int t = 0; t < 33; ++t) a[t] = zp[size_t(t + TSIM_PSF_MODE0) * hw];
   }
 
+  // the pixel's phase as a 2D Chebyshev series C[p][q] = sum_j a_j E[j][p][q]
+  // (lane: entries 2 lane, 2 lane + 1), shared through LDS
+  {
+    float c0 = 0.f, c1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < 33; ++j) {
+      c0 = fmaf(a[j], zc[j * 64 + 2 * lane], c0);
+      c1 = fmaf(a[j], zc[j * 64 + 2 * lane + 1], c1);
+    }
+    cbuf[slot][2 * lane] = c0;
+    cbuf[slot][2 * lane + 1] = c1;
+  }
+  __syncthreads();
+
   // ---- stage 1: lane = window row wr, pupil row offset r' = wr - 16 ----
   float2 E[32], O[32];
   {
     const int wr = lane;
     const int rp = wr - 16;
-    // this row's phase as a Chebyshev series in x: phi(x) = sum_p d_p T_p(x),
-    // d_p = sum_j a_j e_{j,p}(y) from the per-row table [p][j][row]
+    // this row's phase as a Chebyshev series in x: phi(x) = sum_p d_p T_p(x)
     float d[8];
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      float s = 0.f;
-#pragma unroll
-      for (int j = 0; j < 33; ++j) s = fmaf(a[j], zrow[(p * 33 + j) * 32 + wr], s);
-      d[p] = s;
-    }
+    row_series(cbuf[slot], float(rp) * 0.0625f, d);
 #pragma unroll
     for (int n = 0; n < 32; ++n) {
       const int cp = (n < 16) ? n : n - 32;  // signed column offset
@@ -223,11 +247,12 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
 // direct 64-term DFT (row ky = +32 of it: twiddles (-i)^r', a wave sum).
 template <int T>
 __global__ void __launch_bounds__(64)
-k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__restrict__ zrow,
+k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__restrict__ zc,
          float *__restrict__ psf) {
   constexpr int R = (T - 1) / 2;  // crop radius, <= 32
   constexpr int LS = 65;          // LDS row stride (complex)
   __shared__ float2 buf[64 * LS];
+  __shared__ float cbuf[64];      // 2D Chebyshev coefficients of the phase
   const int lane = threadIdx.x;
   const size_t p = blockIdx.x;
 
@@ -240,19 +265,21 @@ k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__r
     for (int t = 0; t < 33; ++t) a[t] = zp[size_t(t + TSIM_PSF_MODE0) * hw];
   }
 
+  {
+    float c = 0.f;
+#pragma unroll
+    for (int j = 0; j < 33; ++j) c = fmaf(a[j], zc[j * 64 + lane], c);
+    cbuf[lane] = c;
+  }
+  __syncthreads();
+
   float2 X[64];
   // ---- stage 1: lane = window row wr, pupil row offset r' = wr - 32 ----
   {
     const int wr = lane, rp = wr - 32;
     float2 *row = buf + wr * LS;
     float d[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      float s = 0.f;
-#pragma unroll
-      for (int j = 0; j < 33; ++j) s = fmaf(a[j], zrow[(q * 33 + j) * 64 + wr], s);
-      d[q] = s;
-    }
+    row_series(cbuf, float(rp) * 0.03125f, d);
 #pragma unroll
     for (int n = 0; n < 64; ++n) {
       const int cp = (n < 32) ? n : n - 64;
@@ -356,87 +383,10 @@ k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__r
   }
 }
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-// beta[p][k] = sum_t h[p][t] psi[k][t] on the FP32 matrix cores
-// (v_mfma_f32_32x32x2f32).  Block: 128 pixels x 128 outputs, 4 waves, wave
-// w owns pixel tile w and all four 32-wide output tiles; 32-tap chunks of h
-// and psi^T are staged through LDS (h rows padded against bank conflicts),
-// and the global loads of chunk c + 1 are in flight in registers while the
-// matrix cores work on chunk c.
-constexpr int PJ_PX = 128, PJ_TK = 32, PJ_N = 128;
-
-__global__ void __launch_bounds__(256)
-k_project_mfma(const float *__restrict__ h, const float *__restrict__ psi_t128 /*[T2][128]*/,
-               float *__restrict__ beta, int n, int T2, int K) {
-  __shared__ float As[PJ_PX][PJ_TK + 1];
-  __shared__ __attribute__((aligned(16))) float Bs[PJ_TK][PJ_N];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int p0 = blockIdx.x * PJ_PX;
-  constexpr int NA = PJ_PX * PJ_TK / 256, NB = PJ_TK * PJ_N / 4 / 256;
-  float ra[NA];
-  float4 rb[NB];
-  auto gload = [&](int t0) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = threadIdx.x + i * 256;
-      const int px = e >> 5, tt = e & 31;
-      const int gp = p0 + px, gt = t0 + tt;
-      ra[i] = (gp < n && gt < T2) ? h[size_t(gp) * T2 + gt] : 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = threadIdx.x + i * 256;
-      const int tt = e >> 5, c4 = e & 31;
-      const int gt = t0 + tt;
-      rb[i] = (gt < T2) ? *reinterpret_cast<const float4 *>(psi_t128 + size_t(gt) * PJ_N + 4 * c4)
-                        : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-  };
-  f32x16 acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
-  gload(0);
-  for (int t0 = 0; t0 < T2; t0 += PJ_TK) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = threadIdx.x + i * 256;
-      As[e >> 5][e & 31] = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = threadIdx.x + i * 256;
-      *reinterpret_cast<float4 *>(&Bs[e >> 5][4 * (e & 31)]) = rb[i];
-    }
-    __syncthreads();
-    if (t0 + PJ_TK < T2) gload(t0 + PJ_TK);
-#pragma unroll
-    for (int s = 0; s < PJ_TK / 2; ++s) {
-      const float a = As[w * 32 + (lane & 31)][2 * s + (lane >> 5)];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const float b = Bs[2 * s + (lane >> 5)][t * 32 + (lane & 31)];
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int k = t * 32 + (lane & 31);
-    if (k >= K) continue;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      const int gp = p0 + w * 32 + m;
-      if (gp < n) beta[size_t(gp) * K + k] = acc[t][r];
-    }
-  }
-}
 
 int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_base, int n, float *psf,
                     hipStream_t s) {
-  const float *zt = pl->d_zrow;
+  const float *zt = pl->d_zcheb;
   if (pl->P == 128) {
     TraceScope tr("k_psf128", s);
     switch (pl->T) {
@@ -466,17 +416,10 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
 // projection tiles (bounds the PSF workspace)
 size_t p2s_chunk_pixels(const tsim_plan *pl, size_t total) {
   const size_t per = size_t(pl->T) * pl->T * sizeof(float);
-  size_t cap = std::min(size_t(1) << 20, (size_t(5) << 30) / per / PJ_PX * PJ_PX);
-  return std::min(total, std::max(cap, size_t(PJ_PX)));
+  size_t cap = std::min(size_t(1) << 20, (size_t(5) << 30) / per / kProjectTile * kProjectTile);
+  return std::min(total, std::max(cap, size_t(kProjectTile)));
 }
 
-int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s) {
-  const int T2 = pl->T * pl->T;
-  dim3 grid((n + PJ_PX - 1) / PJ_PX);
-  TraceScope tr("k_project", s);
-  hipLaunchKernelGGL(k_project_mfma, grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K);
-  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
-}
 
 size_t p2s_ws_bytes(const tsim_plan *pl, int frames) {
   size_t total = size_t(frames) * pl->H * pl->W;

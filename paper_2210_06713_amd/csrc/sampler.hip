@@ -43,8 +43,10 @@ __global__ void __launch_bounds__(512)
 k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, float2 *__restrict__ V,
                int Gh, int Gw, int log2h, int H, int NC, uint32_t key0, uint32_t key1,
                uint32_t frame_base) {
-  extern __shared__ float2 lds[];  // [NC][Gh + Gh/32] (padded), slot-major
+  extern __shared__ float2 lds[];  // [NC][Gh + Gh/32] (padded), slot-major; then Gh/4 twiddles
   const int ghp = Gh + (Gh >> 5);
+  float2 *twq = lds + NC * ghp;
+  load_twiddles(twq, tw, Gh);
   const int q = blockIdx.y;
   const int fl = blockIdx.z;  // frame within this launch
   const uint32_t frame = frame_base + uint32_t(fl);
@@ -113,7 +115,7 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
     }
   }
   __syncthreads();
-  lds_fft_dit(lds, Gh, log2h, NC, ghp, tw);
+  lds_fft_dit(lds, Gh, log2h, NC, ghp, twq, 1.f);
   const float norm = rsqrtf(float(Gh) * float(Gw));
   float2 *Vout = V + (size_t(fl) * TSIM_FIELDS + q) * size_t(H) * Gw + s0;
   const int log2nc = __builtin_ctz(NC);
@@ -180,7 +182,7 @@ constexpr MixPlan kMix = make_mix_plan();
 struct RowArgs {
   float2 *lds;
   const float2 *V;  // this frame's rows: V[q][y][:] at V + (q * H + y) * Gw
-  const float2 *tw;
+  const float2 *twq;  // LDS quarter twiddle table
   const float *Lmat;
   float *out;       // this frame and row: plane t at out + t * H * W
   int Gw, log2w, H, W, y;
@@ -196,7 +198,7 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
   const float2 *row = a.V + (size_t(q) * a.H + a.y) * size_t(a.Gw);
   for (int c = threadIdx.x; c < a.Gw; c += NT) a.lds[lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = row[c];
   __syncthreads();
-  lds_fft_dit(a.lds, a.Gw, a.log2w, 1, a.Gw, a.tw);
+  lds_fft_dit(a.lds, a.Gw, a.log2w, 1, a.Gw, a.twq, 1.f);
   float ya[PX], yb[PX];
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
@@ -259,7 +261,8 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
   RowArgs a;
   a.lds = lds;
   a.V = V + size_t(fl) * TSIM_FIELDS * H * size_t(Gw);
-  a.tw = tw;
+  a.twq = lds + Gw + (Gw >> 5);
+  load_twiddles(lds + Gw + (Gw >> 5), tw, Gw);
   a.Lmat = Lmat;
   a.out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * size_t(H) * W + size_t(y) * W;
   a.Gw = Gw;
@@ -329,9 +332,10 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
   const uint32_t key0 = uint32_t(seed & 0xffffffffu), key1 = uint32_t(seed >> 32);
   float2 *V = static_cast<float2 *>(ws);
   const int chunk = frames_per_chunk(pl, frames);
-  // NC padded columns: 8 x 1056 samples (66 KB) at Gh = 1024, above the
-  // default 64 KB of dynamic LDS; the device limit is checked and raised once
-  const size_t lds1 = size_t(NC) * (Gh + (Gh >> 5)) * sizeof(float2);
+  // NC padded columns plus the quarter twiddle table: 8 x 1056 + 256 samples
+  // (68 KB) at Gh = 1024, above the default 64 KB of dynamic LDS; the device
+  // limit is checked and raised once
+  const size_t lds1 = (size_t(NC) * (Gh + (Gh >> 5)) + (Gh >> 2)) * sizeof(float2);
   if (lds1 > 64 * 1024) {
     static size_t raised = 0;
     if (lds1 > raised) {
@@ -360,7 +364,7 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     for (int i = 0; i < kMaxFramesPerLaunch; ++i) sc.s[i] = 0.f;
     for (int i = 0; i < nf; ++i) sc.s[i] = scale_host[f0 + i];
     dim3 g2(H, nf);
-    size_t lds = size_t(Gw + (Gw >> 5)) * sizeof(float2);
+    size_t lds = size_t(Gw + (Gw >> 5) + (Gw >> 2)) * sizeof(float2);
     TraceScope tr("k_sampler_rows_mix", s);
     if (W <= 256)
       hipLaunchKernelGGL((k_sampler_rows_mix<1, 256>), g2, dim3(256), lds, s, V, pl->d_tw_w, pl->d_L,

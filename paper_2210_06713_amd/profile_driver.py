@@ -31,7 +31,7 @@ CAL_BYTES = 256 << 20
 SOURCES = {"k_sampler_cols": ("k_sampler_cols", "sampler.hip"),
            "k_sampler_rows_mix": ("k_sampler_rows_mix", "sampler.hip"),
            "k_psf64": ("k_psf64", "psf.hip"), "k_psf128": ("k_psf128", "psf.hip"),
-           "k_project_mfma": ("k_project", "psf.hip"),
+           "k_project_mfma": ("k_project", "project.hip"),
            "k_render_f32m": ("k_render_fp32", "render_bf16.hip"),
            "k_render_bf16": ("k_render_bf16", "render_bf16.hip"),
            "k_mlp_infer": ("k_mlp_infer", "mlp.hip"), "k_warp": ("k_warp", "render.hip")}
@@ -146,11 +146,11 @@ def summarize(fetch_dir, write_dir, dst):
         wb = median(w) * 1024 * wr
         path = os.path.join(ROOT, "paper_2210_06713_amd", "csrc", src)
         h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
-        res[trace] = {"kernel": k.split("(")[0], "dispatches": len(f), "read_bytes_per_launch": round(rb),
+        name = k.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0].strip()
+        res[trace] = {"kernel": name, "dispatches": len(f), "read_bytes_per_launch": round(rb),
                       "write_bytes_per_launch": round(wb), "bytes_per_launch": round(rb + wb),
                       "src_hash": h}
-        lines.append(f"| {k.split('(')[0].replace('(anonymous namespace)::', '')} | {len(f)} | "
-                     f"{rb / 1e6:.1f} | {wb / 1e6:.1f} | {(rb + wb) / 1e6:.1f} |")
+        lines.append(f"| {name} | {len(f)} | {rb / 1e6:.1f} | {wb / 1e6:.1f} | {(rb + wb) / 1e6:.1f} |")
     os.makedirs(dst, exist_ok=True)
     json.dump(res, open(os.path.join(dst, "traffic.json"), "w"), indent=1)
     return res, lines, fr, wr

@@ -297,3 +297,18 @@ def test_sampler_ar_matches_oracle(t):
     with pytest.raises(t.TsimError) as e:   # previous frame inside the output range
         plan.sample_zernike_ar(drs2[:2], 7, 25, 0.9, zern2[1:], ws, zern_prev=zern2[1], d_over_r0_prev=1.0)
     assert e.value.status == t.EINVAL
+
+
+def test_p2s_exact_k120_matches_oracle(t):
+    """K = 120 takes the projection's eight-tile variant (K > 112)."""
+    say("p2s exact 24x40 K=120")
+    A, _ = opsf.basis_draws(400, seed=120)
+    Psi, _ = opsf.pca_basis(opsf.psf_batch(A, 64, 33), 120)
+    H, W = 24, 40
+    plan = t.Plan(H, W, 1, 64, 64, basis=Psi, psf_t=33)
+    z32 = osamp.sample_zernike(H, W, 64, 64, 0.125, 2.5, 9, 0).astype(np.float32)
+    beta = torch.empty((1, H, W, 120), dtype=torch.float32, device="cuda")
+    plan.p2s(torch.tensor(z32[None], device="cuda"), beta, plan.workspace(1))
+    torch.cuda.synchronize()
+    ref = opsf.psf_field(z32.astype(np.float64), 64, 33, Psi)
+    assert rel(beta.cpu().numpy()[0], ref) < TOL
