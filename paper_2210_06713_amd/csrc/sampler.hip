@@ -180,33 +180,41 @@ constexpr MixPlan make_mix_plan() {
 constexpr MixPlan kMix = make_mix_plan();
 
 struct RowArgs {
-  float2 *lds;
+  float2 *lds;      // RW padded lines of Gw + Gw/32 samples
   const float2 *V;  // this frame's rows: V[q][y][:] at V + (q * H + y) * Gw
   const float2 *twq;  // LDS quarter twiddle table
   const float *Lmat;
-  float *out;       // this frame and row: plane t at out + t * H * W
-  int Gw, log2w, H, W, y;
+  float *out;       // this frame and first row: plane t at out + t * H * W
+  int Gw, log2w, H, W, y0, nrows;
   float sc;
 };
 
-// Field at position I of kFieldOrder: inverse transform of its row, then its
+// Field at position I of kFieldOrder for the block's RW rows: inverse
+// transform of the rows (one LDS pass over all RW lines), then the field's
 // terms of the mix; outputs whose last field this is are written.
-template <int I, int PX, int NT>
-__device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_MODES][PX]) {
+template <int I, int PX, int NT, int RW>
+__device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_MODES][RW][PX]) {
   constexpr int q = kFieldOrder[I];
   constexpr int ta = 2 * q, tb = 2 * q + 1;
-  const float2 *row = a.V + (size_t(q) * a.H + a.y) * size_t(a.Gw);
-  for (int c = threadIdx.x; c < a.Gw; c += NT) a.lds[lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = row[c];
-  __syncthreads();
-  lds_fft_dit(a.lds, a.Gw, a.log2w, 1, a.Gw, a.twq, 1.f);
-  float ya[PX], yb[PX];
+  const int gwp = a.Gw + (a.Gw >> 5);
 #pragma unroll
-  for (int k = 0; k < PX; ++k) {
-    const int x = threadIdx.x + k * NT;
-    const float2 z = (x < a.W) ? a.lds[lpad(x)] : make_float2(0.f, 0.f);
-    ya[k] = z.x;
-    yb[k] = z.y;
+  for (int r = 0; r < RW; ++r) {
+    const float2 *row = a.V + (size_t(q) * a.H + a.y0 + (r < a.nrows ? r : 0)) * size_t(a.Gw);
+    for (int c = threadIdx.x; c < a.Gw; c += NT)
+      a.lds[r * gwp + lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = row[c];
   }
+  __syncthreads();
+  lds_fft_dit(a.lds, a.Gw, a.log2w, RW, gwp, a.twq, 1.f);
+  float ya[RW][PX], yb[RW][PX];
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      const int x = threadIdx.x + k * NT;
+      const float2 z = (x < a.W) ? a.lds[r * gwp + lpad(x)] : make_float2(0.f, 0.f);
+      ya[r][k] = z.x;
+      yb[r][k] = z.y;
+    }
   __syncthreads();  // lds is overwritten by the next field
 #pragma unroll
   for (int t = 0; t < TSIM_N_MODES; ++t) {
@@ -214,13 +222,17 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
       const float la = a.Lmat[t * TSIM_N_MODES + ta];
       const bool init = kMix.first[t] == I && kMix.first_k[t] == ta;
 #pragma unroll
-      for (int k = 0; k < PX; ++k) acc[t][k] = init ? la * ya[k] : fmaf(la, ya[k], acc[t][k]);
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int k = 0; k < PX; ++k) acc[t][r][k] = init ? la * ya[r][k] : fmaf(la, ya[r][k], acc[t][r][k]);
     }
     if (tb < TSIM_N_MODES && kMix.nz[t][tb]) {
       const float lb = a.Lmat[t * TSIM_N_MODES + tb];
       const bool init = kMix.first[t] == I && kMix.first_k[t] == tb;
 #pragma unroll
-      for (int k = 0; k < PX; ++k) acc[t][k] = init ? lb * yb[k] : fmaf(lb, yb[k], acc[t][k]);
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int k = 0; k < PX; ++k) acc[t][r][k] = init ? lb * yb[r][k] : fmaf(lb, yb[r][k], acc[t][r][k]);
     }
     if (kMix.last[t] == I) {
       // opaque plane size: keeps the compiler from forming all 35 plane
@@ -229,50 +241,57 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
       asm volatile("" : "+s"(plane));
       float *po = a.out + size_t(t) * plane;
 #pragma unroll
-      for (int k = 0; k < PX; ++k) {
-        const int x = threadIdx.x + k * NT;
-        if (x < a.W) po[x] = acc[t][k] * a.sc;
+      for (int r = 0; r < RW; ++r) {
+        if (r >= a.nrows) break;
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          const int x = threadIdx.x + k * NT;
+          if (x < a.W) po[size_t(r) * a.W + x] = acc[t][r][k] * a.sc;
+        }
       }
     }
   }
 }
 
-template <int I, int PX, int NT>
+template <int I, int PX, int NT, int RW>
 struct FieldSteps {
-  __device__ __forceinline__ static void run(const RowArgs &a, float (&acc)[TSIM_N_MODES][PX]) {
-    mix_field<I, PX, NT>(a, acc);
-    FieldSteps<I + 1, PX, NT>::run(a, acc);
+  __device__ __forceinline__ static void run(const RowArgs &a, float (&acc)[TSIM_N_MODES][RW][PX]) {
+    mix_field<I, PX, NT, RW>(a, acc);
+    FieldSteps<I + 1, PX, NT, RW>::run(a, acc);
   }
 };
 
-template <int PX, int NT>
-struct FieldSteps<TSIM_FIELDS, PX, NT> {
-  __device__ __forceinline__ static void run(const RowArgs &, float (&)[TSIM_N_MODES][PX]) {}
+template <int PX, int NT, int RW>
+struct FieldSteps<TSIM_FIELDS, PX, NT, RW> {
+  __device__ __forceinline__ static void run(const RowArgs &, float (&)[TSIM_N_MODES][RW][PX]) {}
 };
 
-template <int PX, int NT>
+// One block per RW consecutive output rows (the last block may hold fewer).
+template <int PX, int NT, int RW>
 __global__ void __launch_bounds__(NT)
 k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
                    const float *__restrict__ Lmat, float *__restrict__ zern, int Gw, int log2w,
                    int H, int W, FrameScales scales, int frame_out0) {
   extern __shared__ float2 lds[];
-  const int y = blockIdx.x;
+  const int y0 = blockIdx.x * RW;
   const int fl = blockIdx.y;
+  const int gwp = Gw + (Gw >> 5);
   RowArgs a;
   a.lds = lds;
   a.V = V + size_t(fl) * TSIM_FIELDS * H * size_t(Gw);
-  a.twq = lds + Gw + (Gw >> 5);
-  load_twiddles(lds + Gw + (Gw >> 5), tw, Gw);
+  a.twq = lds + RW * gwp;
+  load_twiddles(lds + RW * gwp, tw, Gw);
   a.Lmat = Lmat;
-  a.out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * size_t(H) * W + size_t(y) * W;
+  a.out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * size_t(H) * W + size_t(y0) * W;
   a.Gw = Gw;
   a.log2w = log2w;
   a.H = H;
   a.W = W;
-  a.y = y;
+  a.y0 = y0;
+  a.nrows = min(RW, H - y0);
   a.sc = scales.s[fl];
-  float acc[TSIM_N_MODES][PX];  // each output starts at its first term
-  FieldSteps<0, PX, NT>::run(a, acc);
+  float acc[TSIM_N_MODES][RW][PX];  // each output starts at its first term
+  FieldSteps<0, PX, NT, RW>::run(a, acc);
 }
 
 // Temporal auto-regression on the mixed fields, in place over a chunk of
@@ -363,20 +382,24 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     FrameScales sc;
     for (int i = 0; i < kMaxFramesPerLaunch; ++i) sc.s[i] = 0.f;
     for (int i = 0; i < nf; ++i) sc.s[i] = scale_host[f0 + i];
-    dim3 g2(H, nf);
-    size_t lds = size_t(Gw + (Gw >> 5) + (Gw >> 2)) * sizeof(float2);
     TraceScope tr("k_sampler_rows_mix", s);
+    const size_t gwp = size_t(Gw + (Gw >> 5));
+    // two rows per block (one LDS transform pass and one barrier set for both)
+    // up to 1024 columns; 1024-thread blocks over single rows beyond
+    const size_t lds2 = (2 * gwp + (Gw >> 2)) * sizeof(float2);
+    const size_t lds1 = (gwp + (Gw >> 2)) * sizeof(float2);
+    dim3 g2((H + 1) / 2, nf), g1r(H, nf);
     if (W <= 256)
-      hipLaunchKernelGGL((k_sampler_rows_mix<1, 256>), g2, dim3(256), lds, s, V, pl->d_tw_w, pl->d_L,
+      hipLaunchKernelGGL((k_sampler_rows_mix<1, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, pl->d_L,
                          zern, Gw, log2w, H, W, sc, f0);
     else if (W <= 512)
-      hipLaunchKernelGGL((k_sampler_rows_mix<2, 256>), g2, dim3(256), lds, s, V, pl->d_tw_w, pl->d_L,
+      hipLaunchKernelGGL((k_sampler_rows_mix<2, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, pl->d_L,
                          zern, Gw, log2w, H, W, sc, f0);
     else if (W <= 1024)
-      hipLaunchKernelGGL((k_sampler_rows_mix<4, 256>), g2, dim3(256), lds, s, V, pl->d_tw_w, pl->d_L,
+      hipLaunchKernelGGL((k_sampler_rows_mix<4, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, pl->d_L,
                          zern, Gw, log2w, H, W, sc, f0);
     else
-      hipLaunchKernelGGL((k_sampler_rows_mix<4, 1024>), g2, dim3(1024), lds, s, V, pl->d_tw_w, pl->d_L,
+      hipLaunchKernelGGL((k_sampler_rows_mix<4, 1024, 1>), g1r, dim3(1024), lds1, s, V, pl->d_tw_w, pl->d_L,
                          zern, Gw, log2w, H, W, sc, f0);
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
   }
