@@ -43,6 +43,15 @@ __device__ __forceinline__ float2 box_muller(uint32_t a, uint32_t b) {
   return make_float2(r * c, r * s);
 }
 
+// Box-Muller on the hardware transcendental units: r = sqrt(-2 ln 2 log2 u0)
+// and the cosine/sine of 2 pi u1 (v_sin/v_cos take revolutions), each a few
+// ulp from the correctly rounded value; u0 >= 2^-24 is a normal number.
+__device__ __forceinline__ float2 box_muller_hw(uint32_t a, uint32_t b) {
+  const float u0 = u01(a), u1 = u01(b);
+  const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u0));
+  return make_float2(r * __builtin_amdgcn_cosf(u1), r * __builtin_amdgcn_sinf(u1));
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

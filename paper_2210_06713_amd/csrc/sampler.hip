@@ -92,8 +92,8 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
     const bool a_canon = linA <= linB;
     const uint32_t canon = a_canon ? linA : linB;
     u32x4 r = philox4x32_10(u32x4{canon, uint32_t(q), frame, 0u}, key0, key1);
-    const float2 g01 = box_muller(r.x, r.y);
-    const float2 g23 = box_muller(r.z, r.w);
+    const float2 g01 = box_muller_hw(r.x, r.y);
+    const float2 g23 = box_muller_hw(r.z, r.w);
     const int kxq = kx;                // kx <= Gw/2 for every bin A
     const int kyq = kyA < qh ? kyA : Gh - kyA;
     const int qw = Gw / 2 + 1;
