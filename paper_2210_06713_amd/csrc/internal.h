@@ -32,7 +32,7 @@ struct tsim_plan {
   float *d_zcheb = nullptr;    // [33][8][8] 2D Chebyshev coefficients of modes 4..36 over the aperture
   float *d_basis = nullptr;    // [K][T*T] float32
   float *d_basis_t = nullptr;  // [T*T][KP] float32 (tap-major, zero padded)
-  uint16_t *d_basis_bf = nullptr;  // [roundup(T*T, 32)][KP] bfloat16, zero padded (tap-major)
+  uint16_t *d_basis_bf = nullptr;  // [groups of 32 tap pairs][2][32][KP + 8] bfloat16, zero padded
   float *d_basis_t128 = nullptr;   // [T*T][128] float32, zero padded (projection on matrix cores)
   float *d_basis_k2 = nullptr;     // [roundup(T*T,32)][2][K2P] float32: psi[2s+g][tap] (FP32 matrix-core blur)
   uint16_t *d_mlp_w = nullptr;     // packed BF16 network weights (inference layout)

@@ -411,15 +411,23 @@ int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
       }
     if ((st = upload(&pl->d_basis, b.data(), b.size())) != TSIM_OK) goto fail;
     if ((st = upload(&pl->d_basis_t, bt.data(), bt.size())) != TSIM_OK) goto fail;
-    // BF16 tap-major copy for the matrix-core blur, taps padded to 32
-    const int TTP = (T2 + 31) / 32 * 32;
-    std::vector<uint16_t> bb(size_t(TTP) * KP, 0);
-    for (int t = 0; t < T2; ++t)
-      for (int k = 0; k < K; ++k) {
-        float f = float(pl->basis[size_t(k) * T2 + t]);
-        uint32_t u;
-        std::memcpy(&u, &f, 4);
-        bb[size_t(t) * KP + k] = uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    // BF16 copy for the matrix-core blur in groups of 32 horizontal tap
+    // pairs: [group][side][pair][KP + 8], pair j = (uy, i) = (j / NPX, j %
+    // NPX) covers taps (uy, 2i) (side 0) and (uy, 2i + 1) (side 1); taps past
+    // the kernel edge, pairs past the last one and the row pads are zero
+    const int T = pl->T, NPX = (T + 1) / 2, NPR = T * NPX, NTP = (NPR + 31) / 32, KPP = KP + 8;
+    std::vector<uint16_t> bb(size_t(NTP) * 64 * KPP, 0);
+    for (int j = 0; j < NPR; ++j)
+      for (int h = 0; h < 2; ++h) {
+        const int uy = j / NPX, ux = 2 * (j % NPX) + h;
+        if (ux >= T) continue;
+        const size_t row = (size_t(j / 32) * 2 + h) * 32 + j % 32;
+        for (int k = 0; k < K; ++k) {
+          float f = float(pl->basis[size_t(k) * T2 + uy * T + ux]);
+          uint32_t u;
+          std::memcpy(&u, &f, 4);
+          bb[row * KPP + k] = uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+        }
       }
     if ((st = upload(&pl->d_basis_bf, bb.data(), bb.size())) != TSIM_OK) goto fail;
     std::vector<float> b128(size_t(T2) * 128, 0.0f);
@@ -427,7 +435,7 @@ int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
       for (int k = 0; k < K; ++k) b128[size_t(t) * 128 + k] = float(pl->basis[size_t(k) * T2 + t]);
     if ((st = upload(&pl->d_basis_t128, b128.data(), b128.size())) != TSIM_OK) goto fail;
     // lane-contiguous layout for the FP32 matrix-core blur: [tap][g][s] = psi[2s + g][tap]
-    const int K2 = (K + 1) / 2, K2P = (K2 + 3) / 4 * 4;
+    const int K2 = (K + 1) / 2, K2P = (K2 + 3) / 4 * 4, TTP = (T2 + 31) / 32 * 32;
     std::vector<float> bk2(size_t(TTP) * 2 * K2P, 0.0f);
     for (int t = 0; t < T2; ++t)
       for (int g = 0; g < 2; ++g)

@@ -1,15 +1,22 @@
 // The learned form's blur on the BF16 matrix cores (Eq. (8), evaluated in
 // the reconstruct-first order sum_u (sum_k beta_k psi_k(u)) I(x - u)).
 //
-// Block = 8 x 16 output pixels, 4 waves; wave w owns the 32 pixels of rows
-// 2w, 2w+1.  For each block of 32 taps the matrix cores form
-// htilde[32 px][32 taps] = beta (BF16, rows = pixels) x psi^T (BF16), FP32
-// accumulation, so every lane owns ONE tap (column) for 16 of the 32 pixels:
-// it multiplies them by the image samples I(x - u) read from the LDS tile at
-// compile-time offsets from a per-lane base and keeps C x 16 running sums,
-// summed over the lanes once at the end.  Tap blocks are software-
-// pipelined: the psi fragments of block t+2 are in flight and the products
-// of block t+1 are issued while the epilogue of block t runs.
+// Taps are taken in pairs (ux, ux + 1) of horizontally adjacent kernel
+// columns.  A block covers TH x 16 output pixels with TH / 2 waves; wave w
+// owns the 32 pixels of rows 2w, 2w + 1.  For each group of 32 tap pairs the
+// matrix cores form two 32 x 32 products htilde = beta (BF16, rows = pixels)
+// x psi^T (BF16) with FP32 accumulation, one for the left and one for the
+// right taps of the pairs, so every lane owns the two taps of one pair for 16
+// pixels, in runs of 4 horizontally adjacent pixels.  A run meets 5 distinct
+// image samples for its 8 products, read from an FP32 LDS tile whose rows
+// are split by the parity of the column (pairs step the column by two) and
+// padded to a stride congruent to the pair count per kernel row modulo 32,
+// so the 32 lanes of a half-wave, which walk consecutive tap pairs, hit 32
+// distinct banks.  The products are FP32 vector FMAs, which co-issue with
+// the matrix-core instructions; each matrix-core instruction is followed in
+// the schedule by a slice of the previous group's FMAs.  The per-lane sums
+// over taps are reduced across the 32 lanes that share pixels once at the
+// end.
 #include <algorithm>
 
 #include "common.cuh"
@@ -30,30 +37,88 @@ __device__ __forceinline__ f32x16 mfma_bf16(const uint4 &a, const uint4 &b, cons
                                                  c, 0, 0, 0);
 }
 
+// Geometry of the paired-tap blur for kernel size T, TH output rows per block
+// and KP basis coefficients per tap.  Tile word (c, sy, parity, k) =
+// I(column 2k + parity) sits at c CH + sy RSR + parity SWH + k, k < SWH;
+// the row stride RSR >= 2 SWH is congruent to the pair count per kernel row
+// modulo 32, and a lane's words of one channel lie within 255 words of its
+// base.  The basis is staged in groups of 32 tap pairs, rows of KPP = KP + 8
+// coefficients (the 16-byte pad keeps the lanes' 16-byte reads on distinct
+// banks), NS groups in flight.
+template <int T, int TH, int KP, int C>
+struct PairGeom {
+  static_assert(T % 2 == 1, "odd kernel size");
+  static constexpr int R = (T - 1) / 2;
+  static constexpr int NPX = (T + 1) / 2;          // tap pairs per kernel row (last one half padding)
+  static constexpr int NP = T * NPX;               // tap pairs
+  static constexpr int NTP = (NP + 31) / 32;       // groups of 32 pairs
+  static constexpr int SH = TH + T - 1;            // tile rows
+  static constexpr int SW = 16 + T - 1;            // tile columns (even)
+  static constexpr int SWH = SW / 2;               // columns of one parity
+  static constexpr int RSR = 2 * SWH + ((NPX - 2 * SWH) % 32 + 32) % 32;
+  static constexpr int CH = SH * RSR;              // one channel
+  static constexpr int KPP = KP + 8;
+  static constexpr int GB = 64 * KPP * 2;          // bytes of one group: [2 sides][32 pairs][KPP]
+  static constexpr int NCH = GB / 1024;            // 1 KB wave copies per group
+  static constexpr size_t BASE = size_t(C) * CH * 4 + size_t(NTP) * 32 * 4;   // tile + lane bases
+  static constexpr int NS = BASE + 3 * size_t(GB) <= 160 * 1024 ? 3 : 2;
+  static constexpr size_t LDS = BASE + size_t(NS) * GB;
+  static_assert(GB % 1024 == 0, "whole wave copies");
+  static_assert(RSR + SWH + 5 < 256, "read offsets");
+};
+
+// Two waves per SIMD (at most 256 registers); four channels' sums or a
+// 128-wide basis need more.
 template <int KS, int T, int C>
-__global__ void __launch_bounds__(256)
+constexpr bool kWide = C > 3 || KS > 7;
+
+// Copies one 1 KB piece of a basis group from global memory straight into
+// LDS: lane l moves bytes 16 l .. 16 l + 15 of the piece.  The LDS address
+// of the piece must be the same for the whole wave (it goes through M0).
+__device__ __forceinline__ void copy_to_lds(const char *src_piece, uint32_t lds_piece, int lane) {
+  asm volatile(
+      "s_mov_b32 m0, %0\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %1, %2"
+      :
+      : "s"(lds_piece), "v"(uint32_t(lane) * 16u), "s"(src_piece)
+      : "memory", "m0");
+}
+
+template <int KS, int T, int C, int TH>
+__global__ void __launch_bounds__(32 * TH) __attribute__((amdgpu_waves_per_eu(kWide<KS, T, C> ? 1 : 2)))
 k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
-              const uint16_t *__restrict__ psi /*[ntiles*32][KS*16]*/, float *__restrict__ out,
+              const uint16_t *__restrict__ psi /*[NTP][2][32][KPP]*/, float *__restrict__ out,
               int H, int W) {
-  constexpr int TH = 8, TW = 16, KB = KS * 16;
-  constexpr int R = (T - 1) / 2;
-  constexpr int SH = TH + T - 1, SW = TW + T - 1, PLANE = SH * SW;
-  constexpr int NT = (T * T + 31) / 32;
-  extern __shared__ float tile[];             // [C][SH][SW]
+  using G = PairGeom<T, TH, KS * 16, C>;
+  constexpr int KB = KS * 16, R = G::R, SH = G::SH, SW = G::SW, SWH = G::SWH, RSR = G::RSR, CH = G::CH;
+  constexpr int NPX = G::NPX, NP = G::NP, NTP = G::NTP, KPP = G::KPP, GB = G::GB, NCH = G::NCH, NS = G::NS;
+  constexpr int NW = TH / 2, CPW = (NCH + NW - 1) / NW;   // waves, copies per wave and group
+  extern __shared__ float smem[];
+  uint32_t *tile = reinterpret_cast<uint32_t *>(smem);     // [C][SH][RSR] image samples
+  int *ltab = reinterpret_cast<int *>(tile + C * CH);      // NTP * 32 lane bases
+  char *ring = reinterpret_cast<char *>(smem) + G::BASE;   // NS groups of the basis
   const int f = blockIdx.z;
-  const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
+  const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * 16;
   const float *imf = img + size_t(f) * C * H * W;
-  for (int e = threadIdx.x; e < C * PLANE; e += 256) {
-    const int c = e / PLANE;
-    const int rem = e - c * PLANE;
-    const int sy = rem / SW, sx = rem - sy * SW;
-    const int gy = min(max(ty0 + sy - R, 0), H - 1);
-    const int gx = min(max(tx0 + sx - R, 0), W - 1);
-    tile[e] = imf[(size_t(c) * H + gy) * W + gx];
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int pn = lane & 31, g = lane >> 5;
-  // A operand: beta of pixel pn of the wave (rows 2w, 2w+1 of the block)
+  // group tp goes to ring stage tp % NS; wave w copies pieces w, w + NW, ...
+  // (a wave past the last piece repeats it: same bytes to the same place),
+  // groups past the last one repeat it into the stage that was just freed
+  const uint32_t ring_lds = uint32_t(reinterpret_cast<uintptr_t>(ring));
+  auto stage_in = [&](int tp) {
+    const char *src = reinterpret_cast<const char *>(psi) + size_t(min(tp, NTP - 1)) * GB;
+    const uint32_t dst = ring_lds + uint32_t((tp % NS) * GB);
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      const int piece = min(w + k * NW, NCH - 1);
+      copy_to_lds(src + piece * 1024, dst + uint32_t(piece * 1024), lane);
+    }
+  };
+#pragma unroll
+  for (int tp = 0; tp < NS - 1; ++tp) stage_in(tp);
+  // A operand: beta of pixel pn of the wave (rows 2w, 2w + 1 of the block)
   uint4 b[KS];
   {
     const int py = 2 * w + (pn >> 4), px = pn & 15;
@@ -63,11 +128,44 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
 #pragma unroll
     for (int s = 0; s < KS; ++s) b[s] = ok ? ld_frag(bp + 16 * s) : make_uint4(0u, 0u, 0u, 0u);
   }
-  // B operand: psi^T column = tap pn of the 32-tap block, k-slice 8g..8g+7
-  const uint16_t *prow = psi + size_t(pn) * KB + 8 * g;  // + t*32*KB
-  // the lane's accumulator rows are pixels m_r + 4g, m_r = 8(r/4) + r%4: all in
-  // one tile row, so pixel position = wave base + 4g + (compile-time part)
-  const int pbase = (2 * w + R) * SW + R + 4 * g;
+  // tile column q of row sy holds I(ty0 + sy - R, tx0 + q - R) (clamped), at
+  // parity q % 2, index q / 2; all of a thread's samples are requested
+  // before the first is written
+  {
+    constexpr int NE = C * SH * SW, NIT = (NE + 32 * TH - 1) / (32 * TH);
+    const char *imb = reinterpret_cast<const char *>(imf);   // a frame spans < 4 GiB
+    float v[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = min(int(threadIdx.x) + it * 32 * TH, NE - 1);
+      const int c = e / (SH * SW);
+      const int rem = e - c * (SH * SW);
+      const int sy = rem / SW, q = rem - sy * SW;
+      const int gy = min(max(ty0 + sy - R, 0), H - 1);
+      const int gx = min(max(tx0 + q - R, 0), W - 1);
+      v[it] = *reinterpret_cast<const float *>(imb + uint32_t(4u * uint32_t((c * H + gy) * W + gx)));
+    }
+    float *tf = reinterpret_cast<float *>(tile);
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = threadIdx.x + it * 32 * TH;
+      if (e < NE) {
+        const int c = e / (SH * SW);
+        const int rem = e - c * (SH * SW);
+        const int sy = rem / SW, q = rem - sy * SW;
+        tf[c * CH + sy * RSR + (q & 1) * SWH + (q >> 1)] = v[it];
+      }
+    }
+  }
+  // lane base of tap pair j = (uy, i): the left tap (uy, 2i) of pixel (py,
+  // px) reads tile row py + 2R - uy, column px + 2R - 2i, the right tap the
+  // column before; padding pairs (j >= NP, zero psi) point at harmless
+  // in-tile words
+  for (int j = threadIdx.x; j < NTP * 32; j += 32 * TH) {
+    const int uy = j / NPX, i = j - uy * NPX;
+    ltab[j] = j < NP ? (2 * R - uy) * RSR + R - i : 0;
+  }
+  const int wbase = 2 * w * RSR + 2 * g;
   __syncthreads();
 
   float sum[C][16];
@@ -75,78 +173,146 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
   for (int c = 0; c < C; ++c)
 #pragma unroll
     for (int r = 0; r < 16; ++r) sum[c][r] = 0.f;
-  auto epilogue = [&](const f32x16 &acc, int t) {
-    // this lane's tap u = 32t + pn, offset (uy - R) SW + (ux - R); padded taps carry 0
-    const int u = 32 * t + pn;
-    const int uy = u / T, ux = u - uy * T;
-    const int lb = pbase - ((u < T * T) ? (uy - R) * SW + (ux - R) : 0);
-    const float *tl = tile + lb;
+  // accumulator row r = 4 run + j holds pixel py = 2w + run / 2, px = px0 +
+  // j with px0 = 8 (run % 2) + 4g: the left tap reads column q0 + j, q0 =
+  // px0 + 2R - 2i (even), the right tap column q0 + j - 1.  The run's five
+  // columns q0 - 1 .. q0 + 3 are words k0 = q0 / 2 and k0 + 1 of the even
+  // half and k0 - 1 .. k0 + 1 of the odd half, k0 = (lane base) + 4 (run % 2)
+  auto apply = [&](const f32x16 &xl, const f32x16 &xr, int tp) {
+    // one base per channel, kept opaque so that every read folds its
+    // compile-time offset (< 256 words) into the LDS instruction
+    int cb[C];
+    cb[0] = wbase + ltab[32 * tp + pn];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = 8 * (r >> 2) + (r & 3);
-      const int o = (m >> 4) * SW + (m & 15);
-      const float v = acc[r];
+    for (int c = 1; c < C; ++c) {
+      cb[c] = cb[0] + c * CH;
+      asm volatile("" : "+v"(cb[c]));
+    }
+    const float *tf = reinterpret_cast<const float *>(tile);
 #pragma unroll
-      for (int c = 0; c < C; ++c) sum[c][r] = fmaf(v, tl[c * PLANE + o], sum[c][r]);
+    for (int run = 0; run < 4; ++run) {
+      const int ro = (run >> 1) * RSR + 4 * (run & 1);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float *t0 = tf + cb[c] + ro;
+        const float sm[5] = {t0[SWH - 1], t0[0], t0[SWH], t0[1], t0[SWH + 1]};   // columns q0 - 1 .. q0 + 3
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = 4 * run + j;
+          sum[c][r] = fmaf(xl[r], sm[j + 1], sum[c][r]);
+          sum[c][r] = fmaf(xr[r], sm[j], sum[c][r]);
+        }
+      }
     }
   };
-  uint4 pa[KS], pq[KS];
+  // B operand from the ring: psi^T column = tap pair pn, k-slice 8g..8g+7
+  const char *frag = ring + (pn * KPP + 8 * g) * 2;
+  // all fragments of a group are read before its first product (a
+  // scheduling fence keeps the reads ahead), so only that one waits for LDS
+  uint4 fl[KS], fr[KS];
+  auto mul = [&](f32x16 &al, f32x16 &ar, int tp) {
+    const char *st = frag + (tp % NS) * GB;
 #pragma unroll
-  for (int s = 0; s < KS; ++s) pa[s] = ld_frag(prow + 16 * s);
-  f32x16 acc0 = {}, acc1 = {};
+    for (int s = 0; s < KS; ++s) {
+      fl[s] = *reinterpret_cast<const uint4 *>(st + 32 * s);
+      fr[s] = *reinterpret_cast<const uint4 *>(st + 32 * KPP * 2 + 32 * s);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    al = f32x16{};
+    ar = f32x16{};
 #pragma unroll
-  for (int s = 0; s < KS; ++s) acc0 = mfma_bf16(b[s], pa[s], acc0);
-  if (NT > 1) {
+    for (int s = 0; s < KS; ++s) {
+      al = mfma_bf16(b[s], fl[s], al);
+      ar = mfma_bf16(b[s], fr[s], ar);
+    }
+  };
+  // group tp: wait for this wave's copies of it (NS - 2 later groups may
+  // still be in flight), meet the other waves (all copies landed; all reads
+  // of the stage about to be refilled done), refill, multiply.  Each
+  // matrix-core instruction is followed by three LDS reads of image samples
+  // and seven FMAs of the previous group's application.
+  auto arrive = [&](int tp) {
+    static_assert((NS - 2) * CPW < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" : : "n"((NS - 2) * CPW) : "memory");
+    stage_in(tp + NS - 1);
+  };
+  auto interleave = [&]() {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) pq[s] = ld_frag(prow + size_t(32) * KB + 16 * s);
+    for (int i = 0; i < 2 * KS; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);
+    }
+  };
+  f32x16 al, ar, bl, br;
+  arrive(0);
+  mul(al, ar, 0);
+  constexpr int TPE = NTP > 3 ? 2 * ((NTP - 2) / 2) : 0;   // steady state covers tp < TPE
+  for (int tp = 0; tp < TPE; tp += 2) {
+    arrive(tp + 1);
+    mul(bl, br, tp + 1);
+    apply(al, ar, tp);
+    interleave();
+    arrive(tp + 2);
+    mul(al, ar, tp + 2);
+    apply(bl, br, tp + 1);
+    interleave();
   }
-  for (int t = 0; t < NT; t += 2) {
-    // block t+1: products (its psi was loaded an iteration earlier); block t+2: loads
-    if (t + 1 < NT) {
-      acc1 = f32x16{};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acc1 = mfma_bf16(b[s], pq[s], acc1);
+  for (int tp = TPE; tp < NTP; tp += 2) {
+    if (tp + 1 < NTP) {
+      arrive(tp + 1);
+      mul(bl, br, tp + 1);
     }
-    if (t + 2 < NT) {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) pa[s] = ld_frag(prow + size_t(32 * (t + 2)) * KB + 16 * s);
-    }
-    epilogue(acc0, t);
-    if (t + 1 < NT) {
-      if (t + 2 < NT) {
-        acc0 = f32x16{};
-#pragma unroll
-        for (int s = 0; s < KS; ++s) acc0 = mfma_bf16(b[s], pa[s], acc0);
+    apply(al, ar, tp);
+    if (tp + 1 < NTP) {
+      if (tp + 2 < NTP) {
+        arrive(tp + 2);
+        mul(al, ar, tp + 2);
       }
-      if (t + 3 < NT) {
+      apply(bl, br, tp + 1);
+    }
+  }
+  // the copies issued for groups past the last one are still in flight
+  asm volatile("s_waitcnt vmcnt(0)" : : : "memory");
+  // the 32 lanes of a half hold partial sums of the same 16 pixels: halve the
+  // set of rows each lane keeps at every exchange (keep the rows selected by
+  // the lane's bit, send the others), so after lane bits 16, 8, 4, 2 a lane
+  // holds row r = 8 b16 + 4 b8 + 2 b4 + b2; bit 1 completes the sum
+  float v[C][8];
+  {
+    const bool hi = pn & 16;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) pq[s] = ld_frag(prow + size_t(32 * (t + 3)) * KB + 16 * s);
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float send = hi ? sum[c][k] : sum[c][k + 8];
+        const float keep = hi ? sum[c][k + 8] : sum[c][k];
+        v[c][k] = keep + __shfl_xor(send, 16, 64);
       }
-      epilogue(acc1, t + 1);
-    }
   }
-  // the 32 lanes of a half hold the 32 taps-columns of the same 16 pixels: sum them
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
+  for (int bit = 8, n = 4; bit >= 2; bit >>= 1, n >>= 1) {
+    const bool hi = pn & bit;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      float v = sum[c][r];
+    for (int c = 0; c < C; ++c)
 #pragma unroll
-      for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-      sum[c][r] = v;
-    }
+      for (int k = 0; k < n; ++k) {
+        const float send = hi ? v[c][k] : v[c][k + n];
+        const float keep = hi ? v[c][k + n] : v[c][k];
+        v[c][k] = keep + __shfl_xor(send, bit, 64);
+      }
   }
-  // lane pn < 16 of each half writes pixel m_pn + 4g
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    if (pn != r) continue;
-    const int m = 8 * (r >> 2) + (r & 3) + 4 * g;
-    const int y = ty0 + 2 * w + (m >> 4), x = tx0 + (m & 15);
+  for (int c = 0; c < C; ++c) v[c][0] += __shfl_xor(v[c][0], 1, 64);
+  if ((pn & 1) == 0) {
+    const int r = 8 * ((pn >> 4) & 1) + 4 * ((pn >> 3) & 1) + 2 * ((pn >> 2) & 1) + ((pn >> 1) & 1);
+    const int y = ty0 + 2 * w + (r >> 3), x = tx0 + 8 * ((r >> 2) & 1) + (r & 3) + 4 * g;
     if (y < H && x < W) {
       float *of = out + size_t(f) * C * H * W + size_t(y) * W + x;
       const size_t pl = size_t(H) * W;
 #pragma unroll
-      for (int c = 0; c < C; ++c) of[c * pl] = sum[c][r];
+      for (int c = 0; c < C; ++c) of[c * pl] = v[c][0];
     }
   }
 }
@@ -171,13 +337,29 @@ k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
   const int f = blockIdx.z;
   const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
   const float *imf = img + size_t(f) * C * H * W;
-  for (int e = threadIdx.x; e < C * PLANE; e += 256) {
-    const int c = e / PLANE;
-    const int rem = e - c * PLANE;
-    const int sy = rem / SW, sx = rem - sy * SW;
-    const int gy = min(max(ty0 + sy - R, 0), H - 1);
-    const int gx = min(max(tx0 + sx - R, 0), W - 1);
-    tile[e] = imf[(size_t(c) * H + gy) * W + gx];
+  // tile loads in batches of eight per thread, all requested before any is
+  // stored (a frame spans < 4 GiB)
+  {
+    const char *imb = reinterpret_cast<const char *>(imf);
+    const int NE = C * PLANE;
+    for (int e0 = 0; e0 < NE; e0 += 8 * 256) {
+      float v[8];
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int e = min(e0 + it * 256 + int(threadIdx.x), NE - 1);
+        const int c = e / PLANE;
+        const int rem = e - c * PLANE;
+        const int sy = rem / SW, sx = rem - sy * SW;
+        const int gy = min(max(ty0 + sy - R, 0), H - 1);
+        const int gx = min(max(tx0 + sx - R, 0), W - 1);
+        v[it] = *reinterpret_cast<const float *>(imb + uint32_t(4u * uint32_t((c * H + gy) * W + gx)));
+      }
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int e = e0 + it * 256 + int(threadIdx.x);
+        if (e < NE) tile[e] = v[it];
+      }
+    }
   }
   for (int e = threadIdx.x; e < NT * 32; e += 256) {
     const int uy = e / T - R, ux = e % T - R;
@@ -250,11 +432,12 @@ k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
   }
 }
 
-// Dynamic LDS of the image tile; tiles above 64 KB (T = 65) need the
-// device's larger workgroup limit, checked here and raised on the kernel.
+// Dynamic LDS of the image tile (plus, for T > 0, the FP32 kernel's static
+// offset table); tiles above 64 KB need the device's larger workgroup limit,
+// checked here and raised on the kernel.
 template <typename Kern>
 int prepare_lds(Kern kern, size_t lds, int T) {
-  const size_t stat = sizeof(short) * size_t((T * T + 31) / 32 * 32);
+  const size_t stat = T > 0 ? sizeof(short) * size_t((T * T + 31) / 32 * 32) : 0;
   int dev = 0, max_lds = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -267,16 +450,28 @@ int prepare_lds(Kern kern, size_t lds, int T) {
   return TSIM_OK;
 }
 
+template <int KS, int T, int C, int TH>
+int launch_ks_tch(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta, float *out,
+                  hipStream_t s) {
+  using G = PairGeom<T, TH, KS * 16, C>;
+  const int H = pl->H, W = pl->W;
+  if (size_t(C) * H * W * sizeof(float) >= (size_t(1) << 32)) return TSIM_EUNSUPPORTED;
+  if (pl->KP != KS * 16) return TSIM_EINVAL;
+  dim3 grid((W + 15) / 16, (H + TH - 1) / TH, frames);
+  const int st = prepare_lds(k_render_bf16<KS, T, C, TH>, G::LDS, 0);
+  if (st != TSIM_OK) return st;
+  hipLaunchKernelGGL((k_render_bf16<KS, T, C, TH>), grid, dim3(32 * TH), G::LDS, s, img, beta, pl->d_basis_bf,
+                     out, H, W);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+// The 65-tap tile leaves LDS for one block per CU: 16 output rows (8 waves)
+// keep two waves per SIMD there; smaller kernels, and the wide forms that
+// run one wave per SIMD, use 8-row blocks.
 template <int KS, int T, int C>
 int launch_ks_tc(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta, float *out,
                  hipStream_t s) {
-  const int H = pl->H, W = pl->W;
-  dim3 grid((W + 15) / 16, (H + 7) / 8, frames);
-  const size_t lds = size_t(C) * (8 + T - 1) * (16 + T - 1) * sizeof(float);
-  const int st = prepare_lds(k_render_bf16<KS, T, C>, lds, T);
-  if (st != TSIM_OK) return st;
-  hipLaunchKernelGGL((k_render_bf16<KS, T, C>), grid, dim3(256), lds, s, img, beta, pl->d_basis_bf, out, H, W);
-  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+  return launch_ks_tch<KS, T, C, (T == 65 && !kWide<KS, T, C> ? 16 : 8)>(pl, frames, img, beta, out, s);
 }
 
 template <int KS, int T>
@@ -309,6 +504,7 @@ int launch_render_f32_mfma(const tsim_plan *pl, int frames, const float *img, co
                            float *out, hipStream_t s) {
   const int H = pl->H, W = pl->W, C = pl->C, T = pl->T;
   if (!pl->d_basis_k2 || pl->K != 100 || (T != 33 && T != 65)) return TSIM_EUNSUPPORTED;
+  if (size_t(C) * H * W * sizeof(float) >= (size_t(1) << 32)) return TSIM_EUNSUPPORTED;
   dim3 grid((W + 15) / 16, (H + 7) / 8, frames);
   const size_t lds = size_t(C) * (8 + T - 1) * (16 + T - 1) * sizeof(float);
   const int st = T == 33 ? prepare_lds(k_render_f32m<50, 33>, lds, T) : prepare_lds(k_render_f32m<50, 65>, lds, T);

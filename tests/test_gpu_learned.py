@@ -138,6 +138,34 @@ def test_render_bf16_matches_eq8_on_rounded_operands(t, basis):
         assert rel(got[c], ref) < 1e-5, c
 
 
+@pytest.mark.parametrize("T,C,K,H,W", [(15, 1, 20, 19, 37), (21, 2, 60, 24, 33), (33, 4, 120, 17, 48),
+                                       (65, 2, 100, 21, 35)])
+def test_render_bf16_kernel_shapes(t, T, C, K, H, W):
+    """Every (kernel size, channel count, padded basis size) form of the
+    BF16 blur on ragged frames: 32, 64 and 128-wide bases, 4 to 68 groups of
+    tap pairs (steady-state loop and its compile-time tail), 8- and 16-row
+    blocks."""
+    say(f"render bf16 T={T} C={C} K={K} {H}x{W}")
+    P = 128 if T == 65 else 64
+    A, _ = opsf.basis_draws(max(300, 2 * K), seed=40 + T)
+    Psi = opsf.pca_basis(opsf.psf_batch(A, P, T), K)[0]
+    plan = t.Plan(H, W, C, 64, 64, psf_t=T, pupil_n=P, basis=Psi, p2s_mode=t.P2S_LEARNED, precision=t.BF16)
+    KP = 32 if K <= 32 else 64 if K <= 64 else 112 if K <= 112 else 128
+    img = synthetic.test_image(C, H, W, 4, seed=T)[None]
+    b = synthetic.random_coefficients((1, H, W, K), 0.05, T + 1)
+    b[..., 0] += 1.0
+    bpad = np.zeros((1, H, W, KP), dtype=np.float32)
+    bpad[..., :K] = b
+    out = torch.empty((1, C, H, W), dtype=torch.float32, device="cuda")
+    plan.render(torch.tensor(img, device="cuda"), torch.tensor(bpad, device="cuda").to(torch.bfloat16), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0]
+    br, Pr = omlp.to_bf16(b[0].astype(np.float64)), omlp.to_bf16(Psi)
+    for c in range(C):
+        ref = orender.render_basis(img[0, c].astype(np.float64), br, Pr, T)
+        assert rel(got[c], ref) < 1e-5, c
+
+
 def test_training_pairs_match_oracle(t, basis):
     say("training pairs n=2000")
     plan = t.Plan(32, 32, 1, 64, 64, basis=basis)
