@@ -23,10 +23,12 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
           "-Wno-unused-command-line-argument"]
 
 
-# Matrix-core accumulators in ordinary VGPRs for the blur kernels: their
-# epilogues read every accumulator with vector ALU instructions, which
-# otherwise each need a copy out of the accumulation registers first.
-EXTRA = {"render_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Matrix-core accumulators in ordinary VGPRs for the blur and network
+# kernels: their epilogues read every accumulator with vector ALU
+# instructions, which otherwise each need a copy out of the accumulation
+# registers first.
+EXTRA = {"render_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def sources():

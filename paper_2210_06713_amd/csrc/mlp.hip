@@ -11,8 +11,9 @@
 //                      gradient (dZ^T X) products share it; fused epilogues
 //                      add the bias and apply GELU or its derivative.
 //   k_mlp_infer        fused per-pixel inference for the P2S step: each wave
-//                      carries 32 pixels through all four layers, the
-//                      activations staying in LDS, weights streamed from L2.
+//                      carries 64 pixels through all four layers, the
+//                      activations staying in LDS, weights streamed from L2
+//                      three k-steps ahead of their products.
 //   k_prep, k_mse_grad, k_colsum, k_adamw, k_init_normal, k_draws: data
 //                      preparation, loss, bias gradients, optimiser, seeded
 //                      initialisation and training-pair draws.
@@ -245,44 +246,70 @@ constexpr int IPX = 128;     // pixels per inference block (four 32-row tiles)
 // The inference GELU, z Phi(z) = max(z, 0) - |z| erfc(|z| / sqrt 2) / 2 (one
 // expression for both signs), with erfc by Abramowitz & Stegun 7.1.26:
 // erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x),
-// |error| <= 1.5e-7; the coefficients below are a_i / 2 and p / sqrt 2.
+// |error| <= 1.5e-7; the coefficients below are a_i / 2 and p / sqrt 2, and
+// exp(-z^2 / 2) = 2^(-z^2 log2(e) / 2) on the hardware exponential.
 __device__ __forceinline__ float gelu_fast(float z) {
   const float a = fabsf(z);
   const float t = __builtin_amdgcn_rcpf(fmaf(0.231641888f, a, 1.0f));
   const float q = fmaf(fmaf(fmaf(fmaf(0.5307027145f, t, -0.7265760135f), t, 0.7107068705f), t,
-                            -0.142248368f), t, 0.127414796f) * t;
-  const float e = __expf(-0.5f * a * a);
-  return fmaf(-q, e * a, fmaxf(z, 0.f));
+                            -0.142248368f), t, 0.127414796f);
+  const float e = __builtin_amdgcn_exp2f(-0.72134752044448170f * a * a);
+  return fmaf(-(q * t), e * a, fmaxf(z, 0.f));
+}
+
+// Weight fragments of one layer for this wave, WD k-steps in flight: the
+// loads for k-step s + WD are issued as soon as k-step s has been consumed,
+// and the first WD k-steps of a layer while the previous layer's activations
+// are formed.
+constexpr int WD = 3;
+template <int NT>
+struct WRing {
+  uint4 f[WD][NT];
+};
+
+// fragment (row n0 + 32t + lane % 32, k-slice 16s + 8 (lane / 32)) of a
+// weight matrix (< 4 GiB): uniform base, 32-bit per-lane byte offset
+__device__ __forceinline__ uint4 wfrag(const uint16_t *__restrict__ W, uint32_t lane_off, uint32_t off) {
+  return *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(W) + (lane_off + off));
+}
+
+template <int NT, int KSTEPS>
+__device__ __forceinline__ void w_prefetch(WRing<NT> &ring, const uint16_t *__restrict__ W, int ldw, int n0,
+                                           int lane) {
+  const uint32_t lo = uint32_t(((n0 + (lane & 31)) * ldw + 8 * (lane >> 5)) * 2);
+#pragma unroll
+  for (int d = 0; d < WD && d < KSTEPS; ++d)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) ring.f[d][t] = wfrag(W, lo, uint32_t((t * 32 * ldw + d * 16) * 2));
 }
 
 // acc[i][t] (i < 2, t < NT) = act[32 rows of tile i][KSTEPS*16] x W[n0 + 32t + .][.]^T:
 // each weight fragment feeds the two row tiles
 template <int NT, int KSTEPS>
 __device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__restrict__ W, int ldw,
-                                         int n0, f32x16 (&acc)[2][NT], int lane) {
+                                         int n0, f32x16 (&acc)[2][NT], WRing<NT> &ring, int lane) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[0][t] = acc[1][t] = f32x16{};
-  const uint16_t *wrow = W + size_t(n0 + (lane & 31)) * ldw + 8 * (lane >> 5);
+  const uint32_t lo = uint32_t(((n0 + (lane & 31)) * ldw + 8 * (lane >> 5)) * 2);
   const uint16_t *arow = act + (lane & 31) * ACT_LD + 8 * (lane >> 5);
-  uint4 b[NT], bn[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) b[t] = load8(wrow + size_t(t) * 32 * ldw);
+  // activation fragments one k-step ahead of their products
+  uint4 a0n = load8(arow), a1n = load8(arow + 32 * ACT_LD);
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
+    const uint4 a0 = a0n, a1 = a1n;
     if (s + 1 < KSTEPS) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) bn[t] = load8(wrow + size_t(t) * 32 * ldw + (s + 1) * 16);
+      a0n = load8(arow + (s + 1) * 16);
+      a1n = load8(arow + 32 * ACT_LD + (s + 1) * 16);
     }
-    const uint4 a0 = load8(arow + s * 16);
-    const uint4 a1 = load8(arow + 32 * ACT_LD + s * 16);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      acc[0][t] = mfma_bf16(a0, b[t], acc[0][t]);
-      acc[1][t] = mfma_bf16(a1, b[t], acc[1][t]);
+      acc[0][t] = mfma_bf16(a0, ring.f[s % WD][t], acc[0][t]);
+      acc[1][t] = mfma_bf16(a1, ring.f[s % WD][t], acc[1][t]);
     }
-    if (s + 1 < KSTEPS) {
+    if (s + WD < KSTEPS) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = bn[t];
+      for (int t = 0; t < NT; ++t)
+        ring.f[s % WD][t] = wfrag(W, lo, uint32_t((t * 32 * ldw + (s + WD) * 16) * 2));
     }
   }
 }
@@ -324,6 +351,8 @@ k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip
   const int mp = w >> 1, nh = w & 1;
   uint16_t *act = act_all + mp * 64 * ACT_LD;
   const size_t pb = size_t(blockIdx.x) * IPX;
+  WRing<4> ring;
+  w_prefetch<4, IN_PAD / 16>(ring, ip.W1, IN_PAD, nh * 128, lane);
   {
     // inputs: thread -> pixel (tid % 128), modes [24 (tid / 128), +24)
     const int px = threadIdx.x & 127, j0 = (threadIdx.x >> 7) * 24;
@@ -341,20 +370,24 @@ k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip
   }
   __syncthreads();
   f32x16 acc[2][4];
-  mlp_tile<4, IN_PAD / 16>(act, ip.W1, IN_PAD, nh * 128, acc, lane);
+  mlp_tile<4, IN_PAD / 16>(act, ip.W1, IN_PAD, nh * 128, acc, ring, lane);
+  w_prefetch<4, HID / 16>(ring, ip.W2, HID, nh * 128, lane);
   __syncthreads();
   mlp_store_gelu<4>(act, acc, ip.b1, nh * 128, lane);
   __syncthreads();
-  mlp_tile<4, HID / 16>(act, ip.W2, HID, nh * 128, acc, lane);
+  mlp_tile<4, HID / 16>(act, ip.W2, HID, nh * 128, acc, ring, lane);
+  w_prefetch<4, HID / 16>(ring, ip.W3, HID, nh * 128, lane);
   __syncthreads();
   mlp_store_gelu<4>(act, acc, ip.b2, nh * 128, lane);
   __syncthreads();
-  mlp_tile<4, HID / 16>(act, ip.W3, HID, nh * 128, acc, lane);
+  mlp_tile<4, HID / 16>(act, ip.W3, HID, nh * 128, acc, ring, lane);
+  WRing<2> ring2;
+  w_prefetch<2, HID / 16>(ring2, ip.W4, HID, nh * 64, lane);
   __syncthreads();
   mlp_store_gelu<4>(act, acc, ip.b3, nh * 128, lane);
   __syncthreads();
   f32x16 acc2[2][2];
-  mlp_tile<2, HID / 16>(act, ip.W4, HID, nh * 64, acc2, lane);
+  mlp_tile<2, HID / 16>(act, ip.W4, HID, nh * 64, acc2, ring2, lane);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int n = nh * 64 + t * 32 + (lane & 31);

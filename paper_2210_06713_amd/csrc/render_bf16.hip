@@ -44,7 +44,9 @@ __device__ __forceinline__ f32x16 mfma_bf16(const uint4 &a, const uint4 &b, cons
 // modulo 32, and a lane's words of one channel lie within 255 words of its
 // base.  The basis is staged in groups of 32 tap pairs, rows of KPP = KP + 8
 // coefficients (the 16-byte pad keeps the lanes' 16-byte reads on distinct
-// banks), NS groups in flight.
+// banks), in a ring of three stages: while group tp is multiplied, group
+// tp + 1 is resident and group tp + 2 is being copied into the stage that
+// group tp - 1 has just left.
 template <int T, int TH, int KP, int C>
 struct PairGeom {
   static_assert(T % 2 == 1, "odd kernel size");
@@ -61,8 +63,9 @@ struct PairGeom {
   static constexpr int GB = 64 * KPP * 2;          // bytes of one group: [2 sides][32 pairs][KPP]
   static constexpr int NCH = GB / 1024;            // 1 KB wave copies per group
   static constexpr size_t BASE = size_t(C) * CH * 4 + size_t(NTP) * 32 * 4;   // tile + lane bases
-  static constexpr int NS = BASE + 3 * size_t(GB) <= 160 * 1024 ? 3 : 2;
+  static constexpr int NS = 3;
   static constexpr size_t LDS = BASE + size_t(NS) * GB;
+  static constexpr bool kFits = LDS <= 160 * 1024;
   static_assert(GB % 1024 == 0, "whole wave copies");
   static_assert(RSR + SWH + 5 < 256, "read offsets");
 };
@@ -116,8 +119,8 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
       copy_to_lds(src + piece * 1024, dst + uint32_t(piece * 1024), lane);
     }
   };
-#pragma unroll
-  for (int tp = 0; tp < NS - 1; ++tp) stage_in(tp);
+  stage_in(0);
+  stage_in(1);
   // A operand: beta of pixel pn of the wave (rows 2w, 2w + 1 of the block)
   uint4 b[KS];
   {
@@ -178,16 +181,18 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
   // px0 + 2R - 2i (even), the right tap column q0 + j - 1.  The run's five
   // columns q0 - 1 .. q0 + 3 are words k0 = q0 / 2 and k0 + 1 of the even
   // half and k0 - 1 .. k0 + 1 of the odd half, k0 = (lane base) + 4 (run % 2)
-  auto apply = [&](const f32x16 &xl, const f32x16 &xr, int tp) {
-    // one base per channel, kept opaque so that every read folds its
-    // compile-time offset (< 256 words) into the LDS instruction
-    int cb[C];
-    cb[0] = wbase + ltab[32 * tp + pn];
+  // one base per channel, kept opaque so that every read folds its
+  // compile-time offset (< 256 words) into the LDS instruction; the bases of
+  // the group to be applied next are formed a group early
+  auto bases = [&](int tp, int (&cb)[C]) {
+    cb[0] = wbase + ltab[32 * min(tp, NTP - 1) + pn];
 #pragma unroll
     for (int c = 1; c < C; ++c) {
       cb[c] = cb[0] + c * CH;
       asm volatile("" : "+v"(cb[c]));
     }
+  };
+  auto apply = [&](const f32x16 &xl, const f32x16 &xr, const int (&cb)[C]) {
     const float *tf = reinterpret_cast<const float *>(tile);
 #pragma unroll
     for (int run = 0; run < 4; ++run) {
@@ -205,37 +210,24 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
       }
     }
   };
-  // B operand from the ring: psi^T column = tap pair pn, k-slice 8g..8g+7
+  // B operand from the ring: psi^T column = tap pair pn, k-slice 8g..8g+7.
+  // A group's left fragments are read one step before its products, its
+  // right fragments at the start of its own step (needed only after the
+  // seven left products), so no product waits for LDS.
   const char *frag = ring + (pn * KPP + 8 * g) * 2;
-  // all fragments of a group are read before its first product (a
-  // scheduling fence keeps the reads ahead), so only that one waits for LDS
-  uint4 fl[KS], fr[KS];
-  auto mul = [&](f32x16 &al, f32x16 &ar, int tp) {
+  auto read_left = [&](int tp, uint4 (&fl)[KS]) {
     const char *st = frag + (tp % NS) * GB;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      fl[s] = *reinterpret_cast<const uint4 *>(st + 32 * s);
-      fr[s] = *reinterpret_cast<const uint4 *>(st + 32 * KPP * 2 + 32 * s);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    al = f32x16{};
-    ar = f32x16{};
+    for (int s = 0; s < KS; ++s) fl[s] = *reinterpret_cast<const uint4 *>(st + 32 * s);
+  };
+  uint4 fr[KS];
+  auto read_right = [&](int tp) {
+    const char *st = frag + (tp % NS) * GB + 32 * KPP * 2;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      al = mfma_bf16(b[s], fl[s], al);
-      ar = mfma_bf16(b[s], fr[s], ar);
-    }
+    for (int s = 0; s < KS; ++s) fr[s] = *reinterpret_cast<const uint4 *>(st + 32 * s);
   };
-  // group tp: wait for this wave's copies of it (NS - 2 later groups may
-  // still be in flight), meet the other waves (all copies landed; all reads
-  // of the stage about to be refilled done), refill, multiply.  Each
-  // matrix-core instruction is followed by three LDS reads of image samples
-  // and seven FMAs of the previous group's application.
-  auto arrive = [&](int tp) {
-    static_assert((NS - 2) * CPW < 64, "vmcnt range");
-    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" : : "n"((NS - 2) * CPW) : "memory");
-    stage_in(tp + NS - 1);
-  };
+  // each matrix-core instruction is followed by three LDS reads of image
+  // samples and seven FMAs of the previous group's application
   auto interleave = [&]() {
 #pragma unroll
     for (int i = 0; i < 2 * KS; ++i) {
@@ -244,34 +236,48 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
       __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);
     }
   };
-  f32x16 al, ar, bl, br;
-  arrive(0);
-  mul(al, ar, 0);
-  constexpr int TPE = NTP > 3 ? 2 * ((NTP - 2) / 2) : 0;   // steady state covers tp < TPE
-  for (int tp = 0; tp < TPE; tp += 2) {
-    arrive(tp + 1);
-    mul(bl, br, tp + 1);
-    apply(al, ar, tp);
-    interleave();
-    arrive(tp + 2);
-    mul(al, ar, tp + 2);
-    apply(bl, br, tp + 1);
-    interleave();
-  }
+  // step tp: meet the other waves (group tp + 1 has landed: this wave's
+  // copies of it are its only ones in flight; every read of group tp - 1's
+  // stage is done), refill that stage with group tp + 2, read fragments,
+  // multiply group tp and apply group tp - 1
+  auto step = [&](int tp, f32x16 &al, f32x16 &ar, uint4 (&fl)[KS], uint4 (&fln)[KS], bool next,
+                  const f32x16 &pl_, const f32x16 &pr_, int (&cp)[C], bool prev) {
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" : : : "memory");
+    stage_in(tp + 2);
+    read_right(tp);
+    if (next) read_left(tp + 1, fln);
+    __builtin_amdgcn_sched_barrier(0);
+    al = f32x16{};
+    ar = f32x16{};
 #pragma unroll
-  for (int tp = TPE; tp < NTP; tp += 2) {
-    if (tp + 1 < NTP) {
-      arrive(tp + 1);
-      mul(bl, br, tp + 1);
+    for (int s = 0; s < KS; ++s) al = mfma_bf16(b[s], fl[s], al);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) ar = mfma_bf16(b[s], fr[s], ar);
+    if (prev) {
+      apply(pl_, pr_, cp);
+      bases(tp + 1, cp);
+      interleave();
     }
-    apply(al, ar, tp);
-    if (tp + 1 < NTP) {
-      if (tp + 2 < NTP) {
-        arrive(tp + 2);
-        mul(al, ar, tp + 2);
-      }
-      apply(bl, br, tp + 1);
-    }
+  };
+  f32x16 al, ar, bl, br;
+  int ca[C], cbb[C];
+  uint4 fla[KS], flb[KS];
+  bases(0, ca);
+  bases(1, cbb);
+  read_left(0, fla);
+  step(0, al, ar, fla, flb, NTP > 1, bl, br, cbb, false);
+  // steps 1, 2, ... in pairs while both read a next group; the rest resolved at compile time
+  constexpr int TS = 1 + 2 * (NTP > 2 ? (NTP - 2) / 2 : 0);
+  for (int tp = 1; tp < TS; tp += 2) {
+    step(tp, bl, br, flb, fla, true, al, ar, ca, true);
+    step(tp + 1, al, ar, fla, flb, true, bl, br, cbb, true);
+  }
+  if constexpr (NTP - TS >= 1) step(TS, bl, br, flb, fla, TS + 1 < NTP, al, ar, ca, true);
+  if constexpr (NTP - TS >= 2) step(TS + 1, al, ar, fla, flb, TS + 2 < NTP, bl, br, cbb, true);
+  if constexpr (((NTP - 1) & 1) != 0) {
+    apply(bl, br, cbb);
+  } else {
+    apply(al, ar, ca);
   }
   // the copies issued for groups past the last one are still in flight
   asm volatile("s_waitcnt vmcnt(0)" : : : "memory");
@@ -466,12 +472,21 @@ int launch_ks_tch(const tsim_plan *pl, int frames, const float *img, const uint1
 }
 
 // The 65-tap tile leaves LDS for one block per CU: 16 output rows (8 waves)
-// keep two waves per SIMD there; smaller kernels, and the wide forms that
-// run one wave per SIMD, use 8-row blocks.
+// keep two waves per SIMD there; other kernels use 8-row blocks, and the
+// widest forms 4-row blocks where an 8-row tile and the basis ring would not
+// fit the LDS.
 template <int KS, int T, int C>
 int launch_ks_tc(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta, float *out,
                  hipStream_t s) {
-  return launch_ks_tch<KS, T, C, (T == 65 && !kWide<KS, T, C> ? 16 : 8)>(pl, frames, img, beta, out, s);
+  constexpr int KP = KS * 16;
+  if constexpr (T == 65 && !kWide<KS, T, C> && PairGeom<T, 16, KP, C>::kFits)
+    return launch_ks_tch<KS, T, C, 16>(pl, frames, img, beta, out, s);
+  else if constexpr (PairGeom<T, 8, KP, C>::kFits)
+    return launch_ks_tch<KS, T, C, 8>(pl, frames, img, beta, out, s);
+  else if constexpr (PairGeom<T, 4, KP, C>::kFits)
+    return launch_ks_tch<KS, T, C, 4>(pl, frames, img, beta, out, s);
+  else
+    return TSIM_EUNSUPPORTED;
 }
 
 template <int KS, int T>
