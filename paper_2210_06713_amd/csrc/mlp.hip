@@ -14,7 +14,7 @@
 //                      carries 64 pixels through all four layers, the
 //                      activations staying in LDS, weights streamed from L2
 //                      three k-steps ahead of their products.
-//   k_prep, k_mse_grad, k_colsum, k_adamw, k_init_normal, k_draws: data
+//   k_prep, k_mse_grad, k_colsum_*, k_adamw, k_init_normal, k_draws: data
 //                      preparation, loss, bias gradients, optimiser, seeded
 //                      initialisation and training-pair draws.
 #include <algorithm>
@@ -155,16 +155,39 @@ __global__ void k_mse_grad(const float *__restrict__ Y, const float *__restrict_
 }
 
 // db[n] = sum_m dZ[m][n]
-__global__ void k_colsum(const float *__restrict__ dz, int M, int N, float *__restrict__ db) {
+// Column sums db[n] = sum_m dz[m][n] (M x N, N <= 256) in two passes with a
+// fixed order: blocks of 64 columns x one chunk of rows write partial sums,
+// then the partials are added in chunk order.
+constexpr int CS_CHUNKS = 256;
+__global__ void k_colsum_part(const float *__restrict__ dz, int M, int N, int rows, float *__restrict__ part) {
   const int n = blockIdx.x * 64 + (threadIdx.x & 63);
   const int g = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * rows, m1 = min(M, m0 + rows);
   __shared__ float red[4][64];
   float s = 0.f;
   if (n < N)
-    for (int m = g; m < M; m += 4) s += dz[size_t(m) * N + n];
+    for (int m = m0 + g; m < m1; m += 4) s += dz[size_t(m) * N + n];
   red[g][threadIdx.x & 63] = s;
   __syncthreads();
-  if (g == 0 && n < N) db[n] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+  if (g == 0 && n < N)
+    part[size_t(blockIdx.y) * N + n] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                                       red[3][threadIdx.x];
+}
+
+__global__ void k_colsum_fin(const float *__restrict__ part, int chunks, int N, float *__restrict__ db) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[size_t(c) * N + n];
+  db[n] = s;
+}
+
+// part holds CS_CHUNKS * N floats
+void colsum(hipStream_t s, const float *dz, int M, int N, float *db, float *part) {
+  const int chunks = std::max(1, std::min(CS_CHUNKS, (M + 255) / 256));
+  const int rows = (M + chunks - 1) / chunks;
+  hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, chunks), dim3(256), 0, s, dz, M, N, rows, part);
+  hipLaunchKernelGGL(k_colsum_fin, dim3((N + 255) / 256), dim3(256), 0, s, part, chunks, N, db);
 }
 
 // sum of squared deviations from mu over [n][K] (output scale of the network)
@@ -435,6 +458,7 @@ struct tsim_mlp {
   uint16_t *x = nullptr, *act[3] = {nullptr, nullptr, nullptr}, *dzb = nullptr;
   float *z[3] = {nullptr, nullptr, nullptr}, *y = nullptr, *t = nullptr, *dzf = nullptr;
   float *loss = nullptr;
+  float *colpart = nullptr;                                      // [CS_CHUNKS][256] column-sum partials
   int step = 0;
   std::vector<double> A0diag;
 };
@@ -444,7 +468,7 @@ namespace {
 void mlp_free(tsim_mlp *n) {
   if (!n) return;
   void *ptrs[] = {n->w, n->g, n->m, n->v, n->wb, n->inv_s, n->mu, n->x, n->act[0], n->act[1],
-                  n->act[2], n->dzb, n->z[0], n->z[1], n->z[2], n->y, n->t, n->dzf, n->loss};
+                  n->act[2], n->dzb, n->z[0], n->z[1], n->z[2], n->y, n->t, n->dzf, n->loss, n->colpart};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete n;
@@ -487,8 +511,7 @@ int mlp_fwd_bwd(tsim_mlp *n, int Bsz, hipStream_t s) {
       return TSIM_EDEVICE;
     if ((st = gemm<EPI_F32_ADD>(s, n->dzb, 1, dout, in, din, 1, dout, din, Bsz, nullptr, nullptr,
                                 n->g + n->off_w[l], nullptr, din, splits)) != TSIM_OK) return st;
-    hipLaunchKernelGGL(k_colsum, dim3((dout + 63) / 64), dim3(256), 0, s, n->dzf, Bsz, dout,
-                       n->g + n->off_b[l]);
+    colsum(s, n->dzf, Bsz, dout, n->g + n->off_b[l], n->colpart);
     if (l > 0) {
       // dA = dZ W (M = batch, N = din, reduction over dout), then dZ_prev = dA * GELU'(Z_prev).
       // dZ of width din is written after the product has consumed dZ of width dout,
@@ -535,7 +558,8 @@ int tsim_mlp_create(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **ou
   bool ok = dalloc(&n->w, off) && dalloc(&n->g, off) && dalloc(&n->m, off) && dalloc(&n->v, off) &&
             dalloc(&n->wb, off) && dalloc(&n->inv_s, TSIM_N_MODES) && dalloc(&n->mu, 128) &&
             dalloc(&n->x, B * TSIM_N_MODES) && dalloc(&n->y, B * pl->K) && dalloc(&n->t, B * pl->K) &&
-            dalloc(&n->dzf, 2 * B * 256) && dalloc(&n->dzb, 2 * B * 256) && dalloc(&n->loss, 1 << 20);
+            dalloc(&n->dzf, 2 * B * 256) && dalloc(&n->dzb, 2 * B * 256) && dalloc(&n->loss, 1 << 20) &&
+            dalloc(&n->colpart, size_t(CS_CHUNKS) * 256);
   for (int l = 0; l < 3 && ok; ++l) ok = dalloc(&n->act[l], B * HID) && dalloc(&n->z[l], B * HID);
   if (!ok) {
     mlp_free(n);
@@ -683,7 +707,7 @@ int tsim_mlp_grad(tsim_mlp *n, int batch, const float *zvec, const float *target
 int tsim_mlp_fit_output(tsim_mlp *n, const float *target, int n_pairs, tsim_stream stream) {
   if (!n || !target || n_pairs < 1) return TSIM_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_colsum, dim3((n->K + 63) / 64), dim3(256), 0, s, target, n_pairs, n->K, n->mu);
+  colsum(s, target, n_pairs, n->K, n->mu, n->colpart);
   hipLaunchKernelGGL(k_scale, dim3(1), dim3(128), 0, s, n->mu, n->K, 1.0f / float(n_pairs));
   if (hipMemsetAsync(n->loss, 0, 4, s) != hipSuccess) return TSIM_EDEVICE;
   const size_t nel = size_t(n_pairs) * n->K;
