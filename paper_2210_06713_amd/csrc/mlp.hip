@@ -36,6 +36,13 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // float -> bfloat16, nearest with ties to even (the hardware conversion)
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, __bf16(f)); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+// two floats -> two bfloat16 in one word (lo = first), nearest-even, one
+// packed conversion
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{lo, hi}), bf16x2));
+}
 
 __device__ __forceinline__ float gelu(float z) {
   return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
@@ -306,29 +313,36 @@ __device__ __forceinline__ void w_prefetch(WRing<NT> &ring, const uint16_t *__re
     for (int t = 0; t < NT; ++t) ring.f[d][t] = wfrag(W, lo, uint32_t((t * 32 * ldw + d * 16) * 2));
 }
 
-// acc[i][t] (i < 2, t < NT) = act[32 rows of tile i][KSTEPS*16] x W[n0 + 32t + .][.]^T:
-// each weight fragment feeds the two row tiles
-template <int NT, int KSTEPS>
+// acc[i][t] (i < RT, t < NT) = W[n0 + 32t + .][KSTEPS*16] x act[32 rows of tile i][.]^T,
+// the transposed product: each weight fragment feeds the RT pixel tiles, and
+// a lane holds pixel m = 32i + lane % 32 and neurons n0 + 32t + 8(r/4) +
+// 4(lane/32) + r%4, four adjacent neurons per register quad
+template <int RT, int NT, int KSTEPS>
 __device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__restrict__ W, int ldw,
-                                         int n0, f32x16 (&acc)[2][NT], WRing<NT> &ring, int lane) {
+                                         int n0, f32x16 (&acc)[RT][NT], WRing<NT> &ring, int lane) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[0][t] = acc[1][t] = f32x16{};
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[i][t] = f32x16{};
   const uint32_t lo = uint32_t(((n0 + (lane & 31)) * ldw + 8 * (lane >> 5)) * 2);
   const uint16_t *arow = act + (lane & 31) * ACT_LD + 8 * (lane >> 5);
   // activation fragments one k-step ahead of their products
-  uint4 a0n = load8(arow), a1n = load8(arow + 32 * ACT_LD);
+  uint4 an[RT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i) an[i] = load8(arow + 32 * i * ACT_LD);
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
-    const uint4 a0 = a0n, a1 = a1n;
+    uint4 a[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) a[i] = an[i];
     if (s + 1 < KSTEPS) {
-      a0n = load8(arow + (s + 1) * 16);
-      a1n = load8(arow + 32 * ACT_LD + (s + 1) * 16);
+#pragma unroll
+      for (int i = 0; i < RT; ++i) an[i] = load8(arow + 32 * i * ACT_LD + (s + 1) * 16);
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      acc[0][t] = mfma_bf16(a0, ring.f[s % WD][t], acc[0][t]);
-      acc[1][t] = mfma_bf16(a1, ring.f[s % WD][t], acc[1][t]);
-    }
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int i = 0; i < RT; ++i) acc[i][t] = mfma_bf16(ring.f[s % WD][t], a[i], acc[i][t]);
     if (s + WD < KSTEPS) {
 #pragma unroll
       for (int t = 0; t < NT; ++t)
@@ -337,21 +351,26 @@ __device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__
   }
 }
 
-template <int NT>
-__device__ __forceinline__ void mlp_store_gelu(uint16_t *act, const f32x16 (&acc)[2][NT],
+// GELU(acc + bias) of four adjacent neurons packed into one 8-byte LDS write
+template <int RT, int NT>
+__device__ __forceinline__ void mlp_store_gelu(uint16_t *act, const f32x16 (&acc)[RT][NT],
                                                const float *__restrict__ bias, int n0, int lane) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int n = n0 + t * 32 + (lane & 31);
-    const float bn = bias[n];
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int q = 0; q < 4; ++q) {
+      const int n = n0 + 32 * t + 8 * q + 4 * (lane >> 5);
+      const float4 bn = *reinterpret_cast<const float4 *>(bias + n);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        act[m * ACT_LD + n] = f2bf(gelu_fast(acc[i][t][r] + bn));
+      for (int i = 0; i < RT; ++i) {
+        const int m = 32 * i + (lane & 31);
+        const f32x16 &a = acc[i][t];
+        uint2 w;
+        w.x = pack_bf16(gelu_fast(a[4 * q] + bn.x), gelu_fast(a[4 * q + 1] + bn.y));
+        w.y = pack_bf16(gelu_fast(a[4 * q + 2] + bn.z), gelu_fast(a[4 * q + 3] + bn.w));
+        *reinterpret_cast<uint2 *>(act + m * ACT_LD + n) = w;
       }
-  }
+    }
 }
 
 struct InferParams {
@@ -364,18 +383,17 @@ struct InferParams {
   int out_bf16;
 };
 
-// Block: 128 pixels, 4 waves.  Wave w computes rows 64 (w >> 1) .. +63 (two
-// 32-row tiles) and the output columns [128 (w & 1), +128) of each hidden
-// layer (64 for the last), activations in place in LDS between layers.
+// Block: 128 pixels (four 32-row tiles), 4 waves.  Wave w computes the
+// neurons [64 w, +64) of each hidden layer ([32 w, +32) of the last) for all
+// 128 pixels, so a weight fragment feeds four products; activations in
+// place in LDS between layers.
 __global__ void __launch_bounds__(256)
 k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip, void *__restrict__ beta) {
-  __shared__ __attribute__((aligned(16))) uint16_t act_all[IPX * ACT_LD];
+  __shared__ __attribute__((aligned(16))) uint16_t act[IPX * ACT_LD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int mp = w >> 1, nh = w & 1;
-  uint16_t *act = act_all + mp * 64 * ACT_LD;
   const size_t pb = size_t(blockIdx.x) * IPX;
-  WRing<4> ring;
-  w_prefetch<4, IN_PAD / 16>(ring, ip.W1, IN_PAD, nh * 128, lane);
+  WRing<2> ring;
+  w_prefetch<2, IN_PAD / 16>(ring, ip.W1, IN_PAD, w * 64, lane);
   {
     // inputs: thread -> pixel (tid % 128), modes [24 (tid / 128), +24)
     const int px = threadIdx.x & 127, j0 = (threadIdx.x >> 7) * 24;
@@ -388,48 +406,69 @@ k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip
     for (int q = 0; q < 24; ++q) {
       const int j = j0 + q;
       const float v = (ok && j < TSIM_N_MODES) ? zp[size_t(j) * hw] * ip.inv_s[j] : 0.f;
-      act_all[px * ACT_LD + j] = f2bf(v);
+      act[px * ACT_LD + j] = f2bf(v);
     }
   }
   __syncthreads();
-  f32x16 acc[2][4];
-  mlp_tile<4, IN_PAD / 16>(act, ip.W1, IN_PAD, nh * 128, acc, ring, lane);
-  w_prefetch<4, HID / 16>(ring, ip.W2, HID, nh * 128, lane);
+  f32x16 acc[4][2];
+  mlp_tile<4, 2, IN_PAD / 16>(act, ip.W1, IN_PAD, w * 64, acc, ring, lane);
+  w_prefetch<2, HID / 16>(ring, ip.W2, HID, w * 64, lane);
   __syncthreads();
-  mlp_store_gelu<4>(act, acc, ip.b1, nh * 128, lane);
+  mlp_store_gelu<4, 2>(act, acc, ip.b1, w * 64, lane);
   __syncthreads();
-  mlp_tile<4, HID / 16>(act, ip.W2, HID, nh * 128, acc, ring, lane);
-  w_prefetch<4, HID / 16>(ring, ip.W3, HID, nh * 128, lane);
+  mlp_tile<4, 2, HID / 16>(act, ip.W2, HID, w * 64, acc, ring, lane);
+  w_prefetch<2, HID / 16>(ring, ip.W3, HID, w * 64, lane);
   __syncthreads();
-  mlp_store_gelu<4>(act, acc, ip.b2, nh * 128, lane);
+  mlp_store_gelu<4, 2>(act, acc, ip.b2, w * 64, lane);
   __syncthreads();
-  mlp_tile<4, HID / 16>(act, ip.W3, HID, nh * 128, acc, ring, lane);
-  WRing<2> ring2;
-  w_prefetch<2, HID / 16>(ring2, ip.W4, HID, nh * 64, lane);
+  mlp_tile<4, 2, HID / 16>(act, ip.W3, HID, w * 64, acc, ring, lane);
+  WRing<1> ring1;
+  w_prefetch<1, HID / 16>(ring1, ip.W4, HID, w * 32, lane);
   __syncthreads();
-  mlp_store_gelu<4>(act, acc, ip.b3, nh * 128, lane);
+  mlp_store_gelu<4, 2>(act, acc, ip.b3, w * 64, lane);
   __syncthreads();
-  f32x16 acc2[2][2];
-  mlp_tile<2, HID / 16>(act, ip.W4, HID, nh * 64, acc2, ring2, lane);
+  f32x16 acc1[4][1];
+  mlp_tile<4, 1, HID / 16>(act, ip.W4, HID, w * 32, acc1, ring1, lane);
+  // outputs: four adjacent basis weights of one pixel per store
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int n = nh * 64 + t * 32 + (lane & 31);
+  for (int q = 0; q < 4; ++q) {
+    const int n = w * 32 + 8 * q + 4 * (lane >> 5);
     if (n >= ip.KB) continue;
-    const bool real = n < ip.K;
-    const float bn = real ? ip.b4[n] : 0.f, mun = real ? ip.mu[n] : 0.f;
+    float bn[4], mun[4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const bool real = n + j < ip.K;
+      bn[j] = real ? ip.b4[n + j] : 0.f;
+      mun[j] = real ? ip.mu[n + j] : 0.f;
+    }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const size_t p = pb + mp * 64 + m;
-        if (p >= n_pix) continue;
-        const float y = real ? (acc2[i][t][r] + bn) * ip.s_out + mun : 0.f;
-        if (ip.out_bf16)
-          static_cast<uint16_t *>(beta)[p * ip.KB + n] = f2bf(y);
-        else
-          static_cast<float *>(beta)[p * ip.KB + n] = y;
+    for (int i = 0; i < 4; ++i) {
+      const size_t p = pb + 32 * i + (lane & 31);
+      if (p >= n_pix) continue;
+      float y[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) y[j] = (n + j < ip.K) ? (acc1[i][0][4 * q + j] + bn[j]) * ip.s_out + mun[j] : 0.f;
+      if ((ip.KB & 3) == 0) {   // whole, aligned quads
+        if (ip.out_bf16) {
+          uint2 wv;
+          wv.x = pack_bf16(y[0], y[1]);
+          wv.y = pack_bf16(y[2], y[3]);
+          *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(beta) + p * ip.KB + n) = wv;
+        } else {
+          *reinterpret_cast<float4 *>(static_cast<float *>(beta) + p * ip.KB + n) =
+              make_float4(y[0], y[1], y[2], y[3]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (n + j >= ip.KB) break;
+          if (ip.out_bf16)
+            static_cast<uint16_t *>(beta)[p * ip.KB + n + j] = f2bf(y[j]);
+          else
+            static_cast<float *>(beta)[p * ip.KB + n + j] = y[j];
+        }
       }
+    }
   }
 }
 
