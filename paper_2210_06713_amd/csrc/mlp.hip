@@ -274,17 +274,21 @@ constexpr int ACT_LD = HID + 8;
 constexpr int IPX = 128;     // pixels per inference block (four 32-row tiles)
 
 // The inference GELU, z Phi(z) = max(z, 0) - |z| erfc(|z| / sqrt 2) / 2 (one
-// expression for both signs), with erfc by Abramowitz & Stegun 7.1.26:
-// erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x),
-// |error| <= 1.5e-7; the coefficients below are a_i / 2 and p / sqrt 2, and
-// exp(-z^2 / 2) = 2^(-z^2 log2(e) / 2) on the hardware exponential.
+// expression for both signs), with erfc by Abramowitz & Stegun 7.1.28:
+// erfc(x) = (1 + a1 x + ... + a6 x^6)^-16, |error| <= 3e-7; the coefficients
+// below are a_i 2^(-i/2) (argument |z| / sqrt 2) times 2^(1/16) (the factor
+// 1/2), so one reciprocal and four squarings give erfc(|z| / sqrt 2) / 2.
 __device__ __forceinline__ float gelu_fast(float z) {
   const float a = fabsf(z);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.231641888f, a, 1.0f));
-  const float q = fmaf(fmaf(fmaf(fmaf(0.5307027145f, t, -0.7265760135f), t, 0.7107068705f), t,
-                            -0.142248368f), t, 0.127414796f);
-  const float e = __builtin_amdgcn_exp2f(-0.72134752044448170f * a * a);
-  return fmaf(-(q * t), e * a, fmaxf(z, 0.f));
+  const float p = fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(5.6212996640e-06f, a, 5.1055209009e-05f), a, 3.9686137011e-05f), a,
+                                      3.4227392389e-03f), a, 2.2076998457e-02f), a, 5.2075163037e-02f), a,
+                       1.0442737824e+00f);
+  float r = __builtin_amdgcn_rcpf(p);
+  r *= r;
+  r *= r;
+  r *= r;
+  r *= r;
+  return fmaf(-a, r, fmaxf(z, 0.f));
 }
 
 // Weight fragments of one layer for this wave, WD k-steps in flight: the
