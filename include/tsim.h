@@ -164,14 +164,23 @@ int tsim_sample_zernike_ar(const tsim_plan *plan, int frames, const float *d_ove
  *   Learned mode: the network of tsim_mlp_set_weights; output float32 or
  *   bfloat16 per the plan's precision.
  *   zern : device [frames][35][H][W] float32
- *   beta : device [frames][H][W][K] */
+ *   beta : device [frames][H][W][K] float32, or in BF16 plans
+ *          [frames][H][W][KP] bfloat16 with KP = K rounded up to 32, 64, 112
+ *          or 128 (entries K..KP-1 written as 0) */
 int tsim_p2s(const tsim_plan *plan, int frames, const float *zern, void *beta, void *ws,
              tsim_stream stream);
 
 /* (c) Eq. (8): out_c(x) = sum_k beta_k(x) sum_u psi_k(u) img_c(clamp(x - u)),
  * u in [-(T-1)/2, (T-1)/2]^2, a true convolution with replicated borders.
  *   img, out : device [frames][C][H][W] float32, img != out
- *   beta     : device [frames][H][W][K] (float32, or bfloat16 in BF16 plans) */
+ *   beta     : device [frames][H][W][K] float32, or in BF16 plans
+ *              [frames][H][W][KP] bfloat16 as written by tsim_p2s (entries
+ *              K..KP-1 must be finite; they meet zero basis rows)
+ * The BF16 form evaluates Eq. (8) in the order sum_u (sum_k beta_k psi_k(u))
+ * img(x - u) with BF16 operands and FP32 accumulation; it returns
+ * TSIM_EUNSUPPORTED for the one shape whose image tile and basis staging do
+ * not fit the LDS (K > 112 with C = 4 and T = 65), and both forms for frames
+ * of 4 GiB or more (C * H * W * 4 bytes). */
 int tsim_render(const tsim_plan *plan, int frames, const float *img, const void *beta,
                 float *out, void *ws, tsim_stream stream);
 

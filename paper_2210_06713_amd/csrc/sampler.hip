@@ -189,19 +189,46 @@ struct RowArgs {
   float sc;
 };
 
-// Field at position I of kFieldOrder for the block's RW rows: inverse
-// transform of the rows (one LDS pass over all RW lines), then the field's
-// terms of the mix; outputs whose last field this is are written.
-template <int I, int PX, int NT, int RW>
-__device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_MODES][RW][PX]) {
+// The block's RW rows of field position I: GPT = Gw / NT samples per thread
+// and row, read into registers (GPT > 0), or straight into LDS (GPT = 0).
+template <int I, int NT, int RW, int GPT>
+__device__ __forceinline__ void read_field(const RowArgs &a, float2 (&pre)[RW][GPT > 0 ? GPT : 1]) {
   constexpr int q = kFieldOrder[I];
-  constexpr int ta = 2 * q, tb = 2 * q + 1;
-  const int gwp = a.Gw + (a.Gw >> 5);
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     const float2 *row = a.V + (size_t(q) * a.H + a.y0 + (r < a.nrows ? r : 0)) * size_t(a.Gw);
-    for (int c = threadIdx.x; c < a.Gw; c += NT)
-      a.lds[r * gwp + lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = row[c];
+#pragma unroll
+    for (int j = 0; j < GPT; ++j) pre[r][j] = row[threadIdx.x + j * NT];
+  }
+}
+
+// Field at position I of kFieldOrder for the block's RW rows: inverse
+// transform of the rows (one LDS pass over all RW lines), then the field's
+// terms of the mix; outputs whose last field this is are written.  With
+// GPT > 0 the field's samples arrive in registers, read while the previous
+// field was transformed, and the next field's are requested here.
+template <int I, int PX, int NT, int RW, int GPT>
+__device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_MODES][RW][PX],
+                                          float2 (&pre)[RW][GPT > 0 ? GPT : 1]) {
+  constexpr int q = kFieldOrder[I];
+  constexpr int ta = 2 * q, tb = 2 * q + 1;
+  const int gwp = a.Gw + (a.Gw >> 5);
+  if constexpr (GPT > 0) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int j = 0; j < GPT; ++j) {
+        const int c = threadIdx.x + j * NT;
+        a.lds[r * gwp + lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = pre[r][j];
+      }
+    if constexpr (I + 1 < TSIM_FIELDS) read_field<I + 1, NT, RW, GPT>(a, pre);
+  } else {
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const float2 *row = a.V + (size_t(q) * a.H + a.y0 + (r < a.nrows ? r : 0)) * size_t(a.Gw);
+      for (int c = threadIdx.x; c < a.Gw; c += NT)
+        a.lds[r * gwp + lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = row[c];
+    }
   }
   __syncthreads();
   lds_fft_dit(a.lds, a.Gw, a.log2w, RW, gwp, a.twq, 1.f);
@@ -253,21 +280,24 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
   }
 }
 
-template <int I, int PX, int NT, int RW>
+template <int I, int PX, int NT, int RW, int GPT>
 struct FieldSteps {
-  __device__ __forceinline__ static void run(const RowArgs &a, float (&acc)[TSIM_N_MODES][RW][PX]) {
-    mix_field<I, PX, NT, RW>(a, acc);
-    FieldSteps<I + 1, PX, NT, RW>::run(a, acc);
+  __device__ __forceinline__ static void run(const RowArgs &a, float (&acc)[TSIM_N_MODES][RW][PX],
+                                             float2 (&pre)[RW][GPT > 0 ? GPT : 1]) {
+    mix_field<I, PX, NT, RW, GPT>(a, acc, pre);
+    FieldSteps<I + 1, PX, NT, RW, GPT>::run(a, acc, pre);
   }
 };
 
-template <int PX, int NT, int RW>
-struct FieldSteps<TSIM_FIELDS, PX, NT, RW> {
-  __device__ __forceinline__ static void run(const RowArgs &, float (&)[TSIM_N_MODES][RW][PX]) {}
+template <int PX, int NT, int RW, int GPT>
+struct FieldSteps<TSIM_FIELDS, PX, NT, RW, GPT> {
+  __device__ __forceinline__ static void run(const RowArgs &, float (&)[TSIM_N_MODES][RW][PX],
+                                             float2 (&)[RW][GPT > 0 ? GPT : 1]) {}
 };
 
 // One block per RW consecutive output rows (the last block may hold fewer).
-template <int PX, int NT, int RW>
+// GPT = Gw / NT (field samples per thread and row, read one field ahead) or 0.
+template <int PX, int NT, int RW, int GPT>
 __global__ void __launch_bounds__(NT)
 k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
                    const float *__restrict__ Lmat, float *__restrict__ zern, int Gw, int log2w,
@@ -291,7 +321,9 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
   a.nrows = min(RW, H - y0);
   a.sc = scales.s[fl];
   float acc[TSIM_N_MODES][RW][PX];  // each output starts at its first term
-  FieldSteps<0, PX, NT, RW>::run(a, acc);
+  float2 pre[RW][GPT > 0 ? GPT : 1];
+  if constexpr (GPT > 0) read_field<0, NT, RW, GPT>(a, pre);
+  FieldSteps<0, PX, NT, RW, GPT>::run(a, acc, pre);
 }
 
 // Temporal auto-regression on the mixed fields, in place over a chunk of
@@ -342,6 +374,37 @@ size_t sampler_ws_bytes(const tsim_plan *pl, int frames) {
   return size_t(n) * TSIM_FIELDS * pl->H * size_t(pl->Gw) * sizeof(float2);
 }
 
+// pass 2 with the per-thread sample count Gw / NT as a compile-time constant
+// where it is 2, 4 or 8 (the samples of the next field are then read one
+// field ahead), without the look-ahead otherwise and for the 1024-thread
+// blocks (whose extra registers would halve the blocks resident per CU)
+template <int PX, int NT, int RW>
+void launch_rows(dim3 grid, size_t lds, hipStream_t s, const float2 *V, const float2 *tw, const float *L,
+                 float *zern, int Gw, int log2w, int H, int W, FrameScales sc, int f0) {
+  if constexpr (NT > 256) {
+    hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 0>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w, H, W,
+                       sc, f0);
+  } else {
+    switch (Gw / NT) {
+      case 2:
+        hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 2>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
+                           H, W, sc, f0);
+        break;
+      case 4:
+        hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 4>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
+                           H, W, sc, f0);
+        break;
+      case 8:
+        hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 8>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
+                           H, W, sc, f0);
+        break;
+      default:
+        hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 0>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
+                           H, W, sc, f0);
+    }
+  }
+}
+
 int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
                    uint64_t frame0, float *zern, void *ws, hipStream_t s) {
   const int Gh = pl->Gh, Gw = pl->Gw, H = pl->H, W = pl->W;
@@ -390,17 +453,13 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     const size_t lds1 = (gwp + (Gw >> 2)) * sizeof(float2);
     dim3 g2((H + 1) / 2, nf), g1r(H, nf);
     if (W <= 256)
-      hipLaunchKernelGGL((k_sampler_rows_mix<1, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, pl->d_L,
-                         zern, Gw, log2w, H, W, sc, f0);
+      launch_rows<1, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
     else if (W <= 512)
-      hipLaunchKernelGGL((k_sampler_rows_mix<2, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, pl->d_L,
-                         zern, Gw, log2w, H, W, sc, f0);
+      launch_rows<2, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
     else if (W <= 1024)
-      hipLaunchKernelGGL((k_sampler_rows_mix<4, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, pl->d_L,
-                         zern, Gw, log2w, H, W, sc, f0);
+      launch_rows<4, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
     else
-      hipLaunchKernelGGL((k_sampler_rows_mix<4, 1024, 1>), g1r, dim3(1024), lds1, s, V, pl->d_tw_w, pl->d_L,
-                         zern, Gw, log2w, H, W, sc, f0);
+      launch_rows<4, 1024, 1>(g1r, lds1, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
   }
   return TSIM_OK;

@@ -166,6 +166,25 @@ def test_render_bf16_kernel_shapes(t, T, C, K, H, W):
         assert rel(got[c], ref) < 1e-5, c
 
 
+def test_render_bf16_unsupported_shape_is_rejected(t):
+    """The one BF16 shape whose image tile and basis staging exceed the LDS
+    (K > 112, C = 4, T = 65) returns TSIM_EUNSUPPORTED before any launch and
+    leaves the output untouched."""
+    say("render bf16 K=120 C=4 T=65: rejected")
+    H, W, C, K, T = 20, 24, 4, 120, 65
+    rng = np.random.default_rng(9)
+    Psi = np.linalg.qr(rng.standard_normal((T * T, K)))[0].T.copy()
+    plan = t.Plan(H, W, C, 64, 64, psf_t=T, pupil_n=128, basis=Psi, p2s_mode=t.P2S_LEARNED, precision=t.BF16)
+    img = torch.ones((1, C, H, W), dtype=torch.float32, device="cuda")
+    beta = torch.zeros((1, H, W, 128), dtype=torch.bfloat16, device="cuda")
+    out = torch.full((1, C, H, W), 7.0, dtype=torch.float32, device="cuda")
+    with pytest.raises(t.TsimError) as e:
+        plan.render(img, beta, out)
+    assert e.value.status == t.EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool(torch.all(out == 7.0))
+
+
 def test_training_pairs_match_oracle(t, basis):
     say("training pairs n=2000")
     plan = t.Plan(32, 32, 1, 64, 64, basis=basis)
