@@ -66,6 +66,15 @@ def _sample(t, plan, d_over_r0, seed, frame0, frames):
     (64, 64, 128, 128, 0, 0, 2.0),             # 64 x 64 workload, G = 128
     (48, 80, 128, 256, 2 ** 40 + 77, 5, 3.3),  # ragged, non-square, 64-bit seed
     (64, 64, 64, 64, 11, 0, 1.0),              # grid equal to the image
+    # row pass with the next field read ahead: samples per thread and row
+    # Gw / 256 = 2, 4 and 8, for 1, 2 and 4 output columns per thread, odd
+    # row counts (a last block with one row)
+    (13, 200, 64, 512, 3, 1, 2.0),
+    (9, 256, 64, 1024, 8, 0, 2.5),
+    (7, 1000, 64, 1024, 7, 0, 2.5),
+    (11, 130, 64, 2048, 4, 0, 1.5),
+    (9, 400, 64, 2048, 5, 0, 2.5),
+    (7, 1000, 64, 2048, 6, 0, 2.5),
 ])
 def test_sampler_matches_oracle(t, H, W, Gh, Gw, seed, frame0, dr):
     say(f"sampler H={H} W={W} G={Gh}x{Gw} seed={seed} frame0={frame0}")
