@@ -126,8 +126,10 @@ def source_hash(kernel):
     f = files.get(kernel)
     if f is None:
         return None
-    path = os.path.join(ROOT, "paper_2210_06713_amd", "csrc", f)
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    csrc = os.path.join(ROOT, "paper_2210_06713_amd", "csrc")
+    # the kernel's file and the shared device header it includes
+    return hashlib.sha256(open(os.path.join(csrc, f), "rb").read() +
+                          open(os.path.join(csrc, "common.cuh"), "rb").read()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, launches_per_step):

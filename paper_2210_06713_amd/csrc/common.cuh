@@ -60,82 +60,117 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t v, int log2n) {
   return __builtin_bitreverse32(v) >> (32 - log2n);
 }
 
-// LDS element index with one padding slot per 32 complex samples: strided
-// and bit-reversed access patterns then spread over all banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+// LDS layout of the transform lines: line l of length n (power of two,
+// >= 64) occupies buf[l * n, (l + 1) * n), and its element i sits at
+// i ^ x, where x (5 bits) folds the index bits 5-9 and 10-14 and the line
+// term `lt` (the line number shifted so that the lines read out together
+// land on different banks) into bits 0-4.  Bits >= 5 are untouched, so the
+// map is a bijection of [0, n) for every line.  With 64 banks of 4 bytes
+// (8-byte accesses served 32 lanes at a time), the 32 lanes of a half-wave
+// then touch 32 different bank pairs in a bit-reversed scatter of
+// consecutive indices (the top five index bits vary), in the radix-4
+// butterflies at spans 1, 64, 256 and 1024 (index bits 2-6 or 0-4 vary), in
+// natural-order rows and in reads across lines; spans 4 and 16 keep two-way
+// conflicts.
+__device__ __forceinline__ int lds_swz(int i, int lt) { return i ^ (((i >> 5) ^ (i >> 10) ^ lt) & 31); }
 
-// Twiddle exp(sign 2 pi i k / n) for k < n/2 from the quarter table
-// twq[k] (k < n/4): the second quarter is the first times exp(sign i pi/2).
-__device__ __forceinline__ float2 twiddle(const float2 *twq, int k, int quarter, float sign) {
-  const bool hi = k >= quarter;
-  const float2 t = twq[hi ? k - quarter : k];
-  return hi ? make_float2(-sign * t.y, sign * t.x) : t;
+// Number of LDS twiddles lds_fft_dit reads for length n: the radix-4 passes
+// at spans h = 1, 4, 16, ... (while 2h < n) take h entries each, and an odd
+// log2 n adds the final radix-2 pass's quarter table of n/4 entries.
+__host__ __device__ constexpr int fft_twiddle_count(int log2n) {
+  return ((1 << (2 * (log2n / 2))) - 1) / 3 + ((log2n & 1) ? (1 << log2n) / 4 : 0);
 }
 
-// Copy the quarter twiddle table (n/4 entries of `tw`, which holds
-// exp(sign 2 pi i k / n) for k < n/2) into LDS; the caller synchronises.
-__device__ __forceinline__ void load_twiddles(float2 *twq, const float2 *__restrict__ tw, int n) {
-  for (int k = threadIdx.x; k < (n >> 2); k += blockDim.x) twq[k] = tw[k];
+// Fill the LDS twiddle table from `tw`, which holds exp(sign 2 pi i k / n)
+// for k < n/2: the radix-4 pass at span h reads omega_{4h}^j (j < h) at
+// offset (h - 1)/3, so consecutive lanes read consecutive entries; for odd
+// log2 n, omega_n^k (k < n/4) follows.  The caller synchronises.
+__device__ __forceinline__ void load_twiddles(float2 *tws, const float2 *__restrict__ tw, int n, int log2n) {
+  const int r4 = ((1 << (2 * (log2n / 2))) - 1) / 3;
+  const int total = fft_twiddle_count(log2n);
+  for (int k = threadIdx.x; k < total; k += blockDim.x) {
+    if (k < r4) {
+      int h = 1;
+      while ((4 * h - 1) / 3 <= k) h *= 4;
+      const int j = k - (h - 1) / 3;
+      tws[k] = tw[j * (n / (4 * h))];
+    } else {
+      tws[k] = tw[k - r4];
+    }
+  }
 }
 
-// In-place decimation-in-time FFT over `ncol` independent lines of length n
-// (power of two, >= 4) stored line-major in LDS (`buf[line * stride +
-// lpad(i)]`), input in bit-reversed order, output natural.  The twiddles
-// come from the LDS quarter table `twq` of exp(sign 2 pi i k / n), which
-// also sets the direction.  Two radix-2 stages are fused per pass (radix
-// 2^2), so a length-1024 transform takes five barriers.  All threads of the
-// block take part; the caller synchronises before and after.
-__device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int ncol, int stride, const float2 *twq,
+// In-place decimation-in-time FFT over `nlines` independent lines of length
+// n (power of two, 64 <= n <= 32768) in the LDS layout of lds_swz, line l
+// with line term l << lsh; input in bit-reversed order, output natural.
+// The twiddles come from the table of load_twiddles, whose source table
+// also sets the direction `sign`.  Two radix-2 stages are fused per pass
+// (radix 2^2: spans h and 2h on quadruples i, i+h, i+2h, i+3h), so a
+// length-1024 transform takes five barriers.  All threads of the block
+// take part; the caller synchronises before and after.
+__device__ inline void lds_fft_dit(float2 *buf, int n, int log2n, int nlines, int lsh, const float2 *tws,
                                    float sign) {
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
-  const int quarter = n >> 2;
   int h = 1;
   int lh = 0;
+  int toff = 0;  // offset of the pass's twiddles
+  // The swizzle is linear over XOR and the offsets k h (k < 4) occupy index
+  // bits lh, lh + 1, which are clear in a quadruple's base i, so element
+  // i + k h sits at lds_swz(i, lt) ^ lds_swz(k h, 0): one swizzle per
+  // butterfly and three pass-uniform offsets.
   while (h < n) {
     if (2 * h < n) {
-      // stages of span h and 2h on quadruples (i, i+h, i+2h, i+3h)
-      const int groups = ncol << (log2n - 2);
-      const int tstep1 = n / (2 * h);   // omega_{2h}^j = w[j * n/(2h)]
-      const int tstep2 = n / (4 * h);   // omega_{4h}^j = w[j * n/(4h)], index < n/4
+      const int groups = nlines << (log2n - 2);
+      const int d1 = lds_swz(h, 0), d2 = lds_swz(2 * h, 0), d3 = lds_swz(3 * h, 0);
       for (int g = tid; g < groups; g += nthr) {
-        int line = g >> (log2n - 2);
-        int gg = g & ((n >> 2) - 1);
-        int j = gg & (h - 1);
-        int i = ((gg >> lh) << (lh + 2)) + j;
-        float2 *b = buf + line * stride;
-        float2 x0 = b[lpad(i)], x1 = b[lpad(i + h)], x2 = b[lpad(i + 2 * h)], x3 = b[lpad(i + 3 * h)];
-        float2 w1 = twiddle(twq, j * tstep1, quarter, sign);
-        float2 w2 = twq[j * tstep2];
-        float2 t1 = cmul(w1, x1), t3 = cmul(w1, x3);
-        float2 a0 = make_float2(x0.x + t1.x, x0.y + t1.y);
-        float2 a1 = make_float2(x0.x - t1.x, x0.y - t1.y);
-        float2 a2 = make_float2(x2.x + t3.x, x2.y + t3.y);
-        float2 a3 = make_float2(x2.x - t3.x, x2.y - t3.y);
-        float2 u2 = cmul(w2, a2);
+        const int line = g >> (log2n - 2);
+        const int gg = g & ((n >> 2) - 1);
+        const int j = gg & (h - 1);
+        const int i = ((gg >> lh) << (lh + 2)) + j;
+        float2 *b = buf + line * n;
+        const int lt = line << lsh;
+        const int p0 = lds_swz(i, lt), p1 = p0 ^ d1, p2 = p0 ^ d2, p3 = p0 ^ d3;
+        const float2 x0 = b[p0], x1 = b[p1], x2 = b[p2], x3 = b[p3];
+        // omega_{4h}^j from the table; omega_{2h}^j is its square and
         // omega_{4h}^{j+h} = omega_{4h}^j * omega_4, omega_4 = (0, sign)
-        float2 w3 = make_float2(-sign * w2.y, sign * w2.x);
-        float2 u3 = cmul(w3, a3);
-        b[lpad(i)] = make_float2(a0.x + u2.x, a0.y + u2.y);
-        b[lpad(i + 2 * h)] = make_float2(a0.x - u2.x, a0.y - u2.y);
-        b[lpad(i + h)] = make_float2(a1.x + u3.x, a1.y + u3.y);
-        b[lpad(i + 3 * h)] = make_float2(a1.x - u3.x, a1.y - u3.y);
+        const float2 w2 = tws[toff + j];
+        const float2 w1 = make_float2(w2.x * w2.x - w2.y * w2.y, 2.f * w2.x * w2.y);
+        const float2 t1 = cmul(w1, x1), t3 = cmul(w1, x3);
+        const float2 a0 = make_float2(x0.x + t1.x, x0.y + t1.y);
+        const float2 a1 = make_float2(x0.x - t1.x, x0.y - t1.y);
+        const float2 a2 = make_float2(x2.x + t3.x, x2.y + t3.y);
+        const float2 a3 = make_float2(x2.x - t3.x, x2.y - t3.y);
+        const float2 u2 = cmul(w2, a2);
+        const float2 w3 = make_float2(-sign * w2.y, sign * w2.x);
+        const float2 u3 = cmul(w3, a3);
+        b[p0] = make_float2(a0.x + u2.x, a0.y + u2.y);
+        b[p2] = make_float2(a0.x - u2.x, a0.y - u2.y);
+        b[p1] = make_float2(a1.x + u3.x, a1.y + u3.y);
+        b[p3] = make_float2(a1.x - u3.x, a1.y - u3.y);
       }
+      toff += h;
       h <<= 2;
       lh += 2;
     } else {
-      const int groups = ncol << (log2n - 1);
-      const int tstep1 = n / (2 * h);
+      // final radix-2 pass (odd log2 n): span h = n/2, omega_n^j, j < n/2,
+      // from the quarter table after the radix-4 twiddles
+      const int groups = nlines << (log2n - 1);
+      const int quarter = n >> 2;
+      const int d1 = lds_swz(h, 0);
       for (int g = tid; g < groups; g += nthr) {
-        int line = g >> (log2n - 1);
-        int gg = g & ((n >> 1) - 1);
-        int j = gg & (h - 1);
-        int i = ((gg >> lh) << (lh + 1)) + j;
-        float2 *b = buf + line * stride;
-        float2 x0 = b[lpad(i)], x1 = b[lpad(i + h)];
-        float2 t1 = cmul(twiddle(twq, j * tstep1, quarter, sign), x1);
-        b[lpad(i)] = make_float2(x0.x + t1.x, x0.y + t1.y);
-        b[lpad(i + h)] = make_float2(x0.x - t1.x, x0.y - t1.y);
+        const int line = g >> (log2n - 1);
+        const int j = g & ((n >> 1) - 1);
+        float2 *b = buf + line * n;
+        const int lt = line << lsh;
+        const int p0 = lds_swz(j, lt), p1 = p0 ^ d1;
+        const float2 x0 = b[p0], x1 = b[p1];
+        const bool hi = j >= quarter;
+        const float2 tq = tws[toff + (hi ? j - quarter : j)];
+        const float2 w = hi ? make_float2(-sign * tq.y, sign * tq.x) : tq;
+        const float2 t1 = cmul(w, x1);
+        b[p0] = make_float2(x0.x + t1.x, x0.y + t1.y);
+        b[p1] = make_float2(x0.x - t1.x, x0.y - t1.y);
       }
       h <<= 1;
       lh += 1;

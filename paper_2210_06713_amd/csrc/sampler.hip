@@ -22,7 +22,10 @@ namespace {
 
 using namespace tsim;
 
-constexpr int kLdsFloat2 = 8192;  // 64 KB of complex samples per pass-1 block
+// Complex samples per pass-1 block (32 KB): four 1024-point columns, so
+// four 512-thread blocks (the 32-wave limit of a CU) fit in its LDS; never
+// fewer than one mirror pair of columns.
+constexpr int kLdsFloat2 = 4096;
 constexpr int kMaxFramesPerLaunch = 64;
 
 struct FrameScales {
@@ -43,10 +46,13 @@ __global__ void __launch_bounds__(512)
 k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, float2 *__restrict__ V,
                int Gh, int Gw, int log2h, int H, int NC, uint32_t key0, uint32_t key1,
                uint32_t frame_base) {
-  extern __shared__ float2 lds[];  // [NC][Gh + Gh/32] (padded), slot-major; then Gh/4 twiddles
-  const int ghp = Gh + (Gh >> 5);
-  float2 *twq = lds + NC * ghp;
-  load_twiddles(twq, tw, Gh);
+  extern __shared__ float2 lds[];  // [NC][Gh] in the lds_swz layout, slot-major; then the twiddles
+  float2 *tws = lds + NC * Gh;
+  load_twiddles(tws, tw, Gh, log2h);
+  // line term: the read-out below visits 2^ysh rows of each of NC slots per
+  // 32 lanes, so the slot number goes to bank bits ysh and up
+  const int log2nc = __builtin_ctz(NC);
+  const int ysh = log2nc < 5 ? 5 - log2nc : 0;
   const int q = blockIdx.y;
   const int fl = blockIdx.z;  // frame within this launch
   const uint32_t frame = frame_base + uint32_t(fl);
@@ -101,29 +107,34 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
     const float sb = has_b ? sqrtS[(size_t(mb) * qw + kxq) * qh + kyq] : 0.f;
     if (self_conj) {
       // U = sa g0 + i sb g2 (real noise at self-conjugate bins)
-      lds[slotA * ghp + lpad(bitrev(uint32_t(kyA), log2h))] = make_float2(sa * g01.x, sb * g23.x);
+      lds[slotA * Gh + lds_swz(bitrev(uint32_t(kyA), log2h), slotA << ysh)] = make_float2(sa * g01.x, sb * g23.x);
     } else {
       // noise of A: W (canonical) or conj(W); B takes the conjugate
       const float sg = a_canon ? 1.f : -1.f;
       const float2 wa = make_float2(g01.x * rs2, sg * g01.y * rs2);
       const float2 wb = make_float2(g23.x * rs2, sg * g23.y * rs2);
       // U = sa Wa + i sb Wb at A, and sa conj(Wa) + i sb conj(Wb) at B
-      lds[slotA * ghp + lpad(bitrev(uint32_t(kyA), log2h))] =
+      lds[slotA * Gh + lds_swz(bitrev(uint32_t(kyA), log2h), slotA << ysh)] =
           make_float2(sa * wa.x - sb * wb.y, sa * wa.y + sb * wb.x);
-      lds[slotB * ghp + lpad(bitrev(uint32_t(kyB), log2h))] =
+      lds[slotB * Gh + lds_swz(bitrev(uint32_t(kyB), log2h), slotB << ysh)] =
           make_float2(sa * wa.x + sb * wb.y, -sa * wa.y + sb * wb.x);
     }
   }
   __syncthreads();
-  lds_fft_dit(lds, Gh, log2h, NC, ghp, twq, 1.f);
+  lds_fft_dit(lds, Gh, log2h, NC, ysh, tws, 1.f);
   const float norm = rsqrtf(float(Gh) * float(Gw));
   float2 *Vout = V + (size_t(fl) * TSIM_FIELDS + q) * size_t(H) * Gw + s0;
-  const int log2nc = __builtin_ctz(NC);
-  for (int e = threadIdx.x; e < H * NC; e += blockDim.x) {
-    const int y = e >> log2nc;
-    const int c = e & (NC - 1);
-    const float2 v = lds[c * ghp + lpad(y)];
-    Vout[size_t(y) * Gw + c] = make_float2(v.x * norm, v.y * norm);
+  // work item e: row bits 0..ysh-1 from its low bits, then the slot, then
+  // the remaining row bits (a wave writes 64/NC rows of the NC slots)
+  const int ym = (1 << ysh) - 1;
+  const int ritems = ((H + ym) >> ysh) << (ysh + log2nc);
+  for (int e = threadIdx.x; e < ritems; e += blockDim.x) {
+    const int c = (e >> ysh) & (NC - 1);
+    const int y = (e & ym) | ((e >> (ysh + log2nc)) << ysh);
+    if (y < H) {
+      const float2 v = lds[c * Gh + lds_swz(y, c << ysh)];
+      Vout[size_t(y) * Gw + c] = make_float2(v.x * norm, v.y * norm);
+    }
   }
 }
 
@@ -180,9 +191,9 @@ constexpr MixPlan make_mix_plan() {
 constexpr MixPlan kMix = make_mix_plan();
 
 struct RowArgs {
-  float2 *lds;      // RW padded lines of Gw + Gw/32 samples
+  float2 *lds;      // RW lines of Gw samples in the lds_swz layout (line term 0 and 1)
   const float2 *V;  // this frame's rows: V[q][y][:] at V + (q * H + y) * Gw
-  const float2 *twq;  // LDS quarter twiddle table
+  const float2 *tws;  // LDS twiddle table
   const float *Lmat;
   float *out;       // this frame and first row: plane t at out + t * H * W
   int Gw, log2w, H, W, y0, nrows;
@@ -212,14 +223,13 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
                                           float2 (&pre)[RW][GPT > 0 ? GPT : 1]) {
   constexpr int q = kFieldOrder[I];
   constexpr int ta = 2 * q, tb = 2 * q + 1;
-  const int gwp = a.Gw + (a.Gw >> 5);
   if constexpr (GPT > 0) {
 #pragma unroll
     for (int r = 0; r < RW; ++r)
 #pragma unroll
       for (int j = 0; j < GPT; ++j) {
         const int c = threadIdx.x + j * NT;
-        a.lds[r * gwp + lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = pre[r][j];
+        a.lds[r * a.Gw + lds_swz(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w), r)] = pre[r][j];
       }
     if constexpr (I + 1 < TSIM_FIELDS) read_field<I + 1, NT, RW, GPT>(a, pre);
   } else {
@@ -227,18 +237,18 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
     for (int r = 0; r < RW; ++r) {
       const float2 *row = a.V + (size_t(q) * a.H + a.y0 + (r < a.nrows ? r : 0)) * size_t(a.Gw);
       for (int c = threadIdx.x; c < a.Gw; c += NT)
-        a.lds[r * gwp + lpad(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w))] = row[c];
+        a.lds[r * a.Gw + lds_swz(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w), r)] = row[c];
     }
   }
   __syncthreads();
-  lds_fft_dit(a.lds, a.Gw, a.log2w, RW, gwp, a.twq, 1.f);
+  lds_fft_dit(a.lds, a.Gw, a.log2w, RW, 0, a.tws, 1.f);
   float ya[RW][PX], yb[RW][PX];
 #pragma unroll
   for (int r = 0; r < RW; ++r)
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
       const int x = threadIdx.x + k * NT;
-      const float2 z = (x < a.W) ? a.lds[r * gwp + lpad(x)] : make_float2(0.f, 0.f);
+      const float2 z = (x < a.W) ? a.lds[r * a.Gw + lds_swz(x, r)] : make_float2(0.f, 0.f);
       ya[r][k] = z.x;
       yb[r][k] = z.y;
     }
@@ -305,12 +315,11 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
   extern __shared__ float2 lds[];
   const int y0 = blockIdx.x * RW;
   const int fl = blockIdx.y;
-  const int gwp = Gw + (Gw >> 5);
   RowArgs a;
   a.lds = lds;
   a.V = V + size_t(fl) * TSIM_FIELDS * H * size_t(Gw);
-  a.twq = lds + RW * gwp;
-  load_twiddles(lds + RW * gwp, tw, Gw);
+  a.tws = lds + RW * Gw;
+  load_twiddles(lds + RW * Gw, tw, Gw, log2w);
   a.Lmat = Lmat;
   a.out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * size_t(H) * W + size_t(y0) * W;
   a.Gw = Gw;
@@ -409,15 +418,15 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
                    uint64_t frame0, float *zern, void *ws, hipStream_t s) {
   const int Gh = pl->Gh, Gw = pl->Gw, H = pl->H, W = pl->W;
   const int log2h = ilog2(Gh), log2w = ilog2(Gw);
-  int NC = std::min(kLdsFloat2 / Gh, 32);
+  int NC = std::max(2, std::min(kLdsFloat2 / Gh, 32));
   NC = std::min(NC, Gw);
   const uint32_t key0 = uint32_t(seed & 0xffffffffu), key1 = uint32_t(seed >> 32);
   float2 *V = static_cast<float2 *>(ws);
   const int chunk = frames_per_chunk(pl, frames);
-  // NC padded columns plus the quarter twiddle table: 8 x 1056 + 256 samples
-  // (68 KB) at Gh = 1024, above the default 64 KB of dynamic LDS; the device
-  // limit is checked and raised once
-  const size_t lds1 = (size_t(NC) * (Gh + (Gh >> 5)) + (Gh >> 2)) * sizeof(float2);
+  // NC columns plus the twiddle table: 2 x 4096 + 1365 samples (75 KB) at
+  // Gh = 4096, above the default 64 KB of dynamic LDS; the device limit is
+  // checked and raised once
+  const size_t lds1 = (size_t(NC) * Gh + fft_twiddle_count(log2h)) * sizeof(float2);
   if (lds1 > 64 * 1024) {
     static size_t raised = 0;
     if (lds1 > raised) {
@@ -446,11 +455,10 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     for (int i = 0; i < kMaxFramesPerLaunch; ++i) sc.s[i] = 0.f;
     for (int i = 0; i < nf; ++i) sc.s[i] = scale_host[f0 + i];
     TraceScope tr("k_sampler_rows_mix", s);
-    const size_t gwp = size_t(Gw + (Gw >> 5));
     // two rows per block (one LDS transform pass and one barrier set for both)
     // up to 1024 columns; 1024-thread blocks over single rows beyond
-    const size_t lds2 = (2 * gwp + (Gw >> 2)) * sizeof(float2);
-    const size_t lds1 = (gwp + (Gw >> 2)) * sizeof(float2);
+    const size_t lds2 = (2 * size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
+    const size_t lds1 = (size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
     dim3 g2((H + 1) / 2, nf), g1r(H, nf);
     if (W <= 256)
       launch_rows<1, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);

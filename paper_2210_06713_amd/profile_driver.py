@@ -13,7 +13,8 @@ weight values), then one
 element-wise copy of 256 MiB (read 256 MiB, write 256 MiB) whose counter
 readings calibrate the per-kernel byte counts.  ``--summarize`` turns the two
 counter runs into ``traffic.json`` (bytes per launch for each kernel, with
-the hash of the kernel's source file) and a Markdown summary.
+the hash of the kernel's source file and of the shared device header) and a
+Markdown summary.
 """
 import argparse
 import csv
@@ -144,8 +145,10 @@ def summarize(fetch_dir, write_dir, dst):
         # median over dispatches: the one-off basis-build launch is not typical
         rb = median(f) * 1024 * fr
         wb = median(w) * 1024 * wr
-        path = os.path.join(ROOT, "paper_2210_06713_amd", "csrc", src)
-        h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+        csrc = os.path.join(ROOT, "paper_2210_06713_amd", "csrc")
+        # the kernel's file and the shared device header it includes
+        h = hashlib.sha256(open(os.path.join(csrc, src), "rb").read() +
+                           open(os.path.join(csrc, "common.cuh"), "rb").read()).hexdigest()[:16]
         name = k.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0].strip()
         res[trace] = {"kernel": name, "dispatches": len(f), "read_bytes_per_launch": round(rb),
                       "write_bytes_per_launch": round(wb), "bytes_per_launch": round(rb + wb),
