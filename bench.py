@@ -78,6 +78,9 @@ def kernel_work(name, frames, s):
         return "alu", px * (2 * k * t * t + 2 * c * t * t), "flop"
     if name == "k_warp":
         return "hbm", px * (8 + 4 * c + 4 * c), "B"
+    if name == "k_subharmonic_add":
+        # read and write the 8 coefficient planes of the two tilt groups
+        return "hbm", px * 8 * 4 * 2, "B"
     if name == "k_ar_scan":
         # read each fresh frame and write the correlated one, 35 planes
         return "hbm", px * 2 * 35 * 4, "B"
@@ -369,6 +372,37 @@ def ar_sequence(tsim, torch, wl, s, steps):
             "ms_per_chunk": round(ms, 3), "kernels": kern}
 
 
+def subharmonic_sampler(tsim, torch, wl, s, steps):
+    """The sampler alone on the 512^2 workload (16 frames per call), without
+    and with three subharmonic levels for the tilt fields."""
+    n = s["chunk"]
+    drs = [s["drs"][i % len(s["drs"])] for i in range(n)]
+    out = {"workload": f"{n} frames of {s['H']}x{s['W']}, grid {s['G']}^2, sampler only"}
+    for levels in (0, 3):
+        pl = tsim.Plan(s["H"], s["W"], s["C"], s["G"], s["G"], pixel_pitch_over_d=PITCH,
+                       subharmonic_levels=levels)
+        ws = pl.workspace(n)
+        pl.sample_zernike(drs, 0, 0, wl.zern, ws)
+        torch.cuda.synchronize()
+        tsim.trace_enable(True)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(steps):
+            pl.sample_zernike(drs, 0, (1 + i) * n, wl.zern, ws)
+        b.record()
+        torch.cuda.synchronize()
+        rep_ = tsim.trace_report()
+        tsim.trace_enable(False)
+        kern, _ = summarize(rep_, steps, n, s, traffic=False)
+        ms = a.elapsed_time(b) / steps
+        out[f"levels_{levels}"] = {"value": round(n * s["H"] * s["W"] / (ms * 1e-3) / 1e6, 3),
+                                   "unit": "Mpixel/s", "ms_per_call": round(ms, 4), "kernels": kern}
+        del ws
+        pl.close()
+    return out
+
+
 def large_frame(tsim, torch, np, synthetic, dev, args):
     """3840 x 2160 x 3 frames, D/r0 = 3, 4096^2 grid, 128 x 128 pupil, K = 100
     basis of 65 x 65 kernels: a 30-frame sequence of independent draws per
@@ -483,6 +517,7 @@ def main():
         del net
         plan_l.close()
     plan.close()
+    subh = subharmonic_sampler(tsim, torch, wl, s, args.steps)
     del wl
     torch.cuda.empty_cache()
 
@@ -500,7 +535,7 @@ def main():
                        "frames_per_step": FRAMES, "H": H, "W": W, "C": C, "grid": G, "K": K,
                        "T": T, "pupil": P},
             "roofline": roofline, "kernels": kernels, "learned_bf16": learned,
-            "large_4k": large, "setup_s": round(setup_s, 2)}
+            "subharmonic_sampler": subh, "large_4k": large, "setup_s": round(setup_s, 2)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -76,6 +76,15 @@ enum { TSIM_FP32 = 0, TSIM_BF16 = 1 };
  *   p2s_mode       TSIM_P2S_EXACT or TSIM_P2S_LEARNED
  *   precision      TSIM_FP32 (plain form) or TSIM_BF16 (learned form: BF16
  *                  network and basis contraction, FP32 accumulation)
+ *   subharmonic_levels
+ *                  0..4 (0: off).  Subharmonic compensation of the tilt
+ *                  fields (Noll 2, 3), the low-frequency remedy named in
+ *                  Sec. IV-B: level p adds the 8 cells of size (1/(Gw ds),
+ *                  1/(Gh ds))/3^p around the DC bin (ds = pixel pitch over
+ *                  D) as 4 random cosine waves per mode, and the two tilt
+ *                  spectra are normalised over grid bins and cells together,
+ *                  so each field keeps unit variance.  See tsim_plan_table
+ *                  what = 4 and tsim_sample_zernike.
  */
 typedef struct tsim_params {
   int32_t H, W, C;
@@ -90,6 +99,7 @@ typedef struct tsim_params {
   const double *basis;
   int32_t p2s_mode;
   int32_t precision;
+  int32_t subharmonic_levels;
 } tsim_params;
 
 /* Build the FP64 plan tables on the host and upload them: the Noll matrix
@@ -119,6 +129,9 @@ int tsim_workspace_bytes(const tsim_plan *plan, int frames, size_t *bytes);
  *   what = 1: L, [35][35] lower triangular
  *   what = 2: sqrt of the quarter spectra, [35][Gw/2+1][Gh/2+1] (ky fastest)
  *   what = 3: pixel pitch over D, [1]
+ *   what = 4: subharmonic wave amplitudes, [2 modes][4 levels][4 cells]
+ *             (Noll 2, 3; level p = 1..4; cells (m, n) = (1,0), (1,1),
+ *             (0,1), (-1,1)), zero beyond subharmonic_levels
  * `count` is the number of doubles `host_out` can hold. */
 int tsim_plan_table(const tsim_plan *plan, int what, double *host_out, size_t count);
 
@@ -128,6 +141,12 @@ int tsim_plan_table(const tsim_plan *plan, int what, double *host_out, size_t co
  *           key (seed lo, seed hi) and counter (canonical bin, q, frame0+f,
  *           0) is coloured by the square-root spectra and inverse-FFT'd on
  *           the Gh x Gw grid (unitary scaling), then cropped to H x W;
+ *           with subharmonic levels, the tilt fields ybar_2, ybar_3 gain
+ *           sum over levels p and cells (m, n) of A cos t + B sin t,
+ *           t = 2 pi (m x / (Gw 3^p) + n y / (Gh 3^p)) at pixel (x, y),
+ *           where (A2, B2, A3, B3) are the amplitudes of table 4 times the
+ *           four Gaussians of the Philox call with counter (cell, p,
+ *           frame0+f, 5);
  *   step 2: a_x = (D/r0)^{5/6} L ybar_x at every pixel.
  *   d_over_r0 : host [frames], each > 0 and finite
  *   zern      : device [frames][35][H][W] float32, output

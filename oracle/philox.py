@@ -36,6 +36,7 @@ TAG_BASIS = 1
 TAG_MLP_DATA = 2
 TAG_MLP_INIT = 3
 TAG_IMAGE = 4
+TAG_SUBHARMONIC = 5
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):

@@ -21,7 +21,8 @@ import numpy as np
 
 from . import philox
 from .zernike import noll_matrix, cholesky_lower, N_MODES, J_FIRST
-from .spectra import all_spectra, discrete_correlation
+from .spectra import (all_spectra, discrete_correlation, subharmonic_amplitudes, SUBH_MODES,
+                      SUBH_CELLS)
 
 N_FIELDS = (N_MODES + 1) // 2      # 18 complex fields carry 35 real modes
 
@@ -58,12 +59,38 @@ def hermitian_noise(Gh, Gw, q, frame, seed, tag=philox.TAG_SAMPLER):
     return Wa, Wb
 
 
-def unit_fields(spectra, H, W, frame, seed):
+def subharmonic_waves(amps, H, W, Gh, Gw, frame, seed, rows=None):
+    """Low-frequency part of the tilt fields (2, H, W) for one frame: for
+    level p and half-plane cell (m, n), A cos(theta) + B sin(theta) per tilt
+    mode, theta = 2 pi (m x / (Gw 3^p) + n y / (Gh 3^p)) at pixel (x, y).
+    (A, B) of Noll 2 and of Noll 3 are the four Gaussians of the Philox call
+    with counter (cell, p, frame, TAG_SUBHARMONIC), scaled by ``amps``.
+    ``rows``: evaluate only these rows y (then the result has len(rows) rows)."""
+    levels = amps.shape[1]
+    ys = np.arange(H, dtype=np.float64) if rows is None else np.asarray(rows, dtype=np.float64)
+    out = np.zeros((len(SUBH_MODES), len(ys), W))
+    yy, xx = np.meshgrid(ys, np.arange(W, dtype=np.float64), indexing='ij')
+    for p in range(1, levels + 1):
+        for c, (m, n) in enumerate(SUBH_CELLS):
+            g = philox.gaussians4(np.array([c]), p, frame, philox.TAG_SUBHARMONIC, seed)
+            g = [float(v[0]) for v in g]
+            theta = 2.0 * np.pi * (m * xx / (Gw * 3.0 ** p) + n * yy / (Gh * 3.0 ** p))
+            ct, st = np.cos(theta), np.sin(theta)
+            for t in range(len(SUBH_MODES)):
+                a = amps[t, p - 1, c]
+                out[t] += a * g[2 * t] * ct + a * g[2 * t + 1] * st
+    return out
+
+
+def unit_fields(spectra, H, W, frame, seed, subharmonics=None):
     """Step 1: the 35 independent unit-variance fields ybar[j-2] (H x W).
 
     ``spectra`` is the (35, Gh, Gw) stack of discrete spectra Sbar_j.
     U = sqrt(Sbar_a) Wa + i sqrt(Sbar_b) Wb; z = unitary inverse DFT of U;
-    ybar_a = Re z, ybar_b = Im z, cropped to rows [0,H), columns [0,W)."""
+    ybar_a = Re z, ybar_b = Im z, cropped to rows [0,H), columns [0,W).
+    ``subharmonics``: the (2, levels, 4) amplitudes of
+    ``subharmonic_amplitudes`` (spectra built with the same levels); their
+    waves are added to the tilt fields."""
     n_modes, Gh, Gw = spectra.shape
     y = np.zeros((n_modes, H, W))
     for q in range(N_FIELDS):
@@ -76,6 +103,10 @@ def unit_fields(spectra, H, W, frame, seed):
         y[a - J_FIRST] = z.real[:H, :W]
         if b is not None:
             y[b - J_FIRST] = z.imag[:H, :W]
+    if subharmonics is not None and subharmonics.shape[1] > 0:
+        waves = subharmonic_waves(subharmonics, H, W, Gh, Gw, frame, seed)
+        for t, j in enumerate(SUBH_MODES):
+            y[j - J_FIRST] += waves[t]
     return y
 
 
@@ -84,14 +115,19 @@ def mix(y, L, d_over_r0):
     return float(d_over_r0) ** (5.0 / 6.0) * np.einsum('ij,jyx->iyx', L, y)
 
 
-def sample_zernike(H, W, Gh, Gw, ds, d_over_r0, seed, frame, fold=2, spectra=None, L=None):
+def sample_zernike(H, W, Gh, Gw, ds, d_over_r0, seed, frame, fold=2, spectra=None, L=None,
+                   subharmonic_levels=0):
     """Full oracle sampler for one frame: returns a (35, H, W) float64 array
-    zern[j-2, y, x]."""
+    zern[j-2, y, x].  ``subharmonic_levels`` > 0 adds the tilt modes'
+    subharmonic waves (``spectra``, if given, must be built with the same
+    levels)."""
     if spectra is None:
-        spectra = all_spectra(Gh, Gw, ds, fold)
+        spectra = all_spectra(Gh, Gw, ds, fold, subharmonic_levels=subharmonic_levels)
     if L is None:
         L = cholesky_lower(noll_matrix(1.0))
-    y = unit_fields(spectra, H, W, frame, seed)
+    amps = (subharmonic_amplitudes(Gh, Gw, ds, fold, subharmonic_levels)
+            if subharmonic_levels else None)
+    y = unit_fields(spectra, H, W, frame, seed, subharmonics=amps)
     return mix(y, L, d_over_r0)
 
 

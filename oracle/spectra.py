@@ -98,10 +98,78 @@ def discrete_correlation(Sbar):
     return np.real(np.fft.ifft2(Sbar))
 
 
-def all_spectra(Gh, Gw, ds, fold=2, j_first=J_FIRST, j_last=J_LAST):
+# Subharmonic compensation of the low frequencies (the remedy the paper
+# names for the low-frequency deficit of FFT screens, Sec. IV-B), for the two
+# tilt modes only.  Level p = 1..levels refines the grid's central frequency
+# cell 3^p times per axis: its 3 x 3 cells of size (dfx, dfy) / 3^p, the
+# centre excluded (it is the next level's), sit at (m dfx, n dfy) / 3^p with
+# dfx = 1/(Gw ds), dfy = 1/(Gh ds).  The four half-plane cells below stand
+# for the eight (the spectrum is even in each axis).
+SUBH_MODES = (2, 3)
+SUBH_CELLS = ((1, 0), (1, 1), (0, 1), (-1, 1))
+SUBH_MAX_LEVELS = 4
+
+
+def folded_spectrum(j, fx, fy, ds, fold):
+    """S_j summed over the lattice aliases f + l/ds, |l_x|, |l_y| <= fold (the
+    same fold as the grid bins)."""
+    out = 0.0
+    for lx in range(-fold, fold + 1):
+        for ly in range(-fold, fold + 1):
+            out = out + mode_spectrum(j, fx + lx / ds, fy + ly / ds)
+    return out
+
+
+def subharmonic_cell_spectra(j, Gh, Gw, ds, fold, levels):
+    """(levels, 4) array: folded S_j at the half-plane cells of each level."""
+    out = np.zeros((levels, len(SUBH_CELLS)))
+    for p in range(1, levels + 1):
+        for c, (m, n) in enumerate(SUBH_CELLS):
+            fx = m / (Gw * ds * 3.0 ** p)
+            fy = n / (Gh * ds * 3.0 ** p)
+            out[p - 1, c] = folded_spectrum(j, fx, fy, ds, fold)
+    return out
+
+
+def subharmonic_weight(j, Gh, Gw, ds, fold, levels):
+    """The cells' share of the normalising sum, in grid-bin units: a level-p
+    cell has 1/9^p of a bin's area, and each half-plane cell stands for two
+    cells (f and -f)."""
+    cs = subharmonic_cell_spectra(j, Gh, Gw, ds, fold, levels)
+    w = 9.0 ** -np.arange(1, levels + 1)
+    return float(2.0 * (cs.sum(axis=1) * w).sum())
+
+
+def subharmonic_amplitudes(Gh, Gw, ds, fold, levels):
+    """(2, levels, 4) amplitudes for the tilt modes: a level-p half-plane cell
+    adds A cos(theta) + B sin(theta) to the unit field, A, B ~ N(0, amp^2),
+    theta = 2 pi (m x / (Gw 3^p) + n y / (Gh 3^p)) at pixel (x, y).  amp^2 =
+    2 C_j S_j(f) / (Gh Gw 9^p): the power of cells f and -f under the same
+    normalisation C_j as the grid bins (``all_spectra`` with these levels),
+    so the field keeps unit variance."""
+    amps = np.zeros((len(SUBH_MODES), levels, len(SUBH_CELLS)))
+    if levels == 0:
+        return amps
+    kx = signed_index(Gw) / (Gw * ds)
+    ky = signed_index(Gh) / (Gh * ds)
+    FX, FY = np.meshgrid(kx, ky)
+    for t, j in enumerate(SUBH_MODES):
+        grid = folded_spectrum(j, FX, FY, ds, fold)
+        grid[0, 0] = 0.0
+        total = grid.sum() + subharmonic_weight(j, Gh, Gw, ds, fold, levels)
+        cj = Gh * Gw / total
+        cs = subharmonic_cell_spectra(j, Gh, Gw, ds, fold, levels)
+        w = 9.0 ** -np.arange(1, levels + 1)
+        amps[t] = np.sqrt(2.0 * cj * cs * w[:, None] / (Gh * Gw))
+    return amps
+
+
+def all_spectra(Gh, Gw, ds, fold=2, j_first=J_FIRST, j_last=J_LAST, subharmonic_levels=0):
     """Stack of ``discrete_spectrum`` for modes j_first..j_last.  Same sums as
     calling it per mode; the radial factor (one Bessel order per radial order
-    n) is evaluated once per alias and shared by the modes of that order."""
+    n) is evaluated once per alias and shared by the modes of that order.
+    With subharmonic levels, the tilt modes' normalising sum also counts the
+    subharmonic cells (their unit variance is then shared with them)."""
     js = list(range(j_first, j_last + 1))
     kx = signed_index(Gw) / (Gw * ds)
     ky = signed_index(Gh) / (Gh * ds)
@@ -137,8 +205,28 @@ def all_spectra(Gh, Gw, ds, fold=2, j_first=J_FIRST, j_last=J_LAST):
         for part in ex.map(alias_term, aliases):   # summed in alias order
             S += part
     S[:, 0, 0] = 0.0
-    S *= (Gh * Gw) / S.sum(axis=(1, 2), keepdims=True)
+    total = S.sum(axis=(1, 2))
+    if subharmonic_levels:
+        for t, j in enumerate(js):
+            if j in SUBH_MODES:
+                total[t] += subharmonic_weight(j, Gh, Gw, ds, fold, subharmonic_levels)
+    S *= (Gh * Gw) / total[:, None, None]
     return S
+
+
+def model_correlation(j, Gh, Gw, ds, fold, levels, dx, dy):
+    """Covariance of the unit field of mode j at a lag of (dx, dy) pixels, as
+    the sampler draws it: the grid bins' exact lattice correlation plus the
+    subharmonic waves' amp^2 cos(2 pi f . lag)."""
+    S = all_spectra(Gh, Gw, ds, fold, j, j, subharmonic_levels=levels)[0]
+    rho = discrete_correlation(S)[dy % Gh, dx % Gw]
+    if levels and j in SUBH_MODES:
+        amps = subharmonic_amplitudes(Gh, Gw, ds, fold, levels)[SUBH_MODES.index(j)]
+        for p in range(1, levels + 1):
+            for c, (m, n) in enumerate(SUBH_CELLS):
+                rho += amps[p - 1, c] ** 2 * np.cos(2.0 * np.pi * (m * dx / (Gw * 3.0 ** p) +
+                                                                   n * dy / (Gh * 3.0 ** p)))
+    return rho
 
 
 def continuous_correlation(j, sx, sy, fmax=200.0, n_r=20000):

@@ -36,7 +36,7 @@ class _Params(ctypes.Structure):
                 ("alias_fold", ctypes.c_int32), ("pupil_n", ctypes.c_int32),
                 ("psf_t", ctypes.c_int32), ("basis_k", ctypes.c_int32),
                 ("basis", ctypes.POINTER(ctypes.c_double)), ("p2s_mode", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("subharmonic_levels", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -145,20 +145,22 @@ def _stream(stream):
 
 def make_params(H, W, C=1, Gh=None, Gw=None, pixel_pitch_over_d=0.125, aperture_d_m=0.0,
                 wavelength_m=0.0, path_length_m=0.0, alias_fold=2, pupil_n=64, psf_t=33,
-                basis_k=1, p2s_mode=P2S_EXACT, precision=FP32):
+                basis_k=1, p2s_mode=P2S_EXACT, precision=FP32, subharmonic_levels=0):
     if Gh is None:
         Gh = 1 << int(np.ceil(np.log2(2 * H)))
     if Gw is None:
         Gw = 1 << int(np.ceil(np.log2(2 * W)))
     return _Params(H, W, C, Gh, Gw, N_MODES, pixel_pitch_over_d, aperture_d_m, wavelength_m,
-                   path_length_m, alias_fold, pupil_n, psf_t, basis_k, None, p2s_mode, precision)
+                   path_length_m, alias_fold, pupil_n, psf_t, basis_k, None, p2s_mode, precision,
+                   subharmonic_levels)
 
 
 def host_tables(params, what):
     """Run the host half of plan creation (no device) and return one table:
-    0 = A_0, 1 = L, 2 = sqrt quarter spectra [35][Gw/2+1][Gh/2+1], 3 = pitch."""
+    0 = A_0, 1 = L, 2 = sqrt quarter spectra [35][Gw/2+1][Gh/2+1], 3 = pitch,
+    4 = subharmonic amplitudes [2][4][4]."""
     sizes = {0: N_MODES * N_MODES, 1: N_MODES * N_MODES,
-             2: N_MODES * (params.Gw // 2 + 1) * (params.Gh // 2 + 1), 3: 1}
+             2: N_MODES * (params.Gw // 2 + 1) * (params.Gh // 2 + 1), 3: 1, 4: 32}
     out = np.zeros(sizes[what], dtype=np.float64)
     _check(_lib_host_tables(ctypes.byref(params), what,
                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size),
@@ -167,6 +169,8 @@ def host_tables(params, what):
         return out.reshape(N_MODES, N_MODES)
     if what == 2:
         return out.reshape(N_MODES, params.Gw // 2 + 1, params.Gh // 2 + 1)
+    if what == 4:
+        return out.reshape(2, 4, 4)
     return out[0]
 
 
@@ -177,7 +181,7 @@ class Plan:
     def __init__(self, H, W, C=1, Gh=None, Gw=None, pixel_pitch_over_d=0.125,
                  aperture_d_m=0.0, wavelength_m=0.0, path_length_m=0.0, alias_fold=2,
                  pupil_n=64, psf_t=33, basis=None, basis_k=None, p2s_mode=P2S_EXACT,
-                 precision=FP32):
+                 precision=FP32, subharmonic_levels=0):
         if Gh is None:
             Gh = 1 << int(np.ceil(np.log2(2 * H)))
         if Gw is None:
@@ -192,7 +196,7 @@ class Plan:
             basis_k = 1
         self.params = _Params(H, W, C, Gh, Gw, N_MODES, pixel_pitch_over_d, aperture_d_m,
                               wavelength_m, path_length_m, alias_fold, pupil_n, psf_t, basis_k,
-                              bptr, p2s_mode, precision)
+                              bptr, p2s_mode, precision, subharmonic_levels)
         self.H, self.W, self.C, self.Gh, self.Gw = H, W, C, Gh, Gw
         self.T, self.K, self.P = psf_t, basis_k, pupil_n
         h = _vp()
@@ -213,7 +217,7 @@ class Plan:
     # ---- plan tables -------------------------------------------------
     def table(self, what):
         sizes = {0: N_MODES * N_MODES, 1: N_MODES * N_MODES,
-                 2: N_MODES * (self.Gw // 2 + 1) * (self.Gh // 2 + 1), 3: 1}
+                 2: N_MODES * (self.Gw // 2 + 1) * (self.Gh // 2 + 1), 3: 1, 4: 32}
         out = np.zeros(sizes[what], dtype=np.float64)
         _check(_lib_table(self._h, what, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                           out.size), "tsim_plan_table")
@@ -221,6 +225,8 @@ class Plan:
             return out.reshape(N_MODES, N_MODES)
         if what == 2:
             return out.reshape(N_MODES, self.Gw // 2 + 1, self.Gh // 2 + 1)
+        if what == 4:
+            return out.reshape(2, 4, 4)
         return out[0]
 
     def workspace_bytes(self, frames):

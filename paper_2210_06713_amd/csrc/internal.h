@@ -23,6 +23,7 @@ struct tsim_plan {
   std::vector<double> A0;      // [35][35] at D/r0 = 1
   std::vector<double> L;       // [35][35] lower
   std::vector<double> sqrtS;   // [35][Gw/2+1][Gh/2+1]
+  std::vector<double> subh;    // [2][4][4] subharmonic wave amplitudes (tilt modes)
   std::vector<double> basis;   // [K][T*T]
   // device tables
   float *d_sqrtS = nullptr;    // [35][Gw/2+1][Gh/2+1] float32

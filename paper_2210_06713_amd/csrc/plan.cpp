@@ -127,6 +127,32 @@ struct ModeInfo {
   int n, m, kind;  // kind 0: m = 0, 1: cosine (even j), 2: sine (odd j)
 };
 
+// Spectra of all modes at (fx0, fy0) cycles per D, summed over the lattice
+// aliases (fx0 + lx/ds, fy0 + ly/ds), |lx|, |ly| <= A.
+void folded_spectra(const ModeInfo *mi, double fx0, double fy0, double ds, int A, double *acc) {
+  double jb[9];
+  double cm[8], sm[8];
+  for (int t = 0; t < TSIM_N_MODES; ++t) acc[t] = 0.0;
+  for (int lx = -A; lx <= A; ++lx) {
+    for (int ly = -A; ly <= A; ++ly) {
+      double fx = fx0 + lx / ds;
+      double fy = fy0 + ly / ds;
+      double f = std::hypot(fx, fy);
+      if (f == 0.0) continue;
+      bessel_j_orders(kPi * f, 8, jb);
+      double c1 = fx / f, s1 = fy / f;
+      cm[0] = 1.0;
+      sm[0] = 0.0;
+      for (int q = 1; q < 8; ++q) {
+        cm[q] = cm[q - 1] * c1 - sm[q - 1] * s1;
+        sm[q] = sm[q - 1] * c1 + cm[q - 1] * s1;
+      }
+      for (int t = 0; t < TSIM_N_MODES; ++t)
+        acc[t] += mode_spectrum(mi[t].n, mi[t].m, mi[t].kind, f, jb, cm[mi[t].m], sm[mi[t].m]);
+    }
+  }
+}
+
 void build_spectra(tsim_plan *pl) {
   const int Gh = pl->Gh, Gw = pl->Gw;
   const int qh = Gh / 2 + 1, qw = Gw / 2 + 1;
@@ -141,30 +167,11 @@ void build_spectra(tsim_plan *pl) {
   // quarter table S[mode][kx'][ky'] in float64
   std::vector<double> S(size_t(TSIM_N_MODES) * qw * qh, 0.0);
   auto work = [&](int kx0, int kx1) {
-    double jb[9];
-    double cm[8], sm[8];
     for (int kx = kx0; kx < kx1; ++kx) {
       for (int ky = 0; ky < qh; ++ky) {
         if (kx == 0 && ky == 0) continue;  // DC removed
-        double acc[TSIM_N_MODES] = {0};
-        for (int lx = -A; lx <= A; ++lx) {
-          for (int ly = -A; ly <= A; ++ly) {
-            double fx = double(kx) / (Gw * ds) + lx / ds;
-            double fy = double(ky) / (Gh * ds) + ly / ds;
-            double f = std::hypot(fx, fy);
-            if (f == 0.0) continue;
-            bessel_j_orders(kPi * f, 8, jb);
-            double c1 = fx / f, s1 = fy / f;
-            cm[0] = 1.0;
-            sm[0] = 0.0;
-            for (int q = 1; q < 8; ++q) {
-              cm[q] = cm[q - 1] * c1 - sm[q - 1] * s1;
-              sm[q] = sm[q - 1] * c1 + cm[q - 1] * s1;
-            }
-            for (int t = 0; t < TSIM_N_MODES; ++t)
-              acc[t] += mode_spectrum(mi[t].n, mi[t].m, mi[t].kind, f, jb, cm[mi[t].m], sm[mi[t].m]);
-          }
-        }
+        double acc[TSIM_N_MODES];
+        folded_spectra(mi, double(kx) / (Gw * ds), double(ky) / (Gh * ds), ds, A, acc);
         for (int t = 0; t < TSIM_N_MODES; ++t) S[(size_t(t) * qw + kx) * qh + ky] = acc[t];
       }
     }
@@ -177,11 +184,31 @@ void build_spectra(tsim_plan *pl) {
     if (a < b) th.emplace_back(work, a, b);
   }
   for (auto &t : th) t.join();
-  // unit mean over the full Gh x Gw grid: interior quarter bins stand for
-  // two mirror bins per axis, the DC and Nyquist rows/columns for one.
+  // Subharmonic cells of the tilt modes (t = 0, 1): level p, half-plane
+  // cell (m, n) at (m/(Gw ds), n/(Gh ds))/3^p; a level-p cell has 1/9^p of a
+  // bin's area, and each half-plane cell stands for itself and its mirror.
+  const int levels = pl->p.subharmonic_levels;
+  static const int kCell[4][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 1}};
+  double cellS[2][4][4] = {};
+  double cellW[2] = {0.0, 0.0};
+  for (int p = 1; p <= levels; ++p) {
+    const double r = std::pow(3.0, p);
+    for (int c = 0; c < 4; ++c) {
+      double acc[TSIM_N_MODES];
+      folded_spectra(mi, kCell[c][0] / (Gw * ds * r), kCell[c][1] / (Gh * ds * r), ds, A, acc);
+      for (int t = 0; t < 2; ++t) {
+        cellS[t][p - 1][c] = acc[t];
+        cellW[t] += 2.0 * acc[t] / (r * r);
+      }
+    }
+  }
+  pl->subh.assign(2 * 4 * 4, 0.0);
+  // unit mean over the full Gh x Gw grid (plus, for the tilt modes, the
+  // subharmonic cells): interior quarter bins stand for two mirror bins per
+  // axis, the DC and Nyquist rows/columns for one.
   pl->sqrtS.assign(S.size(), 0.0);
   for (int t = 0; t < TSIM_N_MODES; ++t) {
-    double tot = 0.0;
+    double tot = t < 2 ? cellW[t] : 0.0;
     for (int kx = 0; kx < qw; ++kx) {
       double wx = (kx == 0 || kx == Gw / 2) ? 1.0 : 2.0;
       for (int ky = 0; ky < qh; ++ky) {
@@ -192,6 +219,12 @@ void build_spectra(tsim_plan *pl) {
     double scale = double(Gh) * Gw / tot;
     for (size_t i = size_t(t) * qw * qh; i < size_t(t + 1) * qw * qh; ++i)
       pl->sqrtS[i] = std::sqrt(S[i] * scale);
+    // wave amplitude: variance of the cell and its mirror, 2 S scale / (Gh Gw 9^p)
+    if (t < 2)
+      for (int p = 1; p <= levels; ++p)
+        for (int c = 0; c < 4; ++c)
+          pl->subh[(t * 4 + (p - 1)) * 4 + c] =
+              std::sqrt(2.0 * cellS[t][p - 1][c] * scale / (double(Gh) * Gw * std::pow(9.0, p)));
   }
 }
 
@@ -242,6 +275,7 @@ int validate(const tsim_params *p) {
   if (p->basis_k < 1 || p->basis_k > 128) return TSIM_EINVAL;
   if (p->p2s_mode != TSIM_P2S_EXACT && p->p2s_mode != TSIM_P2S_LEARNED) return TSIM_EINVAL;
   if (p->precision != TSIM_FP32 && p->precision != TSIM_BF16) return TSIM_EINVAL;
+  if (p->subharmonic_levels < 0 || p->subharmonic_levels > 4) return TSIM_EINVAL;
   return TSIM_OK;
 }
 
@@ -308,6 +342,7 @@ int copy_table(const tsim_plan *pl, int what, double *host_out, size_t count) {
     case 0: src = &pl->A0; break;
     case 1: src = &pl->L; break;
     case 2: src = &pl->sqrtS; break;
+    case 4: src = &pl->subh; break;
     case 3:
       if (count < 1) return TSIM_EINVAL;
       host_out[0] = pl->ds;

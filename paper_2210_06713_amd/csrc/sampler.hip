@@ -32,6 +32,21 @@ struct FrameScales {
   float s[kMaxFramesPerLaunch];
 };
 
+// Subharmonic compensation of the tilt fields (Noll 2, 3): for level p (0-
+// based here, 1-based in the counter) and half-plane cell c of (m, n) =
+// (1,0), (1,1), (0,1), (-1,1), the wave A cos t + B sin t with t = pi x
+// fx[p] m + pi y fy[p] n, fx[p] = 2/(Gw 3^(p+1)), fy[p] = 2/(Gh 3^(p+1));
+// (A2, B2, A3, B3) = amp times the Gaussians of the Philox call with counter
+// (c, p + 1, frame, kTagSubharmonic).
+constexpr uint32_t kTagSubharmonic = 5u;
+constexpr int kSubhMaxLevels = 4;
+struct SubhArgs {
+  float amp[2][kSubhMaxLevels][4];
+  float fx[kSubhMaxLevels], fy[kSubhMaxLevels];
+  int levels;
+  uint32_t key0, key1, frame_base;
+};
+
 // Column slots of the intermediate: slots 2p and 2p + 1 hold the Hermitian
 // mirror columns kx = p and Gw - p (1 <= p < Gw/2); slots 0 and 1 hold the
 // self-mirror columns 0 and Gw/2.  A pass-1 block owns whole slot pairs, so
@@ -335,6 +350,57 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
   FieldSteps<0, PX, NT, RW, GPT>::run(a, acc, pre);
 }
 
+// Subharmonic waves of the tilt fields, added after the mix: the waves w2,
+// w3 belong to the unit fields of Noll 2 and 3, so output t gains
+// s_f (L[t][0] w2 + L[t][1] w3), non-zero only for the outputs of the two
+// tilt groups (|m| = 1).  One thread per pixel, grid (ceil(W/256), H,
+// frames); the first 4 * levels threads draw the frame's wave amplitudes.
+__global__ void __launch_bounds__(256)
+k_subharmonic_add(float *__restrict__ zern, const float *__restrict__ Lmat, int H, int W,
+                  FrameScales scales, SubhArgs sub, int frame_out0) {
+  __shared__ float coef[kSubhMaxLevels * 16];  // [level][cell][A2, B2, A3, B3]
+  const int fl = blockIdx.z;
+  if (int(threadIdx.x) < 4 * sub.levels) {
+    const int p = threadIdx.x >> 2, c = threadIdx.x & 3;
+    const u32x4 r = philox4x32_10(
+        u32x4{uint32_t(c), uint32_t(p + 1), sub.frame_base + uint32_t(fl), kTagSubharmonic}, sub.key0, sub.key1);
+    const float2 g01 = box_muller_hw(r.x, r.y);
+    const float2 g23 = box_muller_hw(r.z, r.w);
+    float *o = coef + (p * 4 + c) * 4;
+    o[0] = sub.amp[0][p][c] * g01.x;
+    o[1] = sub.amp[0][p][c] * g01.y;
+    o[2] = sub.amp[1][p][c] * g23.x;
+    o[3] = sub.amp[1][p][c] * g23.y;
+  }
+  __syncthreads();
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= W) return;
+  float w2 = 0.f, w3 = 0.f;
+  for (int p = 0; p < sub.levels; ++p) {
+    float sa, ca, sb, cb;
+    sincospif(float(x) * sub.fx[p], &sa, &ca);
+    sincospif(float(y) * sub.fy[p], &sb, &cb);
+    const float cd = ca * cb - sa * sb, sd = sa * cb + ca * sb;  // cell (1, 1): alpha + beta
+    const float ce = ca * cb + sa * sb, se = ca * sb - sa * cb;  // cell (-1, 1): beta - alpha
+    const float *c = coef + p * 16;
+    w2 += c[0] * ca + c[1] * sa + c[4] * cd + c[5] * sd + c[8] * cb + c[9] * sb + c[12] * ce + c[13] * se;
+    w3 += c[2] * ca + c[3] * sa + c[6] * cd + c[7] * sd + c[10] * cb + c[11] * sb + c[14] * ce + c[15] * se;
+  }
+  const float sc = scales.s[fl];
+  const size_t plane = size_t(H) * W;
+  float *out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * plane + size_t(y) * W + x;
+#pragma unroll
+  for (int t = 0; t < TSIM_N_MODES; ++t) {
+    if (kMix.nz[t][0] || kMix.nz[t][1]) {
+      float d = 0.f;
+      if (kMix.nz[t][0]) d = fmaf(Lmat[t * TSIM_N_MODES], w2, d);
+      if (kMix.nz[t][1]) d = fmaf(Lmat[t * TSIM_N_MODES + 1], w3, d);
+      out[size_t(t) * plane] += sc * d;
+    }
+  }
+}
+
 // Temporal auto-regression on the mixed fields, in place over a chunk of
 // frames: a_f = mul_f a_{f-1} + c a_f^new (mul_f = alpha s_f / s_{f-1}); the
 // frame before the chunk comes from `prev` (NULL at the start of a sequence:
@@ -454,21 +520,41 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     FrameScales sc;
     for (int i = 0; i < kMaxFramesPerLaunch; ++i) sc.s[i] = 0.f;
     for (int i = 0; i < nf; ++i) sc.s[i] = scale_host[f0 + i];
-    TraceScope tr("k_sampler_rows_mix", s);
-    // two rows per block (one LDS transform pass and one barrier set for both)
-    // up to 1024 columns; 1024-thread blocks over single rows beyond
-    const size_t lds2 = (2 * size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
-    const size_t lds1 = (size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
-    dim3 g2((H + 1) / 2, nf), g1r(H, nf);
-    if (W <= 256)
-      launch_rows<1, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-    else if (W <= 512)
-      launch_rows<2, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-    else if (W <= 1024)
-      launch_rows<4, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-    else
-      launch_rows<4, 1024, 1>(g1r, lds1, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+    SubhArgs sub{};
+    sub.levels = pl->p.subharmonic_levels;
+    for (int p = 0; p < kSubhMaxLevels; ++p) {
+      const double r = std::pow(3.0, p + 1);
+      sub.fx[p] = float(2.0 / (Gw * r));
+      sub.fy[p] = float(2.0 / (Gh * r));
+      for (int c = 0; c < 4; ++c)
+        for (int t = 0; t < 2; ++t) sub.amp[t][p][c] = float(pl->subh[(t * 4 + p) * 4 + c]);
+    }
+    sub.key0 = key0;
+    sub.key1 = key1;
+    sub.frame_base = uint32_t(frame0 + uint64_t(f0));
+    {
+      TraceScope tr("k_sampler_rows_mix", s);
+      // two rows per block (one LDS transform pass and one barrier set for both)
+      // up to 1024 columns; 1024-thread blocks over single rows beyond
+      const size_t lds2 = (2 * size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
+      const size_t lds1 = (size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
+      dim3 g2((H + 1) / 2, nf), g1r(H, nf);
+      if (W <= 256)
+        launch_rows<1, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
+      else if (W <= 512)
+        launch_rows<2, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
+      else if (W <= 1024)
+        launch_rows<4, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
+      else
+        launch_rows<4, 1024, 1>(g1r, lds1, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
+      if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+    }
+    if (sub.levels > 0) {
+      TraceScope tr("k_subharmonic_add", s);
+      hipLaunchKernelGGL(k_subharmonic_add, dim3((W + 255) / 256, H, nf), dim3(256), 0, s, zern, pl->d_L, H, W,
+                         sc, sub, f0);
+      if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+    }
   }
   return TSIM_OK;
 }

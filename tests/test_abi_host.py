@@ -39,7 +39,8 @@ def test_status_strings(t):
 
 @pytest.mark.parametrize("field,value", [
     ("H", 0), ("Gh", 96), ("Gw", 32), ("n_modes", 36), ("psf_t", 32), ("psf_t", 1),
-    ("basis_k", 0), ("basis_k", 200), ("alias_fold", 7), ("C", 0), ("precision", 5)])
+    ("basis_k", 0), ("basis_k", 200), ("alias_fold", 7), ("C", 0), ("precision", 5),
+    ("subharmonic_levels", -1), ("subharmonic_levels", 5)])
 def test_invalid_parameters_rejected(t, field, value):
     p = t.make_params(64, 64, 1, 128, 128)
     setattr(p, field, value)
@@ -80,3 +81,24 @@ def test_spectra_match_oracle(t, Gh, Gw, ds, fold):
         S = ospec.discrete_spectrum(j, Gh, Gw, ds, fold)   # [ky][kx]
         quarter = np.sqrt(S[:Gh // 2 + 1, :Gw // 2 + 1]).T  # [kx][ky]
         np.testing.assert_allclose(sq[j - 2], quarter, rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("Gh,Gw,ds,fold,levels", [(128, 128, 0.125, 2, 3), (64, 256, 0.25, 1, 4),
+                                                 (256, 128, 0.125, 2, 1)])
+def test_subharmonic_tables_match_oracle(t, Gh, Gw, ds, fold, levels):
+    """With subharmonic levels the tilt spectra share their normalisation with
+    the subharmonic cells, and table 4 holds the wave amplitudes."""
+    p = t.make_params(32, 32, 1, Gh, Gw, pixel_pitch_over_d=ds, alias_fold=fold,
+                      subharmonic_levels=levels)
+    sq = t.host_tables(p, 2)
+    S = ospec.all_spectra(Gh, Gw, ds, fold, subharmonic_levels=levels)
+    for j in [2, 3, 4, 8, 36]:
+        quarter = np.sqrt(S[j - 2, :Gh // 2 + 1, :Gw // 2 + 1]).T
+        np.testing.assert_allclose(sq[j - 2], quarter, rtol=1e-11, atol=1e-14)
+    amp = t.host_tables(p, 4)                # [2][4][4]
+    ref = ospec.subharmonic_amplitudes(Gh, Gw, ds, fold, levels)
+    np.testing.assert_allclose(amp[:, :levels], ref, rtol=1e-11, atol=1e-15)
+    assert not amp[:, levels:].any()
+    # levels 0: the table is all zero and the spectra are the plain ones
+    p0 = t.make_params(32, 32, 1, Gh, Gw, pixel_pitch_over_d=ds, alias_fold=fold)
+    assert not t.host_tables(p0, 4).any()

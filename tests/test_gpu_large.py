@@ -187,6 +187,40 @@ def test_sampler_4k_frames_and_variance(t):
     assert np.all(np.abs(ratio - 1.0) < 0.05), ratio
 
 
+def test_sampler_4k_subharmonics(t):
+    """Full 3840 x 2160 frame on the 4096^2 grid with three subharmonic
+    levels, against the same frame without them.  Outputs outside the two
+    tilt groups (|m| != 1) are bit-identical.  The tilt fields' grid part is
+    the plain one times rho = ratio of the two plans' tilt spectra, so
+    (a_sub - rho a_plain) / (s L_jj) must be the oracle's subharmonic waves,
+    at every pixel."""
+    say("sampler 4K subharmonics levels=3")
+    levels, dr, seed, frame = 3, 2.0, 9, 3
+    p0 = t.Plan(H4, W4, 3, G4, G4, pixel_pitch_over_d=0.125)
+    p3 = t.Plan(H4, W4, 3, G4, G4, pixel_pitch_over_d=0.125, subharmonic_levels=levels)
+    out = []
+    for plan in (p0, p3):
+        z = torch.empty((1, 35, H4, W4), dtype=torch.float32, device="cuda")
+        plan.sample_zernike([dr], seed, frame, z, plan.workspace(1))
+        torch.cuda.synchronize()
+        out.append(z[0].cpu().numpy().astype(np.float64))
+        del z
+    a0, a3 = out
+    L = ozern.cholesky_lower(ozern.noll_matrix(1.0))
+    for j in range(35):
+        if L[j, 0] == 0.0 and L[j, 1] == 0.0:
+            assert np.array_equal(a0[j], a3[j]), j
+    sc = dr ** (5.0 / 6.0)
+    s0, s3 = p0.table(2), p3.table(2)
+    amps = ospec.subharmonic_amplitudes(G4, G4, 0.125, 2, levels)
+    rows = np.arange(0, H4, 97)
+    waves = osamp.subharmonic_waves(amps, H4, W4, G4, G4, frame, seed, rows=rows)  # [2][rows][W]
+    for t_ in (0, 1):
+        rho = s3[t_, 3, 5] / s0[t_, 3, 5]
+        w = (a3[t_, rows] - rho * a0[t_, rows]) / (sc * L[t_, t_])
+        assert rel(w, waves[t_]) < 1e-4, (t_, rel(w, waves[t_]))
+
+
 def test_p2s_exact_4k_sampled_pixels(t, basis65):
     say("p2s exact 4K, sampled pixels")
     plan = t.Plan(H4, W4, 3, G4, G4, pupil_n=128, psf_t=65, basis=basis65)

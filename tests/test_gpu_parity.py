@@ -90,6 +90,30 @@ def test_sampler_matches_oracle(t, H, W, Gh, Gw, seed, frame0, dr):
         assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
 
 
+@pytest.mark.parametrize("H,W,Gh,Gw,levels,seed,frame0", [
+    (64, 64, 128, 128, 3, 5, 2),
+    (48, 80, 128, 256, 4, 2 ** 40 + 77, 5),   # ragged, non-square, 64-bit seed
+    (13, 200, 64, 512, 1, 3, 1),
+    (7, 1000, 64, 1024, 2, 6, 0),
+])
+def test_sampler_subharmonics_match_oracle(t, H, W, Gh, Gw, levels, seed, frame0):
+    """Subharmonic compensation of the tilt fields: every plane against the
+    oracle, which adds the same Philox-drawn waves to its unit fields."""
+    say(f"sampler subharmonics levels={levels} H={H} W={W} G={Gh}x{Gw}")
+    plan = t.Plan(H, W, 1, Gh, Gw, pixel_pitch_over_d=0.125, subharmonic_levels=levels)
+    drs = [2.0, 3.0]
+    zern = _sample(t, plan, drs, seed, frame0, 2).cpu().numpy()
+    S = ospec.all_spectra(Gh, Gw, 0.125, 2, subharmonic_levels=levels)
+    L = ozern.cholesky_lower(ozern.noll_matrix(1.0))
+    np.testing.assert_allclose(plan.table(4)[:, :levels],
+                               ospec.subharmonic_amplitudes(Gh, Gw, 0.125, 2, levels), rtol=1e-11)
+    for f in range(2):
+        ref = osamp.sample_zernike(H, W, Gh, Gw, 0.125, drs[f], seed, frame0 + f, spectra=S, L=L,
+                                   subharmonic_levels=levels)
+        errs = [rel(zern[f, j], ref[j]) for j in range(35)]
+        assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
+
+
 @pytest.mark.slow
 def test_sampler_full_size_frame(t):
     """512 x 512 frame on the 1024 x 1024 grid, the benchmark's launch shape."""
