@@ -157,7 +157,7 @@ int tsim_sample_zernike(const tsim_plan *plan, int frames, const float *d_over_r
 
 /* (a') Temporally correlated Zernike fields by an auto-regressive process,
  * the low-order workaround the paper gives for spatio-temporal correlation
- * (Sec. IV-A): the unit-variance fields of frame t follow
+ * (Sec. III-E): the unit-variance fields of frame t follow
  *   ybar_t = alpha ybar_{t-1} + sqrt(1 - alpha^2) w_t,
  * with w_t the independent fields tsim_sample_zernike draws for frame
  * frame0 + t, and frame t is mixed with its own (D/r0_t)^{5/6} L.  Each

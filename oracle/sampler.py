@@ -134,7 +134,7 @@ def sample_zernike(H, W, Gh, Gw, ds, d_over_r0, seed, frame, fold=2, spectra=Non
 def sample_sequence_ar(H, W, Gh, Gw, ds, d_over_r0s, seed, frame0, alpha, y_prev=None, fold=2,
                        spectra=None, L=None):
     """Temporally correlated frames by an auto-regressive process (the
-    workaround the paper gives for spatio-temporal correlation, Sec. IV-A):
+    workaround the paper gives for spatio-temporal correlation, Sec. III-E):
     the unit-variance fields follow ybar_t = alpha ybar_{t-1} +
     sqrt(1 - alpha^2) w_t, where w_t are frame (frame0 + t)'s own independent
     unit fields, and frame t is mixed with its own (D/r0)^{5/6} L.  Each field
