@@ -372,9 +372,13 @@ def ar_sequence(tsim, torch, wl, s, steps):
             "ms_per_chunk": round(ms, 3), "kernels": kern}
 
 
+STAT_LAG = 64
+
+
 def subharmonic_sampler(tsim, torch, wl, s, steps):
     """The sampler alone on the 512^2 workload (16 frames per call), without
-    and with three subharmonic levels for the tilt fields."""
+    and with three subharmonic levels for the tilt fields; then the spatial
+    tilt statistics of the latter's frames (host-synchronous calls)."""
     n = s["chunk"]
     drs = [s["drs"][i % len(s["drs"])] for i in range(n)]
     out = {"workload": f"{n} frames of {s['H']}x{s['W']}, grid {s['G']}^2, sampler only"}
@@ -398,6 +402,23 @@ def subharmonic_sampler(tsim, torch, wl, s, steps):
         ms = a.elapsed_time(b) / steps
         out[f"levels_{levels}"] = {"value": round(n * s["H"] * s["W"] / (ms * 1e-3) / 1e6, 3),
                                    "unit": "Mpixel/s", "ms_per_call": round(ms, 4), "kernels": kern}
+        if levels:
+            # spatial tilt statistics of these frames, lags 0..64 along x and y
+            corr, dtv = pl.tilt_stats(wl.zern, STAT_LAG)
+            tsim.trace_enable(True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                pl.tilt_stats(wl.zern, STAT_LAG)
+            ms_s = (time.perf_counter() - t0) * 1e3 / steps
+            rep_ = tsim.trace_report()
+            tsim.trace_enable(False)
+            kern_s, _ = summarize(rep_, steps, n, s, traffic=False)
+            out["tilt_stats"] = {"max_lag": STAT_LAG, "frames": n,
+                                 "value": round(n * s["H"] * s["W"] / (ms_s * 1e-3) / 1e6, 3),
+                                 "unit": "Mpixel/s", "ms_per_call": round(ms_s, 4),
+                                 "kernels": kern_s,
+                                 "x_tilt_corr_x_lag_8_over_var": round(corr[0, 0, 8] / corr[0, 0, 0], 4),
+                                 "x_tilt_corr_y_lag_8_over_var": round(corr[0, 1, 8] / corr[0, 1, 0], 4)}
         del ws
         pl.close()
     return out

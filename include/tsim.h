@@ -155,6 +155,24 @@ int tsim_sample_zernike(const tsim_plan *plan, int frames, const float *d_over_r
                         uint64_t seed, uint64_t frame0, float *zern, void *ws,
                         tsim_stream stream);
 
+/* Spatial tilt statistics of coefficient planes (the spatial validation of
+ * Sec. IV-B): for Noll 2 and 3, the tilt correlation (mean product) and the
+ * differential tilt variance (mean squared difference) of all pixel pairs at
+ * lags d = 0..max_lag along x and along y, over `frames` frames.  Pairs stay
+ * inside the frame: H (W - d) per frame for an x lag, (H - d) W for a y lag.
+ * Row sums are FP32, their total FP64 in a fixed order (deterministic).
+ *   zern     : device [frames][35][H][W] float32, 256-byte aligned (e.g. the
+ *              output of tsim_sample_zernike)
+ *   max_lag  : 0 <= max_lag <= 256, below H and W
+ *   host_out : host [2 modes][2 axes (x, y)][2 (correlation, DTV)][max_lag+1]
+ *              float64, written on success
+ *   ws       : device workspace of tsim_tilt_stats_ws_bytes(plan, frames,
+ *              max_lag) bytes, 256-byte aligned
+ * Synchronises `stream` before returning.  TSIM_EINVAL on a bad argument. */
+int tsim_tilt_stats_ws_bytes(const tsim_plan *plan, int frames, int max_lag, size_t *bytes);
+int tsim_tilt_stats(const tsim_plan *plan, int frames, const float *zern, int max_lag,
+                    double *host_out, void *ws, tsim_stream stream);
+
 /* (a') Temporally correlated Zernike fields by an auto-regressive process,
  * the low-order workaround the paper gives for spatio-temporal correlation
  * (Sec. III-E): the unit-variance fields of frame t follow

@@ -59,6 +59,8 @@ _lib_sample = _sig("tsim_sample_zernike", _i,
                    [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64, _vp, _vp, _vp])
 _lib_sample_ar = _sig("tsim_sample_zernike_ar", _i, [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64,
                                                      ctypes.c_float, _vp, ctypes.c_float, _vp, _vp, _vp])
+_lib_stats_ws = _sig("tsim_tilt_stats_ws_bytes", _i, [_vp, _i, _i, ctypes.POINTER(ctypes.c_size_t)])
+_lib_stats = _sig("tsim_tilt_stats", _i, [_vp, _i, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp, _vp])
 _lib_p2s = _sig("tsim_p2s", _i, [_vp, _i, _vp, _vp, _vp, _vp])
 _lib_render = _sig("tsim_render", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp])
 _lib_warp = _sig("tsim_warp", _i, [_vp, _i, _vp, _vp, _vp, _vp])
@@ -95,7 +97,7 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_trace_count", "tsim_trace_get", "tsim_mlp_create", "tsim_mlp_destroy",
             "tsim_mlp_param_count", "tsim_mlp_layout", "tsim_mlp_get", "tsim_mlp_set",
             "tsim_mlp_data_ws_bytes", "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp",
-            "tsim_mlp_fit_output", "tsim_mlp_predict"]
+            "tsim_mlp_fit_output", "tsim_mlp_predict", "tsim_tilt_stats_ws_bytes", "tsim_tilt_stats"]
 
 
 def trace_enable(on=True):
@@ -260,6 +262,21 @@ class Plan:
                               int(seed), int(frame0), float(alpha), _ptr(zern_prev),
                               float(d_over_r0_prev), _ptr(zern), _ptr(ws), _stream(stream)),
                "tsim_sample_zernike_ar")
+
+    def tilt_stats(self, zern, max_lag, ws=None, stream=None):
+        """Spatial tilt statistics (tsim_tilt_stats): returns (corr, dtv), each
+        [2 modes (Noll 2, 3)][2 axes (x, y)][max_lag + 1] float64."""
+        frames = zern.shape[0]
+        if ws is None:
+            n = ctypes.c_size_t()
+            _check(_lib_stats_ws(self._h, frames, int(max_lag), ctypes.byref(n)), "tsim_tilt_stats_ws_bytes")
+            ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=zern.device)
+        out = np.zeros(8 * (int(max_lag) + 1), dtype=np.float64)
+        _check(_lib_stats(self._h, frames, _ptr(zern), int(max_lag),
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), _stream(stream)),
+               "tsim_tilt_stats")
+        out = out.reshape(2, 2, 2, int(max_lag) + 1)
+        return out[:, :, 0].copy(), out[:, :, 1].copy()
 
     def p2s(self, zern, beta, ws, stream=None):
         _check(_lib_p2s(self._h, zern.shape[0], _ptr(zern), _ptr(beta), _ptr(ws), _stream(stream)),

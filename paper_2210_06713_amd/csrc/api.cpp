@@ -40,6 +40,21 @@ int tsim_sample_zernike(const tsim_plan *pl, int frames, const float *d_over_r0,
                         static_cast<hipStream_t>(stream));
 }
 
+int tsim_tilt_stats_ws_bytes(const tsim_plan *pl, int frames, int max_lag, size_t *bytes) {
+  if (!bytes || !frames_ok(pl, frames)) return TSIM_EINVAL;
+  if (max_lag < 0 || max_lag > 256 || max_lag >= pl->H || max_lag >= pl->W) return TSIM_EINVAL;
+  *bytes = tilt_stats_ws_bytes(pl, frames, max_lag);
+  return TSIM_OK;
+}
+
+int tsim_tilt_stats(const tsim_plan *pl, int frames, const float *zern, int max_lag, double *host_out,
+                    void *ws, tsim_stream stream) {
+  if (!frames_ok(pl, frames) || !zern || !host_out || !ws) return TSIM_EINVAL;
+  if (!aligned(zern) || !aligned(ws)) return TSIM_EINVAL;
+  if (max_lag < 0 || max_lag > 256 || max_lag >= pl->H || max_lag >= pl->W) return TSIM_EINVAL;
+  return launch_tilt_stats(pl, frames, zern, max_lag, host_out, ws, static_cast<hipStream_t>(stream));
+}
+
 int tsim_sample_zernike_ar(const tsim_plan *pl, int frames, const float *d_over_r0, uint64_t seed,
                            uint64_t frame0, float alpha, const float *zern_prev, float d_over_r0_prev,
                            float *zern, void *ws, tsim_stream stream) {

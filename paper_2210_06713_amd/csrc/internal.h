@@ -64,6 +64,11 @@ int launch_sampler_ar(const tsim_plan *pl, int frames, const float *scale_host, 
                       const float *zern_prev, float scale_prev, uint64_t seed, uint64_t frame0,
                       float *zern, void *ws, hipStream_t s);
 
+// ---- launchers (stats.hip) ----
+size_t tilt_stats_ws_bytes(const tsim_plan *pl, int frames, int max_lag);
+int launch_tilt_stats(const tsim_plan *pl, int frames, const float *zern, int max_lag, double *host_out,
+                      void *ws, hipStream_t s);
+
 // ---- launchers (psf.hip) ----
 int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, hipStream_t s);
 int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *beta, void *ws,
