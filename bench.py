@@ -404,7 +404,7 @@ def subharmonic_sampler(tsim, torch, wl, s, steps):
                                    "unit": "Mpixel/s", "ms_per_call": round(ms, 4), "kernels": kern}
         if levels:
             # spatial tilt statistics of these frames, lags 0..64 along x and y
-            corr, dtv = pl.tilt_stats(wl.zern, STAT_LAG)
+            pl.tilt_stats(wl.zern, STAT_LAG)
             tsim.trace_enable(True)
             t0 = time.perf_counter()
             for _ in range(steps):
@@ -416,9 +416,21 @@ def subharmonic_sampler(tsim, torch, wl, s, steps):
             out["tilt_stats"] = {"max_lag": STAT_LAG, "frames": n,
                                  "value": round(n * s["H"] * s["W"] / (ms_s * 1e-3) / 1e6, 3),
                                  "unit": "Mpixel/s", "ms_per_call": round(ms_s, 4),
-                                 "kernels": kern_s,
-                                 "x_tilt_corr_x_lag_8_over_var": round(corr[0, 0, 8] / corr[0, 0, 0], 4),
-                                 "x_tilt_corr_y_lag_8_over_var": round(corr[0, 1, 8] / corr[0, 1, 0], 4)}
+                                 "kernels": kern_s}
+            # phase structure function over the aperture (device moments,
+            # host quadratic form)
+            pl.structure_function(wl.zern)
+            tsim.trace_enable(True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                pl.structure_function(wl.zern)
+            ms_f = (time.perf_counter() - t0) * 1e3 / steps
+            rep_ = tsim.trace_report()
+            tsim.trace_enable(False)
+            kern_f, _ = summarize(rep_, steps, n, s, traffic=False)
+            out["structure_function"] = {"frames": n, "ms_per_call": round(ms_f, 4),
+                                         "value": round(n * s["H"] * s["W"] / (ms_f * 1e-3) / 1e6, 3),
+                                         "unit": "Mpixel/s", "kernels": kern_f}
         del ws
         pl.close()
     return out

@@ -173,6 +173,24 @@ int tsim_tilt_stats_ws_bytes(const tsim_plan *plan, int frames, int max_lag, siz
 int tsim_tilt_stats(const tsim_plan *plan, int frames, const float *zern, int max_lag,
                     double *host_out, void *ws, tsim_stream stream);
 
+/* Phase structure function over the aperture (the aperture statistics of
+ * Sec. IV-B; Eq. (4) gives its Kolmogorov form 6.88 (r/r0)^{5/3}): with
+ * phi = sum_{j=2}^{36} a_j Z_j on a 64 x 64 pupil grid (aperture 32 samples
+ * across, points strictly inside), D(r) is the mean of
+ * (phi(p) - phi(p + r x))^2 over the pairs inside the aperture and over all
+ * pixels and frames, for r = 0..30 samples (r/D = r/32).  The device part
+ * is the coefficients' second moments C_jk = mean a_j a_k (FP32 tile sums,
+ * FP64 total in a fixed order); D(r) = sum_jk C_jk mean(dZ_j dZ_k) follows on
+ * the host.
+ *   zern         : device [frames][35][H][W] float32, 256-byte aligned
+ *   host_out     : host [31] float64, D(r)
+ *   host_moments : host [35][35] float64 (C), or NULL
+ *   ws           : device workspace of tsim_structure_function_ws_bytes
+ * Synchronises `stream` before returning. */
+int tsim_structure_function_ws_bytes(const tsim_plan *plan, int frames, size_t *bytes);
+int tsim_structure_function(const tsim_plan *plan, int frames, const float *zern, double *host_out,
+                            double *host_moments, void *ws, tsim_stream stream);
+
 /* (a') Temporally correlated Zernike fields by an auto-regressive process,
  * the low-order workaround the paper gives for spatio-temporal correlation
  * (Sec. III-E): the unit-variance fields of frame t follow

@@ -26,7 +26,7 @@ Modules (each function cites the passage of the paper it follows):
 * ``render``   -- basis-weighted blur (Eq. (8)), gather-form spatially varying
                   convolution (Eq. (1)) and the tilt warp.
 * ``mlp``      -- FP64 forward/backward of the P2S network (Sec. II-C).
-* ``stats``    -- spatial validation statistics of Sec. IV-B: tilt
-                  correlation and differential tilt variance against pixel
-                  lag.
+* ``stats``    -- validation statistics of Sec. IV-B: tilt correlation
+                  and differential tilt variance against pixel lag; the
+                  phase structure function over the aperture (Eq. (4)).
 """

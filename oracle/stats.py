@@ -35,3 +35,31 @@ def tilt_statistics(zern, max_lag):
             corr[m, 1, d] = np.mean(u * v)
             dtv[m, 1, d] = np.mean((u - v) ** 2)
     return corr, dtv
+
+
+# Aperture statistics of Sec. IV-B: the phase structure function, whose
+# Kolmogorov form is Eq. (4), D(r) = 6.88 (r / r0)^{5/3}.
+SF_PUPIL = 64          # pupil grid of the structure function: aperture 32 samples across
+
+
+def structure_function(zern, P=SF_PUPIL):
+    """Direct estimate from coefficient planes (F, 35, H, W): at every pixel
+    the phase phi = sum_{j=2}^{36} a_j Z_j on the P x P pupil grid of
+    ``psf.pupil_grid`` (aperture diameter P/2 samples), then the mean of
+    (phi(p) - phi(p + r x))^2 over the pupil-point pairs with both points
+    inside the aperture, for r = 0..P/2 - 2 samples (r / D = 2 r / P; the
+    points strictly inside the aperture span P/2 - 2 samples), and the mean
+    over pixels and frames.  Returns D[r], float64."""
+    from .psf import pupil_grid
+    from .zernike import zernike
+    rho, theta, mask = pupil_grid(P)
+    Z = np.stack([np.where(mask, zernike(j, rho, theta), 0.0) for j in range(2, 37)])  # [35][P][P]
+    a = np.asarray(zern, dtype=np.float64)
+    a = a.transpose(0, 2, 3, 1).reshape(-1, 35)                    # [pixels][35]
+    out = np.zeros(P // 2 - 1)
+    for r in range(1, P // 2 - 1):
+        pairs = mask[:, :P - r] & mask[:, r:]
+        dZ = (Z[:, :, :P - r] - Z[:, :, r:])[:, pairs]             # [35][pairs]
+        dphi = a @ dZ                                              # [pixels][pairs]
+        out[r] = np.mean(dphi ** 2)
+    return out

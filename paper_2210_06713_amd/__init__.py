@@ -61,6 +61,9 @@ _lib_sample_ar = _sig("tsim_sample_zernike_ar", _i, [_vp, _i, ctypes.POINTER(cty
                                                      ctypes.c_float, _vp, ctypes.c_float, _vp, _vp, _vp])
 _lib_stats_ws = _sig("tsim_tilt_stats_ws_bytes", _i, [_vp, _i, _i, ctypes.POINTER(ctypes.c_size_t)])
 _lib_stats = _sig("tsim_tilt_stats", _i, [_vp, _i, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp, _vp])
+_lib_sf_ws = _sig("tsim_structure_function_ws_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_size_t)])
+_lib_sf = _sig("tsim_structure_function", _i, [_vp, _i, _vp, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_double), _vp, _vp])
 _lib_p2s = _sig("tsim_p2s", _i, [_vp, _i, _vp, _vp, _vp, _vp])
 _lib_render = _sig("tsim_render", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp])
 _lib_warp = _sig("tsim_warp", _i, [_vp, _i, _vp, _vp, _vp, _vp])
@@ -97,7 +100,8 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_trace_count", "tsim_trace_get", "tsim_mlp_create", "tsim_mlp_destroy",
             "tsim_mlp_param_count", "tsim_mlp_layout", "tsim_mlp_get", "tsim_mlp_set",
             "tsim_mlp_data_ws_bytes", "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp",
-            "tsim_mlp_fit_output", "tsim_mlp_predict", "tsim_tilt_stats_ws_bytes", "tsim_tilt_stats"]
+            "tsim_mlp_fit_output", "tsim_mlp_predict", "tsim_tilt_stats_ws_bytes", "tsim_tilt_stats",
+            "tsim_structure_function_ws_bytes", "tsim_structure_function"]
 
 
 def trace_enable(on=True):
@@ -277,6 +281,22 @@ class Plan:
                "tsim_tilt_stats")
         out = out.reshape(2, 2, 2, int(max_lag) + 1)
         return out[:, :, 0].copy(), out[:, :, 1].copy()
+
+    def structure_function(self, zern, ws=None, stream=None):
+        """Phase structure function over the aperture (tsim_structure_function):
+        returns (D [31] for r = 0..30 pupil samples, r/D = r/32, and the
+        coefficients' second moments [35][35])."""
+        frames = zern.shape[0]
+        if ws is None:
+            n = ctypes.c_size_t()
+            _check(_lib_sf_ws(self._h, frames, ctypes.byref(n)), "tsim_structure_function_ws_bytes")
+            ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=zern.device)
+        D = np.zeros(31, dtype=np.float64)
+        C = np.zeros((35, 35), dtype=np.float64)
+        _check(_lib_sf(self._h, frames, _ptr(zern), D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       C.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), _stream(stream)),
+               "tsim_structure_function")
+        return D, C
 
     def p2s(self, zern, beta, ws, stream=None):
         _check(_lib_p2s(self._h, zern.shape[0], _ptr(zern), _ptr(beta), _ptr(ws), _stream(stream)),

@@ -55,6 +55,25 @@ int tsim_tilt_stats(const tsim_plan *pl, int frames, const float *zern, int max_
   return launch_tilt_stats(pl, frames, zern, max_lag, host_out, ws, static_cast<hipStream_t>(stream));
 }
 
+int tsim_structure_function_ws_bytes(const tsim_plan *pl, int frames, size_t *bytes) {
+  if (!bytes || !frames_ok(pl, frames)) return TSIM_EINVAL;
+  *bytes = moments_ws_bytes(pl, frames);
+  return TSIM_OK;
+}
+
+int tsim_structure_function(const tsim_plan *pl, int frames, const float *zern, double *host_out,
+                            double *host_moments, void *ws, tsim_stream stream) {
+  if (!frames_ok(pl, frames) || !zern || !host_out || !ws) return TSIM_EINVAL;
+  if (!aligned(zern) || !aligned(ws)) return TSIM_EINVAL;
+  std::vector<double> C(size_t(TSIM_N_MODES) * TSIM_N_MODES);
+  int st = launch_moments(pl, frames, zern, C.data(), ws, static_cast<hipStream_t>(stream));
+  if (st != TSIM_OK) return st;
+  structure_function_from_moments(C.data(), host_out);
+  if (host_moments)
+    for (size_t i = 0; i < C.size(); ++i) host_moments[i] = C[i];
+  return TSIM_OK;
+}
+
 int tsim_sample_zernike_ar(const tsim_plan *pl, int frames, const float *d_over_r0, uint64_t seed,
                            uint64_t frame0, float alpha, const float *zern_prev, float d_over_r0_prev,
                            float *zern, void *ws, tsim_stream stream) {

@@ -68,6 +68,15 @@ int launch_sampler_ar(const tsim_plan *pl, int frames, const float *scale_host, 
 size_t tilt_stats_ws_bytes(const tsim_plan *pl, int frames, int max_lag);
 int launch_tilt_stats(const tsim_plan *pl, int frames, const float *zern, int max_lag, double *host_out,
                       void *ws, hipStream_t s);
+size_t moments_ws_bytes(const tsim_plan *pl, int frames);
+// mean a_j a_k over all pixels and frames, host [35][35] float64
+int launch_moments(const tsim_plan *pl, int frames, const float *zern, double *host_out, void *ws,
+                   hipStream_t s);
+
+// ---- structure function (plan.cpp, host) ----
+constexpr int kSfPupil = 64;            // pupil grid: aperture 32 samples across
+constexpr int kSfLags = kSfPupil / 2 - 1;  // separations r = 0..30 samples
+void structure_function_from_moments(const double *C, double *out);
 
 // ---- launchers (psf.hip) ----
 int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, hipStream_t s);

@@ -290,6 +290,45 @@ void free_plan(tsim_plan *pl) {
 
 }  // namespace
 
+// Phase structure function over the aperture from the coefficients' second
+// moments C[j][k] = mean a_j a_k (Noll 2..36): on a 64 x 64 pupil grid with
+// the aperture 32 samples across (points strictly inside), D(r) = mean over
+// the pairs (p, p + r x) inside of (sum_j a_j (Z_j(p) - Z_j(p + r x)))^2,
+// whose mean over pixels is sum_jk C_jk mean(dZ_j dZ_k).  r = 0..30 samples.
+void structure_function_from_moments(const double *C, double *out) {
+  constexpr int P = kSfPupil, N = TSIM_N_MODES;
+  const double rad = P / 4.0;
+  std::vector<double> Z(size_t(N) * P * P, 0.0);
+  std::vector<char> in(size_t(P) * P, 0);
+  for (int y = 0; y < P; ++y)
+    for (int x = 0; x < P; ++x) {
+      const double X = (x - P / 2) / rad, Y = (y - P / 2) / rad, rho = std::hypot(X, Y);
+      if (!(rho < 1.0)) continue;
+      in[size_t(y) * P + x] = 1;
+      for (int t = 0; t < N; ++t) Z[(size_t(t) * P + y) * P + x] = zernike(t + 2, rho, std::atan2(Y, X));
+    }
+  out[0] = 0.0;
+  std::vector<double> dz(N);
+  for (int r = 1; r < kSfLags; ++r) {
+    double acc = 0.0;
+    long pairs = 0;
+    for (int y = 0; y < P; ++y)
+      for (int x = 0; x + r < P; ++x) {
+        if (!in[size_t(y) * P + x] || !in[size_t(y) * P + x + r]) continue;
+        for (int t = 0; t < N; ++t) dz[t] = Z[(size_t(t) * P + y) * P + x] - Z[(size_t(t) * P + y) * P + x + r];
+        double q = 0.0;
+        for (int j = 0; j < N; ++j) {
+          double row = 0.0;
+          for (int k = 0; k < N; ++k) row += C[j * N + k] * dz[k];
+          q += dz[j] * row;
+        }
+        acc += q;
+        ++pairs;
+      }
+    out[r] = pairs ? acc / double(pairs) : 0.0;
+  }
+}
+
 extern "C" {
 
 const char *tsim_status_string(int s) {

@@ -84,6 +84,45 @@ k_tilt_stats_sum(const float *__restrict__ part, size_t rows, int n_out, double 
   if (threadIdx.x == 0) out[o] = red[0];
 }
 
+// Second moments of the coefficient vectors, for the aperture statistics
+// (the structure function is a quadratic form in them): one block per tile
+// of 256 pixels of one frame, its 35 x 256 coefficients staged in LDS; the
+// 630 pairs j <= k are shared out over the threads, each summing a_j a_k
+// over the tile into an FP32 partial part[frame][tile][630].
+constexpr int kPairs = TSIM_N_MODES * (TSIM_N_MODES + 1) / 2;
+struct PairTable {
+  unsigned char j[kPairs], k[kPairs];
+};
+constexpr PairTable make_pairs() {
+  PairTable t{};
+  int q = 0;
+  for (int j = 0; j < TSIM_N_MODES; ++j)
+    for (int k = j; k < TSIM_N_MODES; ++k) {
+      t.j[q] = static_cast<unsigned char>(j);
+      t.k[q] = static_cast<unsigned char>(k);
+      ++q;
+    }
+  return t;
+}
+__constant__ PairTable kPairTable = make_pairs();
+
+__global__ void __launch_bounds__(kStatsThreads)
+k_moments_tiles(const float *__restrict__ zern, size_t plane, int tiles, float *__restrict__ part) {
+  __shared__ float tile[TSIM_N_MODES][kStatsThreads + 1];
+  const int f = blockIdx.y, ti = blockIdx.x;
+  const size_t p = size_t(ti) * kStatsThreads + threadIdx.x;
+  const float *a = zern + size_t(f) * TSIM_N_MODES * plane;
+  for (int j = 0; j < TSIM_N_MODES; ++j) tile[j][threadIdx.x] = p < plane ? a[size_t(j) * plane + p] : 0.f;
+  __syncthreads();
+  float *out = part + (size_t(f) * tiles + ti) * kPairs;
+  for (int q = threadIdx.x; q < kPairs; q += kStatsThreads) {
+    const int j = kPairTable.j[q], k = kPairTable.k[q];
+    float acc = 0.f;
+    for (int i = 0; i < kStatsThreads; ++i) acc = fmaf(tile[j][i], tile[k][i], acc);
+    out[q] = acc;
+  }
+}
+
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
@@ -122,6 +161,41 @@ int launch_tilt_stats(const tsim_plan *pl, int frames, const float *zern, int ma
       const double pairs = double(frames) * (axis == 0 ? double(H) * (W - d) : double(H - d) * W);
       host_out[i * (L + 1) + d] = h[size_t(i) * (L + 1) + d] / pairs;
     }
+  }
+  return TSIM_OK;
+}
+
+size_t moments_ws_bytes(const tsim_plan *pl, int frames) {
+  const size_t tiles = (size_t(pl->H) * pl->W + kStatsThreads - 1) / kStatsThreads;
+  return align256(size_t(frames) * tiles * kPairs * sizeof(float)) + align256(kPairs * sizeof(double));
+}
+
+int launch_moments(const tsim_plan *pl, int frames, const float *zern, double *host_out, void *ws,
+                   hipStream_t s) {
+  const size_t plane = size_t(pl->H) * pl->W;
+  const int tiles = int((plane + kStatsThreads - 1) / kStatsThreads);
+  float *part = static_cast<float *>(ws);
+  double *sums = reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                            align256(size_t(frames) * tiles * kPairs * sizeof(float)));
+  {
+    TraceScope tr("k_moments_tiles", s);
+    hipLaunchKernelGGL(k_moments_tiles, dim3(tiles, frames), dim3(kStatsThreads), 0, s, zern, plane, tiles, part);
+    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+  }
+  {
+    TraceScope tr("k_tilt_stats_sum", s);
+    hipLaunchKernelGGL(k_tilt_stats_sum, dim3(kPairs), dim3(kStatsThreads), 0, s, part, size_t(frames) * tiles,
+                       kPairs, sums);
+    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+  }
+  std::vector<double> h(kPairs);
+  TSIM_HIP_CHECK(hipMemcpyAsync(h.data(), sums, kPairs * sizeof(double), hipMemcpyDeviceToHost, s));
+  TSIM_HIP_CHECK(hipStreamSynchronize(s));
+  const double n = double(frames) * double(plane);
+  const PairTable pt = make_pairs();
+  for (int q = 0; q < kPairs; ++q) {
+    const int j = pt.j[q], k = pt.k[q];
+    host_out[j * TSIM_N_MODES + k] = host_out[k * TSIM_N_MODES + j] = h[q] / n;
   }
   return TSIM_OK;
 }

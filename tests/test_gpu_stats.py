@@ -65,3 +65,48 @@ def test_tilt_stats_rejects_bad_lags(t):
         with pytest.raises(t.TsimError) as e:
             plan.tilt_stats(z, L)
         assert e.value.status == t.EINVAL
+
+
+def test_structure_function_matches_oracle(t):
+    """Device moments + host quadratic form against the oracle's direct
+    route (phase on the pupil grid at every pixel), on sampler frames."""
+    say("structure function 2 frames 24x40 G=64")
+    from oracle import stats as os_
+    plan = t.Plan(24, 40, 1, 64, 64, pixel_pitch_over_d=0.125)
+    z = torch.empty((2, 35, 24, 40), dtype=torch.float32, device="cuda")
+    plan.sample_zernike([1.0, 3.0], 4, 0, z, plan.workspace(2))
+    D, C = plan.structure_function(z)
+    zn = z.cpu().numpy().astype(np.float64)
+    ref = os_.structure_function(zn)
+    np.testing.assert_allclose(D[1:], ref[1:], rtol=1e-5)
+    assert D[0] == 0.0
+    a = zn.transpose(0, 2, 3, 1).reshape(-1, 35)
+    np.testing.assert_allclose(C, a.T @ a / a.shape[0], rtol=1e-5, atol=1e-7 * np.abs(C).max())
+
+
+@pytest.mark.parametrize("F,H,W", [(3, 7, 45), (1, 300, 301)])
+def test_moments_random_planes(t, F, H, W):
+    """Tiles of 256 pixels with a ragged last tile."""
+    say(f"moments random F={F} H={H} W={W}")
+    rng = np.random.default_rng(F + H + W)
+    z = rng.standard_normal((F, 35, H, W)).astype(np.float32)
+    plan = t.Plan(H, W, 1, 64 if H <= 64 else 512, 64 if W <= 64 else 512, pixel_pitch_over_d=0.125)
+    _, C = plan.structure_function(torch.tensor(z, device="cuda"))
+    a = z.astype(np.float64).transpose(0, 2, 3, 1).reshape(-1, 35)
+    np.testing.assert_allclose(C, a.T @ a / a.shape[0], rtol=1e-5, atol=1e-6)
+
+
+def test_structure_function_follows_eq4(t):
+    """The statistic the paper validates against (Sec. IV-B): 256 sampled
+    64 x 64 frames at D/r0 = 1 follow Eq. (4)'s 6.88 (r/r0)^{5/3} within 8%
+    for r >= D/4, where the 35 modes carry the phase.  (Many small frames:
+    the tilt, most of the phase variance, varies over several D, so a few
+    large frames hold few independent tilt samples.)"""
+    say("structure function 256 frames 64^2 vs Eq. (4)")
+    plan = t.Plan(64, 64, 1, 128, 128, pixel_pitch_over_d=0.125)
+    z = torch.empty((256, 35, 64, 64), dtype=torch.float32, device="cuda")
+    plan.sample_zernike([1.0] * 256, 21, 0, z, plan.workspace(256))
+    D, _ = plan.structure_function(z)
+    for r in (8, 16, 24):
+        kol = 6.88 * (r / 32.0) ** (5.0 / 3.0)
+        assert abs(D[r] / kol - 1.0) < 0.08, (r, D[r], kol)

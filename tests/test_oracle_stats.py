@@ -63,3 +63,31 @@ def test_sampler_fields_match_model_covariance():
                 assert abs(dtv[m, axis, d] - 2 * var * (1 - rho)) < 0.3 * var, (j, axis, d)
     # longitudinal (x lag of the x-tilt) and transverse correlations differ
     assert corr[0, 1, 8] - corr[0, 0, 8] > 0.3 * A0[0, 0]
+
+
+def test_structure_function_pure_tilt():
+    """phi = c Z_2 = 2 c x (x in aperture radii): D(r) = 4 c^2 (r / R)^2 with
+    R = P/4 samples, whichever pairs are inside."""
+    z = _planes(1, 2, 3)
+    z[:, 0] = 0.7
+    D = ostats.structure_function(z)
+    R = ostats.SF_PUPIL / 4.0
+    r = np.arange(ostats.SF_PUPIL // 2 - 1)
+    np.testing.assert_allclose(D, 4 * 0.49 * (r / R) ** 2, rtol=1e-12, atol=1e-15)
+
+
+def test_structure_function_matches_kolmogorov():
+    """Coefficient vectors drawn from N(0, A_0) at D/r0 = 1: the 35-mode phase
+    follows Eq. (4)'s 6.88 (r/r0)^{5/3} within 8% for r >= D/4 (the modes
+    above Noll 36 carry the missing power at small separations, where the
+    truncated structure function must fall below Eq. (4))."""
+    A0 = ozern.noll_matrix(1.0)
+    Lc = ozern.cholesky_lower(A0)
+    g = np.random.default_rng(5).standard_normal((35, 6000))
+    z = (Lc @ g).T.reshape(6000, 1, 1, 35).transpose(0, 3, 1, 2)   # (F, 35, 1, 1)
+    D = ostats.structure_function(z)
+    P = ostats.SF_PUPIL
+    for r in (8, 16, 24):
+        kol = 6.88 * (2.0 * r / P) ** (5.0 / 3.0)
+        assert abs(D[r] / kol - 1.0) < 0.08, (r, D[r], kol)
+    assert D[2] < 0.85 * 6.88 * (4.0 / P) ** (5.0 / 3.0)
