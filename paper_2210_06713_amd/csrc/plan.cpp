@@ -294,8 +294,12 @@ void free_plan(tsim_plan *pl) {
 // moments C[j][k] = mean a_j a_k (Noll 2..36): on a 64 x 64 pupil grid with
 // the aperture 32 samples across (points strictly inside), D(r) = mean over
 // the pairs (p, p + r x) inside of (sum_j a_j (Z_j(p) - Z_j(p + r x)))^2,
-// whose mean over pixels is sum_jk C_jk mean(dZ_j dZ_k).  r = 0..30 samples.
-void structure_function_from_moments(const double *C, double *out) {
+// whose mean over pixels is sum_jk C_jk M_jk(r), M_jk(r) = mean over the
+// pairs of dZ_j dZ_k.  r = 0..30 samples.  M depends on nothing but the grid
+// and is built once per process.
+namespace {
+
+std::vector<double> build_sf_pair_moments() {
   constexpr int P = kSfPupil, N = TSIM_N_MODES;
   const double rad = P / 4.0;
   std::vector<double> Z(size_t(N) * P * P, 0.0);
@@ -307,25 +311,35 @@ void structure_function_from_moments(const double *C, double *out) {
       in[size_t(y) * P + x] = 1;
       for (int t = 0; t < N; ++t) Z[(size_t(t) * P + y) * P + x] = zernike(t + 2, rho, std::atan2(Y, X));
     }
-  out[0] = 0.0;
+  std::vector<double> M(size_t(kSfLags) * N * N, 0.0);
   std::vector<double> dz(N);
   for (int r = 1; r < kSfLags; ++r) {
-    double acc = 0.0;
+    double *m = M.data() + size_t(r) * N * N;
     long pairs = 0;
     for (int y = 0; y < P; ++y)
       for (int x = 0; x + r < P; ++x) {
         if (!in[size_t(y) * P + x] || !in[size_t(y) * P + x + r]) continue;
         for (int t = 0; t < N; ++t) dz[t] = Z[(size_t(t) * P + y) * P + x] - Z[(size_t(t) * P + y) * P + x + r];
-        double q = 0.0;
-        for (int j = 0; j < N; ++j) {
-          double row = 0.0;
-          for (int k = 0; k < N; ++k) row += C[j * N + k] * dz[k];
-          q += dz[j] * row;
-        }
-        acc += q;
+        for (int j = 0; j < N; ++j)
+          for (int k = 0; k < N; ++k) m[j * N + k] += dz[j] * dz[k];
         ++pairs;
       }
-    out[r] = pairs ? acc / double(pairs) : 0.0;
+    if (pairs)
+      for (int i = 0; i < N * N; ++i) m[i] /= double(pairs);
+  }
+  return M;
+}
+
+}  // namespace
+
+void structure_function_from_moments(const double *C, double *out) {
+  constexpr int N = TSIM_N_MODES;
+  static const std::vector<double> M = build_sf_pair_moments();  // thread-safe, once
+  for (int r = 0; r < kSfLags; ++r) {
+    const double *m = M.data() + size_t(r) * N * N;
+    double acc = 0.0;
+    for (int i = 0; i < N * N; ++i) acc += C[i] * m[i];
+    out[r] = acc;
   }
 }
 
