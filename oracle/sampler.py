@@ -132,7 +132,7 @@ def sample_zernike(H, W, Gh, Gw, ds, d_over_r0, seed, frame, fold=2, spectra=Non
 
 
 def sample_sequence_ar(H, W, Gh, Gw, ds, d_over_r0s, seed, frame0, alpha, y_prev=None, fold=2,
-                       spectra=None, L=None):
+                       spectra=None, L=None, subharmonic_levels=0):
     """Temporally correlated frames by an auto-regressive process (the
     workaround the paper gives for spatio-temporal correlation, Sec. III-E):
     the unit-variance fields follow ybar_t = alpha ybar_{t-1} +
@@ -141,17 +141,21 @@ def sample_sequence_ar(H, W, Gh, Gw, ds, d_over_r0s, seed, frame0, alpha, y_prev
     keeps its spatial correlation and unit variance, and fields of frames
     t and t + k correlate by alpha^k.  ``y_prev`` holds the unit fields of the
     frame before the first (None: the sequence starts from its first draw,
-    which is already stationary).  Returns (frames (F, 35, H, W), the last
-    frame's unit fields)."""
+    which is already stationary).  With subharmonic levels, each frame's
+    own draw w_t carries its subharmonic waves (``spectra``, if given, built
+    with the same levels).  Returns (frames (F, 35, H, W), the last frame's
+    unit fields)."""
     if spectra is None:
-        spectra = all_spectra(Gh, Gw, ds, fold)
+        spectra = all_spectra(Gh, Gw, ds, fold, subharmonic_levels=subharmonic_levels)
     if L is None:
         L = cholesky_lower(noll_matrix(1.0))
+    amps = (subharmonic_amplitudes(Gh, Gw, ds, fold, subharmonic_levels)
+            if subharmonic_levels else None)
     c = np.sqrt(1.0 - alpha * alpha)
     y = y_prev
     out = []
     for t, dr in enumerate(d_over_r0s):
-        w = unit_fields(spectra, H, W, frame0 + t, seed)
+        w = unit_fields(spectra, H, W, frame0 + t, seed, subharmonics=amps)
         y = w if y is None else alpha * y + c * w
         out.append(mix(y, L, dr))
     return np.stack(out), y

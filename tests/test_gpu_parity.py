@@ -114,6 +114,23 @@ def test_sampler_subharmonics_match_oracle(t, H, W, Gh, Gw, levels, seed, frame0
         assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
 
 
+def test_sampler_ar_with_subharmonics_matches_oracle(t):
+    """Auto-regressive sequence on a plan with two subharmonic levels: each
+    frame's fresh draw carries its own waves, then the recursion."""
+    say("sampler AR + subharmonics 40x56 G=128")
+    H, W, G, levels = 40, 56, 128, 2
+    plan = t.Plan(H, W, 1, G, G, pixel_pitch_over_d=0.125, subharmonic_levels=levels)
+    drs = [1.0, 2.0, 3.5, 2.5]
+    ref, _ = osamp.sample_sequence_ar(H, W, G, G, 0.125, drs, 13, 7, 0.8, subharmonic_levels=levels)
+    zern = torch.empty((4, 35, H, W), dtype=torch.float32, device="cuda")
+    plan.sample_zernike_ar(drs, 13, 7, 0.8, zern, plan.workspace(4))
+    torch.cuda.synchronize()
+    got = zern.cpu().numpy()
+    for f in range(4):
+        errs = [rel(got[f, j], ref[f, j]) for j in range(35)]
+        assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
+
+
 @pytest.mark.slow
 def test_sampler_full_size_frame(t):
     """512 x 512 frame on the 1024 x 1024 grid, the benchmark's launch shape."""
