@@ -4,11 +4,12 @@
 // and along y, over all frames and every pixel pair inside the frame.
 //
 // k_tilt_stats_rows: one 256-thread block per (row y, frame).  Row y of both
-// tilt planes is staged in LDS.  For each lag the block sums, along its row,
-// the products and squared differences with the pixel d columns to the right
-// (from LDS) and d rows below (coalesced reads of that row), reduces the 8
-// sums (mode, axis, product / squared difference) over the block in a fixed
-// order and writes them as FP32 partials part[frame][y][8][L + 1].
+// tilt planes is staged in LDS.  Each wave takes every fourth lag and sums,
+// along the row, the products and squared differences with the pixel d
+// columns to the right (from LDS) and d rows below (coalesced reads of that
+// row), reduces the 8 sums (mode, axis, product / squared difference) over
+// its lanes in a fixed order and writes them as FP32 partials
+// part[frame][y][8][L + 1].
 // k_tilt_stats_sum adds the partials of all rows and frames in FP64, one
 // block per output, again in a fixed order: the result is deterministic.
 #include "common.cuh"
@@ -20,8 +21,7 @@ constexpr int kStatsThreads = 256;
 
 __global__ void __launch_bounds__(kStatsThreads)
 k_tilt_stats_rows(const float *__restrict__ zern, int H, int W, int L, float *__restrict__ part) {
-  extern __shared__ float row[];  // [2][W] tilt rows, then [4 waves][8] reduction slots
-  float *red = row + 2 * W;
+  extern __shared__ float row[];  // [2][W] tilt rows
   const int y = blockIdx.x, f = blockIdx.y;
   const size_t plane = size_t(H) * W;
   const float *a = zern + size_t(f) * TSIM_N_MODES * plane;  // Noll 2; Noll 3 at + plane
@@ -32,11 +32,13 @@ k_tilt_stats_rows(const float *__restrict__ zern, int H, int W, int L, float *__
   __syncthreads();
   float *out = part + (size_t(f) * H + y) * 8 * size_t(L + 1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int d = 0; d <= L; ++d) {
+  // each wave owns the lags d = wave, wave + 4, ...: its lanes stride over
+  // the row and a shuffle tree sums them, so no lag waits on a block barrier
+  for (int d = wave; d <= L; d += kStatsThreads / 64) {
     // v[(m * 2 + axis) * 2 + stat]: m = Noll 2 / 3, axis = x / y, stat = product / squared difference
     float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const bool ylag = y + d < H;
-    for (int x = threadIdx.x; x < W; x += kStatsThreads) {
+    for (int x = lane; x < W; x += 64) {
       const float u2 = row[x], u3 = row[W + x];
       if (x + d < W) {
         const float p2 = row[x + d], p3 = row[W + x + d];
@@ -57,15 +59,12 @@ k_tilt_stats_rows(const float *__restrict__ zern, int H, int W, int L, float *__
 #pragma unroll
     for (int i = 0; i < 8; ++i)
       for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
-    if (lane == 0)
+    if (lane < 8) {
+      float r = v[0];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) red[wave * 8 + i] = v[i];
-    __syncthreads();
-    if (threadIdx.x < 8) {
-      const int i = threadIdx.x;
-      out[size_t(i) * (L + 1) + d] = ((red[i] + red[8 + i]) + red[16 + i]) + red[24 + i];
+      for (int i = 1; i < 8; ++i) r = lane == i ? v[i] : r;
+      out[size_t(lane) * (L + 1) + d] = r;
     }
-    __syncthreads();
   }
 }
 
@@ -141,7 +140,7 @@ int launch_tilt_stats(const tsim_plan *pl, int frames, const float *zern, int ma
                                             align256(size_t(frames) * H * n_out * sizeof(float)));
   {
     TraceScope tr("k_tilt_stats_rows", s);
-    const size_t lds = (2 * size_t(W) + 32) * sizeof(float);
+    const size_t lds = 2 * size_t(W) * sizeof(float);
     hipLaunchKernelGGL(k_tilt_stats_rows, dim3(H, frames), dim3(kStatsThreads), lds, s, zern, H, W, L, part);
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
   }
