@@ -213,23 +213,27 @@ def test_render_matches_oracle(t, basis33):
         assert rel(got[c], ref) < TOL, c
 
 
-def test_warp_matches_oracle(t):
-    say("warp C=2 50x70")
-    H, W, C = 50, 70, 2
-    plan = t.Plan(H, W, C, 128, 128)
-    img = synthetic.test_image(C, H, W, 4, seed=2)[None]
+@pytest.mark.parametrize("F,H,W,C", [
+    (1, 50, 70, 2),
+    (2, 64, 300, 3),    # two frames, a ragged last 256-pixel row segment
+])
+def test_warp_matches_oracle(t, F, H, W, C):
+    say(f"warp F={F} C={C} {H}x{W}")
+    plan = t.Plan(H, W, C, 128, 512)
+    img = np.stack([synthetic.test_image(C, H, W, 4, seed=2 + f) for f in range(F)])
     rng = np.random.default_rng(9)
-    zern = np.zeros((1, 35, H, W), dtype=np.float32)
-    zern[0, 0] = rng.standard_normal((H, W)) * 3.0
-    zern[0, 1] = rng.standard_normal((H, W)) * 3.0
-    out = torch.empty((1, C, H, W), dtype=torch.float32, device="cuda")
+    zern = np.zeros((F, 35, H, W), dtype=np.float32)
+    zern[:, 0] = rng.standard_normal((F, H, W)) * 3.0
+    zern[:, 1] = rng.standard_normal((F, H, W)) * 3.0
+    out = torch.empty((F, C, H, W), dtype=torch.float32, device="cuda")
     plan.warp(torch.tensor(img, device="cuda"), torch.tensor(zern, device="cuda"), out)
     torch.cuda.synchronize()
-    got = out.cpu().numpy()[0]
-    tx, ty = orender.tilt_shift(zern[0].astype(np.float64))
-    for c in range(C):
-        ref = orender.warp(img[0, c].astype(np.float64), tx, ty)
-        assert rel(got[c], ref) < TOL, c
+    got = out.cpu().numpy()
+    for f in range(F):
+        tx, ty = orender.tilt_shift(zern[f].astype(np.float64))
+        for c in range(C):
+            ref = orender.warp(img[f, c].astype(np.float64), tx, ty)
+            assert rel(got[f, c], ref) < TOL, (f, c)
 
 
 def test_end_to_end_small_workload(t, basis33):
