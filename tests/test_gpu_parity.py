@@ -75,6 +75,9 @@ def _sample(t, plan, d_over_r0, seed, frame0, frames):
     (11, 130, 64, 2048, 4, 0, 1.5),
     (9, 400, 64, 2048, 5, 0, 2.5),
     (7, 1000, 64, 2048, 6, 0, 2.5),
+    # degenerate frames: a single row, a single column
+    (1, 64, 64, 64, 12, 0, 2.0),
+    (64, 1, 64, 64, 13, 0, 2.0),
 ])
 def test_sampler_matches_oracle(t, H, W, Gh, Gw, seed, frame0, dr):
     say(f"sampler H={H} W={W} G={Gh}x{Gw} seed={seed} frame0={frame0}")
@@ -278,6 +281,17 @@ def test_argument_errors(t, basis33):
     with pytest.raises(t.TsimError) as e:
         nobasis.render(x, torch.zeros((1, 32, 32, 1), device="cuda"), torch.empty_like(x))
     assert e.value.status == t.EARTEFACT
+    # empty calls (no frames) are rejected before any launch
+    z0 = torch.zeros((0, 35, 32, 32), dtype=torch.float32, device="cuda")
+    x0 = torch.zeros((0, 1, 32, 32), dtype=torch.float32, device="cuda")
+    ws = plan.workspace(1)
+    for call in (lambda: plan.sample_zernike([], 0, 0, z0, ws),
+                 lambda: plan.warp(x0, z0, torch.empty_like(x0)),
+                 lambda: plan.tilt_stats(z0, 4, ws=ws),
+                 lambda: plan.structure_function(z0, ws=ws)):
+        with pytest.raises(t.TsimError) as e:
+            call()
+        assert e.value.status == t.EINVAL
 
 
 def test_repeat_run_is_bit_identical(t):
