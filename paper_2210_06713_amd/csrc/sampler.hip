@@ -413,15 +413,24 @@ struct ArCoefs {
 __global__ void __launch_bounds__(256)
 k_ar_scan(float *__restrict__ zern, const float *__restrict__ prev, size_t plane, int nf, ArCoefs co,
           float c) {
+  constexpr int FB = 8;  // frames loaded ahead: their loads are in flight together
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < plane;
        e += size_t(gridDim.x) * blockDim.x) {
     float a = prev ? prev[e] : 0.f;
-    for (int f = 0; f < nf; ++f) {
-      float *p = zern + size_t(f) * plane + e;
-      const float nw = *p;
-      const float v = (f == 0 && !prev) ? nw : fmaf(co.mul[f], a, c * nw);
-      *p = v;
-      a = v;
+    for (int f0 = 0; f0 < nf; f0 += FB) {
+      float nw[FB];
+#pragma unroll
+      for (int i = 0; i < FB; ++i)
+        if (f0 + i < nf) nw[i] = zern[size_t(f0 + i) * plane + e];
+#pragma unroll
+      for (int i = 0; i < FB; ++i) {
+        const int f = f0 + i;
+        if (f < nf) {
+          const float v = (f == 0 && !prev) ? nw[i] : fmaf(co.mul[f], a, c * nw[i]);
+          zern[size_t(f) * plane + e] = v;
+          a = v;
+        }
+      }
     }
   }
 }
