@@ -15,6 +15,7 @@ dozen roundings deep); BF16 paths as in the learned-form tests (network
 outputs <= 2e-3 against the BF16-mirrored oracle, the BF16 blur <= 1e-5 on
 exactly rounded operands).
 """
+import os
 import sys
 
 import numpy as np
@@ -212,7 +213,11 @@ def test_sampler_4k_subharmonics(t):
         if L[j, 0] == 0.0 and L[j, 1] == 0.0:
             assert torch.equal(z0[0, j], z3[0, j]), j
     sc = dr ** (5.0 / 6.0)
-    amps = ospec.subharmonic_amplitudes(G4, G4, 0.125, 2, levels)
+    # the oracle's amplitudes for this grid, written by
+    # tests/golden/make_subharmonic_amplitudes.py (the full-grid normalising
+    # sum takes minutes in numpy)
+    amps = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                   "subharmonic_amplitudes_G4096.txt")).reshape(2, levels, 4)
     rows = np.arange(0, H4, 97)
     waves = osamp.subharmonic_waves(amps, H4, W4, G4, G4, frame, seed, rows=rows)  # [2][rows][W]
     idx = torch.tensor(rows, device="cuda")

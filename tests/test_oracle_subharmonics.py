@@ -104,3 +104,19 @@ def test_sampler_levels_zero_is_the_plain_sampler():
     # the waves use their own Philox tag
     assert philox.TAG_SUBHARMONIC not in (philox.TAG_SAMPLER, philox.TAG_BASIS, philox.TAG_MLP_DATA,
                                           philox.TAG_MLP_INIT, philox.TAG_IMAGE)
+
+
+def test_stored_4096_amplitudes_match_oracle_cells():
+    """The stored 4096^2 amplitudes (tests/golden, written from the oracle)
+    against the oracle's cell spectra: squared-amplitude ratios do not
+    depend on the normalising sum, so they are checked in full, and the
+    first cell of each mode sets the scale for the rest."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "subharmonic_amplitudes_G4096.txt")
+    amps = np.loadtxt(path).reshape(2, 3, 4)
+    for t, j in enumerate(ospec.SUBH_MODES):
+        cs = ospec.subharmonic_cell_spectra(j, 4096, 4096, DS, FOLD, 3)
+        w = 9.0 ** -np.arange(1, 4)
+        model = cs * w[:, None]
+        ref = amps[t, 0, 0] ** 2 / model[0, 0] if j == 2 else amps[t, 0, 2] ** 2 / model[0, 2]
+        np.testing.assert_allclose(amps[t] ** 2, ref * model, rtol=1e-10)
