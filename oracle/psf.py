@@ -6,7 +6,7 @@ Eq. (2): h_x = |Fourier{P(xi) exp(-j phi_x(xi))}|^2 up to constants, with
 phi_x expanded on Zernike modes (Eq. (5)).  Eq. (7): h_x = sum_m beta_{x,m}
 varphi_m with a basis obtained by PCA over a database of PSFs (Sec. II-C).
 
-Readings (listed in the design notes): the pupil is sampled on a P x P grid
+Readings where the paper leaves the choice open: the pupil is sampled on a P x P grid
 whose aperture spans P/2 samples (Nyquist-sampled PSF, so one PSF sample is
 one image pixel); the aperture is centred on sample P/2 and contains the
 samples strictly inside the unit circle; the forward DFT is used; the PSF is

@@ -10,7 +10,7 @@ Sec. III-C gives the method in two steps, which this module follows in order:
 2. mix them per pixel with L, L L^T = A_0 (the Noll matrix), giving the
    approximate tensor A~ = L blockdiag(A_11..A_NN) L^T of Eq. (9).
 
-Project readings used here (all listed with reasons in the design notes):
+Readings of the paper used here, where it leaves the choice open:
 white noise is drawn directly in the frequency domain as Hermitian complex
 Gaussian noise (same law as F(e)); two modes share one complex inverse FFT
 (real and imaginary parts); the field is cropped from the top-left corner of

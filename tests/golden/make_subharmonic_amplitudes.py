@@ -1,6 +1,6 @@
 """Writes subharmonic_amplitudes_G4096.txt: the oracle's subharmonic wave
-amplitudes (Sec. IV-B's low-frequency remedy as read in the design notes,
-R26) for the full-size frame's grid: 4096 x 4096, pixel pitch D/8, aliases
+amplitudes (the low-frequency remedy Sec. IV-B names) for the full-size
+frame's grid: 4096 x 4096, pixel pitch D/8, aliases
 folded to |l| <= 2, three levels.  Calls only ``oracle/``; the full-grid
 normalising sum takes minutes, which is why the GPU test reads this file.
 
