@@ -23,6 +23,11 @@
  *     kernel faults surface at the caller's next synchronisation.
  *   - A plan is immutable after creation: concurrent calls on different
  *     streams are safe if each uses its own workspace.
+ *   - Buffer extents cannot be checked through bare pointers: the caller
+ *     guarantees that every buffer has the shape and element type stated
+ *     for it (the Python binding checks them before each call).
+ *   - A failing call also records its status and name for tsim_last_error
+ *     on the calling thread.
  */
 #ifndef TSIM_H
 #define TSIM_H
@@ -69,7 +74,12 @@ enum { TSIM_FP32 = 0, TSIM_BF16 = 1 };
  *   pupil_n        P, pupil samples per side for exact PSFs (64 or 128); the
  *                  circular aperture spans P/2 samples, so one PSF sample is
  *                  one image pixel
- *   psf_t          T, odd PSF support (3 <= T <= P/2 + 1)
+ *   psf_t          T, odd PSF support: 9, 15, 21, 31 or 33 with P = 64, 33 or
+ *                  65 with P = 128 (the exact-PSF kernels' sizes); in BF16
+ *                  plans also one of 15, 21, 33, 65, excluding K > 112 with
+ *                  C = 4 and T = 65 (the BF16 blur's image tile and basis
+ *                  staging exceed the LDS there).  Other values:
+ *                  TSIM_EUNSUPPORTED at plan creation.
  *   basis_k        K, number of PSF basis functions (1 <= K <= 128)
  *   basis          host [K][T*T] float64, orthonormal rows (Eq. (7)); copied.
  *                  May be NULL for a plan that only samples and warps.
@@ -213,17 +223,24 @@ int tsim_sample_zernike_ar(const tsim_plan *plan, int frames, const float *d_ove
                            float d_over_r0_prev, float *zern, void *ws, tsim_stream stream);
 
 /* (b) Basis weights beta[f][y][x][k] from Zernike fields (Sec. II-C).
- *   Exact mode: the per-pixel PSF of Eq. (2) from modes 4..36 on the P x P
+ *   Exact form: the per-pixel PSF of Eq. (2) from modes 4..36 on the P x P
  *   pupil, cropped to T x T around the zero frequency and normalised to unit
- *   sum, projected on the basis (beta = Psi h).  Output float32.
- *   Learned mode: the network of tsim_mlp_set_weights; output float32 or
- *   bfloat16 per the plan's precision.
+ *   sum, projected on the basis (beta = Psi h).
+ *   Learned form: the network set by tsim_plan_set_mlp.  A learned plan with
+ *   no network yet runs the exact form (the fallback; tsim_p2s_form tells
+ *   which form runs).
+ *   Output float32 in FP32 plans and bfloat16 in BF16 plans, either form.
  *   zern : device [frames][35][H][W] float32
  *   beta : device [frames][H][W][K] float32, or in BF16 plans
  *          [frames][H][W][KP] bfloat16 with KP = K rounded up to 32, 64, 112
  *          or 128 (entries K..KP-1 written as 0) */
 int tsim_p2s(const tsim_plan *plan, int frames, const float *zern, void *beta, void *ws,
              tsim_stream stream);
+
+/* The form tsim_p2s runs on this plan now: *form = TSIM_P2S_LEARNED for a
+ * learned plan holding a network, else TSIM_P2S_EXACT (exact plans, and
+ * learned plans without one, which fall back to the exact path). */
+int tsim_p2s_form(const tsim_plan *plan, int *form);
 
 /* (c) Eq. (8): out_c(x) = sum_k beta_k(x) sum_u psi_k(u) img_c(clamp(x - u)),
  * u in [-(T-1)/2, (T-1)/2]^2, a true convolution with replicated borders.
@@ -290,7 +307,13 @@ int tsim_mlp_layout(const tsim_mlp *net, size_t *off_w /*[4]*/, size_t *off_b /*
 
 /* Copy out / in (host float32): what = 0 parameters [param_count],
  * 1 gradients of the last tsim_mlp_grad/train step [param_count] (get only),
- * 2 inv_s [35], 3 mu [K], 4 s_out [1].  Synchronises the device. */
+ * 2 inv_s [35], 3 mu [K], 4 s_out [1], 5 AdamW first moments [param_count],
+ * 6 AdamW second moments [param_count], 7 training counters [2] = {optimiser
+ * steps taken, cosine schedule length (0: each tsim_mlp_train call spans its
+ * own steps)}, whole numbers below 2^24.  Parameters, moments and counters
+ * together are a training checkpoint: a network restored from them continues
+ * bit-identically.  Setting what = 0 also refreshes the BF16 weight copies.
+ * Synchronises the device. */
 int tsim_mlp_get(const tsim_mlp *net, int what, float *host, size_t count);
 int tsim_mlp_set(tsim_mlp *net, int what, const float *host, size_t count);
 
@@ -321,7 +344,13 @@ int tsim_mlp_predict(const tsim_plan *plan, int n_vec, const float *zvec, float 
 
 /* `steps` AdamW steps (beta1 0.9, beta2 0.999, eps 1e-8, no weight decay,
  * cosine learning rate lr_max -> lr_min) on consecutive batches of the
- * pairs (wrapping around).  loss_host [steps] may be NULL. */
+ * pairs (wrapping around).  Step t of the network's life (t = 0, 1, ...,
+ * counted across calls) trains on pairs [t B, (t + 1) B) modulo n_pairs,
+ * uses bias correction 1 - beta^(t + 1), and, with a schedule length S set
+ * through tsim_mlp_set(what = 7), the rate lr_min + (lr_max - lr_min)(1 +
+ * cos(pi min(t, S - 1) / (S - 1))) / 2; with S = 0 the cosine spans this
+ * call's steps.  Weight-gradient partial sums are added in a fixed order, so
+ * the parameters are bit-reproducible.  loss_host [steps] may be NULL. */
 int tsim_mlp_train(tsim_mlp *net, const float *zvec, const float *target, int n_pairs, int steps,
                    float lr_max, float lr_min, float *loss_host, tsim_stream stream);
 
@@ -345,6 +374,17 @@ int tsim_trace_get(int index, char *name, size_t name_len, double *total_ms, int
 
 /* Human-readable text for a status code. */
 const char *tsim_status_string(int status);
+
+/* The status of the most recent failing call on the calling thread
+ * (TSIM_OK if none since the last query) and, if msg is not NULL, a
+ * NUL-terminated text naming the call (at most msg_len bytes).  Reading it
+ * clears it. */
+int tsim_last_error(char *msg, size_t msg_len);
+
+/* Wait for all work queued on `stream`; a device fault of an earlier
+ * asynchronous launch is returned as TSIM_EDEVICE (and recorded for
+ * tsim_last_error with the runtime's text). */
+int tsim_sync(tsim_stream stream);
 
 #ifdef __cplusplus
 }

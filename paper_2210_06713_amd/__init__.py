@@ -93,6 +93,9 @@ _lib_mlp_fit = _sig("tsim_mlp_fit_output", _i, [_vp, _vp, _i, _vp])
 _lib_mlp_predict = _sig("tsim_mlp_predict", _i, [_vp, _i, _vp, _vp, _vp])
 _lib_host_tables = _sig("tsim_host_tables", _i,
                         [ctypes.POINTER(_Params), _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
+_lib_p2s_form = _sig("tsim_p2s_form", _i, [_vp, ctypes.POINTER(_i)])
+_lib_last_error = _sig("tsim_last_error", _i, [ctypes.c_char_p, ctypes.c_size_t])
+_lib_sync = _sig("tsim_sync", _i, [_vp])
 
 EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "tsim_plan_table",
             "tsim_sample_zernike", "tsim_sample_zernike_ar", "tsim_p2s", "tsim_render", "tsim_warp", "tsim_psf_exact",
@@ -101,7 +104,21 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_mlp_param_count", "tsim_mlp_layout", "tsim_mlp_get", "tsim_mlp_set",
             "tsim_mlp_data_ws_bytes", "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp",
             "tsim_mlp_fit_output", "tsim_mlp_predict", "tsim_tilt_stats_ws_bytes", "tsim_tilt_stats",
-            "tsim_structure_function_ws_bytes", "tsim_structure_function"]
+            "tsim_structure_function_ws_bytes", "tsim_structure_function", "tsim_p2s_form",
+            "tsim_last_error", "tsim_sync"]
+
+
+def last_error():
+    """(status, text) of the last failing library call on this thread, then
+    cleared; (0, "") if none."""
+    buf = ctypes.create_string_buffer(256)
+    st = _lib_last_error(buf, 256)
+    return st, buf.value.decode()
+
+
+def sync(stream=None):
+    """Wait for the stream; an asynchronous device fault raises TsimError."""
+    _check(_lib_sync(_stream(stream)), "tsim_sync")
 
 
 def trace_enable(on=True):
@@ -142,6 +159,43 @@ def _ptr(t):
     if not t.is_contiguous():
         raise ValueError("contiguous tensor expected")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _expect(t, name, shape, dtype, device=None):
+    """Raise ValueError unless `t` is a contiguous device tensor of exactly
+    `shape` and `dtype` (on `device` if given).  The C ABI receives bare
+    pointers and cannot check extents, so every buffer is checked here,
+    before any launch."""
+    if t is None:
+        raise ValueError(f"{name}: tensor expected")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: device tensor expected")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: contiguous tensor expected")
+
+
+def _expect_bytes(t, name, nbytes, device):
+    """A workspace: a contiguous device tensor of at least `nbytes` bytes."""
+    if t is None or not t.is_cuda:
+        raise ValueError(f"{name}: device tensor expected")
+    if t.device != device:
+        raise ValueError(f"{name}: on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: contiguous tensor expected")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name}: {t.numel() * t.element_size()} bytes, {nbytes} needed")
+
+
+def kpad(k):
+    """BF16 weight-row width for K basis functions: K rounded up to 32, 64,
+    112 or 128."""
+    return 32 if k <= 32 else 64 if k <= 64 else 112 if k <= 112 else 128
 
 
 def _stream(stream):
@@ -205,6 +259,8 @@ class Plan:
                               bptr, p2s_mode, precision, subharmonic_levels)
         self.H, self.W, self.C, self.Gh, self.Gw = H, W, C, Gh, Gw
         self.T, self.K, self.P = psf_t, basis_k, pupil_n
+        self.p2s_mode, self.precision = p2s_mode, precision
+        self.KP = kpad(basis_k)
         h = _vp()
         _check(_lib_plan_create(ctypes.byref(self.params), ctypes.byref(h)), "tsim_plan_create")
         self._h = h
@@ -245,12 +301,35 @@ class Plan:
         n = max(self.workspace_bytes(frames), 256)
         return torch.empty(n, dtype=torch.uint8, device=device)
 
+    # ---- buffer checks (shapes the kernels assume) -----------------
+    def _zern(self, zern, name="zern"):
+        if zern is None or zern.dim() != 4:
+            raise ValueError(f"{name}: [frames, 35, H, W] tensor expected")
+        _expect(zern, name, (zern.shape[0], N_MODES, self.H, self.W), torch.float32)
+        return zern.shape[0], zern.device
+
+    def _frames_img(self, img, name, frames, device):
+        _expect(img, name, (frames, self.C, self.H, self.W), torch.float32, device)
+
+    def _beta(self, beta, frames, device):
+        """Weights as tsim_p2s writes and tsim_render reads them: float32
+        [F][H][W][K], or bfloat16 [F][H][W][KP] in BF16 plans."""
+        if self.precision == BF16:
+            _expect(beta, "beta", (frames, self.H, self.W, self.KP), torch.bfloat16, device)
+        else:
+            _expect(beta, "beta", (frames, self.H, self.W, self.K), torch.float32, device)
+
+    def _ws(self, ws, frames, device):
+        _expect_bytes(ws, "ws", self.workspace_bytes(frames), device)
+
     # ---- hot path ----------------------------------------------------
     def sample_zernike(self, d_over_r0, seed, frame0, zern, ws, stream=None):
         d = np.ascontiguousarray(np.atleast_1d(d_over_r0), dtype=np.float32)
-        frames = zern.shape[0]
+        frames, dev = self._zern(zern)
         if d.size != frames:
             raise ValueError("one D/r0 per frame expected")
+        if frames > 0:
+            self._ws(ws, frames, dev)
         _check(_lib_sample(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                            int(seed), int(frame0), _ptr(zern), _ptr(ws), _stream(stream)),
                "tsim_sample_zernike")
@@ -259,9 +338,13 @@ class Plan:
                           d_over_r0_prev=0.0, stream=None):
         """Auto-regressively correlated frames (tsim_sample_zernike_ar)."""
         d = np.ascontiguousarray(np.atleast_1d(d_over_r0), dtype=np.float32)
-        frames = zern.shape[0]
+        frames, dev = self._zern(zern)
         if d.size != frames:
             raise ValueError("one D/r0 per frame expected")
+        if frames > 0:
+            self._ws(ws, frames, dev)
+        if zern_prev is not None:
+            _expect(zern_prev, "zern_prev", (N_MODES, self.H, self.W), torch.float32, dev)
         _check(_lib_sample_ar(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                               int(seed), int(frame0), float(alpha), _ptr(zern_prev),
                               float(d_over_r0_prev), _ptr(zern), _ptr(ws), _stream(stream)),
@@ -270,11 +353,13 @@ class Plan:
     def tilt_stats(self, zern, max_lag, ws=None, stream=None):
         """Spatial tilt statistics (tsim_tilt_stats): returns (corr, dtv), each
         [2 modes (Noll 2, 3)][2 axes (x, y)][max_lag + 1] float64."""
-        frames = zern.shape[0]
-        if ws is None:
-            n = ctypes.c_size_t()
+        frames, dev = self._zern(zern)
+        n = ctypes.c_size_t()
+        if frames > 0:
             _check(_lib_stats_ws(self._h, frames, int(max_lag), ctypes.byref(n)), "tsim_tilt_stats_ws_bytes")
-            ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=zern.device)
+        if ws is None:
+            ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
+        _expect_bytes(ws, "ws", n.value, dev)
         out = np.zeros(8 * (int(max_lag) + 1), dtype=np.float64)
         _check(_lib_stats(self._h, frames, _ptr(zern), int(max_lag),
                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), _stream(stream)),
@@ -286,11 +371,13 @@ class Plan:
         """Phase structure function over the aperture (tsim_structure_function):
         returns (D [31] for r = 0..30 pupil samples, r/D = r/32, and the
         coefficients' second moments [35][35])."""
-        frames = zern.shape[0]
-        if ws is None:
-            n = ctypes.c_size_t()
+        frames, dev = self._zern(zern)
+        n = ctypes.c_size_t()
+        if frames > 0:
             _check(_lib_sf_ws(self._h, frames, ctypes.byref(n)), "tsim_structure_function_ws_bytes")
-            ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=zern.device)
+        if ws is None:
+            ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
+        _expect_bytes(ws, "ws", n.value, dev)
         D = np.zeros(31, dtype=np.float64)
         C = np.zeros((35, 35), dtype=np.float64)
         _check(_lib_sf(self._h, frames, _ptr(zern), D.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -298,16 +385,35 @@ class Plan:
                "tsim_structure_function")
         return D, C
 
+    def p2s_form(self):
+        """P2S_LEARNED if tsim_p2s runs the network now, else P2S_EXACT."""
+        f = _i()
+        _check(_lib_p2s_form(self._h, ctypes.byref(f)), "tsim_p2s_form")
+        return f.value
+
     def p2s(self, zern, beta, ws, stream=None):
-        _check(_lib_p2s(self._h, zern.shape[0], _ptr(zern), _ptr(beta), _ptr(ws), _stream(stream)),
+        frames, dev = self._zern(zern)
+        self._beta(beta, frames, dev)
+        if frames > 0:
+            self._ws(ws, frames, dev)
+        _check(_lib_p2s(self._h, frames, _ptr(zern), _ptr(beta), _ptr(ws), _stream(stream)),
                "tsim_p2s")
 
     def render(self, img, beta, out, ws=None, stream=None):
-        _check(_lib_render(self._h, img.shape[0], _ptr(img), _ptr(beta), _ptr(out), _ptr(ws),
+        if img is None or img.dim() != 4:
+            raise ValueError("img: [frames, C, H, W] tensor expected")
+        frames, dev = img.shape[0], img.device
+        self._frames_img(img, "img", frames, dev)
+        self._frames_img(out, "out", frames, dev)
+        self._beta(beta, frames, dev)
+        _check(_lib_render(self._h, frames, _ptr(img), _ptr(beta), _ptr(out), _ptr(ws),
                            _stream(stream)), "tsim_render")
 
     def warp(self, img, zern, out, stream=None):
-        _check(_lib_warp(self._h, img.shape[0], _ptr(img), _ptr(zern), _ptr(out), _stream(stream)),
+        frames, dev = self._zern(zern)
+        self._frames_img(img, "img", frames, dev)
+        self._frames_img(out, "out", frames, dev)
+        _check(_lib_warp(self._h, frames, _ptr(img), _ptr(zern), _ptr(out), _stream(stream)),
                "tsim_warp")
 
     def basis_build(self, n_psf=20000, seed=0, dr_lo=0.5, dr_hi=5.0):
@@ -321,7 +427,12 @@ class Plan:
         return out, eig
 
     def psf_exact(self, zvec, psf, stream=None):
-        _check(_lib_psf(self._h, zvec.shape[0], _ptr(zvec), _ptr(psf), _stream(stream)),
+        if zvec is None or zvec.dim() != 2:
+            raise ValueError("zvec: [n, 35] tensor expected")
+        n = zvec.shape[0]
+        _expect(zvec, "zvec", (n, N_MODES), torch.float32)
+        _expect(psf, "psf", (n, self.T * self.T), torch.float32, zvec.device)
+        _check(_lib_psf(self._h, n, _ptr(zvec), _ptr(psf), _stream(stream)),
                "tsim_psf_exact")
 
 
@@ -355,10 +466,14 @@ class Mlp:
         except Exception:
             pass
 
-    _SIZES = {0: None, 1: None, 2: N_MODES, 3: None, 4: 1}
+    def _count(self, what):
+        return {0: self.n_params, 1: self.n_params, 2: N_MODES, 3: self.K, 4: 1,
+                5: self.n_params, 6: self.n_params, 7: 2}[what]
 
     def get(self, what):
-        n = {0: self.n_params, 1: self.n_params, 2: N_MODES, 3: self.K, 4: 1}[what]
+        """what: 0 parameters, 1 gradients, 2 inv_s, 3 mu, 4 s_out, 5/6 AdamW
+        first/second moments, 7 [steps taken, schedule length]."""
+        n = self._count(what)
         out = np.zeros(n, dtype=np.float32)
         _check(_lib_mlp_get(self._h, what, out.ctypes.data_as(_fp), n), "tsim_mlp_get")
         return out
@@ -383,17 +498,43 @@ class Mlp:
             flat[self.off_b[l]:self.off_b[l] + b.size] = b
         return flat
 
+    def checkpoint(self):
+        """Training state: parameters, AdamW moments and counters (host)."""
+        return {w: self.get(w) for w in (0, 5, 6, 7)} | {"inv_s": self.get(2), "mu": self.get(3),
+                                                        "s_out": self.get(4)}
+
+    def restore(self, state):
+        for w in (0, 5, 6, 7):
+            self.set(w, state[w])
+        self.set(2, state["inv_s"])
+        self.set(3, state["mu"])
+        self.set(4, state["s_out"])
+
+    def _pairs(self, zvec, target, n=None):
+        if zvec is None or zvec.dim() != 2:
+            raise ValueError("zvec: [n, 35] tensor expected")
+        n = zvec.shape[0] if n is None else n
+        _expect(zvec, "zvec", (n, N_MODES), torch.float32)
+        _expect(target, "target", (n, self.K), torch.float32, zvec.device)
+
     def grad(self, zvec, target, stream=None):
+        self._pairs(zvec, target)
+        if zvec.shape[0] > self.batch:
+            raise ValueError(f"at most {self.batch} pairs per gradient call")
         loss = ctypes.c_float()
         _check(_lib_mlp_grad(self._h, zvec.shape[0], _ptr(zvec), _ptr(target), ctypes.byref(loss),
                              _stream(stream)), "tsim_mlp_grad")
         return loss.value
 
     def fit_output(self, target, stream=None):
+        if target is None or target.dim() != 2:
+            raise ValueError("target: [n, K] tensor expected")
+        _expect(target, "target", (target.shape[0], self.K), torch.float32)
         _check(_lib_mlp_fit(self._h, _ptr(target), target.shape[0], _stream(stream)),
                "tsim_mlp_fit_output")
 
     def train(self, zvec, target, steps, lr_max=1e-3, lr_min=1e-5, stream=None):
+        self._pairs(zvec, target)
         losses = np.zeros(steps, dtype=np.float32)
         _check(_lib_mlp_train(self._h, _ptr(zvec), _ptr(target), zvec.shape[0], int(steps),
                               float(lr_max), float(lr_min), losses.ctypes.data_as(_fp),
@@ -415,6 +556,9 @@ def make_training_data(plan, n_pairs, seed=0, dr_lo=0.5, dr_hi=5.0, stream=None)
 
 def mlp_predict(plan, zvec, stream=None):
     """The plan's network on Zernike vectors [n][35] -> beta [n][K] (float32)."""
+    if zvec is None or zvec.dim() != 2:
+        raise ValueError("zvec: [n, 35] tensor expected")
+    _expect(zvec, "zvec", (zvec.shape[0], N_MODES), torch.float32)
     out = torch.empty((zvec.shape[0], plan.K), dtype=torch.float32, device="cuda")
     _check(_lib_mlp_predict(plan._h, zvec.shape[0], _ptr(zvec), _ptr(out), _stream(stream)),
            "tsim_mlp_predict")

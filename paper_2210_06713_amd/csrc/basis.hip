@@ -242,10 +242,8 @@ int top_eigen(const std::vector<double> &G, int n, int K, std::vector<double> &v
   return TSIM_EARTEFACT;
 }
 
-}  // namespace
-
-extern "C" int tsim_basis_build(const tsim_plan *pl, int n_psf, uint64_t seed, double dr_lo,
-                                double dr_hi, double *basis_out, double *eig_out) {
+int basis_build_impl(const tsim_plan *pl, int n_psf, uint64_t seed, double dr_lo, double dr_hi,
+                     double *basis_out, double *eig_out) {
   if (!pl || !basis_out || n_psf < 1 || n_psf > (1 << 22)) return TSIM_EINVAL;
   if (!(dr_lo > 0.0) || !(dr_hi >= dr_lo) || !std::isfinite(dr_hi)) return TSIM_EINVAL;
   const int T2 = pl->T * pl->T, K = pl->K;
@@ -298,4 +296,11 @@ done:
   if (d_h) (void)hipFree(d_h);
   if (d_G) (void)hipFree(d_G);
   return st;
+}
+
+}  // namespace
+
+extern "C" int tsim_basis_build(const tsim_plan *pl, int n_psf, uint64_t seed, double dr_lo,
+                                double dr_hi, double *basis_out, double *eig_out) {
+  return note_status("tsim_basis_build", basis_build_impl(pl, n_psf, seed, dr_lo, dr_hi, basis_out, eig_out));
 }

@@ -80,13 +80,14 @@ void structure_function_from_moments(const double *C, double *out);
 
 // ---- launchers (psf.hip) ----
 int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, hipStream_t s);
-int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *beta, void *ws,
+// beta: float32 [pixels][K], or with out_bf16 bfloat16 [pixels][KP] (zero padded)
+int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, void *beta, int out_bf16, void *ws,
                      hipStream_t s);
 size_t p2s_ws_bytes(const tsim_plan *pl, int frames);
 size_t p2s_chunk_pixels(const tsim_plan *pl, size_t total);
 
 // ---- launchers (project.hip) ----
-int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s);
+int launch_project(const tsim_plan *pl, const float *h, int n, void *beta, int out_bf16, hipStream_t s);
 
 // ---- launchers (mlp.hip) ----
 int plan_set_mlp_impl(tsim_plan *pl, const tsim_mlp *n);
@@ -100,8 +101,17 @@ int launch_render_bf16(const tsim_plan *pl, int frames, const float *img, const 
                        float *out, hipStream_t s);
 int launch_render_f32_mfma(const tsim_plan *pl, int frames, const float *img, const float *beta,
                            float *out, hipStream_t s);
+// shapes the BF16 blur is built for: T in {15, 21, 33, 65} and an image
+// tile plus basis staging that fit the LDS (all but KP = 128, C = 4, T = 65)
+bool render_bf16_supported(int KP, int T, int C);
+// PSF supports the exact-PSF kernels are built for
+bool psf_size_supported(int P, int T);
 int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
                 hipStream_t s);
+
+// ---- status of the C ABI (status.cpp): records a failing call's status
+// and name for tsim_last_error, returns st unchanged ----
+int note_status(const char *fn, int st);
 
 #define TSIM_HIP_CHECK(expr)                 \
   do {                                       \

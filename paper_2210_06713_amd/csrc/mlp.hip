@@ -61,7 +61,7 @@ __device__ __forceinline__ f32x16 mfma_bf16(const uint4 &a, const uint4 &b, cons
                                                  c, 0, 0, 0);
 }
 
-enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_GELU_GRAD = 3, EPI_F32_ADD = 4 };
+enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_GELU_GRAD = 3 };
 
 constexpr int GT = 64, GK = 32, GKP = GK + 8;
 
@@ -108,9 +108,8 @@ k_gemm_bf16(const uint16_t *__restrict__ A, long sam, long sak, const uint16_t *
     const size_t o = size_t(m) * ldc + n;
     const float v = acc[r];
     if (EPI == EPI_F32) {
-      outf[o] = v;
-    } else if (EPI == EPI_F32_ADD) {
-      atomicAdd(&outf[o], v);
+      // split-K block z writes its partial product to slice z (z = 0 unsplit)
+      outf[size_t(blockIdx.z) * size_t(M) * ldc + o] = v;
     } else if (EPI == EPI_BIAS_F32) {
       outf[o] = v + bias[n];
     } else if (EPI == EPI_BIAS_GELU) {
@@ -122,6 +121,16 @@ k_gemm_bf16(const uint16_t *__restrict__ A, long sam, long sak, const uint16_t *
       outf[o] = dz;
       outb[o] = f2bf(dz);
     }
+  }
+}
+
+// dst[i] = sum over z of part[z][i], z in increasing order: the split-K
+// partial products added in a fixed order, so training is bit-reproducible
+__global__ void k_sum_parts(const float *__restrict__ part, int splits, size_t count, float *__restrict__ dst) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += size_t(gridDim.x) * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[size_t(z) * count + i];
+    dst[i] = s;
   }
 }
 
@@ -502,7 +511,10 @@ struct tsim_mlp {
   float *z[3] = {nullptr, nullptr, nullptr}, *y = nullptr, *t = nullptr, *dzf = nullptr;
   float *loss = nullptr;
   float *colpart = nullptr;                                      // [CS_CHUNKS][256] column-sum partials
-  int step = 0;
+  float *gpart = nullptr;                                        // [splits][dout * din] split-K partials
+  int step = 0;                                                  // step within the current call (loss slot)
+  long long t_done = 0;                                          // optimiser steps taken so far
+  long long sched = 0;                                           // cosine schedule length (0: per call)
   std::vector<double> A0diag;
 };
 
@@ -511,7 +523,8 @@ namespace {
 void mlp_free(tsim_mlp *n) {
   if (!n) return;
   void *ptrs[] = {n->w, n->g, n->m, n->v, n->wb, n->inv_s, n->mu, n->x, n->act[0], n->act[1],
-                  n->act[2], n->dzb, n->z[0], n->z[1], n->z[2], n->y, n->t, n->dzf, n->loss, n->colpart};
+                  n->act[2], n->dzb, n->z[0], n->z[1], n->z[2], n->y, n->t, n->dzf, n->loss, n->colpart,
+                  n->gpart};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete n;
@@ -521,6 +534,11 @@ template <class T>
 bool dalloc(T **p, size_t n) {
   return hipMalloc(p, std::max<size_t>(n, 1) * sizeof(T)) == hipSuccess;
 }
+
+// split-K of the weight gradients: at most this many blocks per product, so
+// the partials (splits x dout x din <= kMaxSplitBlocks x GT x GT floats) fit
+// one buffer
+constexpr int kMaxSplitBlocks = 512;
 
 // forward + backward for the current batch (x, t already prepared)
 int mlp_fwd_bwd(tsim_mlp *n, int Bsz, hipStream_t s) {
@@ -547,13 +565,18 @@ int mlp_fwd_bwd(tsim_mlp *n, int Bsz, hipStream_t s) {
     const int dout = n->dout[l], din = n->din[l];
     const uint16_t *in = (l == 0) ? n->x : n->act[l - 1];
     // dW = dZ^T X: M = dout, N = din, reduction over the batch, split over
-    // the batch so that ~512 blocks run, partial sums added atomically
+    // the batch so that ~512 blocks run; the partial products are added in
+    // split order by a second kernel (no atomics: bit-reproducible)
     const int tiles = ((dout + GT - 1) / GT) * ((din + GT - 1) / GT);
-    const int splits = std::max(1, std::min(Bsz / 256, 512 / tiles));
-    if (hipMemsetAsync(n->g + n->off_w[l], 0, size_t(dout) * din * sizeof(float), s) != hipSuccess)
-      return TSIM_EDEVICE;
-    if ((st = gemm<EPI_F32_ADD>(s, n->dzb, 1, dout, in, din, 1, dout, din, Bsz, nullptr, nullptr,
-                                n->g + n->off_w[l], nullptr, din, splits)) != TSIM_OK) return st;
+    const int splits = std::max(1, std::min(Bsz / 256, kMaxSplitBlocks / tiles));
+    float *gw = n->g + n->off_w[l];
+    if ((st = gemm<EPI_F32>(s, n->dzb, 1, dout, in, din, 1, dout, din, Bsz, nullptr, nullptr,
+                            splits > 1 ? n->gpart : gw, nullptr, din, splits)) != TSIM_OK) return st;
+    if (splits > 1) {
+      const size_t cnt = size_t(dout) * din;
+      hipLaunchKernelGGL(k_sum_parts, dim3(unsigned(std::min<size_t>((cnt + 255) / 256, 1024))), dim3(256), 0, s,
+                         n->gpart, splits, cnt, gw);
+    }
     colsum(s, n->dzf, Bsz, dout, n->g + n->off_b[l], n->colpart);
     if (l > 0) {
       // dA = dZ W (M = batch, N = din, reduction over dout), then dZ_prev = dA * GELU'(Z_prev).
@@ -574,9 +597,9 @@ int mlp_fwd_bwd(tsim_mlp *n, int Bsz, hipStream_t s) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int tsim_mlp_create(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **out) {
+int mlp_create_impl(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **out) {
   if (!pl || !out || batch < 1 || batch > (1 << 20)) return TSIM_EINVAL;
   *out = nullptr;
   if (pl->K > 128) return TSIM_EUNSUPPORTED;
@@ -602,7 +625,7 @@ int tsim_mlp_create(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **ou
             dalloc(&n->wb, off) && dalloc(&n->inv_s, TSIM_N_MODES) && dalloc(&n->mu, 128) &&
             dalloc(&n->x, B * TSIM_N_MODES) && dalloc(&n->y, B * pl->K) && dalloc(&n->t, B * pl->K) &&
             dalloc(&n->dzf, 2 * B * 256) && dalloc(&n->dzb, 2 * B * 256) && dalloc(&n->loss, 1 << 20) &&
-            dalloc(&n->colpart, size_t(CS_CHUNKS) * 256);
+            dalloc(&n->colpart, size_t(CS_CHUNKS) * 256) && dalloc(&n->gpart, size_t(kMaxSplitBlocks) * GT * GT);
   for (int l = 0; l < 3 && ok; ++l) ok = dalloc(&n->act[l], B * HID) && dalloc(&n->z[l], B * HID);
   if (!ok) {
     mlp_free(n);
@@ -634,18 +657,18 @@ int tsim_mlp_create(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **ou
   return TSIM_OK;
 }
 
-int tsim_mlp_destroy(tsim_mlp *n) {
+int mlp_destroy_impl(tsim_mlp *n) {
   mlp_free(n);
   return TSIM_OK;
 }
 
-int tsim_mlp_param_count(const tsim_mlp *n, size_t *count) {
+int mlp_param_count_impl(const tsim_mlp *n, size_t *count) {
   if (!n || !count) return TSIM_EINVAL;
   *count = n->n_par;
   return TSIM_OK;
 }
 
-int tsim_mlp_layout(const tsim_mlp *n, size_t *off_w, size_t *off_b) {
+int mlp_layout_impl(const tsim_mlp *n, size_t *off_w, size_t *off_b) {
   if (!n || !off_w || !off_b) return TSIM_EINVAL;
   for (int l = 0; l < 4; ++l) {
     off_w[l] = n->off_w[l];
@@ -654,7 +677,7 @@ int tsim_mlp_layout(const tsim_mlp *n, size_t *off_w, size_t *off_b) {
   return TSIM_OK;
 }
 
-int tsim_mlp_get(const tsim_mlp *n, int what, float *host, size_t count) {
+int mlp_get_impl(const tsim_mlp *n, int what, float *host, size_t count) {
   if (!n || !host) return TSIM_EINVAL;
   const float *src = nullptr;
   size_t cnt = n->n_par;
@@ -667,6 +690,13 @@ int tsim_mlp_get(const tsim_mlp *n, int what, float *host, size_t count) {
       if (count < 1) return TSIM_EINVAL;
       host[0] = n->s_out;
       return TSIM_OK;
+    case 5: src = n->m; break;
+    case 6: src = n->v; break;
+    case 7:
+      if (count < 2) return TSIM_EINVAL;
+      host[0] = float(n->t_done);
+      host[1] = float(n->sched);
+      return TSIM_OK;
     default: return TSIM_EINVAL;
   }
   if (count < cnt) return TSIM_EINVAL;
@@ -674,7 +704,7 @@ int tsim_mlp_get(const tsim_mlp *n, int what, float *host, size_t count) {
   return hipMemcpy(host, src, cnt * 4, hipMemcpyDeviceToHost) == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
 
-int tsim_mlp_set(tsim_mlp *n, int what, const float *host, size_t count) {
+int mlp_set_impl(tsim_mlp *n, int what, const float *host, size_t count) {
   if (!n || !host) return TSIM_EINVAL;
   if (hipDeviceSynchronize() != hipSuccess) return TSIM_EDEVICE;
   switch (what) {
@@ -701,17 +731,32 @@ int tsim_mlp_set(tsim_mlp *n, int what, const float *host, size_t count) {
       if (count != 1 || !(host[0] > 0.f)) return TSIM_EINVAL;
       n->s_out = host[0];
       return TSIM_OK;
+    case 5:
+    case 6:
+      if (count != n->n_par) return TSIM_EINVAL;
+      return hipMemcpy(what == 5 ? n->m : n->v, host, count * 4, hipMemcpyHostToDevice) == hipSuccess
+                 ? TSIM_OK
+                 : TSIM_EDEVICE;
+    case 7: {
+      // whole numbers in [0, 2^24), where float holds every integer exactly
+      if (count != 2) return TSIM_EINVAL;
+      for (int i = 0; i < 2; ++i)
+        if (!(host[i] >= 0.f && host[i] < 16777216.f) || host[i] != std::floor(host[i])) return TSIM_EINVAL;
+      n->t_done = static_cast<long long>(host[0]);
+      n->sched = static_cast<long long>(host[1]);
+      return TSIM_OK;
+    }
     default: return TSIM_EINVAL;
   }
 }
 
-int tsim_mlp_data_ws_bytes(const tsim_plan *pl, int n_pairs, size_t *bytes) {
+int mlp_data_ws_bytes_impl(const tsim_plan *pl, int n_pairs, size_t *bytes) {
   if (!pl || n_pairs < 1 || !bytes) return TSIM_EINVAL;
   *bytes = p2s_chunk_pixels(pl, size_t(n_pairs)) * size_t(pl->T) * pl->T * sizeof(float);
   return TSIM_OK;
 }
 
-int tsim_mlp_make_data(const tsim_plan *pl, int n_pairs, uint64_t seed, float dr_lo, float dr_hi,
+int mlp_make_data_impl(const tsim_plan *pl, int n_pairs, uint64_t seed, float dr_lo, float dr_hi,
                        float *zvec, float *beta, void *ws, tsim_stream stream) {
   if (!pl || n_pairs < 1 || !zvec || !beta || !ws) return TSIM_EINVAL;
   if (!pl->d_basis) return TSIM_EARTEFACT;
@@ -725,13 +770,13 @@ int tsim_mlp_make_data(const tsim_plan *pl, int n_pairs, uint64_t seed, float dr
     const int cnt = int(std::min(chunk, size_t(n_pairs) - p0));
     int st = launch_psf_exact(pl, cnt, zvec + p0 * TSIM_N_MODES, static_cast<float *>(ws), s);
     if (st != TSIM_OK) return st;
-    st = launch_project(pl, static_cast<float *>(ws), cnt, beta + p0 * pl->K, s);
+    st = launch_project(pl, static_cast<float *>(ws), cnt, beta + p0 * pl->K, 0, s);
     if (st != TSIM_OK) return st;
   }
   return TSIM_OK;
 }
 
-int tsim_mlp_grad(tsim_mlp *n, int batch, const float *zvec, const float *target, float *loss_host,
+int mlp_grad_impl(tsim_mlp *n, int batch, const float *zvec, const float *target, float *loss_host,
                   tsim_stream stream) {
   if (!n || batch < 1 || batch > n->B || !zvec || !target) return TSIM_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -747,7 +792,7 @@ int tsim_mlp_grad(tsim_mlp *n, int batch, const float *zvec, const float *target
   return TSIM_OK;
 }
 
-int tsim_mlp_fit_output(tsim_mlp *n, const float *target, int n_pairs, tsim_stream stream) {
+int mlp_fit_output_impl(tsim_mlp *n, const float *target, int n_pairs, tsim_stream stream) {
   if (!n || !target || n_pairs < 1) return TSIM_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   colsum(s, target, n_pairs, n->K, n->mu, n->colpart);
@@ -765,13 +810,13 @@ int tsim_mlp_fit_output(tsim_mlp *n, const float *target, int n_pairs, tsim_stre
   return TSIM_OK;
 }
 
-int tsim_mlp_predict(const tsim_plan *pl, int n_vec, const float *zvec, float *beta, tsim_stream stream) {
+int mlp_predict_impl(const tsim_plan *pl, int n_vec, const float *zvec, float *beta, tsim_stream stream) {
   if (!pl || n_vec < 1 || !zvec || !beta) return TSIM_EINVAL;
   if (!pl->d_mlp_w) return TSIM_EARTEFACT;
   return launch_mlp_infer(pl, zvec, 1, size_t(n_vec), beta, 0, pl->K, static_cast<hipStream_t>(stream));
 }
 
-int tsim_mlp_train(tsim_mlp *n, const float *zvec, const float *target, int n_pairs, int steps,
+int mlp_train_impl(tsim_mlp *n, const float *zvec, const float *target, int n_pairs, int steps,
                    float lr_max, float lr_min, float *loss_host, tsim_stream stream) {
   if (!n || !zvec || !target || n_pairs < n->B || steps < 1 || steps > (1 << 20)) return TSIM_EINVAL;
   if (!(lr_max > 0.f) || !(lr_min >= 0.f)) return TSIM_EINVAL;
@@ -781,18 +826,24 @@ int tsim_mlp_train(tsim_mlp *n, const float *zvec, const float *target, int n_pa
   const double b1 = 0.9, b2 = 0.999;
   for (int it = 0; it < steps; ++it) {
     n->step = it;
-    const int start = int((size_t(it) * B) % size_t(n_pairs));
+    const long long tg = n->t_done;  // global step: batch position, schedule, bias correction
+    const int start = int((static_cast<unsigned long long>(tg) * unsigned(B)) % size_t(n_pairs));
     hipLaunchKernelGGL(k_prep, dim3((B + 255) / 256), dim3(256), 0, s, zvec, target, n_pairs, start, B,
                        n->inv_s, n->mu, 1.0f / n->s_out, n->K, n->x, n->t);
     int st = mlp_fwd_bwd(n, B, s);
     if (st != TSIM_OK) return st;
-    const double prog = steps > 1 ? double(it) / double(steps - 1) : 1.0;
+    double prog;
+    if (n->sched > 0)
+      prog = n->sched > 1 ? double(std::min(tg, n->sched - 1)) / double(n->sched - 1) : 1.0;
+    else
+      prog = steps > 1 ? double(it) / double(steps - 1) : 1.0;
     const float lr = float(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + std::cos(3.14159265358979 * prog)));
-    const int t = it + 1;
+    const double t = double(tg + 1);
     hipLaunchKernelGGL(k_adamw, dim3(int((n->n_par + 255) / 256)), dim3(256), 0, s, n->w, n->g, n->m,
                        n->v, n->wb, int(n->n_par), lr, float(b1), float(b2),
                        float(1.0 - std::pow(b1, t)), float(1.0 - std::pow(b2, t)), 1e-8f, 0.0f);
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+    ++n->t_done;
   }
   n->step = 0;
   if (loss_host) {
@@ -801,6 +852,62 @@ int tsim_mlp_train(tsim_mlp *n, const float *zvec, const float *target, int n_pa
       return TSIM_EDEVICE;
   }
   return TSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+int tsim_mlp_create(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **out) {
+  return note_status("tsim_mlp_create", mlp_create_impl(pl, batch, seed, out));
+}
+
+int tsim_mlp_destroy(tsim_mlp *n) {
+  return note_status("tsim_mlp_destroy", mlp_destroy_impl(n));
+}
+
+int tsim_mlp_param_count(const tsim_mlp *n, size_t *count) {
+  return note_status("tsim_mlp_param_count", mlp_param_count_impl(n, count));
+}
+
+int tsim_mlp_layout(const tsim_mlp *n, size_t *off_w, size_t *off_b) {
+  return note_status("tsim_mlp_layout", mlp_layout_impl(n, off_w, off_b));
+}
+
+int tsim_mlp_get(const tsim_mlp *n, int what, float *host, size_t count) {
+  return note_status("tsim_mlp_get", mlp_get_impl(n, what, host, count));
+}
+
+int tsim_mlp_set(tsim_mlp *n, int what, const float *host, size_t count) {
+  return note_status("tsim_mlp_set", mlp_set_impl(n, what, host, count));
+}
+
+int tsim_mlp_data_ws_bytes(const tsim_plan *pl, int n_pairs, size_t *bytes) {
+  return note_status("tsim_mlp_data_ws_bytes", mlp_data_ws_bytes_impl(pl, n_pairs, bytes));
+}
+
+int tsim_mlp_make_data(const tsim_plan *pl, int n_pairs, uint64_t seed, float dr_lo, float dr_hi, float *zvec,
+                       float *beta, void *ws, tsim_stream stream) {
+  return note_status("tsim_mlp_make_data",
+                     mlp_make_data_impl(pl, n_pairs, seed, dr_lo, dr_hi, zvec, beta, ws, stream));
+}
+
+int tsim_mlp_grad(tsim_mlp *n, int batch, const float *zvec, const float *target, float *loss_host,
+                  tsim_stream stream) {
+  return note_status("tsim_mlp_grad", mlp_grad_impl(n, batch, zvec, target, loss_host, stream));
+}
+
+int tsim_mlp_fit_output(tsim_mlp *n, const float *target, int n_pairs, tsim_stream stream) {
+  return note_status("tsim_mlp_fit_output", mlp_fit_output_impl(n, target, n_pairs, stream));
+}
+
+int tsim_mlp_predict(const tsim_plan *pl, int n_vec, const float *zvec, float *beta, tsim_stream stream) {
+  return note_status("tsim_mlp_predict", mlp_predict_impl(pl, n_vec, zvec, beta, stream));
+}
+
+int tsim_mlp_train(tsim_mlp *n, const float *zvec, const float *target, int n_pairs, int steps, float lr_max,
+                   float lr_min, float *loss_host, tsim_stream stream) {
+  return note_status("tsim_mlp_train",
+                     mlp_train_impl(n, zvec, target, n_pairs, steps, lr_max, lr_min, loss_host, stream));
 }
 
 }  // extern "C"

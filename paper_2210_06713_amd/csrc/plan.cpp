@@ -276,6 +276,12 @@ int validate(const tsim_params *p) {
   if (p->p2s_mode != TSIM_P2S_EXACT && p->p2s_mode != TSIM_P2S_LEARNED) return TSIM_EINVAL;
   if (p->precision != TSIM_FP32 && p->precision != TSIM_BF16) return TSIM_EINVAL;
   if (p->subharmonic_levels < 0 || p->subharmonic_levels > 4) return TSIM_EINVAL;
+  // the exact path (plain form, basis build, training pairs, and the learned
+  // form's fallback) must exist for the plan's PSF support, and so must the
+  // BF16 blur in BF16 plans
+  if (!psf_size_supported(p->pupil_n, p->psf_t)) return TSIM_EUNSUPPORTED;
+  const int kp = p->basis_k <= 32 ? 32 : p->basis_k <= 64 ? 64 : p->basis_k <= 112 ? 112 : 128;
+  if (p->precision == TSIM_BF16 && !render_bf16_supported(kp, p->psf_t, p->C)) return TSIM_EUNSUPPORTED;
   return TSIM_OK;
 }
 
@@ -407,11 +413,36 @@ int copy_table(const tsim_plan *pl, int what, double *host_out, size_t count) {
   return TSIM_OK;
 }
 
+int host_tables_impl(const tsim_params *p, int what, double *host_out, size_t count);
+int plan_create_impl(const tsim_params *p, tsim_plan **out);
+
 }  // namespace
 
 extern "C" {
 
 int tsim_host_tables(const tsim_params *p, int what, double *host_out, size_t count) {
+  return note_status("tsim_host_tables", host_tables_impl(p, what, host_out, count));
+}
+
+int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
+  return note_status("tsim_plan_create", plan_create_impl(p, out));
+}
+
+int tsim_plan_destroy(tsim_plan *pl) {
+  free_plan(pl);
+  return TSIM_OK;
+}
+
+int tsim_plan_table(const tsim_plan *pl, int what, double *host_out, size_t count) {
+  if (!pl || !host_out) return note_status("tsim_plan_table", TSIM_EINVAL);
+  return note_status("tsim_plan_table", copy_table(pl, what, host_out, count));
+}
+
+}  // extern "C"
+
+namespace {
+
+int host_tables_impl(const tsim_params *p, int what, double *host_out, size_t count) {
   if (!host_out) return TSIM_EINVAL;
   int st = validate(p);
   if (st != TSIM_OK) return st;
@@ -423,7 +454,7 @@ int tsim_host_tables(const tsim_params *p, int what, double *host_out, size_t co
   return st;
 }
 
-int tsim_plan_create(const tsim_params *p, tsim_plan **out) {
+int plan_create_impl(const tsim_params *p, tsim_plan **out) {
   if (!out) return TSIM_EINVAL;
   *out = nullptr;
   int st = validate(p);
@@ -540,14 +571,4 @@ fail:
   return st;
 }
 
-int tsim_plan_destroy(tsim_plan *pl) {
-  free_plan(pl);
-  return TSIM_OK;
-}
-
-int tsim_plan_table(const tsim_plan *pl, int what, double *host_out, size_t count) {
-  if (!pl || !host_out) return TSIM_EINVAL;
-  return copy_table(pl, what, host_out, count);
-}
-
-}  // extern "C"
+}  // namespace

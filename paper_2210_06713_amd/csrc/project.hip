@@ -18,10 +18,12 @@ namespace {
 constexpr int PJ_PX = kProjectTile, PJ_TK = 32, PJ_N = 128;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int PJ_NT>  // 16-wide output tiles: 7 for K <= 112, 8 up to 128
+// OUT_BF16: beta rows of KB bfloat16 (K weights, zeros up to KB <= 16 PJ_NT),
+// the layout BF16 plans use; else rows of K floats.
+template <int PJ_NT, bool OUT_BF16>  // 16-wide output tiles: 7 for KB <= 112, 8 up to 128
 __global__ void __launch_bounds__(256)
 k_project_mfma(const float *__restrict__ h, const float *__restrict__ psi_t128 /*[T2][128]*/,
-               float *__restrict__ beta, int n, int T2, int K) {
+               void *__restrict__ beta, int n, int T2, int K, int KB) {
   __shared__ float As[PJ_PX][PJ_TK + 1];
   __shared__ __attribute__((aligned(16))) float Bs[PJ_TK][PJ_N];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -83,26 +85,37 @@ k_project_mfma(const float *__restrict__ h, const float *__restrict__ psi_t128 /
 #pragma unroll
   for (int j = 0; j < PJ_NT; ++j) {
     const int k = 16 * j + li;
-    if (k >= K) continue;
+    if (k >= (OUT_BF16 ? KB : K)) continue;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gp = p0 + w * 32 + 16 * i + 4 * lk + r;
-        if (gp < n) beta[size_t(gp) * K + k] = acc[i][j][r];
+        if (gp >= n) continue;
+        if constexpr (OUT_BF16)
+          static_cast<__bf16 *>(beta)[size_t(gp) * KB + k] = __bf16(k < K ? acc[i][j][r] : 0.f);
+        else
+          static_cast<float *>(beta)[size_t(gp) * K + k] = acc[i][j][r];
       }
   }
 }
 
 }  // namespace
 
-int launch_project(const tsim_plan *pl, const float *h, int n, float *beta, hipStream_t s) {
-  const int T2 = pl->T * pl->T;
+int launch_project(const tsim_plan *pl, const float *h, int n, void *beta, int out_bf16, hipStream_t s) {
+  const int T2 = pl->T * pl->T, KB = out_bf16 ? pl->KP : pl->K;
   dim3 grid((n + PJ_PX - 1) / PJ_PX);
   TraceScope tr("k_project", s);
-  if (pl->K <= 112)
-    hipLaunchKernelGGL(k_project_mfma<7>, grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K);
-  else
-    hipLaunchKernelGGL(k_project_mfma<8>, grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K);
+  if (KB <= 112) {
+    if (out_bf16)
+      hipLaunchKernelGGL((k_project_mfma<7, true>), grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K, KB);
+    else
+      hipLaunchKernelGGL((k_project_mfma<7, false>), grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K, KB);
+  } else {
+    if (out_bf16)
+      hipLaunchKernelGGL((k_project_mfma<8, true>), grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K, KB);
+    else
+      hipLaunchKernelGGL((k_project_mfma<8, false>), grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K, KB);
+  }
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }

@@ -412,6 +412,12 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
 
 }  // namespace
 
+bool psf_size_supported(int P, int T) {
+  if (P == 128) return T == 65 || T == 33;
+  if (P == 64) return T == 33 || T == 31 || T == 21 || T == 15 || T == 9;
+  return false;
+}
+
 // pixels per P2S chunk: at most 2^20 pixels and about 5 GB of PSFs, in whole
 // projection tiles (bounds the PSF workspace)
 size_t p2s_chunk_pixels(const tsim_plan *pl, size_t total) {
@@ -430,17 +436,19 @@ int launch_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, 
   return launch_psf_impl(pl, zvec, 1, 0, n, psf, s);
 }
 
-int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, float *beta, void *ws,
+int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, void *beta, int out_bf16, void *ws,
                      hipStream_t s) {
   const int hw = pl->H * pl->W;
   const size_t total = size_t(frames) * hw;
   const size_t chunk = p2s_chunk_pixels(pl, total);
+  // bytes of one pixel's weights in the output layout
+  const size_t row = out_bf16 ? size_t(pl->KP) * 2 : size_t(pl->K) * 4;
   float *h = static_cast<float *>(ws);
   for (size_t p0 = 0; p0 < total; p0 += chunk) {
     const int n = int(std::min(chunk, total - p0));
     int st = launch_psf_impl(pl, zern, hw, p0, n, h, s);
     if (st != TSIM_OK) return st;
-    st = launch_project(pl, h, n, beta + p0 * pl->K, s);
+    st = launch_project(pl, h, n, static_cast<char *>(beta) + p0 * row, out_bf16, s);
     if (st != TSIM_OK) return st;
   }
   return TSIM_OK;

@@ -111,24 +111,39 @@ k_warp(const float *__restrict__ img, const float *__restrict__ zern, float *__r
 
 }  // namespace
 
+// The image tile takes C (16 + T - 1)^2 floats of LDS: up to 100 KB (T = 65,
+// C = 4), beyond the default 64 KB of dynamic LDS, so the kernel's limit is
+// raised to the tile's size (gfx950 allows 160 KB per block).
+template <int KP>
+int launch_fp32_kp(const tsim_plan *pl, int frames, const float *img, const float *beta, float *out,
+                   size_t lds, hipStream_t s) {
+  const int H = pl->H, W = pl->W, C = pl->C, T = pl->T, K = pl->K;
+  if (lds > 64 * 1024) {
+    int dev = 0, max_lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return TSIM_EDEVICE;
+    if (lds > size_t(max_lds)) return TSIM_EUNSUPPORTED;
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_render_fp32<KP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+      return TSIM_EDEVICE;
+  }
+  dim3 grid((W + kTile - 1) / kTile, (H + kTile - 1) / kTile, frames);
+  hipLaunchKernelGGL(k_render_fp32<KP>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
 int launch_render_fp32(const tsim_plan *pl, int frames, const float *img, const float *beta,
                        float *out, hipStream_t s) {
-  const int H = pl->H, W = pl->W, C = pl->C, T = pl->T, K = pl->K;
-  const int S = kTile + T - 1;
-  size_t lds = size_t(C) * S * S * sizeof(float);
-  if (lds > 64 * 1024) return TSIM_EUNSUPPORTED;
-  dim3 grid((W + kTile - 1) / kTile, (H + kTile - 1) / kTile, frames);
-  const int KP = pl->KP;
+  const int S = kTile + pl->T - 1;
+  const size_t lds = size_t(pl->C) * S * S * sizeof(float);
   TraceScope tr("k_render_fp32", s);
-  if (KP == 32)
-    hipLaunchKernelGGL(k_render_fp32<32>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
-  else if (KP == 64)
-    hipLaunchKernelGGL(k_render_fp32<64>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
-  else if (KP == 112)
-    hipLaunchKernelGGL(k_render_fp32<112>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
-  else
-    hipLaunchKernelGGL(k_render_fp32<128>, grid, dim3(256), lds, s, img, beta, pl->d_basis_t, out, H, W, C, T, K);
-  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+  switch (pl->KP) {
+    case 32: return launch_fp32_kp<32>(pl, frames, img, beta, out, lds, s);
+    case 64: return launch_fp32_kp<64>(pl, frames, img, beta, out, lds, s);
+    case 112: return launch_fp32_kp<112>(pl, frames, img, beta, out, lds, s);
+    default: return launch_fp32_kp<128>(pl, frames, img, beta, out, lds, s);
+  }
 }
 
 int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,

@@ -489,6 +489,32 @@ int launch_ks_tc(const tsim_plan *pl, int frames, const float *img, const uint16
     return TSIM_EUNSUPPORTED;
 }
 
+// Whether one of the block heights above fits the LDS for this shape.
+template <int KS, int T, int C>
+constexpr bool bf16_shape_fits() {
+  constexpr int KP = KS * 16;
+  return (T == 65 && !kWide<KS, T, C> && PairGeom<T, 16, KP, C>::kFits) || PairGeom<T, 8, KP, C>::kFits ||
+         PairGeom<T, 4, KP, C>::kFits;
+}
+
+template <int KS, int T>
+constexpr bool bf16_fits_c(int C) {
+  return C == 1 ? bf16_shape_fits<KS, T, 1>()
+       : C == 2 ? bf16_shape_fits<KS, T, 2>()
+       : C == 3 ? bf16_shape_fits<KS, T, 3>()
+       : C == 4 ? bf16_shape_fits<KS, T, 4>()
+                : false;
+}
+
+template <int KS>
+constexpr bool bf16_fits_tc(int T, int C) {
+  return T == 65 ? bf16_fits_c<KS, 65>(C)
+       : T == 33 ? bf16_fits_c<KS, 33>(C)
+       : T == 21 ? bf16_fits_c<KS, 21>(C)
+       : T == 15 ? bf16_fits_c<KS, 15>(C)
+                 : false;
+}
+
 template <int KS, int T>
 int launch_ks_t(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta, float *out,
                 hipStream_t s) {
@@ -544,5 +570,15 @@ int launch_render_bf16(const tsim_plan *pl, int frames, const float *img, const 
     case 112: return launch_ks<7>(pl, frames, img, beta, out, s);
     case 128: return launch_ks<8>(pl, frames, img, beta, out, s);
     default: return TSIM_EUNSUPPORTED;
+  }
+}
+
+bool render_bf16_supported(int KP, int T, int C) {
+  switch (KP) {
+    case 32: return bf16_fits_tc<2>(T, C);
+    case 64: return bf16_fits_tc<4>(T, C);
+    case 112: return bf16_fits_tc<7>(T, C);
+    case 128: return bf16_fits_tc<8>(T, C);
+    default: return false;
   }
 }

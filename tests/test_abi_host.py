@@ -49,6 +49,46 @@ def test_invalid_parameters_rejected(t, field, value):
     assert e.value.status == t.EINVAL
 
 
+@pytest.mark.parametrize("P,T,C,K,precision", [
+    (64, 17, 1, 100, 0),     # no exact-PSF kernel for this support
+    (128, 31, 1, 100, 0),
+    (64, 9, 1, 100, 1),      # BF16 blur: T in {15, 21, 33, 65} only
+    (128, 65, 4, 120, 1),    # BF16 blur: image tile + basis staging exceed the LDS
+])
+def test_unbuilt_kernel_shapes_rejected_at_plan_creation(t, P, T, C, K, precision):
+    """A plan whose exact-PSF or BF16-blur shape has no kernel is refused
+    when it is made, not when a later call would launch it."""
+    p = t.make_params(64, 64, C, 128, 128, pupil_n=P, psf_t=T, basis_k=K, precision=precision)
+    with pytest.raises(t.TsimError) as e:
+        t.host_tables(p, 0)
+    assert e.value.status == t.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("P,T,C,K,precision", [
+    (128, 65, 4, 120, 0),    # FP32: the vector-ALU blur takes any shape
+    (128, 65, 4, 112, 1),
+    (64, 15, 4, 128, 1),
+    (64, 9, 2, 10, 0),
+])
+def test_built_kernel_shapes_accepted(t, P, T, C, K, precision):
+    p = t.make_params(64, 64, C, 128, 128, pupil_n=P, psf_t=T, basis_k=K, precision=precision)
+    assert t.host_tables(p, 3) == 0.125
+
+
+def test_last_error_names_the_failing_call(t):
+    t.last_error()                                  # clear
+    p = t.make_params(64, 64, 1, 128, 128)
+    p.C = 0
+    with pytest.raises(t.TsimError):
+        t.host_tables(p, 0)
+    st, msg = t.last_error()
+    assert st == t.EINVAL and msg == "tsim_host_tables: invalid argument"
+    assert t.last_error() == (0, "")                # reading clears it
+    p.C = 1
+    t.host_tables(p, 3)                             # a successful call leaves it clear
+    assert t.last_error() == (0, "")
+
+
 def test_grid_smaller_than_image_rejected(t):
     p = t.make_params(200, 64, 1, 128, 128)
     with pytest.raises(t.TsimError):

@@ -9,11 +9,12 @@ chunk seams, seeded random pixels); the sampler, whose full-size oracle needs
 the 4096^2 spectra of every mode, is checked at its full transform lengths
 on slim grids and at full size through properties that hold at any size.
 
-Tolerances as for the 512^2 workload: FP32 paths <= 1e-5 relative L2 (the
-65 x 65 crop adds a 4225-term projection and 64-point transforms, still a few
+Tolerances as for the 512^2 workload: FP32 paths <= 1e-5 in both relative
+L2 and largest element error over the largest reference magnitude (the 65 x
+65 crop adds a 4225-term projection and 64-point transforms, still a few
 dozen roundings deep); BF16 paths as in the learned-form tests (network
-outputs <= 2e-3 against the BF16-mirrored oracle, the BF16 blur <= 1e-5 on
-exactly rounded operands).
+outputs <= 2e-3 relative L2 and <= 1e-2 largest element error against the
+BF16-mirrored oracle, the BF16 blur <= 1e-5 on exactly rounded operands).
 """
 import os
 import sys
@@ -31,6 +32,7 @@ from oracle import sampler as osamp  # noqa: E402
 from oracle import spectra as ospec  # noqa: E402
 from oracle import zernike as ozern  # noqa: E402
 import synthetic  # noqa: E402
+from parity import err, maxrel, rel  # noqa: E402
 
 TOL = 1e-5
 H4, W4, G4 = 2160, 3840, 4096
@@ -41,10 +43,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.fixture(scope="module")
@@ -104,7 +102,7 @@ def test_psf128_matches_oracle(t, T):
     torch.cuda.synchronize()
     got = out.cpu().numpy().reshape(120, T, T)
     ref = opsf.psf_batch(A.astype(np.float32).astype(np.float64), 128, T)
-    errs = [rel(got[i], ref[i]) for i in range(120)]
+    errs = [err(got[i], ref[i]) for i in range(120)]
     assert max(errs) < TOL, (int(np.argmax(errs)), max(errs))
     np.testing.assert_allclose(got.sum(axis=(1, 2)), 1.0, atol=1e-5)
 
@@ -118,7 +116,7 @@ def test_p2s_exact_p128_small(t, basis65):
     plan.p2s(torch.tensor(z32[None], device="cuda"), beta, plan.workspace(1))
     torch.cuda.synchronize()
     ref = opsf.psf_field(z32.astype(np.float64), 128, 65, basis65)
-    assert rel(beta.cpu().numpy()[0], ref) < TOL
+    assert err(beta.cpu().numpy()[0], ref) < TOL
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
@@ -145,7 +143,7 @@ def test_render_t65_small(t, basis65, precision):
     got = out.cpu().numpy()[0]
     for c in range(C):
         ref = orender.render_basis(img[0, c].astype(np.float64), br, Pr, 65)
-        assert rel(got[c], ref) < TOL, c
+        assert err(got[c], ref) < TOL, (c, rel(got[c], ref), maxrel(got[c], ref))
 
 
 @pytest.mark.parametrize("H,W,Gh,Gw", [
@@ -161,7 +159,7 @@ def test_sampler_full_length_transforms(t, H, W, Gh, Gw):
     got = zern.cpu().numpy()[0]
     ref = osamp.sample_zernike(H, W, Gh, Gw, 0.125, 3.0, 17, 4,
                                spectra=ospec.all_spectra(Gh, Gw, 0.125, 2))
-    errs = [rel(got[j], ref[j]) for j in range(35)]
+    errs = [err(got[j], ref[j]) for j in range(35)]
     assert max(errs) < TOL, (int(np.argmax(errs)), max(errs))
 
 
@@ -226,7 +224,7 @@ def test_sampler_4k_subharmonics(t):
         a0 = z0[0, t_].index_select(0, idx).double().cpu().numpy()
         a3 = z3[0, t_].index_select(0, idx).double().cpu().numpy()
         w = (a3 - rho * a0) / (sc * L[t_, t_])
-        assert rel(w, waves[t_]) < 1e-4, (t_, rel(w, waves[t_]))
+        assert err(w, waves[t_]) < 1e-4, (t_, rel(w, waves[t_]), maxrel(w, waves[t_]))
 
 
 def test_p2s_exact_4k_sampled_pixels(t, basis65):
@@ -242,7 +240,7 @@ def test_p2s_exact_4k_sampled_pixels(t, basis65):
     got = beta[0, ys, xs].cpu().numpy()
     a = table[idx[ys, xs]].astype(np.float32).astype(np.float64)
     ref = opsf.project(opsf.psf_batch(a, 128, 65), basis65)
-    assert rel(got, ref) < TOL
+    assert err(got, ref) < TOL, (rel(got, ref), maxrel(got, ref))
 
 
 def _random_net(t, net, seed):
@@ -282,7 +280,9 @@ def test_p2s_learned_4k_sampled_pixels(t, basis65):
     y, _ = omlp.forward(params, omlp.to_bf16(a * inv.astype(np.float64)), bf16=True)
     ref = omlp.to_bf16(0.3 * y + mu.astype(np.float64))
     assert np.all(got[:, 100:] == 0)
+    say(f"  rel {rel(got[:, :100], ref):.2e} maxrel {maxrel(got[:, :100], ref):.2e}")
     assert rel(got[:, :100], ref) < 2e-3
+    assert maxrel(got[:, :100], ref) < 1e-2
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
@@ -313,7 +313,7 @@ def test_render_4k_sampled_pixels(t, basis65, precision):
         bpx, Psi = omlp.to_bf16(bpx), omlp.to_bf16(basis65)
     for c in range(3):
         ref = orender.render_at(img[c].astype(np.float64), bpx, Psi, 65, ys, xs)
-        assert rel(got[c], ref) < TOL, c
+        assert err(got[c], ref) < TOL, (c, rel(got[c], ref), maxrel(got[c], ref))
 
 
 def test_warp_4k_sampled_pixels(t):
@@ -331,4 +331,4 @@ def test_warp_4k_sampled_pixels(t):
     tx, ty = orender.tilt_shift(tilt[:, ys, xs].astype(np.float64))
     for c in range(3):
         ref = orender.warp_at(img[c].astype(np.float64), tx, ty, ys, xs)
-        assert rel(got[c], ref) < TOL, c
+        assert err(got[c], ref) < TOL, (c, rel(got[c], ref), maxrel(got[c], ref))

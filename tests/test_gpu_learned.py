@@ -6,8 +6,11 @@ Tolerances: the oracle rounds every GEMM operand to bfloat16 at the same
 points as the kernels, so the remaining differences come from FP32 versus
 FP64 accumulation (~1e-6 relative) and from the rare elements where that
 difference flips a bfloat16 rounding (one unit, 2^-8, in a small fraction
-of elements): relative L2 <= 1e-3 for gradients and network outputs.  The
-BF16 blur accumulates in FP32 on exactly rounded operands: <= 1e-5.
+of elements): relative L2 <= 1e-3 for gradients and <= 2e-3 for network
+outputs (which are themselves rounded to bfloat16), and the largest element
+error over the largest reference magnitude <= 1e-2 (one bfloat16 unit of the
+largest output is 2^-8 of it).  The BF16 blur accumulates in FP32 on exactly
+rounded operands: <= 1e-5 in both measures.
 """
 import sys
 
@@ -22,6 +25,7 @@ from oracle import psf as opsf  # noqa: E402
 from oracle import render as orender  # noqa: E402
 from oracle import philox  # noqa: E402
 import synthetic  # noqa: E402
+from parity import err, maxrel, rel  # noqa: E402
 
 
 def say(*a):
@@ -29,10 +33,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.fixture(scope="module")
@@ -67,23 +67,29 @@ def _inv_s(seed):
     return v.astype(np.float32)
 
 
-def test_mlp_gradients_match_bf16_mirror(t):
-    say("mlp gradients B=192 K=24")
+@pytest.mark.parametrize("B", [192, 2048])
+def test_mlp_gradients_match_bf16_mirror(t, B):
+    """B = 192 reduces each weight gradient in one block per tile; B = 2048
+    splits the batch over 8 blocks per tile (the split-K path of training
+    batches), whose partial products are added in a fixed order."""
+    say(f"mlp gradients B={B} K=24")
     plan = t.Plan(32, 32, 1, 64, 64, basis_k=24)
-    net = t.Mlp(plan, batch=192, seed=1)
+    net = t.Mlp(plan, batch=B, seed=1)
     params = _random_net(t, net, 100)
     inv = _inv_s(7)
     net.set(2, inv)
-    z = synthetic.random_coefficients((192, 35), 0.7, 3)
-    tgt = synthetic.random_coefficients((192, 24), 1.0, 4)
+    z = synthetic.random_coefficients((B, 35), 0.7, 3)
+    tgt = synthetic.random_coefficients((B, 24), 1.0, 4)
     loss = net.grad(torch.tensor(z, device="cuda"), torch.tensor(tgt, device="cuda"))
     g = net.unpack(net.get(1))
     x = omlp.to_bf16(z.astype(np.float64) * inv.astype(np.float64))
     ref_loss, ref = omlp.loss_and_grads(params, x, tgt.astype(np.float64), bf16=True)
     assert abs(loss - ref_loss) / ref_loss < 1e-4
     for l in range(4):
-        assert rel(g[l][0], ref[l][0]) < 1e-3, ("dW", l, rel(g[l][0], ref[l][0]))
-        assert rel(g[l][1], ref[l][1]) < 1e-3, ("db", l, rel(g[l][1], ref[l][1]))
+        for k, name in ((0, "dW"), (1, "db")):
+            say(f"  {name}{l}: rel {rel(g[l][k], ref[l][k]):.2e} maxrel {maxrel(g[l][k], ref[l][k]):.2e}")
+            assert rel(g[l][k], ref[l][k]) < 1e-3, (name, l, rel(g[l][k], ref[l][k]))
+            assert maxrel(g[l][k], ref[l][k]) < 1e-2, (name, l, maxrel(g[l][k], ref[l][k]))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
@@ -114,7 +120,9 @@ def test_mlp_inference_matches_bf16_mirror(t, basis, precision):
     if precision == "bf16":
         ref = omlp.to_bf16(ref)
         assert np.all(got[:, 100:] == 0)
+    say(f"  rel {rel(got[:, :100], ref):.2e} maxrel {maxrel(got[:, :100], ref):.2e}")
     assert rel(got[:, :100], ref) < 2e-3
+    assert maxrel(got[:, :100], ref) < 1e-2
 
 
 def test_render_bf16_matches_eq8_on_rounded_operands(t, basis):
@@ -135,7 +143,7 @@ def test_render_bf16_matches_eq8_on_rounded_operands(t, basis):
     Pr = omlp.to_bf16(basis)
     for c in range(C):
         ref = orender.render_basis(img[0, c].astype(np.float64), br, Pr, 33)
-        assert rel(got[c], ref) < 1e-5, c
+        assert err(got[c], ref) < 1e-5, (c, rel(got[c], ref), maxrel(got[c], ref))
 
 
 @pytest.mark.parametrize("T,C,K,H,W", [(15, 1, 20, 19, 37), (21, 2, 60, 24, 33), (33, 4, 120, 17, 48),
@@ -163,26 +171,22 @@ def test_render_bf16_kernel_shapes(t, T, C, K, H, W):
     br, Pr = omlp.to_bf16(b[0].astype(np.float64)), omlp.to_bf16(Psi)
     for c in range(C):
         ref = orender.render_basis(img[0, c].astype(np.float64), br, Pr, T)
-        assert rel(got[c], ref) < 1e-5, c
+        assert err(got[c], ref) < 1e-5, (c, rel(got[c], ref), maxrel(got[c], ref))
 
 
 def test_render_bf16_unsupported_shape_is_rejected(t):
     """The one BF16 shape whose image tile and basis staging exceed the LDS
-    (K > 112, C = 4, T = 65) returns TSIM_EUNSUPPORTED before any launch and
-    leaves the output untouched."""
+    (K > 112, C = 4, T = 65) is refused at plan creation, with the call
+    named by tsim_last_error."""
     say("render bf16 K=120 C=4 T=65: rejected")
     H, W, C, K, T = 20, 24, 4, 120, 65
     rng = np.random.default_rng(9)
     Psi = np.linalg.qr(rng.standard_normal((T * T, K)))[0].T.copy()
-    plan = t.Plan(H, W, C, 64, 64, psf_t=T, pupil_n=128, basis=Psi, p2s_mode=t.P2S_LEARNED, precision=t.BF16)
-    img = torch.ones((1, C, H, W), dtype=torch.float32, device="cuda")
-    beta = torch.zeros((1, H, W, 128), dtype=torch.bfloat16, device="cuda")
-    out = torch.full((1, C, H, W), 7.0, dtype=torch.float32, device="cuda")
+    t.last_error()
     with pytest.raises(t.TsimError) as e:
-        plan.render(img, beta, out)
+        t.Plan(H, W, C, 64, 64, psf_t=T, pupil_n=128, basis=Psi, p2s_mode=t.P2S_LEARNED, precision=t.BF16)
     assert e.value.status == t.EUNSUPPORTED
-    torch.cuda.synchronize()
-    assert bool(torch.all(out == 7.0))
+    assert t.last_error() == (t.EUNSUPPORTED, "tsim_plan_create: unsupported configuration")
 
 
 def test_training_pairs_match_oracle(t, basis):
@@ -191,9 +195,9 @@ def test_training_pairs_match_oracle(t, basis):
     z, b = t.make_training_data(plan, 2000, seed=5)
     torch.cuda.synchronize()
     A, _ = opsf.basis_draws(2000, seed=5, tag=philox.TAG_MLP_DATA)
-    assert rel(z.cpu().numpy(), A) < 1e-6
+    assert err(z.cpu().numpy(), A) < 1e-6
     ref = opsf.project(opsf.psf_batch(A.astype(np.float32).astype(np.float64), 64, 33), basis)
-    assert rel(b.cpu().numpy(), ref) < 1e-5
+    assert err(b.cpu().numpy(), ref) < 1e-5
 
 
 def test_training_reduces_loss(t, basis):
@@ -207,3 +211,131 @@ def test_training_reduces_loss(t, basis):
     losses = net.train(z, b, 400, lr_max=2e-3, lr_min=1e-4)
     assert np.all(np.isfinite(losses))
     assert losses[-20:].mean() < 0.2 * losses[:5].mean(), (losses[:5], losses[-5:])
+
+
+def _cosine_lr(i, steps, lr_max, lr_min):
+    prog = i / (steps - 1) if steps > 1 else 1.0
+    return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + np.cos(np.pi * prog))
+
+
+def test_training_steps_match_oracle_adamw(t):
+    """Three AdamW steps of tsim_mlp_train at batch 1024 (split-K weight
+    gradients, 4 blocks per tile) against the oracle: the BF16-mirrored
+    gradients of each batch, then ``oracle.mlp.adamw_step`` at the cosine
+    learning rate of that step.  The parameters are compared as a whole
+    (relative L2 <= 1e-5) and through the updates they received: an update
+    is lr m_hat / (sqrt(v_hat) + eps), of size lr for every gradient not at
+    rounding level, so updates agree to 1e-2 of lr in all but a few
+    elements (those whose gradient is within rounding of zero) and their
+    relative L2 is <= 1e-2.  The losses and AdamW moments agree too."""
+    say("mlp train 3 steps B=1024 vs oracle AdamW")
+    B, K, steps, lr_max, lr_min = 1024, 24, 3, 2e-3, 2e-4
+    plan = t.Plan(32, 32, 1, 64, 64, basis_k=K)
+    net = t.Mlp(plan, batch=B, seed=1)
+    params = _random_net(t, net, 500)
+    p0 = net.get(0).astype(np.float64)
+    inv = _inv_s(17)
+    net.set(2, inv)
+    mu = synthetic.random_coefficients((K,), 0.1, 18)
+    net.set(3, mu)
+    net.set(4, [0.5])
+    z = synthetic.random_coefficients((steps * B, 35), 0.7, 19)
+    tgt = synthetic.random_coefficients((steps * B, K), 1.0, 20)
+    losses = net.train(torch.tensor(z, device="cuda"), torch.tensor(tgt, device="cuda"), steps,
+                       lr_max=lr_max, lr_min=lr_min)
+    got = net.get(0).astype(np.float64)
+    # oracle: same batches, same rounding points, FP64 AdamW
+    x_all = omlp.to_bf16(z.astype(np.float64) * inv.astype(np.float64))
+    t_all = (tgt.astype(np.float64) - mu.astype(np.float32).astype(np.float64)) * np.float64(np.float32(1 / 0.5))
+    state = omlp.init_state(params)
+    cur = params
+    ref_losses = []
+    for i in range(steps):
+        sl = slice(i * B, (i + 1) * B)
+        loss, grads = omlp.loss_and_grads(cur, x_all[sl], t_all[sl], bf16=True)
+        ref_losses.append(loss)
+        cur, state = omlp.adamw_step(cur, grads, state, _cosine_lr(i, steps, lr_max, lr_min))
+    ref = net.pack([(W.astype(np.float32), b.astype(np.float32)) for W, b in cur]).astype(np.float64)
+    # the packed layout's padding stays 0 on both sides
+    ref_exact = np.zeros_like(ref)
+    for l, (W, b) in enumerate(cur):
+        ref_exact[net.off_w[l]:net.off_w[l] + W.size] = W.ravel()
+        ref_exact[net.off_b[l]:net.off_b[l] + b.size] = b
+    say(f"  losses gpu {losses} oracle {np.array(ref_losses)}")
+    np.testing.assert_allclose(losses, ref_losses, rtol=1e-4)
+    assert rel(got, ref_exact) < 1e-5, rel(got, ref_exact)
+    du, dr = got - p0, ref_exact - p0
+    bad = np.abs(du - dr) > 1e-2 * lr_max
+    say(f"  update rel {rel(du, dr):.2e}, elements off by > 1e-2 lr: {int(bad.sum())} of {du.size}")
+    assert rel(du, dr) < 1e-2
+    assert bad.sum() <= max(3, du.size // 20000)
+    m_ref = np.zeros_like(ref_exact)
+    for l, (mW, mb) in enumerate(state[1]):
+        m_ref[net.off_w[l]:net.off_w[l] + mW.size] = mW.ravel()
+        m_ref[net.off_b[l]:net.off_b[l] + mb.size] = mb
+    assert rel(net.get(5), m_ref) < 1e-3
+    np.testing.assert_array_equal(net.get(7), [steps, 0])
+
+
+def test_training_checkpoint_resumes_bit_identically(t):
+    """Six steps in one run versus three steps, a checkpoint (parameters,
+    AdamW moments, step counter, schedule length) restored into a fresh
+    network, and three more: the parameters are bit-identical, because the
+    batches, learning rates and bias corrections follow the step counter and
+    the split-K gradient sums run in a fixed order."""
+    say("mlp checkpoint / resume B=2048")
+    B, K = 2048, 24
+    plan = t.Plan(32, 32, 1, 64, 64, basis_k=K)
+    z = torch.tensor(synthetic.random_coefficients((4 * B, 35), 0.7, 21), device="cuda")
+    tgt = torch.tensor(synthetic.random_coefficients((4 * B, K), 1.0, 22), device="cuda")
+    a = t.Mlp(plan, batch=B, seed=3)
+    a.set(7, [0, 6])
+    a.train(z, tgt, 6, lr_max=2e-3, lr_min=1e-4)
+    b = t.Mlp(plan, batch=B, seed=3)
+    b.set(7, [0, 6])
+    b.train(z, tgt, 3, lr_max=2e-3, lr_min=1e-4)
+    ck = b.checkpoint()
+    b.close()
+    c = t.Mlp(plan, batch=B, seed=99)          # different initialisation, overwritten
+    c.restore(ck)
+    c.train(z, tgt, 3, lr_max=2e-3, lr_min=1e-4)
+    np.testing.assert_array_equal(c.get(0), a.get(0))
+    np.testing.assert_array_equal(c.get(5), a.get(5))
+    np.testing.assert_array_equal(c.get(7), [6, 6])
+    # and a repeat of the whole run is bit-identical
+    d = t.Mlp(plan, batch=B, seed=3)
+    d.set(7, [0, 6])
+    d.train(z, tgt, 6, lr_max=2e-3, lr_min=1e-4)
+    np.testing.assert_array_equal(d.get(0), a.get(0))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_learned_plan_without_network_falls_back_to_exact(t, basis, precision):
+    """A learned plan that holds no network runs the exact path (Eq. (2)
+    PSFs projected by Eq. (7)), says so through tsim_p2s_form, and writes
+    the plan's weight layout: float32 [F][H][W][K], or bfloat16 [F][H][W][KP]
+    with zero padding, each weight the FP32 projection rounded once."""
+    say(f"learned plan without network: exact fallback ({precision})")
+    H, W = 24, 40
+    bf = precision == "bf16"
+    plan = t.Plan(H, W, 1, 64, 64, basis=basis, p2s_mode=t.P2S_LEARNED,
+                  precision=t.BF16 if bf else t.FP32)
+    assert plan.p2s_form() == t.P2S_EXACT
+    z32 = synthetic.random_coefficients((1, 35, H, W), 0.5, 23)
+    KB = 112 if bf else 100
+    beta = torch.zeros((1, H, W, KB), dtype=torch.bfloat16 if bf else torch.float32, device="cuda")
+    plan.p2s(torch.tensor(z32, device="cuda"), beta, plan.workspace(1))
+    torch.cuda.synchronize()
+    got = beta.float().cpu().numpy()[0]
+    ref = opsf.psf_field(z32[0].astype(np.float64), 64, 33, basis)
+    if bf:
+        assert np.all(got[..., 100:] == 0)
+        got = got[..., :100]
+        # round to nearest bfloat16: within half a unit (2^-9 relative) of
+        # the FP32 value, itself within 1e-5 of the oracle
+        assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+    else:
+        assert err(got, ref) < 1e-5
+    net = t.Mlp(plan, batch=64, seed=5)
+    t.plan_set_mlp(plan, net)
+    assert plan.p2s_form() == t.P2S_LEARNED

@@ -1,8 +1,9 @@
 """GPU parity: every hot-path call through the C ABI against the FP64 oracle
 on the same seeded inputs.
 
-Bar (FP32 paths): relative L2 error ||gpu - oracle|| / ||oracle|| <= 1e-5 per
-coefficient plane, per PSF batch, per weight array and per image; the FP32
+Bar (FP32 paths): per coefficient plane, PSF, weight array and image, both
+the relative L2 error ||gpu - oracle|| / ||oracle|| and the largest element
+error max|gpu - oracle| / max|oracle| are <= 1e-5 (``parity.err``); the FP32
 kernels accumulate a few dozen rounding steps (two FFT passes, a 33-term
 phase sum, 1089-term projections), each ~6e-8 relative.
 """
@@ -22,6 +23,7 @@ from oracle import sampler as osamp  # noqa: E402
 from oracle import spectra as ospec  # noqa: E402
 from oracle import zernike as ozern  # noqa: E402
 import synthetic  # noqa: E402
+from parity import err  # noqa: E402
 
 TOL = 1e-5
 
@@ -31,10 +33,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-def rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.fixture(scope="module")
@@ -89,7 +87,7 @@ def test_sampler_matches_oracle(t, H, W, Gh, Gw, seed, frame0, dr):
     for f in range(frames):
         ref = osamp.sample_zernike(H, W, Gh, Gw, 0.125, [dr, 0.5 * dr][f], seed, frame0 + f,
                                    spectra=S, L=L)
-        errs = [rel(zern[f, j], ref[j]) for j in range(35)]
+        errs = [err(zern[f, j], ref[j]) for j in range(35)]
         assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
 
 
@@ -113,7 +111,7 @@ def test_sampler_subharmonics_match_oracle(t, H, W, Gh, Gw, levels, seed, frame0
     for f in range(2):
         ref = osamp.sample_zernike(H, W, Gh, Gw, 0.125, drs[f], seed, frame0 + f, spectra=S, L=L,
                                    subharmonic_levels=levels)
-        errs = [rel(zern[f, j], ref[j]) for j in range(35)]
+        errs = [err(zern[f, j], ref[j]) for j in range(35)]
         assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
 
 
@@ -130,7 +128,7 @@ def test_sampler_ar_with_subharmonics_matches_oracle(t):
     torch.cuda.synchronize()
     got = zern.cpu().numpy()
     for f in range(4):
-        errs = [rel(got[f, j], ref[f, j]) for j in range(35)]
+        errs = [err(got[f, j], ref[f, j]) for j in range(35)]
         assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
 
 
@@ -142,7 +140,7 @@ def test_sampler_full_size_frame(t):
     plan = t.Plan(H, W, 3, 1024, 1024, pixel_pitch_over_d=0.125)
     zern = _sample(t, plan, [2.0, 4.0], 0, 0, 2).cpu().numpy()
     ref = osamp.sample_zernike(H, W, 1024, 1024, 0.125, 4.0, 0, 1)
-    errs = [rel(zern[1, j], ref[j]) for j in range(35)]
+    errs = [err(zern[1, j], ref[j]) for j in range(35)]
     assert max(errs) < TOL, max(errs)
 
 
@@ -163,7 +161,7 @@ def test_psf_exact_matches_oracle(t):
     torch.cuda.synchronize()
     got = out.cpu().numpy().reshape(300, 33, 33)
     ref = opsf.psf_batch(A.astype(np.float32).astype(np.float64), 64, 33)
-    errs = [rel(got[i], ref[i]) for i in range(300)]
+    errs = [err(got[i], ref[i]) for i in range(300)]
     assert max(errs) < TOL, (int(np.argmax(errs)), max(errs))
     np.testing.assert_allclose(got.sum(axis=(1, 2)), 1.0, atol=1e-5)
 
@@ -178,7 +176,7 @@ def test_psf_exact_smaller_crops(t, T):
     torch.cuda.synchronize()
     got = out.cpu().numpy().reshape(40, T, T)
     ref = opsf.psf_batch(A.astype(np.float32).astype(np.float64), 64, T)
-    assert max(rel(got[i], ref[i]) for i in range(40)) < TOL
+    assert max(err(got[i], ref[i]) for i in range(40)) < TOL
 
 
 def test_p2s_exact_matches_oracle(t, basis33):
@@ -195,7 +193,7 @@ def test_p2s_exact_matches_oracle(t, basis33):
     got = beta.cpu().numpy()
     for f in range(2):
         ref = opsf.psf_field(z[f], 64, 33, basis33)
-        assert rel(got[f], ref) < TOL, f
+        assert err(got[f], ref) < TOL, f
 
 
 def test_render_matches_oracle(t, basis33):
@@ -213,7 +211,7 @@ def test_render_matches_oracle(t, basis33):
     for c in range(C):
         ref = orender.render_basis(img[0, c].astype(np.float64), beta[0].astype(np.float64),
                                    basis33, 33)
-        assert rel(got[c], ref) < TOL, c
+        assert err(got[c], ref) < TOL, c
 
 
 @pytest.mark.parametrize("F,H,W,C", [
@@ -236,7 +234,7 @@ def test_warp_matches_oracle(t, F, H, W, C):
         tx, ty = orender.tilt_shift(zern[f].astype(np.float64))
         for c in range(C):
             ref = orender.warp(img[f, c].astype(np.float64), tx, ty)
-            assert rel(got[f, c], ref) < TOL, (f, c)
+            assert err(got[f, c], ref) < TOL, (f, c)
 
 
 def test_end_to_end_small_workload(t, basis33):
@@ -258,8 +256,8 @@ def test_end_to_end_small_workload(t, basis33):
     zr = osamp.sample_zernike(H, W, 128, 128, 0.125, 2.0, 0, 0)
     br = opsf.psf_field(zr, 64, 33, basis33)
     ref = orender.render_frame(img[0].astype(np.float64), zr, br, basis33, 33)
-    assert rel(zern.cpu().numpy()[0], zr) < TOL
-    assert rel(out.cpu().numpy()[0], ref) < TOL
+    assert err(zern.cpu().numpy()[0], zr) < TOL
+    assert err(out.cpu().numpy()[0], ref) < TOL
 
 
 def test_argument_errors(t, basis33):
@@ -347,7 +345,7 @@ def test_sampler_ar_matches_oracle(t):
     torch.cuda.synchronize()
     got = zern.cpu().numpy()
     for f in range(5):
-        errs = [rel(got[f, j], ref[f, j]) for j in range(35)]
+        errs = [err(got[f, j], ref[f, j]) for j in range(35)]
         assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
     drs2 = [1.5, 3.0, 2.0]
     ref2, _ = osamp.sample_sequence_ar(H, W, G, G, 0.125, drs2, 7, 25, 0.9, y_prev=ylast, spectra=S, L=L)
@@ -357,7 +355,7 @@ def test_sampler_ar_matches_oracle(t):
     torch.cuda.synchronize()
     got2 = zern2.cpu().numpy()
     for f in range(3):
-        errs = [rel(got2[f, j], ref2[f, j]) for j in range(35)]
+        errs = [err(got2[f, j], ref2[f, j]) for j in range(35)]
         assert max(errs) < TOL, (f, int(np.argmax(errs)), max(errs))
     with pytest.raises(t.TsimError) as e:
         plan.sample_zernike_ar(drs2, 7, 25, 1.5, zern2, ws)
@@ -379,4 +377,57 @@ def test_p2s_exact_k120_matches_oracle(t):
     plan.p2s(torch.tensor(z32[None], device="cuda"), beta, plan.workspace(1))
     torch.cuda.synchronize()
     ref = opsf.psf_field(z32.astype(np.float64), 64, 33, Psi)
-    assert rel(beta.cpu().numpy()[0], ref) < TOL
+    assert err(beta.cpu().numpy()[0], ref) < TOL
+
+
+def test_binding_rejects_mismatched_buffers(t, basis33):
+    """The binding checks every buffer's shape, element type, device and
+    size against the plan before calling the library (the C ABI cannot see
+    extents): each mismatch raises ValueError and launches nothing."""
+    say("binding buffer checks")
+    H, W, C = 32, 48, 2
+    dev = torch.device("cuda")
+    plan = t.Plan(H, W, C, 64, 64, basis=basis33, psf_t=33)
+    bplan = t.Plan(H, W, C, 64, 64, basis=basis33, psf_t=33, p2s_mode=t.P2S_LEARNED, precision=t.BF16)
+    z = torch.zeros((2, 35, H, W), device=dev)
+    img = torch.zeros((2, C, H, W), device=dev)
+    out = torch.empty_like(img)
+    beta = torch.zeros((2, H, W, 100), device=dev)
+    ws = plan.workspace(2)
+    bad = [
+        lambda: plan.sample_zernike([1.0, 2.0], 0, 0, z[:, :34].contiguous(), ws),        # 34 planes
+        lambda: plan.sample_zernike([1.0, 2.0], 0, 0, z.double(), ws),                    # float64
+        lambda: plan.sample_zernike([1.0, 2.0], 0, 0, z, plan.workspace(1)[:1024]),       # small workspace
+        lambda: plan.sample_zernike([1.0], 0, 0, z, ws),                                  # D/r0 count
+        lambda: plan.p2s(z, beta[:1], ws),                                                # frame count
+        lambda: plan.p2s(z, torch.zeros((2, H, W, 112), device=dev), ws),                 # K
+        lambda: bplan.p2s(z, beta, ws),                                                   # f32 for a BF16 plan
+        lambda: bplan.render(img, torch.zeros((2, H, W, 100), dtype=torch.bfloat16, device=dev), out),  # KP
+        lambda: plan.render(img, beta, out[:1]),                                          # out frames
+        lambda: plan.render(img[:, :1].contiguous(), beta[:, :, :, :], out),              # channels
+        lambda: plan.warp(img, z[:1], out),                                               # zern frames
+        lambda: plan.warp(img.cpu(), z, out),                                             # host tensor
+        lambda: plan.warp(img, z.transpose(2, 3), out),                                   # layout
+        lambda: plan.psf_exact(z[0, 0, :4, :35], torch.empty((4, 33 * 33), device=dev)),  # not contiguous
+        lambda: plan.psf_exact(torch.zeros((4, 35), device=dev), torch.empty((4, 32 * 32), device=dev)),
+    ]
+    out.fill_(3.0)
+    for i, call in enumerate(bad):
+        with pytest.raises(ValueError):
+            call()
+    torch.cuda.synchronize()
+    assert bool(torch.all(out == 3.0))
+
+
+def test_sync_and_last_error_on_device(t):
+    """A failing call on the device path is named by tsim_last_error; a
+    clean stream synchronises with TSIM_OK."""
+    plan = t.Plan(32, 32, 1, 64, 64)
+    z = torch.zeros((1, 35, 32, 32), device="cuda")
+    t.last_error()
+    with pytest.raises(t.TsimError):
+        plan.sample_zernike([-1.0], 0, 0, z, plan.workspace(1))
+    assert t.last_error() == (t.EINVAL, "tsim_sample_zernike: invalid argument")
+    plan.sample_zernike([1.0], 0, 0, z, plan.workspace(1))
+    t.sync()
+    assert t.last_error() == (0, "")
