@@ -231,12 +231,14 @@ __global__ void k_scale(float *__restrict__ v, int n, float s) {
 
 __global__ void k_adamw(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                         float *__restrict__ v, uint16_t *__restrict__ wb, int n, float lr, float b1,
-                        float b2, float c1, float c2, float eps, float wd) {
+                        float omb1, float b2, float omb2, float c1, float c2, float eps, float wd) {
+  // omb1 = 1 - beta1 and omb2 = 1 - beta2 come rounded once from double:
+  // 1.f - float(0.999) would be 1.3e-5 away from 0.001
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
   m[i] = mi;
   v[i] = vi;
   const float mh = mi / c1, vh = vi / c2;
@@ -631,7 +633,8 @@ int mlp_create_impl(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **ou
     mlp_free(n);
     return TSIM_ENOMEM;
   }
-  if (hipMemset(n->w, 0, off * 4) != hipSuccess || hipMemset(n->m, 0, off * 4) != hipSuccess ||
+  if (hipMemset(n->w, 0, off * 4) != hipSuccess || hipMemset(n->g, 0, off * 4) != hipSuccess ||
+      hipMemset(n->m, 0, off * 4) != hipSuccess ||
       hipMemset(n->v, 0, off * 4) != hipSuccess || hipMemset(n->wb, 0, off * 2) != hipSuccess ||
       hipMemset(n->mu, 0, 128 * 4) != hipSuccess || hipMemset(n->loss, 0, (1 << 20) * 4) != hipSuccess) {
     mlp_free(n);
@@ -840,8 +843,9 @@ int mlp_train_impl(tsim_mlp *n, const float *zvec, const float *target, int n_pa
     const float lr = float(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + std::cos(3.14159265358979 * prog)));
     const double t = double(tg + 1);
     hipLaunchKernelGGL(k_adamw, dim3(int((n->n_par + 255) / 256)), dim3(256), 0, s, n->w, n->g, n->m,
-                       n->v, n->wb, int(n->n_par), lr, float(b1), float(b2),
-                       float(1.0 - std::pow(b1, t)), float(1.0 - std::pow(b2, t)), 1e-8f, 0.0f);
+                       n->v, n->wb, int(n->n_par), lr, float(b1), float(1.0 - b1), float(b2),
+                       float(1.0 - b2), float(1.0 - std::pow(b1, t)), float(1.0 - std::pow(b2, t)), 1e-8f,
+                       0.0f);
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
     ++n->t_done;
   }
