@@ -165,6 +165,27 @@ int tsim_sample_zernike(const tsim_plan *plan, int frames, const float *d_over_r
                         uint64_t seed, uint64_t frame0, float *zern, void *ws,
                         tsim_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fields as tsim_sample_zernike, bit for bit, with no workspace argument and
+ * no allocation of any kind.  The pass-1 intermediate lives in a fixed
+ * device array of the library, TSIM_NOALLOC_SCRATCH_BYTES (256 MiB) on each
+ * GPU the library runs on, held until the process ends; its address is
+ * looked up at plan creation.  Frames are processed in chunks that fit it.
+ *   Limit: one frame's intermediate, 18 * H * Gw * 8 bytes, must fit the
+ *   array (e.g. 768 x 1024 on a 2048-wide grid fits, 2160 x 3840 on 4096
+ *   does not): larger plans return TSIM_EUNSUPPORTED before any launch.
+ *   Every call on one GPU shares that GPU's array, so calls that overlap in
+ *   time on one GPU (other threads, other streams without ordering) race;
+ *   calls on one stream are ordered and safe.  The array's contents from
+ *   the previous call are never read.  Launches are not traced.
+ *   d_over_r0 : host [frames], each > 0 and finite
+ *   zern      : device [frames][35][H][W] float32, output, 256-byte aligned */
+#define TSIM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int tsim_sample_zernike_noalloc(const tsim_plan *plan, int frames, const float *d_over_r0,
+                                uint64_t seed, uint64_t frame0, float *zern,
+                                tsim_stream stream);
+
 /* Spatial tilt statistics of coefficient planes (the spatial validation of
  * Sec. IV-B): for Noll 2 and 3, the tilt correlation (mean product) and the
  * differential tilt variance (mean squared difference) of all pixel pairs at

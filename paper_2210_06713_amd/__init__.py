@@ -57,6 +57,8 @@ _lib_ws = _sig("tsim_workspace_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_siz
 _lib_table = _sig("tsim_plan_table", _i, [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
 _lib_sample = _sig("tsim_sample_zernike", _i,
                    [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64, _vp, _vp, _vp])
+_lib_sample_noalloc = _sig("tsim_sample_zernike_noalloc", _i,
+                           [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64, _vp, _vp])
 _lib_sample_ar = _sig("tsim_sample_zernike_ar", _i, [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64,
                                                      ctypes.c_float, _vp, ctypes.c_float, _vp, _vp, _vp])
 _lib_stats_ws = _sig("tsim_tilt_stats_ws_bytes", _i, [_vp, _i, _i, ctypes.POINTER(ctypes.c_size_t)])
@@ -105,7 +107,7 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_mlp_data_ws_bytes", "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp",
             "tsim_mlp_fit_output", "tsim_mlp_predict", "tsim_tilt_stats_ws_bytes", "tsim_tilt_stats",
             "tsim_structure_function_ws_bytes", "tsim_structure_function", "tsim_p2s_form",
-            "tsim_last_error", "tsim_sync"]
+            "tsim_last_error", "tsim_sync", "tsim_sample_zernike_noalloc"]
 
 
 def last_error():
@@ -333,6 +335,17 @@ class Plan:
         _check(_lib_sample(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                            int(seed), int(frame0), _ptr(zern), _ptr(ws), _stream(stream)),
                "tsim_sample_zernike")
+
+    def sample_zernike_noalloc(self, d_over_r0, seed, frame0, zern, stream=None):
+        """tsim_sample_zernike without a workspace and without any allocation
+        (the library's fixed scratch array holds the intermediate)."""
+        d = np.ascontiguousarray(np.atleast_1d(d_over_r0), dtype=np.float32)
+        frames, _ = self._zern(zern)
+        if d.size != frames:
+            raise ValueError("one D/r0 per frame expected")
+        _check(_lib_sample_noalloc(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   int(seed), int(frame0), _ptr(zern), _stream(stream)),
+               "tsim_sample_zernike_noalloc")
 
     def sample_zernike_ar(self, d_over_r0, seed, frame0, alpha, zern, ws, zern_prev=None,
                           d_over_r0_prev=0.0, stream=None):

@@ -56,6 +56,16 @@ class TraceScope {
   int slot_;
 };
 
+// Launches on the calling thread are not traced while one is alive (for
+// calls that must create no events).
+class TraceQuiet {
+ public:
+  TraceQuiet();
+  ~TraceQuiet();
+  TraceQuiet(const TraceQuiet &) = delete;
+  TraceQuiet &operator=(const TraceQuiet &) = delete;
+};
+
 // ---- launchers (sampler.hip) ----
 int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
                    uint64_t frame0, float *zern, void *ws, hipStream_t s);
@@ -63,6 +73,10 @@ size_t sampler_ws_bytes(const tsim_plan *pl, int frames);
 int launch_sampler_ar(const tsim_plan *pl, int frames, const float *scale_host, float alpha,
                       const float *zern_prev, float scale_prev, uint64_t seed, uint64_t frame0,
                       float *zern, void *ws, hipStream_t s);
+
+// ---- allocation-free sampling (noalloc.hip): looks up the device address
+// of the library's fixed scratch array for the current device, once ----
+int noalloc_scratch_init();
 
 // ---- launchers (stats.hip) ----
 size_t tilt_stats_ws_bytes(const tsim_plan *pl, int frames, int max_lag);
@@ -112,6 +126,8 @@ int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *
 // ---- status of the C ABI (status.cpp): records a failing call's status
 // and name for tsim_last_error, returns st unchanged ----
 int note_status(const char *fn, int st);
+// a reason for the status the next note_status records (a string literal)
+void note_detail(const char *why);
 
 #define TSIM_HIP_CHECK(expr)                 \
   do {                                       \

@@ -564,6 +564,9 @@ int plan_create_impl(const tsim_params *p, tsim_plan **out) {
         }
     if ((st = upload(&pl->d_basis_k2, bk2.data(), bk2.size())) != TSIM_OK) goto fail;
   }
+  // device address of the allocation-free sampler's scratch array, looked
+  // up now (once per device) so that its calls do no set-up work
+  if ((st = noalloc_scratch_init()) != TSIM_OK) goto fail;
   *out = pl;
   return TSIM_OK;
 fail:

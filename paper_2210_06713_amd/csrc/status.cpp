@@ -10,14 +10,21 @@ namespace {
 
 thread_local int t_status = TSIM_OK;
 thread_local char t_msg[256] = {0};
+thread_local const char *t_detail = nullptr;  // reason given by the failing call, if any
 
 }  // namespace
+
+void note_detail(const char *why) { t_detail = why; }
 
 int note_status(const char *fn, int st) {
   if (st != TSIM_OK) {
     t_status = st;
-    std::snprintf(t_msg, sizeof(t_msg), "%s: %s", fn, tsim_status_string(st));
+    if (t_detail)
+      std::snprintf(t_msg, sizeof(t_msg), "%s: %s (%s)", fn, tsim_status_string(st), t_detail);
+    else
+      std::snprintf(t_msg, sizeof(t_msg), "%s: %s", fn, tsim_status_string(st));
   }
+  t_detail = nullptr;
   return st;
 }
 

@@ -26,6 +26,7 @@ struct Agg {
 
 std::mutex g_mu;
 bool g_on = false;
+thread_local int t_quiet = 0;  // > 0 inside a TraceQuiet scope: launches are not traced
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 std::vector<Agg> g_agg;
@@ -65,7 +66,11 @@ void fold() {
 
 }  // namespace
 
+TraceQuiet::TraceQuiet() { ++t_quiet; }
+TraceQuiet::~TraceQuiet() { --t_quiet; }
+
 TraceScope::TraceScope(const char *name, hipStream_t s) : s_(s), slot_(-1) {
+  if (t_quiet > 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
   Rec r{name, take(), take()};
