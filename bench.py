@@ -28,6 +28,7 @@ PEAK_BF16_TFLOPS = 2500.0
 N_TRAIN = 2_000_000
 N_HELDOUT = 100_000
 TRAIN_BATCH = 8192
+TRAIN_LR = 2e-3
 
 H = W = 512
 C = 3
@@ -154,6 +155,7 @@ def measured_traffic(kernel, launches_per_step):
 # ---- CPU baseline: the FP64 oracle, unchanged, run by a pool of worker
 # processes (one BLAS thread each) over independent pieces of the workload.
 _ORC = {}
+_ORC_PARENT = {}     # the oracle's spectra and mixing matrix, kept for accuracy_vs_oracle
 
 
 def _orc_init(basis_np, spectra_np, L_np):
@@ -214,6 +216,7 @@ def cpu_baseline(frames_sample=3):
         outs = list(ex.map(_orc_render, [(zs[i], full[i], c) for i in range(len(zs)) for c in range(C)]))
         t3 = time.perf_counter()
     assert all(np.isfinite(o).all() for o in outs)
+    _ORC_PARENT.update(S=S, L=L)
     wall = t3 - t0
     px = len(drs) * H * W
     return {"value": round(px / wall / 1e6, 6), "unit": "Mpixel/s", "cores": workers,
@@ -227,56 +230,109 @@ def cpu_baseline(frames_sample=3):
 BATCH_SIZES = ((24, 256, 256, 512, 512), (24, 512, 512, 1024, 1024), (16, 768, 1024, 2048, 2048))
 
 
+ACC_BLOCK = (240, 272, 240, 272)    # rows y0..y1, columns x0..x1 of the compared block
+
+
+def accuracy_vs_oracle(basis, zern_gpu, outs_gpu):
+    """Part of the CPU-baseline leg: the FP64 oracle's fields and output
+    pixels for the first three frames of the timed 512^2 workload (frame
+    counters 0, 1, 2; D/r0 1, 2, 4; seed 0), with the GPU plan's own basis
+    as data, against the GPU's.  Fields: relative L2 error over each whole
+    frame.  Images: PSNR (peak 1) and relative L2 error over a 32 x 32 block
+    of all three channels, for each form in `outs_gpu` ({form: [3][C][H][W]}).
+    The block's blur needs the weights only at the bilinear taps of its
+    pixels, so the oracle computes exact PSFs there alone."""
+    import numpy as np
+    from oracle import psf as opsf, render as orender, sampler as osamp, spectra as ospec, zernike as ozern
+    import synthetic
+    S = _ORC_PARENT.get("S")
+    if S is None:
+        S = ospec.all_spectra(G, G, PITCH, 2)
+    L = _ORC_PARENT.get("L")
+    if L is None:
+        L = ozern.cholesky_lower(ozern.noll_matrix(1.0))
+    y0, y1, x0, x1 = ACC_BLOCK
+    ys, xs = [a.ravel() for a in np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")]
+    img = synthetic.test_image(C, H, W, 16, 0).astype(np.float64)
+    res = {"block": f"rows {y0}..{y1 - 1}, columns {x0}..{x1 - 1}, 3 channels",
+           "frames": "frame counters 0, 1, 2 (D/r0 1, 2, 4), seed 0"}
+    field_err, ref_px = [], []
+    for f, dr in enumerate(DR_CYCLE):
+        z = osamp.mix(osamp.unit_fields(S, H, W, f, 0), L, dr)
+        zg = zern_gpu[f].astype(np.float64)
+        field_err.append(float(np.linalg.norm(zg - z) / np.linalg.norm(z)))
+        tx, ty = orender.tilt_shift(z)
+        taps = set()
+        for y, x in zip(ys, xs):
+            py, px = y - ty[y, x], x - tx[y, x]
+            fy, fx = int(np.floor(py)), int(np.floor(px))
+            for yy in (fy, fy + 1):
+                for xx in (fx, fx + 1):
+                    taps.add((min(max(yy, 0), H - 1), min(max(xx, 0), W - 1)))
+        ty_, tx_ = np.array(sorted(taps)).T
+        beta = opsf.project(opsf.psf_batch(z[:, ty_, tx_].T, P, T), basis)
+        out = np.empty((C, len(ys)))
+        for c in range(C):
+            blur = np.zeros((H, W))
+            blur[ty_, tx_] = orender.render_at(img[c], beta, basis, T, ty_, tx_)
+            out[c] = orender.warp_at(blur, tx[ys, xs], ty[ys, xs], ys, xs)
+        ref_px.append(out)
+    res["field_rel_err_per_frame"] = [float(f"{e:.3g}") for e in field_err]
+    for form, outs in outs_gpu.items():
+        per = []
+        for f in range(len(DR_CYCLE)):
+            got = outs[f][:, ys, xs].astype(np.float64)
+            ref = ref_px[f]
+            mse = float(((got - ref) ** 2).mean())
+            per.append({"d_over_r0": DR_CYCLE[f],
+                        "psnr_db": round(10 * math.log10(1.0 / mse), 2) if mse > 0 else None,
+                        "rel_err": float(f"{np.linalg.norm(got - ref) / np.linalg.norm(ref):.3g}")})
+        res[form] = per
+    return res
+
+
 def batched_graph(tsim, basis, net, steps):
     """Mixed-size batch (24 x 256^2, 24 x 512^2, 16 x 768x1024, 3 channels,
-    per-frame D/r0 ~ U[1, 4]) in the learned BF16 form, captured once into a
-    HIP graph and replayed: whole-batch Mpixel/s."""
+    per-frame D/r0 ~ U[1, 4]) in the learned BF16 form through the library's
+    batch API (tsim_batch_create records every call into one HIP graph,
+    tsim_batch_launch replays it): whole-batch Mpixel/s."""
     import numpy as np
     import torch
     import synthetic
     dev = torch.device("cuda:0")
     kp = 32 if K <= 32 else 64 if K <= 64 else 112 if K <= 112 else 128
-    work = []
+    items, plans = [], []
+    f0 = 0
     for i, (F, Hb, Wb, Gh, Gw) in enumerate(BATCH_SIZES):
         pl = tsim.Plan(Hb, Wb, C, Gh, Gw, pixel_pitch_over_d=PITCH, psf_t=T, pupil_n=P, basis=basis,
                        p2s_mode=tsim.P2S_LEARNED, precision=tsim.BF16)
         tsim.plan_set_mlp(pl, net)
+        plans.append(pl)
         img = torch.tensor(np.repeat(synthetic.test_image(C, Hb, Wb, 16, i)[None], F, 0), device=dev)
-        work.append(dict(pl=pl, F=F, img=img, dr=list(synthetic.d_over_r0_uniform(F, 1.0, 4.0, i)),
-                         zern=torch.empty((F, 35, Hb, Wb), device=dev),
-                         beta=torch.empty((F, Hb, Wb, kp), dtype=torch.bfloat16, device=dev),
-                         blur=torch.empty((F, C, Hb, Wb), device=dev),
-                         out=torch.empty((F, C, Hb, Wb), device=dev), ws=pl.workspace(F)))
-
-    def run_all():
-        for w in work:
-            w["pl"].sample_zernike(w["dr"], 3, 0, w["zern"], w["ws"])
-            w["pl"].p2s(w["zern"], w["beta"], w["ws"])
-            w["pl"].render(w["img"], w["beta"], w["blur"])
-            w["pl"].warp(w["blur"], w["zern"], w["out"])
-
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        run_all()
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        run_all()
-    g.replay()
+        items.append(dict(plan=pl, d_over_r0=list(synthetic.d_over_r0_uniform(F, 1.0, 4.0, i)), frame0=f0,
+                          img=img, zern=torch.empty((F, 35, Hb, Wb), device=dev),
+                          beta=torch.empty((F, Hb, Wb, kp), dtype=torch.bfloat16, device=dev),
+                          blur=torch.empty((F, C, Hb, Wb), device=dev),
+                          out=torch.empty((F, C, Hb, Wb), device=dev), ws=pl.workspace(F)))
+        f0 += F
+    batch = tsim.Batch(items, 3)
+    batch.launch()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
-        g.replay()
+        batch.launch()
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
+    batch.close()
+    for pl in plans:
+        pl.close()
     px = sum(F * Hb * Wb for (F, Hb, Wb, _, _) in BATCH_SIZES)
     return {"workload": "64 frames: 24x256^2 (G=512), 24x512^2 (G=1024), 16x768x1024 (G=2048), "
-                        "3 channels, D/r0 ~ U[1,4], learned BF16 form, one HIP graph",
+                        "3 channels, D/r0 ~ U[1,4], learned BF16 form, one library-built HIP graph "
+                        "(tsim_batch_create / tsim_batch_launch)",
             "value": round(px / (ms * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_batch": round(ms, 3)}
 
 
@@ -353,6 +409,7 @@ class Workload:
             raise RuntimeError("non-finite output")
         chunk(0, 0)              # fixed frames (the first chunk of step 0) for comparing forms
         torch.cuda.synchronize()
+        self.zern_first = self.zern[:min(3, n, frames)].cpu().numpy()
         return ms, rep, self.out[:min(n, frames)].clone()
 
 
@@ -364,21 +421,30 @@ def train_network(tsim, torch, np, plan_l, train_steps):
     net = tsim.Mlp(plan_l, batch=TRAIN_BATCH, seed=0)
     net.fit_output(b_tr)
     t1 = time.perf_counter()
-    losses = net.train(z_tr, b_tr, train_steps, lr_max=1e-3, lr_min=1e-5)
+    losses = net.train(z_tr, b_tr, train_steps, lr_max=TRAIN_LR, lr_min=1e-5)
     train_s = time.perf_counter() - t1
     tsim.plan_set_mlp(plan_l, net)
     del z_tr, b_tr
-    z_te, b_te = tsim.make_training_data(plan_l, N_HELDOUT, seed=2)
-    pred = tsim.mlp_predict(plan_l, z_te)
-    torch.cuda.synchronize()
-    err = (torch.linalg.vector_norm(pred - b_te, dim=1)
-           / torch.linalg.vector_norm(b_te, dim=1)).cpu().numpy()
+
+    def psf_err(z_te, b_te):
+        pred = tsim.mlp_predict(plan_l, z_te)
+        torch.cuda.synchronize()
+        return (torch.linalg.vector_norm(pred - b_te, dim=1)
+                / torch.linalg.vector_norm(b_te, dim=1)).cpu().numpy()
+
+    err = psf_err(*tsim.make_training_data(plan_l, N_HELDOUT, seed=2))
+    # the timed workload's own turbulence strengths
+    at = {str(d): round(float(psf_err(*tsim.make_training_data(plan_l, 20000, seed=3 + i, dr_lo=d,
+                                                                dr_hi=d)).mean()), 5)
+          for i, d in enumerate(DR_CYCLE)}
     info = {"psf_rel_err_mean": round(float(err.mean()), 5),
             "psf_rel_err_median": round(float(np.median(err)), 5),
             "psf_rel_err_p95": round(float(np.percentile(err, 95)), 5),
+            "psf_rel_err_mean_at_d_over_r0": at,
             "psf_err_definition": "||beta_net - beta_exact|| / ||beta_exact|| on 1e5 held-out "
-                                  "pairs (= relative L2 error of the projected PSF)",
-            "train": {"pairs": N_TRAIN, "batch": TRAIN_BATCH, "steps": train_steps,
+                                  "pairs, D/r0 ~ U[0.5, 5] (= relative L2 error of the projected PSF); "
+                                  "and on 2e4 pairs at each D/r0 of the timed frames",
+            "train": {"pairs": N_TRAIN, "batch": TRAIN_BATCH, "steps": train_steps, "lr_max": TRAIN_LR,
                       "seconds": round(train_s, 2),
                       "loss_first": float(losses[:10].mean()),
                       "loss_last": float(losses[-10:].mean())},
@@ -522,7 +588,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=12000)
+    ap.add_argument("--train-steps", type=int, default=24000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-4k", action="store_true")
     args = ap.parse_args()
@@ -555,6 +621,8 @@ def main():
     # ---- plain FP32 form (exact P2S) ----
     beta32 = torch.empty((FRAMES, H, W, K), dtype=torch.float32, device=dev)
     ms, rep, out_plain = wl.run(tsim, plan, beta32, args.steps, args.warmup, FRAMES)
+    zern_first = wl.zern_first
+    outs_first = {"plain_fp32": out_plain[:3].cpu().numpy()}
     kernels, roofline = summarize(rep, args.steps, FRAMES, s)
     value = FRAMES * H * W / (ms * 1e-3) / 1e6
     del beta32
@@ -567,6 +635,7 @@ def main():
         net, info = train_network(tsim, torch, np, plan_l, args.train_steps)
         beta16 = torch.empty((FRAMES, H, W, kpad(K)), dtype=torch.bfloat16, device=dev)
         ms_l, rep_l, out_l = wl.run(tsim, plan_l, beta16, args.steps, args.warmup, FRAMES)
+        outs_first["learned_bf16"] = out_l[:3].cpu().numpy()
         kern_l, roof_l = summarize(rep_l, args.steps, FRAMES, s, traffic=False)
         learned = {"value": round(FRAMES * H * W / (ms_l * 1e-3) / 1e6, 3), "unit": "Mpixel/s",
                    "ms_per_step": round(ms_l, 3), "dtype": "bf16 MFMA, fp32 accumulate",
@@ -601,6 +670,7 @@ def main():
             "subharmonic_sampler": subh, "large_4k": large, "setup_s": round(setup_s, 2)}
     if cpu is not None:
         line["cpu_baseline"] = cpu
+        line["accuracy_vs_fp64_oracle"] = accuracy_vs_oracle(basis, zern_first, outs_first)
     print(json.dumps(line), flush=True)
 
 

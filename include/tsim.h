@@ -286,6 +286,44 @@ int tsim_render(const tsim_plan *plan, int frames, const float *img, const void 
 int tsim_warp(const tsim_plan *plan, int frames, const float *img, const float *zern,
               float *out, tsim_stream stream);
 
+/* Batches of frames of mixed sizes (many frames and uneven image sizes per
+ * launch): each item is one plan's frames through the whole path of
+ * Sec. III-C and Eq. (8) -- tsim_sample_zernike, tsim_p2s, tsim_render
+ * into `blur`, tsim_warp into `out` -- and tsim_batch_create records the
+ * calls of all items, in item order, into one HIP graph that the library
+ * captures on a private stream and instantiates; tsim_batch_launch replays
+ * it on the caller's stream.  Every replay recomputes the same frames
+ * (same seed, frame counters and D/r0) from the buffers' current contents:
+ * refill `img` between launches to render new images.
+ *   Each item: plan, frames >= 1, d_over_r0 host [frames] (read at create),
+ *   frame0 (the frame counter of its first frame), and device buffers as
+ *   for the individual calls, all 256-byte aligned, owned by the caller and
+ *   kept alive and unmoved until tsim_batch_destroy: img, blur, out
+ *   [frames][C][H][W] float32 (three distinct buffers), zern
+ *   [frames][35][H][W] float32, beta per the plan's precision, ws of at
+ *   least tsim_workspace_bytes(plan, frames) bytes (items may share one ws:
+ *   the graph runs them in order).  The plans must outlive the batch.
+ *   Every item is checked before anything is recorded (TSIM_EINVAL,
+ *   TSIM_EARTEFACT without a basis); tsim_batch_launch returns
+ *   TSIM_EDEVICE if the replay cannot be queued. */
+typedef struct tsim_batch tsim_batch;
+typedef struct tsim_batch_item {
+  const tsim_plan *plan;
+  int frames;
+  const float *d_over_r0;
+  uint64_t frame0;
+  const float *img;
+  float *zern;
+  void *beta;
+  float *blur;
+  float *out;
+  void *ws;
+} tsim_batch_item;
+int tsim_batch_create(const tsim_batch_item *items, int n_items, uint64_t seed,
+                      tsim_batch **out);
+int tsim_batch_launch(const tsim_batch *batch, tsim_stream stream);
+int tsim_batch_destroy(tsim_batch *batch);
+
 /* Exact PSFs of Eq. (2) for n Zernike vectors (modes 4..36 used):
  *   zvec : device [n][35] float32;  psf : device [n][T*T] float32, unit sum. */
 int tsim_psf_exact(const tsim_plan *plan, int n, const float *zvec, float *psf,

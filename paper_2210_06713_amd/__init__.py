@@ -44,6 +44,12 @@ _i = ctypes.c_int
 _u64 = ctypes.c_uint64
 
 
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("plan", _vp), ("frames", ctypes.c_int32), ("d_over_r0", ctypes.POINTER(ctypes.c_float)),
+                ("frame0", ctypes.c_uint64), ("img", _vp), ("zern", _vp), ("beta", _vp), ("blur", _vp),
+                ("out", _vp), ("ws", _vp)]
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -96,6 +102,9 @@ _lib_mlp_predict = _sig("tsim_mlp_predict", _i, [_vp, _i, _vp, _vp, _vp])
 _lib_host_tables = _sig("tsim_host_tables", _i,
                         [ctypes.POINTER(_Params), _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
 _lib_p2s_form = _sig("tsim_p2s_form", _i, [_vp, ctypes.POINTER(_i)])
+_lib_batch_create = _sig("tsim_batch_create", _i, [ctypes.POINTER(_BatchItem), _i, _u64, ctypes.POINTER(_vp)])
+_lib_batch_launch = _sig("tsim_batch_launch", _i, [_vp, _vp])
+_lib_batch_destroy = _sig("tsim_batch_destroy", _i, [_vp])
 _lib_last_error = _sig("tsim_last_error", _i, [ctypes.c_char_p, ctypes.c_size_t])
 _lib_sync = _sig("tsim_sync", _i, [_vp])
 
@@ -107,7 +116,8 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_mlp_data_ws_bytes", "tsim_mlp_make_data", "tsim_mlp_grad", "tsim_mlp_train", "tsim_plan_set_mlp",
             "tsim_mlp_fit_output", "tsim_mlp_predict", "tsim_tilt_stats_ws_bytes", "tsim_tilt_stats",
             "tsim_structure_function_ws_bytes", "tsim_structure_function", "tsim_p2s_form",
-            "tsim_last_error", "tsim_sync", "tsim_sample_zernike_noalloc"]
+            "tsim_last_error", "tsim_sync", "tsim_sample_zernike_noalloc", "tsim_batch_create",
+            "tsim_batch_launch", "tsim_batch_destroy"]
 
 
 def last_error():
@@ -553,6 +563,51 @@ class Mlp:
                               float(lr_max), float(lr_min), losses.ctypes.data_as(_fp),
                               _stream(stream)), "tsim_mlp_train")
         return losses
+
+
+class Batch:
+    """Mixed-size frames through the whole path in one library-built HIP
+    graph (``tsim_batch``).  ``items``: dicts with keys plan, d_over_r0
+    (one per frame), frame0, img, zern, beta, blur, out, ws (device tensors,
+    shaped as for the individual calls).  The tensors are kept referenced
+    for the batch's lifetime."""
+
+    def __init__(self, items, seed):
+        self._keep = []
+        arr = (_BatchItem * len(items))()
+        for k, it in enumerate(items):
+            pl = it["plan"]
+            d = np.ascontiguousarray(np.atleast_1d(it["d_over_r0"]), dtype=np.float32)
+            frames, dev = pl._zern(it["zern"])
+            if d.size != frames:
+                raise ValueError("one D/r0 per frame expected")
+            pl._frames_img(it["img"], "img", frames, dev)
+            pl._frames_img(it["blur"], "blur", frames, dev)
+            pl._frames_img(it["out"], "out", frames, dev)
+            pl._beta(it["beta"], frames, dev)
+            pl._ws(it["ws"], frames, dev)
+            self._keep += [pl, d, it["img"], it["zern"], it["beta"], it["blur"], it["out"], it["ws"]]
+            arr[k] = _BatchItem(pl._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                int(it.get("frame0", 0)), _ptr(it["img"]).value, _ptr(it["zern"]).value,
+                                _ptr(it["beta"]).value, _ptr(it["blur"]).value, _ptr(it["out"]).value,
+                                _ptr(it["ws"]).value)
+        h = _vp()
+        _check(_lib_batch_create(arr, len(items), int(seed), ctypes.byref(h)), "tsim_batch_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_lib_batch_launch(self._h, _stream(stream)), "tsim_batch_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def make_training_data(plan, n_pairs, seed=0, dr_lo=0.5, dr_hi=5.0, stream=None):

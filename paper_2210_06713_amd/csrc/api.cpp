@@ -2,9 +2,17 @@
 // Every entry point records a failing status for tsim_last_error.
 #include <cmath>
 #include <cstdint>
+#include <new>
 #include <vector>
 
 #include "internal.h"
+
+// A captured, instantiated graph of a batch's calls (tsim_batch_create).
+struct tsim_batch {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int n_items = 0;
+};
 
 namespace {
 
@@ -117,9 +125,99 @@ int warp_impl(const tsim_plan *pl, int frames, const float *img, const float *ze
 
 hipStream_t hs(tsim_stream s) { return static_cast<hipStream_t>(s); }
 
+// One item's four calls on stream s, in the order of the path (sample, P2S,
+// blur, warp), with the same checks as the individual entry points.
+int batch_item_calls(const tsim_batch_item &it, uint64_t seed, hipStream_t s) {
+  int st = sample_impl(it.plan, it.frames, it.d_over_r0, seed, it.frame0, it.zern, it.ws, s);
+  if (st == TSIM_OK) st = p2s_impl(it.plan, it.frames, it.zern, it.beta, it.ws, s);
+  if (st == TSIM_OK) st = render_impl(it.plan, it.frames, it.img, it.beta, it.blur, s);
+  if (st == TSIM_OK) st = warp_impl(it.plan, it.frames, it.blur, it.zern, it.out, s);
+  return st;
+}
+
+int batch_check(const tsim_batch_item &it) {
+  const tsim_plan *pl = it.plan;
+  if (!frames_ok(pl, it.frames) || !it.d_over_r0 || !it.img || !it.zern || !it.beta || !it.blur || !it.out ||
+      !it.ws)
+    return TSIM_EINVAL;
+  if (!aligned(it.img) || !aligned(it.zern) || !aligned(it.beta) || !aligned(it.blur) || !aligned(it.out) ||
+      !aligned(it.ws))
+    return TSIM_EINVAL;
+  if (it.img == it.blur || it.blur == it.out || it.img == it.out) return TSIM_EINVAL;
+  if (it.frame0 + uint64_t(it.frames) > (uint64_t(1) << 32)) return TSIM_EINVAL;
+  for (int f = 0; f < it.frames; ++f)
+    if (!(it.d_over_r0[f] > 0.f) || !std::isfinite(it.d_over_r0[f])) return TSIM_EINVAL;
+  if (!pl->d_basis) return TSIM_EARTEFACT;
+  if (pl->p.precision == TSIM_BF16 && !render_bf16_supported(pl->KP, pl->T, pl->C)) return TSIM_EUNSUPPORTED;
+  return TSIM_OK;
+}
+
+int batch_create_impl(const tsim_batch_item *items, int n_items, uint64_t seed, tsim_batch **out) {
+  if (!out) return TSIM_EINVAL;
+  *out = nullptr;
+  if (!items || n_items < 1 || n_items > 4096) return TSIM_EINVAL;
+  for (int i = 0; i < n_items; ++i) {
+    const int st = batch_check(items[i]);
+    if (st != TSIM_OK) return st;
+  }
+  tsim_batch *b = new (std::nothrow) tsim_batch();
+  if (!b) return TSIM_ENOMEM;
+  b->n_items = n_items;
+  // capture on a private stream (default priority); the launchers' one-time
+  // set-up (LDS limits) is not a stream operation, hence relaxed mode, and
+  // launches are not traced (no event nodes in the graph)
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return TSIM_EDEVICE;
+  }
+  int st = TSIM_OK;
+  {
+    TraceQuiet quiet;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      st = TSIM_EDEVICE;
+    } else {
+      for (int i = 0; i < n_items && st == TSIM_OK; ++i) st = batch_item_calls(items[i], seed, cs);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(cs, &g);
+      if (st == TSIM_OK && (e != hipSuccess || !g)) st = TSIM_EDEVICE;
+      if (g && st != TSIM_OK) (void)hipGraphDestroy(g);
+      if (st == TSIM_OK) b->graph = g;
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (st == TSIM_OK && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+    st = TSIM_EDEVICE;
+  if (st != TSIM_OK) {
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return TSIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int tsim_batch_create(const tsim_batch_item *items, int n_items, uint64_t seed, tsim_batch **out) {
+  return note_status("tsim_batch_create", batch_create_impl(items, n_items, seed, out));
+}
+
+int tsim_batch_launch(const tsim_batch *batch, tsim_stream stream) {
+  if (!batch || !batch->exec) return note_status("tsim_batch_launch", TSIM_EINVAL);
+  if (hipGraphLaunch(batch->exec, hs(stream)) != hipSuccess) return note_status("tsim_batch_launch", TSIM_EDEVICE);
+  return TSIM_OK;
+}
+
+int tsim_batch_destroy(tsim_batch *batch) {
+  if (!batch) return TSIM_OK;
+  if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+  if (batch->graph) (void)hipGraphDestroy(batch->graph);
+  delete batch;
+  return TSIM_OK;
+}
 
 int tsim_workspace_bytes(const tsim_plan *pl, int frames, size_t *bytes) {
   if (!bytes || !frames_ok(pl, frames)) return note_status("tsim_workspace_bytes", TSIM_EINVAL);

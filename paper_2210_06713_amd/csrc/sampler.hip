@@ -6,7 +6,9 @@
 // (kx, Gw - kx), the white noise is drawn in registers from Philox once per
 // bin pair, coloured by the square-root spectra at both bins, and
 // inverse-transformed along ky in LDS; rows y < H of the result are written
-// to the workspace V[f][q][y][slot], columns in mirror-pair slot order.
+// to the workspace V[f][q][y][slot], columns in mirror-pair slot order.  A
+// block serves every frame of the launch in turn, so the spectra and the
+// draws' LDS positions are read and formed once.
 // Pass 2 (k_sampler_rows_mix): one block per output row y inverse-transforms
 // V[f][q][y][:] along kx for every field, keeps columns x < W, and mixes the
 // 35 unit-variance fields at each pixel with (D/r0)^{5/6} L before writing
@@ -57,10 +59,84 @@ __device__ __forceinline__ int slot_col(int c, int Gw) {
   return (c & 1) ? Gw - p : p;
 }
 
+// Position and colour of one noise draw of a pass-1 block (work item e):
+// LDS positions of bin A and its Hermitian mirror B (posB < 0 when A is
+// self-conjugate), the canonical bin's counter, the sign that turns the
+// canonical draw into A's noise, and the square-root spectra of the two
+// modes at A's quarter-table bin.  None of it depends on the frame.
+struct DrawItem {
+  int posA, posB;
+  uint32_t canon;
+  float sg, sa, sb;
+};
+
+__device__ __forceinline__ DrawItem draw_item(int e, const float *__restrict__ sqrtS, int Gh, int Gw, int log2h,
+                                              int s0, int ysh, int ma, int mb, bool has_b) {
+  const bool zero_pair = s0 == 0;
+  int slotA, slotB, kyA, kyB, kx;
+  bool self_conj = false;
+  if (zero_pair && e < Gh + 2) {
+    const int half = Gh / 2 + 1;
+    const int c = e < half ? 0 : 1;
+    kyA = e < half ? e : e - half;   // 0..Gh/2
+    kx = c ? (Gw >> 1) : 0;
+    kyB = (Gh - kyA) & (Gh - 1);
+    slotA = slotB = c;
+    self_conj = kyA == kyB;
+  } else {
+    const int e2 = zero_pair ? e - 2 : e;
+    const int pp = e2 >> log2h;     // pair within the block
+    kyA = e2 & (Gh - 1);
+    kx = (s0 >> 1) + pp;            // >= 1 here
+    kyB = (Gh - kyA) & (Gh - 1);
+    slotA = 2 * pp;
+    slotB = 2 * pp + 1;
+  }
+  // bin A = (kyA, kx); its mirror B = (kyB, -kx mod Gw); canonical = smaller linear index
+  const uint32_t linA = uint32_t(kyA) * Gw + kx;
+  const uint32_t linB = uint32_t(kyB) * Gw + ((Gw - kx) & (Gw - 1));
+  DrawItem d;
+  d.canon = linA <= linB ? linA : linB;
+  d.sg = linA <= linB ? 1.f : -1.f;
+  const int qh = Gh / 2 + 1, qw = Gw / 2 + 1;
+  const int kyq = kyA < qh ? kyA : Gh - kyA;   // kx <= Gw/2 for every bin A
+  d.sa = sqrtS[(size_t(ma) * qw + kx) * qh + kyq];
+  d.sb = has_b ? sqrtS[(size_t(mb) * qw + kx) * qh + kyq] : 0.f;
+  d.posA = slotA * Gh + lds_swz(bitrev(uint32_t(kyA), log2h), slotA << ysh);
+  d.posB = self_conj ? -1 : slotB * Gh + lds_swz(bitrev(uint32_t(kyB), log2h), slotB << ysh);
+  return d;
+}
+
+// The coloured noise of one draw for one frame, into the block's LDS lines.
+__device__ __forceinline__ void draw_noise(float2 *lds, const DrawItem &d, int q, uint32_t frame, uint32_t key0,
+                                           uint32_t key1) {
+  const float rs2 = 0.70710678118654752f;
+  u32x4 r = philox4x32_10(u32x4{d.canon, uint32_t(q), frame, 0u}, key0, key1);
+  const float2 g01 = box_muller_hw(r.x, r.y);
+  const float2 g23 = box_muller_hw(r.z, r.w);
+  if (d.posB < 0) {
+    // U = sa g0 + i sb g2 (real noise at self-conjugate bins)
+    lds[d.posA] = make_float2(d.sa * g01.x, d.sb * g23.x);
+  } else {
+    // noise of A: W (canonical) or conj(W); B takes the conjugate
+    const float2 wa = make_float2(g01.x * rs2, d.sg * g01.y * rs2);
+    const float2 wb = make_float2(g23.x * rs2, d.sg * g23.y * rs2);
+    // U = sa Wa + i sb Wb at A, and sa conj(Wa) + i sb conj(Wb) at B
+    lds[d.posA] = make_float2(d.sa * wa.x - d.sb * wb.y, d.sa * wa.y + d.sb * wb.x);
+    lds[d.posB] = make_float2(d.sa * wa.x + d.sb * wb.y, -d.sa * wa.y + d.sb * wb.x);
+  }
+}
+
+// One block per (slot group, field) for all frames of the launch: the
+// twiddles, the draws' LDS positions and their square-root spectra are set
+// up once and kept (IPT draws per thread, in registers), then each frame
+// draws its noise, transforms and writes out.  The self-mirror pair of the
+// first block has two draws more than IPT x 512; threads 0 and 1 take them.
+template <int IPT>
 __global__ void __launch_bounds__(512)
 k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, float2 *__restrict__ V,
                int Gh, int Gw, int log2h, int H, int NC, uint32_t key0, uint32_t key1,
-               uint32_t frame_base) {
+               uint32_t frame_base, int nf) {
   extern __shared__ float2 lds[];  // [NC][Gh] in the lds_swz layout, slot-major; then the twiddles
   float2 *tws = lds + NC * Gh;
   load_twiddles(tws, tw, Gh, log2h);
@@ -69,8 +145,6 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
   const int log2nc = __builtin_ctz(NC);
   const int ysh = log2nc < 5 ? 5 - log2nc : 0;
   const int q = blockIdx.y;
-  const int fl = blockIdx.z;  // frame within this launch
-  const uint32_t frame = frame_base + uint32_t(fl);
   // XCD-aware order: consecutive blocks go to different XCDs (round robin over
   // 8), so give the blocks of one XCD adjacent slot groups; their row
   // segments then share 128-byte lines in that XCD's L2.
@@ -78,78 +152,38 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
   const int b = blockIdx.x;
   const int grp = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
   const int s0 = grp * NC;          // first slot of this block
-  const int qh = Gh / 2 + 1;
   const int ma = 2 * q, mb = 2 * q + 1;  // 0-based mode indices (Noll 2+2q, 3+2q)
   const bool has_b = mb < TSIM_N_MODES;
-  const float rs2 = 0.70710678118654752f;
-  const bool zero_pair = s0 == 0;
-  // work items: one per noise draw; the self-mirror pair (columns 0, Gw/2)
-  // has Gh/2 + 1 draws per column, the others Gh per pair
-  const int items = (NC / 2) * Gh + (zero_pair ? 2 : 0);
-
-  for (int e = threadIdx.x; e < items; e += blockDim.x) {
-    int slotA, slotB, kyA, kyB, kx;
-    bool self_conj = false;
-    if (zero_pair && e < Gh + 2) {
-      const int half = Gh / 2 + 1;
-      const int c = e < half ? 0 : 1;
-      kyA = e < half ? e : e - half;   // 0..Gh/2
-      kx = c ? (Gw >> 1) : 0;
-      kyB = (Gh - kyA) & (Gh - 1);
-      slotA = slotB = c;
-      self_conj = kyA == kyB;
-    } else {
-      const int e2 = zero_pair ? e - 2 : e;
-      const int pp = e2 >> log2h;     // pair within the block
-      kyA = e2 & (Gh - 1);
-      kx = (s0 >> 1) + pp;            // >= 1 here
-      kyB = (Gh - kyA) & (Gh - 1);
-      slotA = 2 * pp;
-      slotB = 2 * pp + 1;
-    }
-    // bin A = (kyA, kx); its mirror B = (kyB, -kx mod Gw); canonical = smaller linear index
-    const uint32_t linA = uint32_t(kyA) * Gw + kx;
-    const uint32_t linB = uint32_t(kyB) * Gw + ((Gw - kx) & (Gw - 1));
-    const bool a_canon = linA <= linB;
-    const uint32_t canon = a_canon ? linA : linB;
-    u32x4 r = philox4x32_10(u32x4{canon, uint32_t(q), frame, 0u}, key0, key1);
-    const float2 g01 = box_muller_hw(r.x, r.y);
-    const float2 g23 = box_muller_hw(r.z, r.w);
-    const int kxq = kx;                // kx <= Gw/2 for every bin A
-    const int kyq = kyA < qh ? kyA : Gh - kyA;
-    const int qw = Gw / 2 + 1;
-    const float sa = sqrtS[(size_t(ma) * qw + kxq) * qh + kyq];
-    const float sb = has_b ? sqrtS[(size_t(mb) * qw + kxq) * qh + kyq] : 0.f;
-    if (self_conj) {
-      // U = sa g0 + i sb g2 (real noise at self-conjugate bins)
-      lds[slotA * Gh + lds_swz(bitrev(uint32_t(kyA), log2h), slotA << ysh)] = make_float2(sa * g01.x, sb * g23.x);
-    } else {
-      // noise of A: W (canonical) or conj(W); B takes the conjugate
-      const float sg = a_canon ? 1.f : -1.f;
-      const float2 wa = make_float2(g01.x * rs2, sg * g01.y * rs2);
-      const float2 wb = make_float2(g23.x * rs2, sg * g23.y * rs2);
-      // U = sa Wa + i sb Wb at A, and sa conj(Wa) + i sb conj(Wb) at B
-      lds[slotA * Gh + lds_swz(bitrev(uint32_t(kyA), log2h), slotA << ysh)] =
-          make_float2(sa * wa.x - sb * wb.y, sa * wa.y + sb * wb.x);
-      lds[slotB * Gh + lds_swz(bitrev(uint32_t(kyB), log2h), slotB << ysh)] =
-          make_float2(sa * wa.x + sb * wb.y, -sa * wa.y + sb * wb.x);
-    }
-  }
-  __syncthreads();
-  lds_fft_dit(lds, Gh, log2h, NC, ysh, tws, 1.f);
+  // (NC / 2) Gh = IPT x 512 draws, plus two in the self-mirror pair
+  const int tail = (s0 == 0 && threadIdx.x < 2) ? IPT * 512 + threadIdx.x : -1;
+  DrawItem it[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k)
+    it[k] = draw_item(threadIdx.x + k * 512, sqrtS, Gh, Gw, log2h, s0, ysh, ma, mb, has_b);
+  DrawItem itt = it[0];
+  if (tail >= 0) itt = draw_item(tail, sqrtS, Gh, Gw, log2h, s0, ysh, ma, mb, has_b);
   const float norm = rsqrtf(float(Gh) * float(Gw));
-  float2 *Vout = V + (size_t(fl) * TSIM_FIELDS + q) * size_t(H) * Gw + s0;
-  // work item e: row bits 0..ysh-1 from its low bits, then the slot, then
-  // the remaining row bits (a wave writes 64/NC rows of the NC slots)
+  // read-out item e: row bits 0..ysh-1 from its low bits, then the slot,
+  // then the remaining row bits (a wave writes 64/NC rows of the NC slots)
   const int ym = (1 << ysh) - 1;
   const int ritems = ((H + ym) >> ysh) << (ysh + log2nc);
-  for (int e = threadIdx.x; e < ritems; e += blockDim.x) {
-    const int c = (e >> ysh) & (NC - 1);
-    const int y = (e & ym) | ((e >> (ysh + log2nc)) << ysh);
-    if (y < H) {
-      const float2 v = lds[c * Gh + lds_swz(y, c << ysh)];
-      Vout[size_t(y) * Gw + c] = make_float2(v.x * norm, v.y * norm);
+  for (int fl = 0; fl < nf; ++fl) {
+    const uint32_t frame = frame_base + uint32_t(fl);
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) draw_noise(lds, it[k], q, frame, key0, key1);
+    if (tail >= 0) draw_noise(lds, itt, q, frame, key0, key1);
+    __syncthreads();
+    lds_fft_dit(lds, Gh, log2h, NC, ysh, tws, 1.f);
+    float2 *Vout = V + (size_t(fl) * TSIM_FIELDS + q) * size_t(H) * Gw + s0;
+    for (int e = threadIdx.x; e < ritems; e += blockDim.x) {
+      const int c = (e >> ysh) & (NC - 1);
+      const int y = (e & ym) | ((e >> (ysh + log2nc)) << ysh);
+      if (y < H) {
+        const float2 v = lds[c * Gh + lds_swz(y, c << ysh)];
+        Vout[size_t(y) * Gw + c] = make_float2(v.x * norm, v.y * norm);
+      }
     }
+    __syncthreads();  // the next frame's draws overwrite the lines
   }
 }
 
@@ -510,20 +544,30 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
           hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return TSIM_EDEVICE;
       if (lds1 > size_t(max_lds)) return TSIM_EUNSUPPORTED;
-      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_sampler_cols),
+      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_sampler_cols<8>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds1)) != hipSuccess)
         return TSIM_EDEVICE;
       raised = lds1;
     }
   }
+  // draws per thread of a pass-1 block: (NC / 2) Gh / 512 = 2, 4 or 8
+  const int ipt = (NC / 2) * Gh / 512;
+  if (ipt != 2 && ipt != 4 && ipt != 8) return TSIM_EUNSUPPORTED;
   for (int f0 = 0; f0 < frames; f0 += chunk) {
     const int nf = std::min(chunk, frames - f0);
-    dim3 g1(Gw / NC, TSIM_FIELDS, nf);
+    dim3 g1(Gw / NC, TSIM_FIELDS);
     {
       TraceScope tr("k_sampler_cols", s);
-      hipLaunchKernelGGL(k_sampler_cols, g1, dim3(512), lds1, s, pl->d_sqrtS,
-                       pl->d_tw_h, V, Gh, Gw, log2h, H, NC, key0, key1,
-                       uint32_t(frame0 + uint64_t(f0)));
+      const uint32_t fb = uint32_t(frame0 + uint64_t(f0));
+      if (ipt == 2)
+        hipLaunchKernelGGL(k_sampler_cols<2>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
+                           H, NC, key0, key1, fb, nf);
+      else if (ipt == 4)
+        hipLaunchKernelGGL(k_sampler_cols<4>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
+                           H, NC, key0, key1, fb, nf);
+      else
+        hipLaunchKernelGGL(k_sampler_cols<8>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
+                           H, NC, key0, key1, fb, nf);
     }
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
     FrameScales sc;
