@@ -312,8 +312,11 @@ struct WRing {
   uint4 f[WD][NT];
 };
 
-// fragment (row n0 + 32t + lane % 32, k-slice 16s + 8 (lane / 32)) of a
-// weight matrix (< 4 GiB): uniform base, 32-bit per-lane byte offset
+// The weights are stored in matrix-core fragment order: for a layer of R
+// rows (neurons) and KS = ldw / 16 k-steps, fragment (row tile nt, k-step s)
+// is 1 KB at byte ((nt KS + s) 64 + lane) 16, lane l holding row
+// 32 nt + l % 32, columns 16 s + 8 (l / 32) + 0..7; a wave's fragment load is
+// one contiguous kilobyte.  Uniform base, 32-bit per-lane byte offset.
 __device__ __forceinline__ uint4 wfrag(const uint16_t *__restrict__ W, uint32_t lane_off, uint32_t off) {
   return *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(W) + (lane_off + off));
 }
@@ -321,75 +324,15 @@ __device__ __forceinline__ uint4 wfrag(const uint16_t *__restrict__ W, uint32_t 
 template <int NT, int KSTEPS>
 __device__ __forceinline__ void w_prefetch(WRing<NT> &ring, const uint16_t *__restrict__ W, int ldw, int n0,
                                            int lane) {
-  const uint32_t lo = uint32_t(((n0 + (lane & 31)) * ldw + 8 * (lane >> 5)) * 2);
+  const uint32_t lo = uint32_t(lane * 16);
 #pragma unroll
   for (int d = 0; d < WD && d < KSTEPS; ++d)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) ring.f[d][t] = wfrag(W, lo, uint32_t((t * 32 * ldw + d * 16) * 2));
-}
-
-// acc[i][t] (i < RT, t < NT) = W[n0 + 32t + .][KSTEPS*16] x act[32 rows of tile i][.]^T,
-// the transposed product: each weight fragment feeds the RT pixel tiles, and
-// a lane holds pixel m = 32i + lane % 32 and neurons n0 + 32t + 8(r/4) +
-// 4(lane/32) + r%4, four adjacent neurons per register quad
-template <int RT, int NT, int KSTEPS>
-__device__ __forceinline__ void mlp_tile(const uint16_t *act, const uint16_t *__restrict__ W, int ldw,
-                                         int n0, f32x16 (&acc)[RT][NT], WRing<NT> &ring, int lane) {
-#pragma unroll
-  for (int i = 0; i < RT; ++i)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[i][t] = f32x16{};
-  const uint32_t lo = uint32_t(((n0 + (lane & 31)) * ldw + 8 * (lane >> 5)) * 2);
-  const uint16_t *arow = act + (lane & 31) * ACT_LD + 8 * (lane >> 5);
-  // activation fragments one k-step ahead of their products
-  uint4 an[RT];
-#pragma unroll
-  for (int i = 0; i < RT; ++i) an[i] = load8(arow + 32 * i * ACT_LD);
-#pragma unroll
-  for (int s = 0; s < KSTEPS; ++s) {
-    uint4 a[RT];
-#pragma unroll
-    for (int i = 0; i < RT; ++i) a[i] = an[i];
-    if (s + 1 < KSTEPS) {
-#pragma unroll
-      for (int i = 0; i < RT; ++i) an[i] = load8(arow + 32 * i * ACT_LD + (s + 1) * 16);
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int i = 0; i < RT; ++i) acc[i][t] = mfma_bf16(ring.f[s % WD][t], a[i], acc[i][t]);
-    if (s + WD < KSTEPS) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-        ring.f[s % WD][t] = wfrag(W, lo, uint32_t((t * 32 * ldw + (s + WD) * 16) * 2));
-    }
-  }
-}
-
-// GELU(acc + bias) of four adjacent neurons packed into one 8-byte LDS write
-template <int RT, int NT>
-__device__ __forceinline__ void mlp_store_gelu(uint16_t *act, const f32x16 (&acc)[RT][NT],
-                                               const float *__restrict__ bias, int n0, int lane) {
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int n = n0 + 32 * t + 8 * q + 4 * (lane >> 5);
-      const float4 bn = *reinterpret_cast<const float4 *>(bias + n);
-#pragma unroll
-      for (int i = 0; i < RT; ++i) {
-        const int m = 32 * i + (lane & 31);
-        const f32x16 &a = acc[i][t];
-        uint2 w;
-        w.x = pack_bf16(gelu_fast(a[4 * q] + bn.x), gelu_fast(a[4 * q + 1] + bn.y));
-        w.y = pack_bf16(gelu_fast(a[4 * q + 2] + bn.z), gelu_fast(a[4 * q + 3] + bn.w));
-        *reinterpret_cast<uint2 *>(act + m * ACT_LD + n) = w;
-      }
-    }
+    for (int t = 0; t < NT; ++t) ring.f[d][t] = wfrag(W, lo, uint32_t(((n0 / 32 + t) * (ldw / 16) + d) * 1024));
 }
 
 struct InferParams {
-  const uint16_t *W1, *W2, *W3, *W4;  // [256][48], [256][256], [256][256], [128][256] bf16
+  const uint16_t *W1, *W2, *W3, *W4;  // 256 x 48, 256 x 256, 256 x 256, 128 x 256 bf16, fragment order
   const float *b1, *b2, *b3, *b4;     // [256] x3, [128]
   const float *inv_s;                 // [35]
   const float *mu;                    // [128] output means (0 beyond K)
@@ -398,56 +341,93 @@ struct InferParams {
   int out_bf16;
 };
 
-// Block: 128 pixels (four 32-row tiles), 4 waves.  Wave w computes the
-// neurons [64 w, +64) of each hidden layer ([32 w, +32) of the last) for all
-// 128 pixels, so a weight fragment feeds four products; activations in
-// place in LDS between layers.
-__global__ void __launch_bounds__(256)
-k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip, void *__restrict__ beta) {
-  __shared__ __attribute__((aligned(16))) uint16_t act[IPX * ACT_LD];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const size_t pb = size_t(blockIdx.x) * IPX;
-  WRing<2> ring;
-  w_prefetch<2, IN_PAD / 16>(ring, ip.W1, IN_PAD, w * 64, lane);
-  {
-    // inputs: thread -> pixel (tid % 128), modes [24 (tid / 128), +24)
-    const int px = threadIdx.x & 127, j0 = (threadIdx.x >> 7) * 24;
-    const size_t p = pb + px;
-    const bool ok = p < n_pix;
-    const size_t pc = ok ? p : 0;
-    const size_t fr = pc / size_t(hw), yx = pc - fr * size_t(hw);
-    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
+// GELU(acc + bias) of quads [Q0, Q1) of a pixel half's products (quad =
+// four adjacent neurons of one pixel, one 8-byte LDS write): quad idx is
+// tile i = idx / (4 NT) of the half, neuron tile t = (idx / 4) % NT, group
+// q = idx % 4 of the accumulator registers.
+template <int NT, int Q0, int Q1>
+__device__ __forceinline__ void gelu_quads(uint16_t *act, const f32x16 (&acc)[2][NT],
+                                           const float *__restrict__ bias, int n0, int half, int lane) {
 #pragma unroll
-    for (int q = 0; q < 24; ++q) {
-      const int j = j0 + q;
-      const float v = (ok && j < TSIM_N_MODES) ? zp[size_t(j) * hw] * ip.inv_s[j] : 0.f;
-      act[px * ACT_LD + j] = f2bf(v);
+  for (int idx = Q0; idx < Q1; ++idx) {
+    const int i = idx / (4 * NT), t = (idx / 4) % NT, q = idx % 4;
+    const int n = n0 + 32 * t + 8 * q + 4 * (lane >> 5);
+    const int m = 32 * (2 * half + i) + (lane & 31);
+    const float4 bn = *reinterpret_cast<const float4 *>(bias + n);
+    const f32x16 &a = acc[i][t];
+    uint2 w;
+    w.x = pack_bf16(gelu_fast(a[4 * q] + bn.x), gelu_fast(a[4 * q + 1] + bn.y));
+    w.y = pack_bf16(gelu_fast(a[4 * q + 2] + bn.z), gelu_fast(a[4 * q + 3] + bn.w));
+    *reinterpret_cast<uint2 *>(act + m * ACT_LD + n) = w;
+  }
+}
+
+template <int NT, int GNT, int KSTEPS, int S>
+struct GeluSlice {
+  // quads of the other half taken at k-step S: an even share of the 8 GNT
+  static constexpr int Q0 = S * 8 * GNT / KSTEPS, Q1 = (S + 1) * 8 * GNT / KSTEPS;
+};
+
+// One phase of the pipelined network: the products of one layer for pixel
+// half `half` (tiles 2 half, 2 half + 1), acc = W[n0 + 32t + .][k] x act^T,
+// with the GELU of the other half's products of the previous step (gacc,
+// bias gbias, neurons gn0 + ..., written to that half's activation rows)
+// spread over the k-steps, so the vector ALU works while the matrix cores
+// do.  GNT = 0: no GELU in this phase (gacc unused), else GNT = 2.
+template <int NT, int KSTEPS, int GNT, int S = 0>
+struct Phase {
+  __device__ __forceinline__ static void step(uint16_t *act, const uint16_t *__restrict__ W, uint32_t lo,
+                                              int ldw, f32x16 (&acc)[2][NT], WRing<NT> &ring, uint4 (&an)[2],
+                                              const uint16_t *arow, const f32x16 (&gacc)[2][2],
+                                              const float *__restrict__ gbias, int gn0, int ghalf, int lane) {
+    if constexpr (S < KSTEPS) {
+      uint4 a[2] = {an[0], an[1]};
+      if constexpr (S + 1 < KSTEPS) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) an[i] = load8(arow + 32 * i * ACT_LD + (S + 1) * 16);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) acc[i][t] = mfma_bf16(ring.f[S % WD][t], a[i], acc[i][t]);
+      if constexpr (S + WD < KSTEPS) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          ring.f[S % WD][t] = wfrag(W, lo, uint32_t((t * (ldw / 16) + S + WD) * 1024));
+      }
+      if constexpr (GNT > 0) {
+        using G = GeluSlice<NT, GNT, KSTEPS, S>;
+        gelu_quads<GNT, G::Q0, G::Q1>(act, gacc, gbias, gn0, ghalf, lane);
+      }
+      Phase<NT, KSTEPS, GNT, S + 1>::step(act, W, lo, ldw, acc, ring, an, arow, gacc, gbias, gn0, ghalf, lane);
     }
   }
-  __syncthreads();
-  f32x16 acc[4][2];
-  mlp_tile<4, 2, IN_PAD / 16>(act, ip.W1, IN_PAD, w * 64, acc, ring, lane);
-  w_prefetch<2, HID / 16>(ring, ip.W2, HID, w * 64, lane);
-  __syncthreads();
-  mlp_store_gelu<4, 2>(act, acc, ip.b1, w * 64, lane);
-  __syncthreads();
-  mlp_tile<4, 2, HID / 16>(act, ip.W2, HID, w * 64, acc, ring, lane);
-  w_prefetch<2, HID / 16>(ring, ip.W3, HID, w * 64, lane);
-  __syncthreads();
-  mlp_store_gelu<4, 2>(act, acc, ip.b2, w * 64, lane);
-  __syncthreads();
-  mlp_tile<4, 2, HID / 16>(act, ip.W3, HID, w * 64, acc, ring, lane);
-  WRing<1> ring1;
-  w_prefetch<1, HID / 16>(ring1, ip.W4, HID, w * 32, lane);
-  __syncthreads();
-  mlp_store_gelu<4, 2>(act, acc, ip.b3, w * 64, lane);
-  __syncthreads();
-  f32x16 acc1[4][1];
-  mlp_tile<4, 1, HID / 16>(act, ip.W4, HID, w * 32, acc1, ring1, lane);
-  // outputs: four adjacent basis weights of one pixel per store
+};
+
+template <int NT, int KSTEPS, int GNT>
+__device__ __forceinline__ void phase(uint16_t *act, int half, const uint16_t *__restrict__ W, int ldw, int n0,
+                                      f32x16 (&acc)[2][NT], WRing<NT> &ring,
+                                      const f32x16 (&gacc)[2][2], const float *__restrict__ gbias,
+                                      int gn0, int lane) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[i][t] = f32x16{};
+  const uint32_t lo = uint32_t(lane * 16 + (n0 / 32) * (ldw / 16) * 1024);
+  const uint16_t *arow = act + (64 * half + (lane & 31)) * ACT_LD + 8 * (lane >> 5);
+  uint4 an[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) an[i] = load8(arow + 32 * i * ACT_LD);
+  Phase<NT, KSTEPS, GNT>::step(act, W, lo, ldw, acc, ring, an, arow, gacc, gbias, gn0, 1 - half, lane);
+}
+
+// Output layer epilogue for one pixel half: beta = (acc + b4) s_out + mu,
+// four adjacent basis weights of one pixel per store.
+__device__ __forceinline__ void mlp_out_half(const f32x16 (&acc)[2][1], const InferParams &ip, size_t pb, int n0w,
+                                             int half, int lane, size_t n_pix, void *__restrict__ beta) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int n = w * 32 + 8 * q + 4 * (lane >> 5);
+    const int n = n0w + 8 * q + 4 * (lane >> 5);
     if (n >= ip.KB) continue;
     float bn[4], mun[4];
 #pragma unroll
@@ -457,12 +437,12 @@ k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip
       mun[j] = real ? ip.mu[n + j] : 0.f;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const size_t p = pb + 32 * i + (lane & 31);
+    for (int i = 0; i < 2; ++i) {
+      const size_t p = pb + 32 * (2 * half + i) + (lane & 31);
       if (p >= n_pix) continue;
       float y[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) y[j] = (n + j < ip.K) ? (acc1[i][0][4 * q + j] + bn[j]) * ip.s_out + mun[j] : 0.f;
+      for (int j = 0; j < 4; ++j) y[j] = (n + j < ip.K) ? (acc[i][0][4 * q + j] + bn[j]) * ip.s_out + mun[j] : 0.f;
       if ((ip.KB & 3) == 0) {   // whole, aligned quads
         if (ip.out_bf16) {
           uint2 wv;
@@ -485,6 +465,68 @@ k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip
       }
     }
   }
+}
+
+// Block: 128 pixels in two halves of 64 (two 32-row tiles each), 4 waves.
+// Wave w computes the neurons [64 w, +64) of each hidden layer ([32 w, +32)
+// of the last) for all 128 pixels, one half at a time, so a weight fragment
+// feeds two products.  The halves are pipelined: while the matrix cores
+// take layer l for one half, the vector ALU forms the other half's GELU
+// activations of the layer before, in place in LDS.  One barrier per phase
+// (every wave has read the rows a phase overwrites, and written the rows the
+// next phase reads).
+__global__ void __launch_bounds__(256)
+k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip, void *__restrict__ beta) {
+  __shared__ __attribute__((aligned(16))) uint16_t act[IPX * ACT_LD];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const size_t pb = size_t(blockIdx.x) * IPX;
+  const int n0 = w * 64;
+  WRing<2> ring;
+  w_prefetch<2, IN_PAD / 16>(ring, ip.W1, IN_PAD, n0, lane);
+  {
+    // inputs: thread -> pixel (tid % 128), modes [24 (tid / 128), +24)
+    const int px = threadIdx.x & 127, j0 = (threadIdx.x >> 7) * 24;
+    const size_t p = pb + px;
+    const bool ok = p < n_pix;
+    const size_t pc = ok ? p : 0;
+    const size_t fr = pc / size_t(hw), yx = pc - fr * size_t(hw);
+    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
+#pragma unroll
+    for (int q = 0; q < 24; ++q) {
+      const int j = j0 + q;
+      const float v = (ok && j < TSIM_N_MODES) ? zp[size_t(j) * hw] * ip.inv_s[j] : 0.f;
+      act[px * ACT_LD + j] = f2bf(v);
+    }
+  }
+  __syncthreads();
+  f32x16 A[2][2], B[2][2];
+  // layer 1 (inputs in columns 0..47 of every row)
+  phase<2, IN_PAD / 16, 0>(act, 0, ip.W1, IN_PAD, n0, A, ring, B, nullptr, 0, lane);
+  w_prefetch<2, IN_PAD / 16>(ring, ip.W1, IN_PAD, n0, lane);
+  __syncthreads();
+  phase<2, IN_PAD / 16, 2>(act, 1, ip.W1, IN_PAD, n0, B, ring, A, ip.b1, n0, lane);    // + GELU1 half 0
+  w_prefetch<2, HID / 16>(ring, ip.W2, HID, n0, lane);
+  __syncthreads();
+  phase<2, HID / 16, 2>(act, 0, ip.W2, HID, n0, A, ring, B, ip.b1, n0, lane);          // + GELU1 half 1
+  w_prefetch<2, HID / 16>(ring, ip.W2, HID, n0, lane);
+  __syncthreads();
+  phase<2, HID / 16, 2>(act, 1, ip.W2, HID, n0, B, ring, A, ip.b2, n0, lane);          // + GELU2 half 0
+  w_prefetch<2, HID / 16>(ring, ip.W3, HID, n0, lane);
+  __syncthreads();
+  phase<2, HID / 16, 2>(act, 0, ip.W3, HID, n0, A, ring, B, ip.b2, n0, lane);          // + GELU2 half 1
+  w_prefetch<2, HID / 16>(ring, ip.W3, HID, n0, lane);
+  __syncthreads();
+  phase<2, HID / 16, 2>(act, 1, ip.W3, HID, n0, B, ring, A, ip.b3, n0, lane);          // + GELU3 half 0
+  WRing<1> ring1;
+  w_prefetch<1, HID / 16>(ring1, ip.W4, HID, w * 32, lane);
+  __syncthreads();
+  f32x16 A1[2][1], B1[2][1];
+  phase<1, HID / 16, 2>(act, 0, ip.W4, HID, w * 32, A1, ring1, B, ip.b3, n0, lane);    // + GELU3 half 1
+  w_prefetch<1, HID / 16>(ring1, ip.W4, HID, w * 32, lane);
+  __syncthreads();
+  phase<1, HID / 16, 0>(act, 1, ip.W4, HID, w * 32, B1, ring1, B, nullptr, 0, lane);
+  mlp_out_half(A1, ip, pb, w * 32, 0, lane, n_pix, beta);
+  mlp_out_half(B1, ip, pb, w * 32, 1, lane, n_pix, beta);
 }
 
 template <int EPI>
@@ -930,15 +972,29 @@ int plan_set_mlp_impl(tsim_plan *pl, const tsim_mlp *n) {
     std::memcpy(&u, &f, 4);
     return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
   };
-  // packed: W1 [256][48] | W2 [256][256] | W3 [256][256] | W4 [128][256]
+  // row-major, zero padded: W1 [256][48] | W2 [256][256] | W3 [256][256] | W4 [128][256]
   const size_t s1 = size_t(HID) * IN_PAD, s2 = size_t(HID) * HID, s4 = size_t(128) * HID;
-  std::vector<uint16_t> pk(s1 + 2 * s2 + s4, 0);
+  std::vector<uint16_t> rm(s1 + 2 * s2 + s4, 0);
   for (int o = 0; o < HID; ++o)
-    for (int i = 0; i < TSIM_N_MODES; ++i) pk[size_t(o) * IN_PAD + i] = bf(w[n->off_w[0] + size_t(o) * TSIM_N_MODES + i]);
+    for (int i = 0; i < TSIM_N_MODES; ++i) rm[size_t(o) * IN_PAD + i] = bf(w[n->off_w[0] + size_t(o) * TSIM_N_MODES + i]);
   for (int l = 1; l < 3; ++l)
-    for (size_t e = 0; e < s2; ++e) pk[s1 + (l - 1) * s2 + e] = bf(w[n->off_w[l] + e]);
+    for (size_t e = 0; e < s2; ++e) rm[s1 + (l - 1) * s2 + e] = bf(w[n->off_w[l] + e]);
   for (int o = 0; o < n->K; ++o)
-    for (int i = 0; i < HID; ++i) pk[s1 + 2 * s2 + size_t(o) * HID + i] = bf(w[n->off_w[3] + size_t(o) * HID + i]);
+    for (int i = 0; i < HID; ++i) rm[s1 + 2 * s2 + size_t(o) * HID + i] = bf(w[n->off_w[3] + size_t(o) * HID + i]);
+  // the same matrices in matrix-core fragment order (the kernel's wfrag):
+  // element (row r, column k) of an R x 16 KS layer goes to
+  // ((r / 32 * KS + k / 16) * 64 + r % 32 + 32 (k % 16 / 8)) * 8 + k % 8
+  std::vector<uint16_t> pk(rm.size(), 0);
+  const size_t base[4] = {0, s1, s1 + s2, s1 + 2 * s2};
+  const int rows[4] = {HID, HID, HID, 128}, cols[4] = {IN_PAD, HID, HID, HID};
+  for (int l = 0; l < 4; ++l) {
+    const int ks = cols[l] / 16;
+    for (int r = 0; r < rows[l]; ++r)
+      for (int k = 0; k < cols[l]; ++k) {
+        const size_t dst = (size_t((r / 32) * ks + k / 16) * 64 + r % 32 + 32 * ((k % 16) / 8)) * 8 + k % 8;
+        pk[base[l] + dst] = rm[base[l] + size_t(r) * cols[l] + k];
+      }
+  }
   // FP32: b1 | b2 | b3 | b4[128] | inv_s[35] (pad 64) | mu[128]
   std::vector<float> fb(3 * HID + 128 + 64 + 128, 0.f);
   for (int l = 0; l < 3; ++l)
