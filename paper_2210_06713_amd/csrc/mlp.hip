@@ -10,10 +10,13 @@
 //                      the forward (X W^T), input-gradient (dZ W) and weight-
 //                      gradient (dZ^T X) products share it; fused epilogues
 //                      add the bias and apply GELU or its derivative.
-//   k_mlp_infer        fused per-pixel inference for the P2S step: each wave
-//                      carries 64 pixels through all four layers, the
-//                      activations staying in LDS, weights streamed from L2
-//                      three k-steps ahead of their products.
+//   k_mlp_infer        fused per-pixel inference for the P2S step: a block
+//                      of 8 waves carries 128 pixels through all four
+//                      layers in two pipelined halves (one half's GELU on
+//                      the vector ALU while the matrix cores take the other
+//                      half's products), activations staying in LDS, weights
+//                      in fragment order streamed from L2 three k-steps
+//                      ahead of their products.
 //   k_prep, k_mse_grad, k_colsum_*, k_adamw, k_init_normal, k_draws: data
 //                      preparation, loss, bias gradients, optimiser, seeded
 //                      initialisation and training-pair draws.
@@ -321,16 +324,6 @@ __device__ __forceinline__ uint4 wfrag(const uint16_t *__restrict__ W, uint32_t 
   return *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(W) + (lane_off + off));
 }
 
-template <int NT, int KSTEPS>
-__device__ __forceinline__ void w_prefetch(WRing<NT> &ring, const uint16_t *__restrict__ W, int ldw, int n0,
-                                           int lane) {
-  const uint32_t lo = uint32_t(lane * 16);
-#pragma unroll
-  for (int d = 0; d < WD && d < KSTEPS; ++d)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) ring.f[d][t] = wfrag(W, lo, uint32_t(((n0 / 32 + t) * (ldw / 16) + d) * 1024));
-}
-
 struct InferParams {
   const uint16_t *W1, *W2, *W3, *W4;  // 256 x 48, 256 x 256, 256 x 256, 128 x 256 bf16, fragment order
   const float *b1, *b2, *b3, *b4;     // [256] x3, [128]
@@ -346,8 +339,8 @@ struct InferParams {
 // tile i = idx / (4 NT) of the half, neuron tile t = (idx / 4) % NT, group
 // q = idx % 4 of the accumulator registers.
 template <int NT, int Q0, int Q1>
-__device__ __forceinline__ void gelu_quads(uint16_t *act, const f32x16 (&acc)[2][NT],
-                                           const float *__restrict__ bias, int n0, int half, int lane) {
+__device__ __forceinline__ void gelu_quads(uint16_t *act, const f32x16 (&acc)[2][NT], const float *bias, int n0,
+                                           int half, int lane) {
 #pragma unroll
   for (int idx = Q0; idx < Q1; ++idx) {
     const int i = idx / (4 * NT), t = (idx / 4) % NT, q = idx % 4;
@@ -362,172 +355,170 @@ __device__ __forceinline__ void gelu_quads(uint16_t *act, const f32x16 (&acc)[2]
   }
 }
 
-template <int NT, int GNT, int KSTEPS, int S>
-struct GeluSlice {
-  // quads of the other half taken at k-step S: an even share of the 8 GNT
-  static constexpr int Q0 = S * 8 * GNT / KSTEPS, Q1 = (S + 1) * 8 * GNT / KSTEPS;
-};
+// Inference is pipelined over the two 64-pixel halves of a block: each
+// wave owns one 32-neuron tile of every hidden layer, so its accumulators
+// fit 128 registers and four waves share a SIMD.
 
-// One phase of the pipelined network: the products of one layer for pixel
-// half `half` (tiles 2 half, 2 half + 1), acc = W[n0 + 32t + .][k] x act^T,
-// with the GELU of the other half's products of the previous step (gacc,
-// bias gbias, neurons gn0 + ..., written to that half's activation rows)
-// spread over the k-steps, so the vector ALU works while the matrix cores
-// do.  GNT = 0: no GELU in this phase (gacc unused), else GNT = 2.
-template <int NT, int KSTEPS, int GNT, int S = 0>
-struct Phase {
+// Steps S.. of a phase: acc[i] = W[32 nt0 + .][k] x
+// act[tile tile0 + i][k]^T for RT pixel tiles, with the GELU of the other
+// half's two tiles of the step before (gacc, 8 quads) spread over the
+// k-steps.
+template <int RT, int KS, bool GELU, int S = 0>
+struct Phase8 {
   __device__ __forceinline__ static void step(uint16_t *act, const uint16_t *__restrict__ W, uint32_t lo,
-                                              int ldw, f32x16 (&acc)[2][NT], WRing<NT> &ring, uint4 (&an)[2],
-                                              const uint16_t *arow, const f32x16 (&gacc)[2][2],
-                                              const float *__restrict__ gbias, int gn0, int ghalf, int lane) {
-    if constexpr (S < KSTEPS) {
-      uint4 a[2] = {an[0], an[1]};
-      if constexpr (S + 1 < KSTEPS) {
+                                              f32x16 (&acc)[RT][1], WRing<1> &ring, uint4 (&an)[RT],
+                                              const uint16_t *arow, const f32x16 (&gacc)[2][1],
+                                              const float *gbias, int gn0, int ghalf, int lane) {
+    if constexpr (S < KS) {
+      uint4 a[RT];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) an[i] = load8(arow + 32 * i * ACT_LD + (S + 1) * 16);
+      for (int i = 0; i < RT; ++i) a[i] = an[i];
+      if constexpr (S + 1 < KS) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i) an[i] = load8(arow + 32 * i * ACT_LD + (S + 1) * 16);
       }
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int i = 0; i < 2; ++i) acc[i][t] = mfma_bf16(ring.f[S % WD][t], a[i], acc[i][t]);
-      if constexpr (S + WD < KSTEPS) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          ring.f[S % WD][t] = wfrag(W, lo, uint32_t((t * (ldw / 16) + S + WD) * 1024));
-      }
-      if constexpr (GNT > 0) {
-        using G = GeluSlice<NT, GNT, KSTEPS, S>;
-        gelu_quads<GNT, G::Q0, G::Q1>(act, gacc, gbias, gn0, ghalf, lane);
-      }
-      Phase<NT, KSTEPS, GNT, S + 1>::step(act, W, lo, ldw, acc, ring, an, arow, gacc, gbias, gn0, ghalf, lane);
+      for (int i = 0; i < RT; ++i) acc[i][0] = mfma_bf16(ring.f[S % WD][0], a[i], acc[i][0]);
+      if constexpr (S + WD < KS) ring.f[S % WD][0] = wfrag(W, lo, uint32_t((S + WD) * 1024));
+      if constexpr (GELU) gelu_quads<1, S * 8 / KS, (S + 1) * 8 / KS>(act, gacc, gbias, gn0, ghalf, lane);
+      Phase8<RT, KS, GELU, S + 1>::step(act, W, lo, acc, ring, an, arow, gacc, gbias, gn0, ghalf, lane);
     }
   }
 };
 
-template <int NT, int KSTEPS, int GNT>
-__device__ __forceinline__ void phase(uint16_t *act, int half, const uint16_t *__restrict__ W, int ldw, int n0,
-                                      f32x16 (&acc)[2][NT], WRing<NT> &ring,
-                                      const f32x16 (&gacc)[2][2], const float *__restrict__ gbias,
-                                      int gn0, int lane) {
+template <int RT, int KS, bool GELU>
+__device__ __forceinline__ void phase8(uint16_t *act, int tile0, const uint16_t *__restrict__ W, int nt0,
+                                       f32x16 (&acc)[RT][1], WRing<1> &ring, const f32x16 (&gacc)[2][1],
+                                       const float *gbias, int gn0, int ghalf, int lane) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RT; ++i) acc[i][0] = f32x16{};
+  const uint32_t lo = uint32_t(lane * 16 + nt0 * KS * 1024);
+  const uint16_t *arow = act + (32 * tile0 + (lane & 31)) * ACT_LD + 8 * (lane >> 5);
+  uint4 an[RT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[i][t] = f32x16{};
-  const uint32_t lo = uint32_t(lane * 16 + (n0 / 32) * (ldw / 16) * 1024);
-  const uint16_t *arow = act + (64 * half + (lane & 31)) * ACT_LD + 8 * (lane >> 5);
-  uint4 an[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) an[i] = load8(arow + 32 * i * ACT_LD);
-  Phase<NT, KSTEPS, GNT>::step(act, W, lo, ldw, acc, ring, an, arow, gacc, gbias, gn0, 1 - half, lane);
+  for (int i = 0; i < RT; ++i) an[i] = load8(arow + 32 * i * ACT_LD);
+  Phase8<RT, KS, GELU>::step(act, W, lo, acc, ring, an, arow, gacc, gbias, gn0, ghalf, lane);
 }
 
-// Output layer epilogue for one pixel half: beta = (acc + b4) s_out + mu,
-// four adjacent basis weights of one pixel per store.
-__device__ __forceinline__ void mlp_out_half(const f32x16 (&acc)[2][1], const InferParams &ip, size_t pb, int n0w,
-                                             int half, int lane, size_t n_pix, void *__restrict__ beta) {
+template <int KS>
+__device__ __forceinline__ void w_prefetch1(WRing<1> &ring, const uint16_t *__restrict__ W, int nt0, int lane) {
+  const uint32_t lo = uint32_t(lane * 16 + nt0 * KS * 1024);
+#pragma unroll
+  for (int d = 0; d < WD && d < KS; ++d) ring.f[d][0] = wfrag(W, lo, uint32_t(d * 1024));
+}
+
+// Output epilogue of one 32-pixel tile and one 32-output tile (n0w):
+// beta = (acc + b4) s_out + mu, four adjacent basis weights of a pixel per store.
+__device__ __forceinline__ void mlp_out_tile(const f32x16 &acc, const InferParams &ip, const float *b4,
+                                             const float *mu, size_t p, int n0w, int lane, size_t n_pix,
+                                             void *__restrict__ beta) {
+  if (p >= n_pix) return;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int n = n0w + 8 * q + 4 * (lane >> 5);
     if (n >= ip.KB) continue;
-    float bn[4], mun[4];
+    const float4 bn = *reinterpret_cast<const float4 *>(b4 + n);
+    const float4 mn = *reinterpret_cast<const float4 *>(mu + n);
+    const float bv[4] = {bn.x, bn.y, bn.z, bn.w}, mv[4] = {mn.x, mn.y, mn.z, mn.w};
+    float y[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bool real = n + j < ip.K;
-      bn[j] = real ? ip.b4[n + j] : 0.f;
-      mun[j] = real ? ip.mu[n + j] : 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const size_t p = pb + 32 * (2 * half + i) + (lane & 31);
-      if (p >= n_pix) continue;
-      float y[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) y[j] = (n + j < ip.K) ? (acc[i][0][4 * q + j] + bn[j]) * ip.s_out + mun[j] : 0.f;
-      if ((ip.KB & 3) == 0) {   // whole, aligned quads
-        if (ip.out_bf16) {
-          uint2 wv;
-          wv.x = pack_bf16(y[0], y[1]);
-          wv.y = pack_bf16(y[2], y[3]);
-          *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(beta) + p * ip.KB + n) = wv;
-        } else {
-          *reinterpret_cast<float4 *>(static_cast<float *>(beta) + p * ip.KB + n) =
-              make_float4(y[0], y[1], y[2], y[3]);
-        }
+    for (int j = 0; j < 4; ++j) y[j] = (n + j < ip.K) ? (acc[4 * q + j] + bv[j]) * ip.s_out + mv[j] : 0.f;
+    if ((ip.KB & 3) == 0) {   // whole, aligned quads
+      if (ip.out_bf16) {
+        uint2 wv;
+        wv.x = pack_bf16(y[0], y[1]);
+        wv.y = pack_bf16(y[2], y[3]);
+        *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(beta) + p * ip.KB + n) = wv;
       } else {
+        *reinterpret_cast<float4 *>(static_cast<float *>(beta) + p * ip.KB + n) = make_float4(y[0], y[1], y[2], y[3]);
+      }
+    } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (n + j >= ip.KB) break;
-          if (ip.out_bf16)
-            static_cast<uint16_t *>(beta)[p * ip.KB + n + j] = f2bf(y[j]);
-          else
-            static_cast<float *>(beta)[p * ip.KB + n + j] = y[j];
-        }
+      for (int j = 0; j < 4; ++j) {
+        if (n + j >= ip.KB) break;
+        if (ip.out_bf16)
+          static_cast<uint16_t *>(beta)[p * ip.KB + n + j] = f2bf(y[j]);
+        else
+          static_cast<float *>(beta)[p * ip.KB + n + j] = y[j];
       }
     }
   }
 }
 
-// Block: 128 pixels in two halves of 64 (two 32-row tiles each), 4 waves.
-// Wave w computes the neurons [64 w, +64) of each hidden layer ([32 w, +32)
-// of the last) for all 128 pixels, one half at a time, so a weight fragment
-// feeds two products.  The halves are pipelined: while the matrix cores
-// take layer l for one half, the vector ALU forms the other half's GELU
-// activations of the layer before, in place in LDS.  One barrier per phase
-// (every wave has read the rows a phase overwrites, and written the rows the
-// next phase reads).
-__global__ void __launch_bounds__(256)
+// Block: 128 pixels in two halves of 64 (two 32-row tiles each), 8 waves.
+// Wave w computes the neurons [32 w, +32) of each hidden layer for all 128
+// pixels, one half at a time (a weight fragment feeds two products); in the
+// output layer it takes output tile w % 4 of pixel tile w / 4 of the half.
+// The halves are pipelined: while the matrix cores take layer l for one
+// half, the vector ALU forms the other half's GELU activations of the layer
+// before, in place in LDS.  One barrier per phase (every wave has read the
+// rows a phase overwrites, and written the rows the next phase reads).
+// Biases and output means are staged in LDS.
+__global__ void __launch_bounds__(512, 4)
 k_mlp_infer(const float *__restrict__ zern, int hw, size_t n_pix, InferParams ip, void *__restrict__ beta) {
   __shared__ __attribute__((aligned(16))) uint16_t act[IPX * ACT_LD];
+  __shared__ __attribute__((aligned(16))) float sb[3 * HID + 128 + 128];   // b1 b2 b3 b4 mu
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const size_t pb = size_t(blockIdx.x) * IPX;
-  const int n0 = w * 64;
-  WRing<2> ring;
-  w_prefetch<2, IN_PAD / 16>(ring, ip.W1, IN_PAD, n0, lane);
+  const int n0 = w * 32;
+  constexpr int K1 = IN_PAD / 16, KH = HID / 16;
+  WRing<1> ring;
+  w_prefetch1<K1>(ring, ip.W1, w, lane);
+  for (int e = threadIdx.x; e < 3 * HID + 256; e += 512) {
+    float v;
+    if (e < HID) v = ip.b1[e];
+    else if (e < 2 * HID) v = ip.b2[e - HID];
+    else if (e < 3 * HID) v = ip.b3[e - 2 * HID];
+    else if (e < 3 * HID + 128) v = ip.b4[e - 3 * HID];
+    else v = ip.mu[e - 3 * HID - 128];
+    sb[e] = v;
+  }
   {
-    // inputs: thread -> pixel (tid % 128), modes [24 (tid / 128), +24)
-    const int px = threadIdx.x & 127, j0 = (threadIdx.x >> 7) * 24;
+    // inputs: thread -> pixel (tid % 128), modes [12 (tid / 128), +12)
+    const int px = threadIdx.x & 127, j0 = (threadIdx.x >> 7) * 12;
     const size_t p = pb + px;
     const bool ok = p < n_pix;
     const size_t pc = ok ? p : 0;
     const size_t fr = pc / size_t(hw), yx = pc - fr * size_t(hw);
     const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
 #pragma unroll
-    for (int q = 0; q < 24; ++q) {
+    for (int q = 0; q < 12; ++q) {
       const int j = j0 + q;
       const float v = (ok && j < TSIM_N_MODES) ? zp[size_t(j) * hw] * ip.inv_s[j] : 0.f;
       act[px * ACT_LD + j] = f2bf(v);
     }
   }
   __syncthreads();
-  f32x16 A[2][2], B[2][2];
-  // layer 1 (inputs in columns 0..47 of every row)
-  phase<2, IN_PAD / 16, 0>(act, 0, ip.W1, IN_PAD, n0, A, ring, B, nullptr, 0, lane);
-  w_prefetch<2, IN_PAD / 16>(ring, ip.W1, IN_PAD, n0, lane);
+  const float *b1 = sb, *b2 = sb + HID, *b3 = sb + 2 * HID, *b4 = sb + 3 * HID, *mu = sb + 3 * HID + 128;
+  f32x16 A[2][1], B[2][1];
+  phase8<2, K1, false>(act, 0, ip.W1, w, A, ring, B, nullptr, 0, 0, lane);     // layer 1, half 0
+  w_prefetch1<K1>(ring, ip.W1, w, lane);
   __syncthreads();
-  phase<2, IN_PAD / 16, 2>(act, 1, ip.W1, IN_PAD, n0, B, ring, A, ip.b1, n0, lane);    // + GELU1 half 0
-  w_prefetch<2, HID / 16>(ring, ip.W2, HID, n0, lane);
+  phase8<2, K1, true>(act, 2, ip.W1, w, B, ring, A, b1, n0, 0, lane);          // layer 1 half 1 + GELU1 half 0
+  w_prefetch1<KH>(ring, ip.W2, w, lane);
   __syncthreads();
-  phase<2, HID / 16, 2>(act, 0, ip.W2, HID, n0, A, ring, B, ip.b1, n0, lane);          // + GELU1 half 1
-  w_prefetch<2, HID / 16>(ring, ip.W2, HID, n0, lane);
+  phase8<2, KH, true>(act, 0, ip.W2, w, A, ring, B, b1, n0, 1, lane);          // layer 2 half 0 + GELU1 half 1
+  w_prefetch1<KH>(ring, ip.W2, w, lane);
   __syncthreads();
-  phase<2, HID / 16, 2>(act, 1, ip.W2, HID, n0, B, ring, A, ip.b2, n0, lane);          // + GELU2 half 0
-  w_prefetch<2, HID / 16>(ring, ip.W3, HID, n0, lane);
+  phase8<2, KH, true>(act, 2, ip.W2, w, B, ring, A, b2, n0, 0, lane);          // layer 2 half 1 + GELU2 half 0
+  w_prefetch1<KH>(ring, ip.W3, w, lane);
   __syncthreads();
-  phase<2, HID / 16, 2>(act, 0, ip.W3, HID, n0, A, ring, B, ip.b2, n0, lane);          // + GELU2 half 1
-  w_prefetch<2, HID / 16>(ring, ip.W3, HID, n0, lane);
+  phase8<2, KH, true>(act, 0, ip.W3, w, A, ring, B, b2, n0, 1, lane);          // layer 3 half 0 + GELU2 half 1
+  w_prefetch1<KH>(ring, ip.W3, w, lane);
   __syncthreads();
-  phase<2, HID / 16, 2>(act, 1, ip.W3, HID, n0, B, ring, A, ip.b3, n0, lane);          // + GELU3 half 0
-  WRing<1> ring1;
-  w_prefetch<1, HID / 16>(ring1, ip.W4, HID, w * 32, lane);
+  phase8<2, KH, true>(act, 2, ip.W3, w, B, ring, A, b3, n0, 0, lane);          // layer 3 half 1 + GELU3 half 0
+  const int ot = w & 3, pt = w >> 2;   // output tile and pixel tile (within a half) of this wave
+  w_prefetch1<KH>(ring, ip.W4, ot, lane);
   __syncthreads();
-  f32x16 A1[2][1], B1[2][1];
-  phase<1, HID / 16, 2>(act, 0, ip.W4, HID, w * 32, A1, ring1, B, ip.b3, n0, lane);    // + GELU3 half 1
-  w_prefetch<1, HID / 16>(ring1, ip.W4, HID, w * 32, lane);
+  f32x16 A1[1][1], B1[1][1];
+  phase8<1, KH, true>(act, pt, ip.W4, ot, A1, ring, B, b3, n0, 1, lane);       // layer 4 half 0 + GELU3 half 1
+  w_prefetch1<KH>(ring, ip.W4, ot, lane);
   __syncthreads();
-  phase<1, HID / 16, 0>(act, 1, ip.W4, HID, w * 32, B1, ring1, B, nullptr, 0, lane);
-  mlp_out_half(A1, ip, pb, w * 32, 0, lane, n_pix, beta);
-  mlp_out_half(B1, ip, pb, w * 32, 1, lane, n_pix, beta);
+  phase8<1, KH, false>(act, 2 + pt, ip.W4, ot, B1, ring, B, nullptr, 0, 0, lane);   // layer 4 half 1
+  mlp_out_tile(A1[0][0], ip, b4, mu, pb + 32 * pt + (lane & 31), 32 * ot, lane, n_pix, beta);
+  mlp_out_tile(B1[0][0], ip, b4, mu, pb + 32 * (2 + pt) + (lane & 31), 32 * ot, lane, n_pix, beta);
 }
+
 
 template <int EPI>
 int gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const uint16_t *B, long sbk, long sbn,
@@ -1032,6 +1023,6 @@ int launch_mlp_infer(const tsim_plan *pl, const float *zern, int hw, size_t n_pi
   ip.out_bf16 = out_bf16;
   const size_t blocks = (n_pix + IPX - 1) / IPX;
   TraceScope tr("k_mlp_infer", s);
-  hipLaunchKernelGGL(k_mlp_infer, dim3(unsigned(blocks)), dim3(256), 0, s, zern, hw, n_pix, ip, beta);
+  hipLaunchKernelGGL(k_mlp_infer, dim3(unsigned(blocks)), dim3(512), 0, s, zern, hw, n_pix, ip, beta);
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
