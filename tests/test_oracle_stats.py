@@ -2,6 +2,7 @@
 ramps and constants, and the sampler's own fields against the exact model
 covariance by Monte Carlo (which also fixes which axis is which)."""
 import numpy as np
+import pytest
 
 from oracle import sampler as osamp
 from oracle import spectra as ospec
@@ -91,3 +92,97 @@ def test_structure_function_matches_kolmogorov():
         kol = 6.88 * (2.0 * r / P) ** (5.0 / 3.0)
         assert abs(D[r] / kol - 1.0) < 0.08, (r, D[r], kol)
     assert D[2] < 0.85 * 6.88 * (4.0 / P) ** (5.0 / 3.0)
+
+
+# ---- optical transfer functions (Sec. IV-B: LE and SE OTFs) ----
+
+def _shift_overlap(mask, dy, dx):
+    """Number of aperture samples x with x - (dy, dx) also in the aperture."""
+    P = mask.shape[0]
+    a = np.zeros((3 * P, 3 * P), bool)
+    a[P:2 * P, P:2 * P] = mask
+    b = np.zeros_like(a)
+    b[P + dy:2 * P + dy, P + dx:2 * P + dx] = mask
+    return int((a & b).sum())
+
+
+@pytest.mark.parametrize("tilt_removed", [False, True])
+def test_otf_fft_route_equals_definition(tilt_removed):
+    """The autocorrelation theorem route of otf_mean equals the double sum of
+    the definition, realisation by realisation (brute force, 16 x 16 grid)."""
+    rng = np.random.default_rng(31)
+    for _ in range(3):
+        a = rng.normal(size=35) * 0.4
+        H = ostats.otf_mean(a[None], 16, tilt_removed)
+        Hd = ostats.otf_direct(a, 16, tilt_removed)
+        assert np.abs(H - Hd).max() < 1e-12
+
+
+def test_otf_diffraction_limited():
+    """a = 0: the OTF is the aperture's overlap with its shifted copy over the
+    aperture size (counted by integer shifts of the mask), real, 1 at zero
+    lag, and close to the continuous disc's (2/pi)(acos u - u sqrt(1 - u^2)),
+    u = |xi| / D."""
+    from oracle.psf import pupil_grid
+    P = 64
+    H = ostats.otf_mean(np.zeros((1, 35)), P)
+    _, _, mask = pupil_grid(P)
+    n = mask.sum()
+    c = P // 2
+    assert abs(H[c, c] - 1) < 1e-12 and np.abs(H.imag).max() < 1e-12
+    for dy, dx in [(0, 1), (3, -7), (-12, 5), (20, 20), (0, 31), (-31, 0), (16, -16)]:
+        assert abs(H[c + dy, c + dx].real - _shift_overlap(mask, dy, dx) / n) < 1e-12
+    yy, xx = np.mgrid[-c:c, -c:c]
+    u = np.minimum(np.hypot(yy, xx) / (P / 2), 1.0)
+    cont = 2 / np.pi * (np.arccos(u) - u * np.sqrt(1 - u * u))
+    assert np.abs(H.real - cont).max() < 0.05
+
+
+def test_otf_symmetry_and_tilt_removal():
+    """H(-xi) = conj H(xi) for each realisation; a pure tilt is a linear
+    phase (|H| is the diffraction OTF) that the short-exposure OTF removes
+    exactly; the SE OTF of any vector is the LE OTF of the vector without
+    its tilt coefficients."""
+    P = 32
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=35) * 0.5
+    H = ostats.otf_mean(a[None], P)
+    i = np.arange(P)
+    Hm = H[np.ix_((P - i) % P, (P - i) % P)]
+    assert np.abs(Hm - np.conj(H)).max() < 1e-12
+    H0 = ostats.otf_mean(np.zeros((1, 35)), P)
+    tilt = np.zeros(35)
+    tilt[:2] = [0.9, -0.6]
+    Ht = ostats.otf_mean(tilt[None], P)
+    assert np.abs(np.abs(Ht) - H0.real).max() < 1e-12 and np.abs(Ht - H0).max() > 0.1
+    assert np.abs(ostats.otf_mean(tilt[None], P, tilt_removed=True) - H0).max() < 1e-12
+    b = a.copy()
+    b[:2] = 0
+    assert np.abs(ostats.otf_mean(a[None], P, True) - ostats.otf_mean(b[None], P)).max() < 1e-12
+
+
+@pytest.mark.parametrize("tilt_removed", [False, True])
+def test_otf_monte_carlo_matches_gaussian_expectation(tilt_removed):
+    """For a ~ N(0, (D/r0)^{5/3} A_0) the sample mean of the OTF tends to
+    exp(-D(x, x') / 2) averaged over the aperture pairs (Gaussian phase):
+    2000 draws at D/r0 = 1.5 agree with otf_gaussian within 5 standard
+    errors (batch means) plus 1e-3 at every lag."""
+    P = 32
+    dr = 1.5
+    A0 = ozern.noll_matrix(1.0)
+    L = ozern.cholesky_lower(A0)
+    C = dr ** (5 / 3) * A0
+    rng = np.random.default_rng(77)
+    g = rng.standard_normal((2000, 35))
+    a = dr ** (5 / 6) * g @ L.T
+    means = np.stack([ostats.otf_mean(a[k::20], P, tilt_removed) for k in range(20)])
+    m = means.mean(0)
+    se_re = means.real.std(0, ddof=1) / np.sqrt(20)
+    se_im = means.imag.std(0, ddof=1) / np.sqrt(20)
+    ref = ostats.otf_gaussian(C, P, tilt_removed)
+    assert abs(ref[P // 2, P // 2] - 1) < 1e-12
+    assert np.all(np.abs(m.real - ref) <= 5 * se_re + 1e-3)
+    assert np.all(np.abs(m.imag) <= 5 * se_im + 1e-3)
+    # the mean OTF at mid lags lies clearly below the diffraction OTF
+    H0 = ostats.otf_mean(np.zeros((1, 35)), P).real
+    assert ref[P // 2, P // 2 + 8] < 0.9 * H0[P // 2, P // 2 + 8]
