@@ -222,6 +222,30 @@ int tsim_structure_function_ws_bytes(const tsim_plan *plan, int frames, size_t *
 int tsim_structure_function(const tsim_plan *plan, int frames, const float *zern, double *host_out,
                             double *host_moments, void *ws, tsim_stream stream);
 
+/* Long- and short-exposure optical transfer functions (the aperture
+ * statistics of Sec. IV-B): one realisation's OTF is the autocorrelation of
+ * the generalised pupil, H(xi) = sum_x G(x) conj(G(x - xi)) with
+ * G = P exp(-j phi) and phi = sum_j a_j Z_j over Noll 2..36; the long-
+ * exposure OTF is its mean over realisations, the short-exposure OTF the
+ * same with the tilt-corrected phase (the plane of best fit over the
+ * aperture, i.e. the Zernike tilts Noll 2 and 3, removed).  Every pixel of
+ * every frame is one realisation.  The pupil grid is the plan's P x P
+ * (P = 64 only: aperture 32 samples across, points strictly inside), and H
+ * is normalised so that H(0) = 1.  The device sums |DFT(G)|^2 over the
+ * realisations (FP32 per block, FP64 across blocks, fixed order); the host
+ * takes the inverse DFT of the mean in FP64.  Synchronises the stream.
+ *   zern           : device [frames][35][H][W] float32, 256-byte aligned
+ *   short_exposure : 0 for the long-exposure OTF, 1 for the short-exposure
+ *   host_out       : host [2][64][64] float64, real then imaginary part,
+ *                    lag (dy, dx) at index (32 + dy, 32 + dx), dy, dx in
+ *                    [-32, 32); written on success
+ *   ws             : device workspace of tsim_otf_ws_bytes(plan, frames)
+ *                    bytes, 256-byte aligned
+ * TSIM_EUNSUPPORTED for plans with P != 64. */
+int tsim_otf_ws_bytes(const tsim_plan *plan, int frames, size_t *bytes);
+int tsim_otf(const tsim_plan *plan, int frames, const float *zern, int short_exposure,
+             double *host_out, void *ws, tsim_stream stream);
+
 /* (a') Temporally correlated Zernike fields by an auto-regressive process,
  * the low-order workaround the paper gives for spatio-temporal correlation
  * (Sec. III-E): the unit-variance fields of frame t follow

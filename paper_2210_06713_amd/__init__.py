@@ -72,6 +72,8 @@ _lib_stats = _sig("tsim_tilt_stats", _i, [_vp, _i, _vp, _i, ctypes.POINTER(ctype
 _lib_sf_ws = _sig("tsim_structure_function_ws_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_size_t)])
 _lib_sf = _sig("tsim_structure_function", _i, [_vp, _i, _vp, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double), _vp, _vp])
+_lib_otf_ws = _sig("tsim_otf_ws_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_size_t)])
+_lib_otf = _sig("tsim_otf", _i, [_vp, _i, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp, _vp])
 _lib_p2s = _sig("tsim_p2s", _i, [_vp, _i, _vp, _vp, _vp, _vp])
 _lib_render = _sig("tsim_render", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp])
 _lib_warp = _sig("tsim_warp", _i, [_vp, _i, _vp, _vp, _vp, _vp])
@@ -117,7 +119,7 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_mlp_fit_output", "tsim_mlp_predict", "tsim_tilt_stats_ws_bytes", "tsim_tilt_stats",
             "tsim_structure_function_ws_bytes", "tsim_structure_function", "tsim_p2s_form",
             "tsim_last_error", "tsim_sync", "tsim_sample_zernike_noalloc", "tsim_batch_create",
-            "tsim_batch_launch", "tsim_batch_destroy"]
+            "tsim_batch_launch", "tsim_batch_destroy", "tsim_otf_ws_bytes", "tsim_otf"]
 
 
 def last_error():
@@ -407,6 +409,23 @@ class Plan:
                        C.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), _stream(stream)),
                "tsim_structure_function")
         return D, C
+
+    def otf(self, zern, short_exposure=False, ws=None, stream=None):
+        """Mean optical transfer function over all pixels of the frames
+        (tsim_otf): complex [64][64], lag (dy, dx) at (32 + dy, 32 + dx),
+        H(0) = 1; the short-exposure form removes the Zernike tilts."""
+        frames, dev = self._zern(zern)
+        n = ctypes.c_size_t()
+        if frames > 0:
+            _check(_lib_otf_ws(self._h, frames, ctypes.byref(n)), "tsim_otf_ws_bytes")
+        if ws is None:
+            ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
+        _expect_bytes(ws, "ws", n.value, dev)
+        out = np.zeros((2, 64, 64), dtype=np.float64)
+        _check(_lib_otf(self._h, frames, _ptr(zern), 1 if short_exposure else 0,
+                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), _stream(stream)),
+               "tsim_otf")
+        return out[0] + 1j * out[1]
 
     def p2s_form(self):
         """P2S_LEARNED if tsim_p2s runs the network now, else P2S_EXACT."""

@@ -86,6 +86,65 @@ int sample_ar_impl(const tsim_plan *pl, int frames, const float *d_over_r0, uint
   return launch_sampler_ar(pl, frames, scale.data(), alpha, zern_prev, sprev, seed, frame0, zern, ws, s);
 }
 
+// Mean OTF over all pixels of all frames (Sec. IV-B): the device sums
+// |DFT(G)|^2 over the vectors; the host takes the inverse 64 x 64 DFT of the
+// mean in FP64, moves lag 0 to index 32 and divides by the number of
+// aperture samples (H(0) = 1).
+int otf_impl(const tsim_plan *pl, int frames, const float *zern, int short_exposure, double *host_out, void *ws,
+             hipStream_t s) {
+  if (!frames_ok(pl, frames) || !zern || !host_out || !ws) return TSIM_EINVAL;
+  if (!aligned(zern) || !aligned(ws)) return TSIM_EINVAL;
+  if (short_exposure != 0 && short_exposure != 1) return TSIM_EINVAL;
+  if (pl->P != 64) return TSIM_EUNSUPPORTED;
+  constexpr int P = 64;
+  const size_t n = size_t(frames) * pl->H * pl->W;
+  double *dev_sums = reinterpret_cast<double *>(static_cast<char *>(ws) + otf_ws_bytes(pl, frames) -
+                                                size_t(P) * P * sizeof(double));
+  int st = launch_otf_sums(pl, frames, zern, short_exposure, ws, dev_sums, s);
+  if (st != TSIM_OK) return st;
+  std::vector<double> S(size_t(P) * P);
+  if (hipMemcpyAsync(S.data(), dev_sums, S.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return TSIM_EDEVICE;
+  int n_ap = 0;
+  for (int r = -16; r < 16; ++r)
+    for (int c = -16; c < 16; ++c) n_ap += (r * r + c * c < 256);
+  // H[ly][lx] = (1 / P^2) sum_k mean S[ky][kx] exp(+2 pi i (ky ly + kx lx) / P), separably
+  std::vector<double> cw(P), sw(P);
+  for (int j = 0; j < P; ++j) {
+    cw[j] = std::cos(2.0 * 3.14159265358979323846 * j / P);
+    sw[j] = std::sin(2.0 * 3.14159265358979323846 * j / P);
+  }
+  std::vector<double> Tr(size_t(P) * P), Ti(size_t(P) * P);   // [ky][lx]
+  for (int ky = 0; ky < P; ++ky)
+    for (int lx = 0; lx < P; ++lx) {
+      double re = 0.0, im = 0.0;
+      for (int kx = 0; kx < P; ++kx) {
+        const double v = S[size_t(ky) * P + kx];
+        const int j = (kx * lx) % P;
+        re += v * cw[j];
+        im += v * sw[j];
+      }
+      Tr[size_t(ky) * P + lx] = re;
+      Ti[size_t(ky) * P + lx] = im;
+    }
+  const double scale = 1.0 / (double(n) * P * P * n_ap);
+  for (int ly = 0; ly < P; ++ly)
+    for (int lx = 0; lx < P; ++lx) {
+      double re = 0.0, im = 0.0;
+      for (int ky = 0; ky < P; ++ky) {
+        const int j = (ky * ly) % P;
+        const double a = Tr[size_t(ky) * P + lx], b = Ti[size_t(ky) * P + lx];
+        re += a * cw[j] - b * sw[j];
+        im += a * sw[j] + b * cw[j];
+      }
+      const size_t o = size_t((ly + P / 2) % P) * P + (lx + P / 2) % P;
+      host_out[o] = re * scale;
+      host_out[size_t(P) * P + o] = im * scale;
+    }
+  return TSIM_OK;
+}
+
 // The form tsim_p2s runs: the network once one is set on a learned plan,
 // else the exact pupil-FFT path (also the learned form's fallback).
 int p2s_form(const tsim_plan *pl) {
@@ -255,6 +314,18 @@ int tsim_structure_function(const tsim_plan *pl, int frames, const float *zern, 
                             double *host_moments, void *ws, tsim_stream stream) {
   return note_status("tsim_structure_function",
                      sf_impl(pl, frames, zern, host_out, host_moments, ws, hs(stream)));
+}
+
+int tsim_otf_ws_bytes(const tsim_plan *pl, int frames, size_t *bytes) {
+  if (!bytes || !frames_ok(pl, frames)) return note_status("tsim_otf_ws_bytes", TSIM_EINVAL);
+  if (pl->P != 64) return note_status("tsim_otf_ws_bytes", TSIM_EUNSUPPORTED);
+  *bytes = otf_ws_bytes(pl, frames);
+  return TSIM_OK;
+}
+
+int tsim_otf(const tsim_plan *pl, int frames, const float *zern, int short_exposure, double *host_out, void *ws,
+             tsim_stream stream) {
+  return note_status("tsim_otf", otf_impl(pl, frames, zern, short_exposure, host_out, ws, hs(stream)));
 }
 
 int tsim_sample_zernike_ar(const tsim_plan *pl, int frames, const float *d_over_r0, uint64_t seed,

@@ -87,6 +87,18 @@ size_t moments_ws_bytes(const tsim_plan *pl, int frames);
 int launch_moments(const tsim_plan *pl, int frames, const float *zern, double *host_out, void *ws,
                    hipStream_t s);
 
+// sum over rows of part[rows][n_out] in FP64, in a fixed order, into the
+// device array out[n_out]
+int launch_partial_sum(const float *part, size_t rows, int n_out, double *out, hipStream_t s);
+
+// ---- optical transfer functions (psf.hip): the sums over all pixels of
+// all frames of |DFT(P exp(-i phi))|^2 on the 64 x 64 pupil grid, into the
+// device array dev_sums[64][64] (DFT order, kx fastest); workspace of
+// otf_ws_bytes (the sums' array may be its tail) ----
+size_t otf_ws_bytes(const tsim_plan *pl, int frames);
+int launch_otf_sums(const tsim_plan *pl, int frames, const float *zern, int short_exposure, void *ws,
+                    double *dev_sums, hipStream_t s);
+
 // ---- structure function (plan.cpp, host) ----
 constexpr int kSfPupil = 64;            // pupil grid: aperture 32 samples across
 constexpr int kSfLags = kSfPupil / 2 - 1;  // separations r = 0..30 samples

@@ -410,6 +410,103 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
 
+// The optical transfer functions of Sec. IV-B need the whole 64 x 64
+// spectrum of each generalised pupil G = P exp(-i phi): the OTF is the
+// autocorrelation of G, i.e. the inverse DFT of |DFT(G)|^2, and its sample
+// mean over coefficient vectors is the inverse DFT of the mean |DFT(G)|^2.
+// k_otf64 (P = 64): one wavefront per block takes the vectors s = block,
+// block + grid, ... in turn.  Stage 1: lanes 0-31 take window row wr = lane
+// and its 32-point DFT at even frequencies (E), lanes 32-63 the same row's
+// odd frequencies (O, input times exp(-2 pi i c'/64)); the 32 x 64 row
+// spectra go to LDS.  Stage 2: lane = frequency column kx = 2 (lane % 32) +
+// lane / 32, the even and odd row frequencies of the column by two more
+// 32-point DFTs; |.|^2 of all 64 is added to the lane's running sums.  At
+// the end the block writes its 64 x 64 sums (kx fastest, frequencies in
+// DFT order).  With TILT = false the tilt modes (Noll 2, 3: 2x and 2y on the
+// unit disc) enter the phase's Chebyshev series; TILT = true leaves them out
+// (the short-exposure OTF's tilt-corrected phase).
+template <bool TILT>
+__global__ void __launch_bounds__(64)
+k_otf64(const float *__restrict__ zern, int hw, size_t n, const float *__restrict__ zc, float *__restrict__ part) {
+  constexpr int LS = 33;
+  __shared__ float2 buf[2][32 * LS];
+  __shared__ float cbuf[64];
+  const int lane = threadIdx.x;
+  const int par = lane >> 5, m = lane & 31;
+  float acc[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) acc[k] = 0.f;
+  for (size_t smp = blockIdx.x; smp < n; smp += gridDim.x) {
+    const size_t fr = smp / size_t(hw), yx = smp - fr * size_t(hw);
+    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
+    {
+      // Chebyshev coefficient `lane` of the phase: modes 4..36 from the
+      // plan's table; the tilts 2 a2 x (entry p = 1, q = 0) and 2 a3 y (p =
+      // 0, q = 1) unless removed
+      float c = 0.f;
+#pragma unroll
+      for (int j = 0; j < 33; ++j) c = fmaf(zp[size_t(j + TSIM_PSF_MODE0) * hw], zc[j * 64 + lane], c);
+      if (!TILT) {
+        if (lane == 8) c = fmaf(2.f, zp[0], c);
+        if (lane == 1) c = fmaf(2.f, zp[size_t(hw)], c);
+      }
+      cbuf[lane] = c;
+    }
+    __syncthreads();
+    {
+      // ---- stage 1: row wr = m, parity par ----
+      const int rp = m - 16;
+      float d[8];
+      row_series(cbuf, float(rp) * 0.0625f, d);
+      float2 X[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) {
+        const int cp = (k < 16) ? k : k - 32;  // signed column offset
+        float2 v = make_float2(0.f, 0.f);
+        if (rp * rp + cp * cp < 256) {
+          float phi = 0.f;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) phi = fmaf(d[q], kChebCol[k][q], phi);
+          const float rev = phi * 0.15915494309189535f;
+          v = make_float2(__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev));
+        }
+        if (par) {
+          const int w = (cp + 64) & 63;
+          v = cmul(make_float2(kW64re[w], kW64im[w]), v);
+        }
+        X[k] = v;
+      }
+      fft_fwd<32>(X);
+#pragma unroll
+      for (int k = 0; k < 32; ++k) buf[par][m * LS + k] = X[k];
+    }
+    __syncthreads();
+    {
+      // ---- stage 2: column kx = 2 m + par (row spectra of parity par, entry m) ----
+      // even row frequencies, then odd ones (the column re-read from LDS,
+      // so one 32-point array is live at a time)
+#pragma unroll
+      for (int odd = 0; odd < 2; ++odd) {
+        float2 X[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+          const int rp = (k < 16) ? k : k - 32;
+          const float2 v = buf[par][(rp + 16) * LS + m];
+          const int w = (rp + 64) & 63;
+          X[k] = odd ? cmul(make_float2(kW64re[w], kW64im[w]), v) : v;
+        }
+        fft_fwd<32>(X);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) acc[2 * k + odd] += X[k].x * X[k].x + X[k].y * X[k].y;
+      }
+    }
+    __syncthreads();  // cbuf and buf are rewritten by the next vector
+  }
+  float *out = part + size_t(blockIdx.x) * 4096 + 2 * m + par;
+#pragma unroll
+  for (int ky = 0; ky < 64; ++ky) out[ky * 64] = acc[ky];
+}
+
 }  // namespace
 
 bool psf_size_supported(int P, int T) {
@@ -452,4 +549,32 @@ int launch_p2s_exact(const tsim_plan *pl, int frames, const float *zern, void *b
     if (st != TSIM_OK) return st;
   }
   return TSIM_OK;
+}
+
+// ---- optical transfer functions (Sec. IV-B) ----
+constexpr int kOtfMaxBlocks = 2048;
+
+size_t otf_blocks(size_t n) { return std::max<size_t>(1, std::min<size_t>(kOtfMaxBlocks, (n + 63) / 64)); }
+
+size_t otf_ws_bytes(const tsim_plan *pl, int frames) {
+  const size_t n = size_t(frames) * pl->H * pl->W;
+  return otf_blocks(n) * 4096 * sizeof(float) + 4096 * sizeof(double);
+}
+
+int launch_otf_sums(const tsim_plan *pl, int frames, const float *zern, int short_exposure, void *ws,
+                    double *dev_sums, hipStream_t s) {
+  if (pl->P != 64) return TSIM_EUNSUPPORTED;
+  const int hw = pl->H * pl->W;
+  const size_t n = size_t(frames) * hw;
+  const size_t blocks = otf_blocks(n);
+  float *part = static_cast<float *>(ws);
+  {
+    TraceScope tr("k_otf64", s);
+    if (short_exposure)
+      hipLaunchKernelGGL(k_otf64<true>, dim3(unsigned(blocks)), dim3(64), 0, s, zern, hw, n, pl->d_zcheb, part);
+    else
+      hipLaunchKernelGGL(k_otf64<false>, dim3(unsigned(blocks)), dim3(64), 0, s, zern, hw, n, pl->d_zcheb, part);
+    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+  }
+  return launch_partial_sum(part, blocks, 4096, dev_sums, s);
 }

@@ -198,3 +198,9 @@ int launch_moments(const tsim_plan *pl, int frames, const float *zern, double *h
   }
   return TSIM_OK;
 }
+
+int launch_partial_sum(const float *part, size_t rows, int n_out, double *out, hipStream_t s) {
+  TraceScope tr("k_tilt_stats_sum", s);
+  hipLaunchKernelGGL(k_tilt_stats_sum, dim3(n_out), dim3(kStatsThreads), 0, s, part, rows, n_out, out);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}

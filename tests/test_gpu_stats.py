@@ -110,3 +110,82 @@ def test_structure_function_follows_eq4(t):
     for r in (8, 16, 24):
         kol = 6.88 * (r / 32.0) ** (5.0 / 3.0)
         assert abs(D[r] / kol - 1.0) < 0.08, (r, D[r], kol)
+
+
+# ---- optical transfer functions (tsim_otf, Sec. IV-B) ----
+
+def _otf_err(got, ref):
+    d = np.abs(got - ref)
+    return float(np.linalg.norm(d) / np.linalg.norm(ref)), float(d.max() / np.abs(ref).max())
+
+
+@pytest.mark.parametrize("short", [False, True])
+def test_otf_random_planes(t, short):
+    """Mean OTF over the pixels of seeded random coefficient planes (ragged
+    size, two frames) against the oracle on the same float32 vectors: FP32
+    32-point transforms and per-block FP32 sums of |DFT|^2, FP64 totals and
+    inverse DFT, so relative L2 and largest element error <= 1e-5."""
+    say(f"otf random planes short={short}")
+    rng = np.random.default_rng(911)
+    F, H, W = 2, 13, 17
+    z = (rng.standard_normal((F, 35, H, W)) * 0.5).astype(np.float32)
+    plan = t.Plan(H, W, 1, 64, 64)
+    got = plan.otf(torch.tensor(z, device="cuda"), short_exposure=short)
+    ref = ostats.otf_mean(z.transpose(0, 2, 3, 1).reshape(-1, 35).astype(np.float64), 64, short)
+    e = _otf_err(got, ref)
+    say(f"  rel {e[0]:.2e} max {e[1]:.2e}")
+    assert max(e) < 1e-5
+
+
+@pytest.mark.parametrize("short", [False, True])
+def test_otf_sampler_frames(t, short):
+    """The same on the sampler's own fields (two 32 x 32 frames, D/r0 = 2)."""
+    say(f"otf sampler frames short={short}")
+    plan = t.Plan(32, 32, 1, 64, 64, pixel_pitch_over_d=0.125)
+    zern = torch.empty((2, 35, 32, 32), dtype=torch.float32, device="cuda")
+    plan.sample_zernike([2.0, 2.0], 3, 0, zern, plan.workspace(2))
+    got = plan.otf(zern, short_exposure=short)
+    z = zern.cpu().numpy().astype(np.float64)
+    ref = ostats.otf_mean(z.transpose(0, 2, 3, 1).reshape(-1, 35), 64, short)
+    e = _otf_err(got, ref)
+    say(f"  rel {e[0]:.2e} max {e[1]:.2e}")
+    assert max(e) < 1e-5
+
+
+def test_otf_diffraction_and_full_frames(t):
+    """Zero coefficients give the aperture's autocorrelation (the oracle's a =
+    0 OTF); on the timed workload's frames (16 of 512 x 512, D/r0 cycling
+    1, 2, 4) H(0) = 1, H(-xi) = conj H(xi), the short-exposure OTF lies
+    above the long-exposure one at mid lags (the tilt blur it removes), and
+    both lie below the diffraction OTF."""
+    say("otf diffraction limit and 16 frames of 512^2")
+    plan = t.Plan(20, 24, 1, 64, 64)
+    got = plan.otf(torch.zeros((1, 35, 20, 24), dtype=torch.float32, device="cuda"))
+    H0 = ostats.otf_mean(np.zeros((1, 35)), 64)
+    assert np.abs(got - H0).max() < 1e-6
+    big = t.Plan(512, 512, 1, 1024, 1024, pixel_pitch_over_d=0.125)
+    zern = torch.empty((16, 35, 512, 512), dtype=torch.float32, device="cuda")
+    big.sample_zernike([1.0, 2.0, 4.0] * 5 + [1.0], 0, 0, zern, big.workspace(16))
+    le = big.otf(zern)
+    se = big.otf(zern, short_exposure=True)
+    i = np.arange(64)
+    for H in (le, se):
+        assert abs(H[32, 32] - 1) < 1e-6
+        assert np.abs(H[np.ix_((64 - i) % 64, (64 - i) % 64)] - np.conj(H)).max() < 1e-6
+    assert se[32, 40].real > le[32, 40].real
+    assert le[32, 40].real < H0[32, 40].real and se[32, 40].real < H0[32, 40].real
+
+
+def test_otf_arguments(t):
+    say("otf argument checks")
+    plan = t.Plan(16, 16, 1, 64, 64)
+    z = torch.zeros((1, 35, 16, 16), dtype=torch.float32, device="cuda")
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    out = np.zeros((2, 64, 64))
+    st = t._lib_otf(plan._h, 1, t._ptr(z), 2, out.ctypes.data_as(t.ctypes.POINTER(t.ctypes.c_double)),
+                    t._ptr(ws), t._stream(None))
+    assert st == t.EINVAL
+    p128 = t.Plan(16, 16, 1, 64, 64, pupil_n=128, psf_t=65)
+    with pytest.raises(t.TsimError) as e:
+        p128.otf(z)
+    assert e.value.status == t.EUNSUPPORTED
