@@ -86,6 +86,12 @@ def kernel_work(name, frames, s):
     if name == "k_ar_scan":
         # read each fresh frame and write the correlated one, 35 planes
         return "hbm", px * 2 * 35 * 4, "B"
+    if name == "k_otf64":
+        # per pixel: the phase at the aperture samples (35 modes), the full
+        # 64 x 64 DFT of the pupil (31 window rows and 64 columns, each two
+        # pruned 32-point DFTs) and |.|^2
+        fft = 16 * 5 * 10 + 32 * 6
+        return "alu", px * (2 * 35 * n_aperture(64) + 31 * 2 * fft + 64 * 2 * fft + 3 * 64 * 64), "flop"
     if name == "k_mlp_infer":
         return "mfma", px * 2 * (35 * 256 + 2 * 256 * 256 + 256 * k), "flop"
     if name == "k_render_bf16":
@@ -523,6 +529,16 @@ def subharmonic_sampler(tsim, torch, wl, s, steps):
             out["structure_function"] = {"frames": n, "ms_per_call": round(ms_f, 4),
                                          "value": round(n * s["H"] * s["W"] / (ms_f * 1e-3) / 1e6, 3),
                                          "unit": "Mpixel/s", "kernels": kern_f}
+            # long- and short-exposure OTFs (each pixel's full 64 x 64 pupil
+            # spectrum on the device, inverse DFT of the mean on the host)
+            for name, short in (("otf_long_exposure", False), ("otf_short_exposure", True)):
+                pl.otf(wl.zern, short_exposure=short)
+                ms_o, rep_ = time_then_trace(tsim, torch, lambda i: pl.otf(wl.zern, short_exposure=short),
+                                             steps, host_clock=True)
+                kern_o, _ = summarize(rep_, steps, n, s, traffic=False)
+                out[name] = {"frames": n, "ms_per_call": round(ms_o, 4),
+                             "value": round(n * s["H"] * s["W"] / (ms_o * 1e-3) / 1e6, 3),
+                             "unit": "Mpixel/s", "kernels": kern_o}
         del ws
         pl.close()
     return out
