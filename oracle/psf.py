@@ -38,7 +38,7 @@ def zernike_stack(P, modes):
 
 def phase(a, P, modes=range(4, 37), zstack=None):
     """phi(xi) = sum_j a_j Z_j(xi) on the pupil grid (Eq. (5)); ``a`` is the
-    35-vector of Noll 2..36 coefficients."""
+    vector of Noll 2.. coefficients (35 of them for Noll 2..36)."""
     modes = list(modes)
     if zstack is None:
         zstack, _ = zernike_stack(P, modes)
@@ -77,14 +77,15 @@ def psf_batch(A, P, T, modes=range(4, 37)):
     return np.stack([psf_exact(a, P, T, modes, zstack) for a in A])
 
 
-def basis_draws(n, seed, dr_lo=0.5, dr_hi=5.0, tag=philox.TAG_BASIS):
+def basis_draws(n, seed, dr_lo=0.5, dr_hi=5.0, tag=philox.TAG_BASIS, n_modes=35):
     """Zernike vectors for the PSF database: a = (D/r0)^{5/6} L g with
-    g ~ N(0, I_35) from Philox counters (i, w, 0, tag), w = 0..8, and
-    D/r0 = lo + (hi - lo) u with u from word 0 of call (i, 9, 0, tag); tag 1
-    for the basis database, tag 2 for network training pairs."""
-    L = cholesky_lower(noll_matrix(1.0))
-    g = philox.gaussian_vectors(n, 35, 0, tag, seed)
-    u = philox.uniforms_extra(n, 9, 0, tag, seed)
+    g ~ N(0, I_N) from Philox counters (i, w, 0, tag), w = 0..ceil(N/4) - 1
+    (0..8 for N = 35), and D/r0 = lo + (hi - lo) u with u from word 0 of call
+    (i, ceil(N/4), 0, tag); tag 1 for the basis database, tag 2 for network
+    training pairs."""
+    L = cholesky_lower(noll_matrix(1.0, j_last=J_FIRST + n_modes - 1))
+    g = philox.gaussian_vectors(n, n_modes, 0, tag, seed)
+    u = philox.uniforms_extra(n, (n_modes + 3) // 4, 0, tag, seed)
     dr = dr_lo + (dr_hi - dr_lo) * u
     return (g @ L.T) * (dr ** (5.0 / 6.0))[:, None], dr
 
@@ -113,9 +114,12 @@ def project(psfs, Psi):
     return X @ Psi.T
 
 
-def psf_field(zern, P, T, Psi, modes=range(4, 37)):
-    """Plain-form P2S for a whole field: zern (35, H, W) -> beta (H, W, K)."""
+def psf_field(zern, P, T, Psi, modes=None):
+    """Plain-form P2S for a whole field: zern (N, H, W) -> beta (H, W, K);
+    the PSF takes modes 4..N+1 unless ``modes`` says otherwise."""
     n, H, W = zern.shape
+    if modes is None:
+        modes = range(4, n + 2)
     A = zern.reshape(n, -1).T
     h = psf_batch(A, P, T, modes)
     return project(h, Psi).reshape(H, W, -1)

@@ -15,7 +15,8 @@ white noise is drawn directly in the frequency domain as Hermitian complex
 Gaussian noise (same law as F(e)); two modes share one complex inverse FFT
 (real and imaginary parts); the field is cropped from the top-left corner of
 a zero-padded periodic grid; the L factor is the lower Cholesky factor in Noll
-order; modes are Noll j = 2..36.
+order; modes are Noll j = 2..36 by default, 2..J for n_modes = J - 1
+(Sec. II-B keeps N = 36 and notes that N can be raised at some cost).
 """
 import numpy as np
 
@@ -27,12 +28,12 @@ from .spectra import (all_spectra, discrete_correlation, subharmonic_amplitudes,
 N_FIELDS = (N_MODES + 1) // 2      # 18 complex fields carry 35 real modes
 
 
-def field_modes(q):
+def field_modes(q, n_modes=N_MODES):
     """Noll modes carried by complex field q: real part 2+2q, imaginary part
-    3+2q (absent for the last field)."""
+    3+2q (absent for the last field when n_modes is odd)."""
     a = J_FIRST + 2 * q
     b = a + 1
-    return a, (b if b <= J_FIRST + N_MODES - 1 else None)
+    return a, (b if b <= J_FIRST + n_modes - 1 else None)
 
 
 def hermitian_noise(Gh, Gw, q, frame, seed, tag=philox.TAG_SAMPLER):
@@ -93,8 +94,8 @@ def unit_fields(spectra, H, W, frame, seed, subharmonics=None):
     waves are added to the tilt fields."""
     n_modes, Gh, Gw = spectra.shape
     y = np.zeros((n_modes, H, W))
-    for q in range(N_FIELDS):
-        a, b = field_modes(q)
+    for q in range((n_modes + 1) // 2):
+        a, b = field_modes(q, n_modes)
         Wa, Wb = hermitian_noise(Gh, Gw, q, frame, seed)
         U = np.sqrt(spectra[a - J_FIRST]) * Wa
         if b is not None:
@@ -116,15 +117,16 @@ def mix(y, L, d_over_r0):
 
 
 def sample_zernike(H, W, Gh, Gw, ds, d_over_r0, seed, frame, fold=2, spectra=None, L=None,
-                   subharmonic_levels=0):
-    """Full oracle sampler for one frame: returns a (35, H, W) float64 array
-    zern[j-2, y, x].  ``subharmonic_levels`` > 0 adds the tilt modes'
-    subharmonic waves (``spectra``, if given, must be built with the same
-    levels)."""
+                   subharmonic_levels=0, n_modes=N_MODES):
+    """Full oracle sampler for one frame: returns a (n_modes, H, W) float64
+    array zern[j-2, y, x] (Noll 2..n_modes + 1).  ``subharmonic_levels`` > 0
+    adds the tilt modes' subharmonic waves (``spectra``, if given, must be
+    built with the same levels and modes)."""
     if spectra is None:
-        spectra = all_spectra(Gh, Gw, ds, fold, subharmonic_levels=subharmonic_levels)
+        spectra = all_spectra(Gh, Gw, ds, fold, j_last=J_FIRST + n_modes - 1,
+                              subharmonic_levels=subharmonic_levels)
     if L is None:
-        L = cholesky_lower(noll_matrix(1.0))
+        L = cholesky_lower(noll_matrix(1.0, j_last=J_FIRST + n_modes - 1))
     amps = (subharmonic_amplitudes(Gh, Gw, ds, fold, subharmonic_levels)
             if subharmonic_levels else None)
     y = unit_fields(spectra, H, W, frame, seed, subharmonics=amps)
@@ -132,7 +134,7 @@ def sample_zernike(H, W, Gh, Gw, ds, d_over_r0, seed, frame, fold=2, spectra=Non
 
 
 def sample_sequence_ar(H, W, Gh, Gw, ds, d_over_r0s, seed, frame0, alpha, y_prev=None, fold=2,
-                       spectra=None, L=None, subharmonic_levels=0):
+                       spectra=None, L=None, subharmonic_levels=0, n_modes=N_MODES):
     """Temporally correlated frames by an auto-regressive process (the
     workaround the paper gives for spatio-temporal correlation, Sec. III-E):
     the unit-variance fields follow ybar_t = alpha ybar_{t-1} +
@@ -146,9 +148,10 @@ def sample_sequence_ar(H, W, Gh, Gw, ds, d_over_r0s, seed, frame0, alpha, y_prev
     with the same levels).  Returns (frames (F, 35, H, W), the last frame's
     unit fields)."""
     if spectra is None:
-        spectra = all_spectra(Gh, Gw, ds, fold, subharmonic_levels=subharmonic_levels)
+        spectra = all_spectra(Gh, Gw, ds, fold, j_last=J_FIRST + n_modes - 1,
+                              subharmonic_levels=subharmonic_levels)
     if L is None:
-        L = cholesky_lower(noll_matrix(1.0))
+        L = cholesky_lower(noll_matrix(1.0, j_last=J_FIRST + n_modes - 1))
     amps = (subharmonic_amplitudes(Gh, Gw, ds, fold, subharmonic_levels)
             if subharmonic_levels else None)
     c = np.sqrt(1.0 - alpha * alpha)

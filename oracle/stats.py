@@ -80,23 +80,24 @@ def structure_function(zern, P=SF_PUPIL):
 # the circular lags of the grid hold it without wrap-around.
 
 
-def _otf_pupil(P, tilt_removed):
+def _otf_pupil(P, tilt_removed, n_modes=35):
     from .psf import pupil_grid
     from .zernike import zernike
     rho, theta, mask = pupil_grid(P)
     first = 4 if tilt_removed else 2
     Z = np.stack([np.where(mask, zernike(j, rho, theta), 0.0) if j >= first else np.zeros((P, P))
-                  for j in range(2, 37)])                          # [35][P][P]
+                  for j in range(2, n_modes + 2)])                 # [N][P][P]
     return Z, mask
 
 
 def otf_mean(zvecs, P, tilt_removed=False):
-    """Sample mean of the OTF over coefficient vectors ``zvecs`` (n, 35),
-    Noll 2..36.  Each realisation's autocorrelation is taken with the
+    """Sample mean of the OTF over coefficient vectors ``zvecs`` (n, N),
+    Noll 2..N+1.  Each realisation's autocorrelation is taken with the
     autocorrelation theorem, H = IFFT2(|FFT2(G)|^2) on the P x P grid.
     Returns a complex (P, P) array, zero lag at (P/2, P/2)."""
-    Z, mask = _otf_pupil(P, tilt_removed)
-    A = np.asarray(zvecs, dtype=np.float64).reshape(-1, 35)
+    A = np.asarray(zvecs, dtype=np.float64)
+    A = A.reshape(-1, A.shape[-1])
+    Z, mask = _otf_pupil(P, tilt_removed, A.shape[1])
     acc = np.zeros((P, P))
     for a in A:
         G = np.where(mask, np.exp(-1j * np.tensordot(a, Z, axes=1)), 0.0)
@@ -108,8 +109,9 @@ def otf_mean(zvecs, P, tilt_removed=False):
 def otf_direct(a, P, tilt_removed=False):
     """One realisation's OTF by the definition, sum over aperture points x of
     G(x) conj(G(x - xi)), for small grids (brute force)."""
-    Z, mask = _otf_pupil(P, tilt_removed)
-    phi = np.tensordot(np.asarray(a, dtype=np.float64), Z, axes=1)
+    a = np.asarray(a, dtype=np.float64)
+    Z, mask = _otf_pupil(P, tilt_removed, a.size)
+    phi = np.tensordot(a, Z, axes=1)
     G = np.where(mask, np.exp(-1j * phi), 0.0)
     H = np.zeros((P, P), dtype=complex)
     c = P // 2
@@ -127,10 +129,10 @@ def otf_direct(a, P, tilt_removed=False):
 
 def otf_gaussian(C, P, tilt_removed=False):
     """Expectation of the OTF for Gaussian coefficients a ~ N(0, C) (C the
-    35 x 35 covariance, Noll 2..36): E[exp(-j (phi(x) - phi(x - xi)))] =
+    N x N covariance, Noll 2..N+1): E[exp(-j (phi(x) - phi(x - xi)))] =
     exp(-D(x, x - xi) / 2) with D the phase structure function of the pair,
     (Z(x) - Z(x'))^T C (Z(x) - Z(x')).  Real, (P, P), zero lag at (P/2, P/2)."""
-    Z, mask = _otf_pupil(P, tilt_removed)
+    Z, mask = _otf_pupil(P, tilt_removed, C.shape[0])
     pts = np.argwhere(mask)
     Zp = Z[:, mask]                                                # [35][n_ap], same order as pts
     index = -np.ones((P, P), dtype=np.int64)

@@ -92,12 +92,14 @@ def _disc_quadrature(nr=48, nt=96):
 
 def test_zernike_orthonormal_on_disc():
     R, TH, Wt = _disc_quadrature()
-    Zs = np.stack([zernike.zernike(j, R, TH) for j in range(1, 37)])
+    # Noll 1..66: complete radial orders up to 10 (the largest mode count a
+    # plan takes)
+    Zs = np.stack([zernike.zernike(j, R, TH) for j in range(1, 67)])
     G = np.einsum('iab,jab,ab->ij', Zs, Zs, Wt) / np.pi
-    np.testing.assert_allclose(G, np.eye(36), atol=1e-12)
+    np.testing.assert_allclose(G, np.eye(66), atol=1e-12)
 
 
-@pytest.mark.parametrize("j", [2, 3, 4, 5, 6, 7, 8, 11, 12, 16, 22, 29, 36])
+@pytest.mark.parametrize("j", [2, 3, 4, 5, 6, 7, 8, 11, 12, 16, 22, 29, 36, 37, 44, 45, 52, 56, 61, 66])
 def test_zernike_fourier_transform_matches_direct_integral(j):
     R, TH, Wt = _disc_quadrature(64, 128)
     Z = zernike.zernike(j, R, TH)
@@ -147,9 +149,10 @@ def _a0_by_quadrature(i, j):
 
 
 @pytest.mark.parametrize("i,j", [(2, 2), (4, 4), (36, 36), (2, 8), (3, 7), (4, 11), (8, 16),
-                                 (11, 22), (6, 12), (5, 13), (2, 3), (4, 5), (7, 9)])
+                                 (11, 22), (6, 12), (5, 13), (2, 3), (4, 5), (7, 9),
+                                 (45, 45), (66, 66), (37, 56), (22, 37), (30, 46), (45, 53), (37, 38)])
 def test_noll_matrix_matches_spectral_quadrature(i, j):
-    A0 = zernike.noll_matrix(1.0)
+    A0 = zernike.noll_matrix(1.0, j_last=66)
     q = _a0_by_quadrature(i, j)
     closed = A0[i - 2, j - 2]
     assert abs(q - closed) <= 2e-5 * max(abs(A0[i - 2, i - 2]), 1e-3), (i, j, q, closed)

@@ -28,28 +28,34 @@ def test_spectrum_symmetry_and_normalisation():
         np.testing.assert_allclose(rho[0, 0], 1.0, rtol=1e-13)
 
 
-@pytest.mark.parametrize("j,tol", [(4, 5e-4), (5, 5e-4), (7, 2e-5), (11, 2e-5), (22, 2e-5), (36, 2e-5)])
-def test_lattice_correlation_matches_hankel_quadrature(j, tol):
+@pytest.mark.parametrize("j,tol,fold", [(4, 5e-4, 2), (5, 5e-4, 2), (7, 2e-5, 2), (11, 2e-5, 2), (22, 2e-5, 2),
+                                        (36, 2e-5, 2), (45, 5e-6, 4), (56, 5e-6, 4), (66, 5e-6, 4)])
+def test_lattice_correlation_matches_hankel_quadrature(j, tol, fold):
     """rho_bar_j[d] (FFT of the folded lattice spectrum) equals the continuous
     correlation rho_j(d ds) from direct quadrature.  Residuals come from the
     removed DC bin and the grid period; they shrink with radial order (the
-    n = 2 spectrum still carries a little power below the grid fundamental)."""
+    n = 2 spectrum still carries a little power below the grid fundamental).
+    Radial orders 8-10 carry more power beyond Nyquist, so they are checked
+    with aliases folded to |l| <= 4 (with the default |l| <= 2 the residual
+    of Noll 66 is 2.4e-5, the truncated alias sum)."""
     G, ds = 256, 0.125
-    rho = spectra.discrete_correlation(spectra.discrete_spectrum(j, G, G, ds))
+    rho = spectra.discrete_correlation(spectra.discrete_spectrum(j, G, G, ds, fold))
     for dy, dx in [(0, 1), (1, 0), (2, 3), (0, 8), (5, -4)]:
         c = spectra.continuous_correlation(j, dx * ds, dy * ds)
         assert abs(rho[dy % G, dx % G] - c) < tol, (j, dy, dx, rho[dy % G, dx % G], c)
 
 
-@pytest.mark.parametrize("Gh,Gw,ds,fold", [(64, 128, 0.125, 2), (32, 32, 0.3, 1)])
-def test_all_spectra_equals_per_mode_spectra(Gh, Gw, ds, fold):
+@pytest.mark.parametrize("Gh,Gw,ds,fold,jl", [(64, 128, 0.125, 2, 36), (32, 32, 0.3, 1, 36),
+                                              (32, 64, 0.125, 2, 66)])
+def test_all_spectra_equals_per_mode_spectra(Gh, Gw, ds, fold, jl):
     """The stacked, threaded route the sampler oracle uses (one Bessel order
     per radial order, aliases summed in parallel) equals ``discrete_spectrum``
     (pinned above against Hankel quadrature) mode by mode, for all 35 modes,
-    on a non-square grid and on a coarse grid with one alias fold."""
-    S = spectra.all_spectra(Gh, Gw, ds, fold)
-    assert S.shape == (35, Gh, Gw)
-    for t, j in enumerate(range(2, 37)):
+    on a non-square grid and on a coarse grid with one alias fold, and for
+    the 65 modes of Noll 2..66."""
+    S = spectra.all_spectra(Gh, Gw, ds, fold, j_last=jl)
+    assert S.shape == (jl - 1, Gh, Gw)
+    for t, j in enumerate(range(2, jl + 1)):
         ref = spectra.discrete_spectrum(j, Gh, Gw, ds, fold)
         np.testing.assert_allclose(S[t], ref, rtol=1e-12, atol=1e-14 * ref.max(), err_msg=f"j={j}")
 
@@ -111,6 +117,34 @@ def test_sampler_covariance_matches_eq9(mc, d):
     if d != (0, 0):
         A0 = zernike.noll_matrix(dr)
         assert np.max(np.abs(emp - A0) / (se + 1e-12)) > 20
+
+
+@pytest.fixture(scope="module")
+def mc44():
+    """Monte Carlo frames of the sampler with 44 modes (Noll 2..45, radial
+    orders up to 8)."""
+    Gh = Gw = 16
+    S = spectra.all_spectra(Gh, Gw, 0.5, j_last=45)
+    L = zernike.cholesky_lower(zernike.noll_matrix(1.0, j_last=45))
+    zs = np.array([sampler.mix(sampler.unit_fields(S, 8, 8, f, 11), L, 2.0) for f in range(1500)])
+    return S, L, zs
+
+
+@pytest.mark.parametrize("d", [(0, 0), (1, 0), (2, 3)])
+def test_sampler_covariance_matches_eq9_44_modes(mc44, d):
+    """The same identity of Eq. (9) with 44 modes (the paper's remark that N
+    can be raised): the sampler's lagged covariance equals the model's
+    entry by entry at 5.5 standard errors; at zero lag it is A_0."""
+    S, L, zs = mc44
+    assert zs.shape[1] == 44
+    per = _lagged_stats(zs, *d)
+    emp = per.mean(0)
+    se = per.std(0, ddof=1) / np.sqrt(per.shape[0])
+    At = sampler.approx_tensor(S, L, 2.0, [d])[0]
+    z = np.abs(emp - At) / (se + 1e-12)
+    assert np.max(z) < 5.5, (d, np.unravel_index(np.argmax(z), z.shape), np.max(z))
+    if d == (0, 0):
+        assert np.allclose(At, zernike.noll_matrix(2.0, j_last=45), atol=1e-12)
 
 
 def test_fig5_structure_before_and_after_mixing(mc):
