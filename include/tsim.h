@@ -55,6 +55,7 @@ enum { TSIM_P2S_EXACT = 0, TSIM_P2S_LEARNED = 1 };
 enum { TSIM_FP32 = 0, TSIM_BF16 = 1 };
 
 #define TSIM_N_MODES 35  /* Noll j = 2..36 (Sec. II-B keeps N = 36 modes; piston dropped) */
+#define TSIM_MAX_MODES 65 /* Noll j = 2..66: complete radial orders up to 10 */
 
 /*
  * Problem statement (Sec. II and its footnote on s = (x - x')/D).
@@ -62,7 +63,14 @@ enum { TSIM_FP32 = 0, TSIM_BF16 = 1 };
  *   H, W, C        image rows, columns, channels (1 <= H, W <= 4096, 1 <= C <= 4)
  *   Gh, Gw         zero-padded periodic FFT grid for the sampler; powers of
  *                  two, 64 <= G <= 4096, Gh >= H, Gw >= W
- *   n_modes        must be TSIM_N_MODES
+ *   n_modes        number of Zernike modes sampled, Noll j = 2..n_modes + 1:
+ *                  35 (Noll 2..36, radial orders up to 7, the paper's
+ *                  N = 36 with piston dropped), or 44, 54, 65 (complete
+ *                  radial orders up to 8, 9, 10: Sec. II-B notes that N
+ *                  can be raised at some cost in speed).  Coefficient
+ *                  planes are [frames][n_modes][H][W] throughout.  The
+ *                  learned P2S form and tsim_structure_function take
+ *                  n_modes = 35 only (TSIM_EUNSUPPORTED otherwise).
  *   pixel_pitch_over_d
  *                  one image pixel in units of the aperture diameter D
  *                  (the displacement unit of the Zernike space).  If <= 0 it
@@ -135,9 +143,9 @@ int tsim_plan_destroy(tsim_plan *plan);
 int tsim_workspace_bytes(const tsim_plan *plan, int frames, size_t *bytes);
 
 /* Copy a plan table to host memory as float64, for inspection and tests.
- *   what = 0: A_0 at D/r0 = 1, [35][35]
- *   what = 1: L, [35][35] lower triangular
- *   what = 2: sqrt of the quarter spectra, [35][Gw/2+1][Gh/2+1] (ky fastest)
+ *   what = 0: A_0 at D/r0 = 1, [N][N] (N = n_modes)
+ *   what = 1: L, [N][N] lower triangular
+ *   what = 2: sqrt of the quarter spectra, [N][Gw/2+1][Gh/2+1] (ky fastest)
  *   what = 3: pixel pitch over D, [1]
  *   what = 4: subharmonic wave amplitudes, [2 modes][4 levels][4 cells]
  *             (Noll 2, 3; level p = 1..4; cells (m, n) = (1,0), (1,1),
@@ -159,7 +167,7 @@ int tsim_plan_table(const tsim_plan *plan, int what, double *host_out, size_t co
  *           frame0+f, 5);
  *   step 2: a_x = (D/r0)^{5/6} L ybar_x at every pixel.
  *   d_over_r0 : host [frames], each > 0 and finite
- *   zern      : device [frames][35][H][W] float32, output
+ *   zern      : device [frames][N][H][W] float32, output
  *   ws        : device workspace of tsim_workspace_bytes(plan, frames) */
 int tsim_sample_zernike(const tsim_plan *plan, int frames, const float *d_over_r0,
                         uint64_t seed, uint64_t frame0, float *zern, void *ws,
@@ -180,7 +188,7 @@ int tsim_sample_zernike(const tsim_plan *plan, int frames, const float *d_over_r
  *   calls on one stream are ordered and safe.  The array's contents from
  *   the previous call are never read.  Launches are not traced.
  *   d_over_r0 : host [frames], each > 0 and finite
- *   zern      : device [frames][35][H][W] float32, output, 256-byte aligned */
+ *   zern      : device [frames][N][H][W] float32, output, 256-byte aligned */
 #define TSIM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 int tsim_sample_zernike_noalloc(const tsim_plan *plan, int frames, const float *d_over_r0,
                                 uint64_t seed, uint64_t frame0, float *zern,
@@ -192,7 +200,7 @@ int tsim_sample_zernike_noalloc(const tsim_plan *plan, int frames, const float *
  * lags d = 0..max_lag along x and along y, over `frames` frames.  Pairs stay
  * inside the frame: H (W - d) per frame for an x lag, (H - d) W for a y lag.
  * Row sums are FP32, their total FP64 in a fixed order (deterministic).
- *   zern     : device [frames][35][H][W] float32, 256-byte aligned (e.g. the
+ *   zern     : device [frames][N][H][W] float32, 256-byte aligned (e.g. the
  *              output of tsim_sample_zernike)
  *   max_lag  : 0 <= max_lag <= 256, below H and W
  *   host_out : host [2 modes][2 axes (x, y)][2 (correlation, DTV)][max_lag+1]
@@ -213,7 +221,7 @@ int tsim_tilt_stats(const tsim_plan *plan, int frames, const float *zern, int ma
  * is the coefficients' second moments C_jk = mean a_j a_k (FP32 tile sums,
  * FP64 total in a fixed order); D(r) = sum_jk C_jk mean(dZ_j dZ_k) follows on
  * the host.
- *   zern         : device [frames][35][H][W] float32, 256-byte aligned
+ *   zern         : device [frames][N][H][W] float32, 256-byte aligned
  *   host_out     : host [31] float64, D(r)
  *   host_moments : host [35][35] float64 (C), or NULL
  *   ws           : device workspace of tsim_structure_function_ws_bytes
@@ -234,7 +242,7 @@ int tsim_structure_function(const tsim_plan *plan, int frames, const float *zern
  * is normalised so that H(0) = 1.  The device sums |DFT(G)|^2 over the
  * realisations (FP32 per block, FP64 across blocks, fixed order); the host
  * takes the inverse DFT of the mean in FP64.  Synchronises the stream.
- *   zern           : device [frames][35][H][W] float32, 256-byte aligned
+ *   zern           : device [frames][N][H][W] float32, 256-byte aligned
  *   short_exposure : 0 for the long-exposure OTF, 1 for the short-exposure
  *   host_out       : host [2][64][64] float64, real then imaginary part,
  *                    lag (dy, dx) at index (32 + dy, 32 + dx), dy, dx in
@@ -257,7 +265,7 @@ int tsim_otf(const tsim_plan *plan, int frames, const float *zern, int short_exp
  *   a_t = alpha (s_t / s_{t-1}) a_{t-1} + sqrt(1 - alpha^2) a_t^new,
  * s = (D/r0)^{5/6}, which is the same recursion.
  *   alpha          : in [0, 1]
- *   zern_prev      : device [35][H][W] float32, the coefficients of the frame
+ *   zern_prev      : device [N][H][W] float32, the coefficients of the frame
  *                    before frame0, or NULL to start the sequence from
  *                    frame0's own (already stationary) draw; must not
  *                    overlap zern
@@ -275,7 +283,7 @@ int tsim_sample_zernike_ar(const tsim_plan *plan, int frames, const float *d_ove
  *   no network yet runs the exact form (the fallback; tsim_p2s_form tells
  *   which form runs).
  *   Output float32 in FP32 plans and bfloat16 in BF16 plans, either form.
- *   zern : device [frames][35][H][W] float32
+ *   zern : device [frames][N][H][W] float32
  *   beta : device [frames][H][W][K] float32, or in BF16 plans
  *          [frames][H][W][KP] bfloat16 with KP = K rounded up to 32, 64, 112
  *          or 128 (entries K..KP-1 written as 0) */
@@ -306,7 +314,7 @@ int tsim_render(const tsim_plan *plan, int frames, const float *img, const void 
  * from planes 0 and 1 of zern (a pure tilt a_2 moves the Eq. (2) PSF by
  * -4 a_2/pi samples).
  *   img, out : device [frames][C][H][W] float32, img != out
- *   zern     : device [frames][35][H][W] float32 */
+ *   zern     : device [frames][N][H][W] float32 */
 int tsim_warp(const tsim_plan *plan, int frames, const float *img, const float *zern,
               float *out, tsim_stream stream);
 
@@ -324,7 +332,7 @@ int tsim_warp(const tsim_plan *plan, int frames, const float *img, const float *
  *   for the individual calls, all 256-byte aligned, owned by the caller and
  *   kept alive and unmoved until tsim_batch_destroy: img, blur, out
  *   [frames][C][H][W] float32 (three distinct buffers), zern
- *   [frames][35][H][W] float32, beta per the plan's precision, ws of at
+ *   [frames][N][H][W] float32, beta per the plan's precision, ws of at
  *   least tsim_workspace_bytes(plan, frames) bytes (items may share one ws:
  *   the graph runs them in order).  The plans must outlive the batch.
  *   Every item is checked before anything is recorded (TSIM_EINVAL,
@@ -348,8 +356,9 @@ int tsim_batch_create(const tsim_batch_item *items, int n_items, uint64_t seed,
 int tsim_batch_launch(const tsim_batch *batch, tsim_stream stream);
 int tsim_batch_destroy(tsim_batch *batch);
 
-/* Exact PSFs of Eq. (2) for n Zernike vectors (modes 4..36 used):
- *   zvec : device [n][35] float32;  psf : device [n][T*T] float32, unit sum. */
+/* Exact PSFs of Eq. (2) for n Zernike vectors:
+ *   zvec : device [n][N] float32 (N the plan's n_modes; modes 4..N+1 enter
+ *          the phase);  psf : device [n][T*T] float32, unit sum. */
 int tsim_psf_exact(const tsim_plan *plan, int n, const float *zvec, float *psf,
                    tsim_stream stream);
 

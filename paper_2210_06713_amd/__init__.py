@@ -219,30 +219,30 @@ def _stream(stream):
 
 def make_params(H, W, C=1, Gh=None, Gw=None, pixel_pitch_over_d=0.125, aperture_d_m=0.0,
                 wavelength_m=0.0, path_length_m=0.0, alias_fold=2, pupil_n=64, psf_t=33,
-                basis_k=1, p2s_mode=P2S_EXACT, precision=FP32, subharmonic_levels=0):
+                basis_k=1, p2s_mode=P2S_EXACT, precision=FP32, subharmonic_levels=0, n_modes=N_MODES):
     if Gh is None:
         Gh = 1 << int(np.ceil(np.log2(2 * H)))
     if Gw is None:
         Gw = 1 << int(np.ceil(np.log2(2 * W)))
-    return _Params(H, W, C, Gh, Gw, N_MODES, pixel_pitch_over_d, aperture_d_m, wavelength_m,
+    return _Params(H, W, C, Gh, Gw, n_modes, pixel_pitch_over_d, aperture_d_m, wavelength_m,
                    path_length_m, alias_fold, pupil_n, psf_t, basis_k, None, p2s_mode, precision,
                    subharmonic_levels)
 
 
 def host_tables(params, what):
     """Run the host half of plan creation (no device) and return one table:
-    0 = A_0, 1 = L, 2 = sqrt quarter spectra [35][Gw/2+1][Gh/2+1], 3 = pitch,
+    0 = A_0, 1 = L, 2 = sqrt quarter spectra [N][Gw/2+1][Gh/2+1], 3 = pitch,
     4 = subharmonic amplitudes [2][4][4]."""
-    sizes = {0: N_MODES * N_MODES, 1: N_MODES * N_MODES,
-             2: N_MODES * (params.Gw // 2 + 1) * (params.Gh // 2 + 1), 3: 1, 4: 32}
+    N = params.n_modes
+    sizes = {0: N * N, 1: N * N, 2: N * (params.Gw // 2 + 1) * (params.Gh // 2 + 1), 3: 1, 4: 32}
     out = np.zeros(sizes[what], dtype=np.float64)
     _check(_lib_host_tables(ctypes.byref(params), what,
                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size),
            "tsim_host_tables")
     if what in (0, 1):
-        return out.reshape(N_MODES, N_MODES)
+        return out.reshape(N, N)
     if what == 2:
-        return out.reshape(N_MODES, params.Gw // 2 + 1, params.Gh // 2 + 1)
+        return out.reshape(N, params.Gw // 2 + 1, params.Gh // 2 + 1)
     if what == 4:
         return out.reshape(2, 4, 4)
     return out[0]
@@ -255,7 +255,7 @@ class Plan:
     def __init__(self, H, W, C=1, Gh=None, Gw=None, pixel_pitch_over_d=0.125,
                  aperture_d_m=0.0, wavelength_m=0.0, path_length_m=0.0, alias_fold=2,
                  pupil_n=64, psf_t=33, basis=None, basis_k=None, p2s_mode=P2S_EXACT,
-                 precision=FP32, subharmonic_levels=0):
+                 precision=FP32, subharmonic_levels=0, n_modes=N_MODES):
         if Gh is None:
             Gh = 1 << int(np.ceil(np.log2(2 * H)))
         if Gw is None:
@@ -268,10 +268,11 @@ class Plan:
             bptr = self._basis.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         if basis_k is None:
             basis_k = 1
-        self.params = _Params(H, W, C, Gh, Gw, N_MODES, pixel_pitch_over_d, aperture_d_m,
+        self.params = _Params(H, W, C, Gh, Gw, n_modes, pixel_pitch_over_d, aperture_d_m,
                               wavelength_m, path_length_m, alias_fold, pupil_n, psf_t, basis_k,
                               bptr, p2s_mode, precision, subharmonic_levels)
         self.H, self.W, self.C, self.Gh, self.Gw = H, W, C, Gh, Gw
+        self.N = n_modes
         self.T, self.K, self.P = psf_t, basis_k, pupil_n
         self.p2s_mode, self.precision = p2s_mode, precision
         self.KP = kpad(basis_k)
@@ -292,15 +293,15 @@ class Plan:
 
     # ---- plan tables -------------------------------------------------
     def table(self, what):
-        sizes = {0: N_MODES * N_MODES, 1: N_MODES * N_MODES,
-                 2: N_MODES * (self.Gw // 2 + 1) * (self.Gh // 2 + 1), 3: 1, 4: 32}
+        N = self.N
+        sizes = {0: N * N, 1: N * N, 2: N * (self.Gw // 2 + 1) * (self.Gh // 2 + 1), 3: 1, 4: 32}
         out = np.zeros(sizes[what], dtype=np.float64)
         _check(_lib_table(self._h, what, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                           out.size), "tsim_plan_table")
         if what in (0, 1):
-            return out.reshape(N_MODES, N_MODES)
+            return out.reshape(N, N)
         if what == 2:
-            return out.reshape(N_MODES, self.Gw // 2 + 1, self.Gh // 2 + 1)
+            return out.reshape(N, self.Gw // 2 + 1, self.Gh // 2 + 1)
         if what == 4:
             return out.reshape(2, 4, 4)
         return out[0]
@@ -318,8 +319,8 @@ class Plan:
     # ---- buffer checks (shapes the kernels assume) -----------------
     def _zern(self, zern, name="zern"):
         if zern is None or zern.dim() != 4:
-            raise ValueError(f"{name}: [frames, 35, H, W] tensor expected")
-        _expect(zern, name, (zern.shape[0], N_MODES, self.H, self.W), torch.float32)
+            raise ValueError(f"{name}: [frames, n_modes, H, W] tensor expected")
+        _expect(zern, name, (zern.shape[0], self.N, self.H, self.W), torch.float32)
         return zern.shape[0], zern.device
 
     def _frames_img(self, img, name, frames, device):
@@ -369,7 +370,7 @@ class Plan:
         if frames > 0:
             self._ws(ws, frames, dev)
         if zern_prev is not None:
-            _expect(zern_prev, "zern_prev", (N_MODES, self.H, self.W), torch.float32, dev)
+            _expect(zern_prev, "zern_prev", (self.N, self.H, self.W), torch.float32, dev)
         _check(_lib_sample_ar(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                               int(seed), int(frame0), float(alpha), _ptr(zern_prev),
                               float(d_over_r0_prev), _ptr(zern), _ptr(ws), _stream(stream)),
@@ -470,9 +471,9 @@ class Plan:
 
     def psf_exact(self, zvec, psf, stream=None):
         if zvec is None or zvec.dim() != 2:
-            raise ValueError("zvec: [n, 35] tensor expected")
+            raise ValueError("zvec: [n, n_modes] tensor expected")
         n = zvec.shape[0]
-        _expect(zvec, "zvec", (n, N_MODES), torch.float32)
+        _expect(zvec, "zvec", (n, self.N), torch.float32)
         _expect(psf, "psf", (n, self.T * self.T), torch.float32, zvec.device)
         _check(_lib_psf(self._h, n, _ptr(zvec), _ptr(psf), _stream(stream)),
                "tsim_psf_exact")

@@ -54,6 +54,7 @@ int stats_impl(const tsim_plan *pl, int frames, const float *zern, int max_lag, 
 int sf_impl(const tsim_plan *pl, int frames, const float *zern, double *host_out, double *host_moments, void *ws,
             hipStream_t s) {
   if (!frames_ok(pl, frames) || !zern || !host_out || !ws) return TSIM_EINVAL;
+  if (pl->N != TSIM_N_MODES) return TSIM_EUNSUPPORTED;   // moments and pair table of 35 modes
   if (!aligned(zern) || !aligned(ws)) return TSIM_EINVAL;
   std::vector<double> C(size_t(TSIM_N_MODES) * TSIM_N_MODES);
   int st = launch_moments(pl, frames, zern, C.data(), ws, s);
@@ -75,7 +76,7 @@ int sample_ar_impl(const tsim_plan *pl, int frames, const float *d_over_r0, uint
   if (zern_prev) {
     if (!aligned(zern_prev)) return TSIM_EINVAL;
     if (!(d_over_r0_prev > 0.f) || !std::isfinite(d_over_r0_prev)) return TSIM_EINVAL;
-    const size_t plane = size_t(TSIM_N_MODES) * pl->H * pl->W * sizeof(float);
+    const size_t plane = size_t(pl->N) * pl->H * pl->W * sizeof(float);
     const uintptr_t a0 = reinterpret_cast<uintptr_t>(zern), a1 = a0 + plane * size_t(frames);
     const uintptr_t b0 = reinterpret_cast<uintptr_t>(zern_prev), b1 = b0 + plane;
     if (b0 < a1 && a0 < b1) return TSIM_EINVAL;  // overlap

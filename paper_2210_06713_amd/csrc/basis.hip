@@ -21,13 +21,18 @@ namespace {
 
 using namespace tsim;
 
-__global__ void k_basis_draws(const float *__restrict__ Lmat, float *__restrict__ zvec, int n,
+// Coefficient vectors of the PSF database, N modes: g ~ N(0, I_N) from
+// the Gaussians of Philox calls (i, w, 0, 1), w < ceil(N/4), and D/r0 from
+// word 0 of call (i, ceil(N/4), 0, 1); a = (D/r0)^{5/6} L g.
+__global__ void k_basis_draws(const float *__restrict__ Lmat, float *__restrict__ zvec, int n, int N,
                               uint32_t key0, uint32_t key1, float lo, float hi) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float g[36];
+  float g[4 * ((kMaxModes + 3) / 4)];
+  const int calls = (N + 3) / 4;
 #pragma unroll
-  for (int w = 0; w < 9; ++w) {
+  for (int w = 0; w < (kMaxModes + 3) / 4; ++w) {
+    if (w >= calls) break;
     u32x4 r = philox4x32_10(u32x4{uint32_t(i), uint32_t(w), 0u, 1u}, key0, key1);
     float2 a = box_muller(r.x, r.y), b = box_muller(r.z, r.w);
     g[4 * w + 0] = a.x;
@@ -35,13 +40,13 @@ __global__ void k_basis_draws(const float *__restrict__ Lmat, float *__restrict_
     g[4 * w + 2] = b.x;
     g[4 * w + 3] = b.y;
   }
-  u32x4 r = philox4x32_10(u32x4{uint32_t(i), 9u, 0u, 1u}, key0, key1);
+  u32x4 r = philox4x32_10(u32x4{uint32_t(i), uint32_t(calls), 0u, 1u}, key0, key1);
   const float dr = lo + (hi - lo) * u01(r.x);
   const float sc = powf(dr, 5.0f / 6.0f);
-  for (int j = 0; j < TSIM_N_MODES; ++j) {
+  for (int j = 0; j < N; ++j) {
     float s = 0.f;
-    for (int k = 0; k <= j; ++k) s = fmaf(Lmat[j * TSIM_N_MODES + k], g[k], s);
-    zvec[size_t(i) * TSIM_N_MODES + j] = s * sc;
+    for (int k = 0; k <= j; ++k) s = fmaf(Lmat[j * N + k], g[k], s);
+    zvec[size_t(i) * N + j] = s * sc;
   }
 }
 
@@ -252,13 +257,13 @@ int basis_build_impl(const tsim_plan *pl, int n_psf, uint64_t seed, double dr_lo
   double *d_G = nullptr;
   int st = TSIM_OK;
   std::vector<double> G(size_t(T2) * T2), vecs, vals;
-  if (hipMalloc(&d_z, size_t(n_psf) * TSIM_N_MODES * sizeof(float)) != hipSuccess ||
+  if (hipMalloc(&d_z, size_t(n_psf) * pl->N * sizeof(float)) != hipSuccess ||
       hipMalloc(&d_h, size_t(n_psf) * T2 * sizeof(float)) != hipSuccess ||
       hipMalloc(&d_G, size_t(T2) * T2 * sizeof(double)) != hipSuccess) {
     st = TSIM_ENOMEM;
     goto done;
   }
-  hipLaunchKernelGGL(k_basis_draws, dim3((n_psf + 255) / 256), dim3(256), 0, 0, pl->d_L, d_z, n_psf,
+  hipLaunchKernelGGL(k_basis_draws, dim3((n_psf + 255) / 256), dim3(256), 0, 0, pl->d_L, d_z, n_psf, pl->N,
                      uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32), float(dr_lo), float(dr_hi));
   if (hipGetLastError() != hipSuccess) {
     st = TSIM_EDEVICE;

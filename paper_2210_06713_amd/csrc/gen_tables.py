@@ -4,7 +4,7 @@
 
 twiddle64.h / twiddle128.h: exp(-2 pi i k / N), k = 0..N-1, rounded to
 binary32 (forward-DFT twiddles).  cheb32.h / cheb64.h: Chebyshev T_p(x),
-p = 0..7, at the pupil-window columns of the pruned DFT input (entry n is
+p = 0..10 (phases up to radial order 10), at the pupil-window columns of the pruned DFT input (entry n is
 column offset c' = n for n < N/2, else n - N, and x = c' / (N/2)), by the
 three-term recurrence in binary64.
 """
@@ -41,13 +41,13 @@ def cheb(n):
     name = "kChebCol" if n == 32 else f"kChebCol{n}"
     out = ["#pragma once",
            f"// Chebyshev T_p(x) at the {n} pupil-window columns of the pruned DFT input:",
-           f"// entry n is column offset c' = n (n < {half}) or n - {n}, x = c'/{half}, p = 0..7.",
-           f"constexpr float {name}[{n}][8] = {{"]
+           f"// entry n is column offset c' = n (n < {half}) or n - {n}, x = c'/{half}, p = 0..10.",
+           f"constexpr float {name}[{n}][11] = {{"]
     for i in range(n):
         c = i if i < half else i - n
         x = c / half
         t = [1.0, x]
-        for _ in range(6):
+        for _ in range(9):
             t.append(2 * x * t[-1] - t[-2])
         out.append("    {" + ", ".join(f"{float(np.float32(v)):.9e}f" for v in t) + "},")
     out.append("};")

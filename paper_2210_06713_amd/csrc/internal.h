@@ -9,7 +9,13 @@
 
 #include "../../include/tsim.h"
 
-#define TSIM_FIELDS 18        // complex fields carrying the 35 real modes
+#define TSIM_FIELDS 18        // complex fields carrying the 35 real modes (the default plan)
+constexpr int kMaxModes = TSIM_MAX_MODES;   // Noll 2..66
+// mode counts a plan takes: complete radial orders up to 7, 8, 9, 10
+constexpr bool modes_supported(int n) { return n == 35 || n == 44 || n == 54 || n == 65; }
+// Chebyshev terms per axis of the pupil phase series: the modes' highest
+// radial order plus one (8 for Noll 2..36, 11 otherwise)
+constexpr int cheb_terms(int n) { return n == 35 ? 8 : 11; }
 #define TSIM_PSF_MODE0 2      // first mode index (0-based, Noll 4) inside the PSF
 
 constexpr int kProjectTile = 128;  // pixels per projection block (P2S chunks are multiples)
@@ -18,19 +24,20 @@ struct tsim_plan {
   tsim_params p;
   double ds;                   // pixel pitch over D
   int Gh, Gw, H, W, C, P, T, K;
+  int N, NF, NCH;              // modes (Noll 2..N+1), complex sampler fields, Chebyshev terms
   int KP;                      // K padded to 32, 64, 112 or 128
   // host FP64 copies (for tsim_plan_table)
-  std::vector<double> A0;      // [35][35] at D/r0 = 1
-  std::vector<double> L;       // [35][35] lower
-  std::vector<double> sqrtS;   // [35][Gw/2+1][Gh/2+1]
+  std::vector<double> A0;      // [N][N] at D/r0 = 1
+  std::vector<double> L;       // [N][N] lower
+  std::vector<double> sqrtS;   // [N][Gw/2+1][Gh/2+1]
   std::vector<double> subh;    // [2][4][4] subharmonic wave amplitudes (tilt modes)
   std::vector<double> basis;   // [K][T*T]
   // device tables
-  float *d_sqrtS = nullptr;    // [35][Gw/2+1][Gh/2+1] float32
+  float *d_sqrtS = nullptr;    // [N][Gw/2+1][Gh/2+1] float32
   float2 *d_tw_h = nullptr;    // twiddles exp(+2 pi i k / Gh), k < Gh/2
   float2 *d_tw_w = nullptr;    // twiddles exp(+2 pi i k / Gw), k < Gw/2
-  float *d_L = nullptr;        // [35][35] float32 lower
-  float *d_zcheb = nullptr;    // [33][8][8] 2D Chebyshev coefficients of modes 4..36 over the aperture
+  float *d_L = nullptr;        // [N][N] float32 lower
+  float *d_zcheb = nullptr;    // [N-2][NCH][NCH] 2D Chebyshev coefficients of modes 4..N+1 over the aperture
   float *d_basis = nullptr;    // [K][T*T] float32
   float *d_basis_t = nullptr;  // [T*T][KP] float32 (tap-major, zero padded)
   uint16_t *d_basis_bf = nullptr;  // [groups of 32 tap pairs][2][32][KP + 8] bfloat16, zero padded
@@ -130,8 +137,10 @@ int launch_render_f32_mfma(const tsim_plan *pl, int frames, const float *img, co
 // shapes the BF16 blur is built for: T in {15, 21, 33, 65} and an image
 // tile plus basis staging that fit the LDS (all but KP = 128, C = 4, T = 65)
 bool render_bf16_supported(int KP, int T, int C);
-// PSF supports the exact-PSF kernels are built for
-bool psf_size_supported(int P, int T);
+// PSF supports the exact-PSF kernels are built for: P = 64 with T in {9, 15,
+// 21, 31, 33} and P = 128 with T in {33, 65} for 35 modes; T = 33 (P = 64)
+// and T in {33, 65} (P = 128) for more
+bool psf_size_supported(int P, int T, int n_modes);
 int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
                 hipStream_t s);
 

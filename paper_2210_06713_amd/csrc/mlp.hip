@@ -637,7 +637,7 @@ namespace {
 int mlp_create_impl(const tsim_plan *pl, int batch, uint64_t seed, tsim_mlp **out) {
   if (!pl || !out || batch < 1 || batch > (1 << 20)) return TSIM_EINVAL;
   *out = nullptr;
-  if (pl->K > 128) return TSIM_EUNSUPPORTED;
+  if (pl->K > 128 || pl->N != TSIM_N_MODES) return TSIM_EUNSUPPORTED;   // 35 network inputs
   tsim_mlp *n = new (std::nothrow) tsim_mlp();
   if (!n) return TSIM_ENOMEM;
   n->K = pl->K;
@@ -795,6 +795,7 @@ int mlp_data_ws_bytes_impl(const tsim_plan *pl, int n_pairs, size_t *bytes) {
 int mlp_make_data_impl(const tsim_plan *pl, int n_pairs, uint64_t seed, float dr_lo, float dr_hi,
                        float *zvec, float *beta, void *ws, tsim_stream stream) {
   if (!pl || n_pairs < 1 || !zvec || !beta || !ws) return TSIM_EINVAL;
+  if (pl->N != TSIM_N_MODES) return TSIM_EUNSUPPORTED;
   if (!pl->d_basis) return TSIM_EARTEFACT;
   if (!(dr_lo > 0.f) || !(dr_hi >= dr_lo)) return TSIM_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -952,6 +953,7 @@ int tsim_mlp_train(tsim_mlp *n, const float *zvec, const float *target, int n_pa
 // Pack the network into the plan's inference layout (padded BF16 weights).
 int plan_set_mlp_impl(tsim_plan *pl, const tsim_mlp *n) {
   if (!pl || !n || n->K != pl->K) return TSIM_EINVAL;
+  if (pl->N != TSIM_N_MODES) return TSIM_EUNSUPPORTED;
   if (hipDeviceSynchronize() != hipSuccess) return TSIM_EDEVICE;
   std::vector<float> w(n->n_par), inv(TSIM_N_MODES), mu(n->K);
   if (hipMemcpy(w.data(), n->w, w.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||

@@ -9,7 +9,7 @@
 // current, at plan creation (noalloc_scratch_init); host code uses only that
 // address.  Frames are processed in chunks whose intermediate fits the
 // array, so any frame count works as long as one frame's intermediate
-// (18 * H * Gw * 8 bytes) fits in kScratchBytes.
+// (fields * H * Gw * 8 bytes, fields = ceil(n_modes / 2)) fits in kScratchBytes.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -49,7 +49,7 @@ int sample_noalloc_impl(const tsim_plan *pl, int frames, const float *d_over_r0,
   if (!pl || frames < 1 || frames > 65535 || !d_over_r0 || !zern) return TSIM_EINVAL;
   if ((reinterpret_cast<uintptr_t>(zern) & 255u) != 0) return TSIM_EINVAL;
   if (frame0 + uint64_t(frames) > (uint64_t(1) << 32)) return TSIM_EINVAL;
-  const size_t per_frame = size_t(TSIM_FIELDS) * pl->H * size_t(pl->Gw) * 2 * sizeof(float);
+  const size_t per_frame = size_t(pl->NF) * pl->H * size_t(pl->Gw) * 2 * sizeof(float);
   if (per_frame > kScratchBytes) {
     note_detail("one frame's intermediate exceeds the fixed scratch array (TSIM_NOALLOC_SCRATCH_BYTES)");
     return TSIM_EUNSUPPORTED;
@@ -64,7 +64,7 @@ int sample_noalloc_impl(const tsim_plan *pl, int frames, const float *d_over_r0,
   if (st != TSIM_OK) return st;
   TraceQuiet quiet;  // tracing would create timing events
   int chunk = int(std::min<size_t>(kScratchBytes / per_frame, size_t(kMaxChunkFrames)));
-  const size_t plane = size_t(TSIM_N_MODES) * pl->H * pl->W;
+  const size_t plane = size_t(pl->N) * pl->H * pl->W;
   float scale[kMaxChunkFrames];
   for (int f0 = 0; f0 < frames; f0 += chunk) {
     const int nf = std::min(chunk, frames - f0);

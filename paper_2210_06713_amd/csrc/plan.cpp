@@ -114,7 +114,7 @@ void bessel_j_orders(double x, int nmax, double *out) {
 
 // Spectrum of mode j (without its constant): f^{-11/3} |Q_j(f)|^2 with
 // |Q_j|^2 = (n+1) [2 J_{n+1}(pi f)/(pi f)]^2 Theta_j(phi), f in cycles per D.
-// `jb` holds J_0..J_8(pi f).  cos(m phi), sin(m phi) come from the caller.
+// `jb` holds J_0..J_11(pi f).  cos(m phi), sin(m phi) come from the caller.
 inline double mode_spectrum(int n, int m, int kind, double f, const double *jb, double cm,
                             double sm) {
   double x = kPi * f;
@@ -129,25 +129,25 @@ struct ModeInfo {
 
 // Spectra of all modes at (fx0, fy0) cycles per D, summed over the lattice
 // aliases (fx0 + lx/ds, fy0 + ly/ds), |lx|, |ly| <= A.
-void folded_spectra(const ModeInfo *mi, double fx0, double fy0, double ds, int A, double *acc) {
-  double jb[9];
-  double cm[8], sm[8];
-  for (int t = 0; t < TSIM_N_MODES; ++t) acc[t] = 0.0;
+void folded_spectra(const ModeInfo *mi, int N, double fx0, double fy0, double ds, int A, double *acc) {
+  double jb[12];
+  double cm[11], sm[11];
+  for (int t = 0; t < N; ++t) acc[t] = 0.0;
   for (int lx = -A; lx <= A; ++lx) {
     for (int ly = -A; ly <= A; ++ly) {
       double fx = fx0 + lx / ds;
       double fy = fy0 + ly / ds;
       double f = std::hypot(fx, fy);
       if (f == 0.0) continue;
-      bessel_j_orders(kPi * f, 8, jb);
+      bessel_j_orders(kPi * f, 11, jb);
       double c1 = fx / f, s1 = fy / f;
       cm[0] = 1.0;
       sm[0] = 0.0;
-      for (int q = 1; q < 8; ++q) {
+      for (int q = 1; q < 11; ++q) {
         cm[q] = cm[q - 1] * c1 - sm[q - 1] * s1;
         sm[q] = sm[q - 1] * c1 + cm[q - 1] * s1;
       }
-      for (int t = 0; t < TSIM_N_MODES; ++t)
+      for (int t = 0; t < N; ++t)
         acc[t] += mode_spectrum(mi[t].n, mi[t].m, mi[t].kind, f, jb, cm[mi[t].m], sm[mi[t].m]);
     }
   }
@@ -158,21 +158,22 @@ void build_spectra(tsim_plan *pl) {
   const int qh = Gh / 2 + 1, qw = Gw / 2 + 1;
   const int A = pl->p.alias_fold;
   const double ds = pl->ds;
-  ModeInfo mi[TSIM_N_MODES];
-  for (int t = 0; t < TSIM_N_MODES; ++t) {
+  const int N = pl->N;
+  ModeInfo mi[kMaxModes];
+  for (int t = 0; t < N; ++t) {
     int j = t + 2, n, m;
     noll_nm(j, &n, &m);
     mi[t] = {n, m, m == 0 ? 0 : (j % 2 == 0 ? 1 : 2)};
   }
   // quarter table S[mode][kx'][ky'] in float64
-  std::vector<double> S(size_t(TSIM_N_MODES) * qw * qh, 0.0);
+  std::vector<double> S(size_t(N) * qw * qh, 0.0);
   auto work = [&](int kx0, int kx1) {
     for (int kx = kx0; kx < kx1; ++kx) {
       for (int ky = 0; ky < qh; ++ky) {
         if (kx == 0 && ky == 0) continue;  // DC removed
-        double acc[TSIM_N_MODES];
-        folded_spectra(mi, double(kx) / (Gw * ds), double(ky) / (Gh * ds), ds, A, acc);
-        for (int t = 0; t < TSIM_N_MODES; ++t) S[(size_t(t) * qw + kx) * qh + ky] = acc[t];
+        double acc[kMaxModes];
+        folded_spectra(mi, N, double(kx) / (Gw * ds), double(ky) / (Gh * ds), ds, A, acc);
+        for (int t = 0; t < N; ++t) S[(size_t(t) * qw + kx) * qh + ky] = acc[t];
       }
     }
   };
@@ -194,8 +195,8 @@ void build_spectra(tsim_plan *pl) {
   for (int p = 1; p <= levels; ++p) {
     const double r = std::pow(3.0, p);
     for (int c = 0; c < 4; ++c) {
-      double acc[TSIM_N_MODES];
-      folded_spectra(mi, kCell[c][0] / (Gw * ds * r), kCell[c][1] / (Gh * ds * r), ds, A, acc);
+      double acc[kMaxModes];
+      folded_spectra(mi, N, kCell[c][0] / (Gw * ds * r), kCell[c][1] / (Gh * ds * r), ds, A, acc);
       for (int t = 0; t < 2; ++t) {
         cellS[t][p - 1][c] = acc[t];
         cellW[t] += 2.0 * acc[t] / (r * r);
@@ -207,7 +208,7 @@ void build_spectra(tsim_plan *pl) {
   // subharmonic cells): interior quarter bins stand for two mirror bins per
   // axis, the DC and Nyquist rows/columns for one.
   pl->sqrtS.assign(S.size(), 0.0);
-  for (int t = 0; t < TSIM_N_MODES; ++t) {
+  for (int t = 0; t < N; ++t) {
     double tot = t < 2 ? cellW[t] : 0.0;
     for (int kx = 0; kx < qw; ++kx) {
       double wx = (kx == 0 || kx == Gw / 2) ? 1.0 : 2.0;
@@ -264,7 +265,9 @@ int validate(const tsim_params *p) {
   if (!pow2(p->Gh) || !pow2(p->Gw) || p->Gh < 64 || p->Gw < 64 || p->Gh > 4096 || p->Gw > 4096)
     return TSIM_EINVAL;
   if (p->Gh < p->H || p->Gw < p->W) return TSIM_EINVAL;
-  if (p->n_modes != TSIM_N_MODES) return TSIM_EINVAL;
+  if (!modes_supported(p->n_modes)) return TSIM_EINVAL;
+  // the network's input layer is 35 wide
+  if (p->p2s_mode == TSIM_P2S_LEARNED && p->n_modes != TSIM_N_MODES) return TSIM_EUNSUPPORTED;
   if (p->alias_fold < 0 || p->alias_fold > 4) return TSIM_EINVAL;
   if (!(p->pixel_pitch_over_d > 0.0) || !std::isfinite(p->pixel_pitch_over_d)) {
     if (!(p->aperture_d_m > 0.0) || !(p->wavelength_m > 0.0) || !(p->path_length_m > 0.0))
@@ -279,7 +282,7 @@ int validate(const tsim_params *p) {
   // the exact path (plain form, basis build, training pairs, and the learned
   // form's fallback) must exist for the plan's PSF support, and so must the
   // BF16 blur in BF16 plans
-  if (!psf_size_supported(p->pupil_n, p->psf_t)) return TSIM_EUNSUPPORTED;
+  if (!psf_size_supported(p->pupil_n, p->psf_t, p->n_modes)) return TSIM_EUNSUPPORTED;
   const int kp = p->basis_k <= 32 ? 32 : p->basis_k <= 64 ? 64 : p->basis_k <= 112 ? 112 : 128;
   if (p->precision == TSIM_BF16 && !render_bf16_supported(kp, p->psf_t, p->C)) return TSIM_EUNSUPPORTED;
   return TSIM_OK;
@@ -383,8 +386,11 @@ int build_host(const tsim_params *p, tsim_plan *pl) {
   pl->ds = (p->pixel_pitch_over_d > 0.0)
                ? p->pixel_pitch_over_d
                : p->path_length_m * p->wavelength_m / (2.0 * p->aperture_d_m * p->aperture_d_m);
+  pl->N = p->n_modes;
+  pl->NF = (p->n_modes + 1) / 2;
+  pl->NCH = cheb_terms(p->n_modes);
   // Noll matrix and its Cholesky factor
-  const int N = TSIM_N_MODES;
+  const int N = pl->N;
   double c = kolmogorov_c();
   double kc = 8.0 * c * std::pow(kPi, 8.0 / 3.0) * std::tgamma(14.0 / 3.0) / std::pow(2.0, 14.0 / 3.0);
   pl->A0.assign(size_t(N) * N, 0.0);
@@ -487,16 +493,19 @@ int plan_create_impl(const tsim_params *p, tsim_plan **out) {
     if ((st = upload(&pl->d_L, Lf.data(), Lf.size())) != TSIM_OK) goto fail;
   }
   {
-    // Phase of modes 4..36 as 2D Chebyshev series over the aperture square:
-    // Z_j(x, y) = sum_{p,q < 8} E[j][p][q] T_p(x) T_q(y) exactly (each mode up
-    // to radial order 7 is a polynomial of degree <= 7 in x and in y), with E
-    // by interpolation at the 8 x 8 Chebyshev nodes.  Coordinates are
-    // normalised to the aperture radius (P/4 samples), so the table does not
-    // depend on P.  Stored [j][p][q].
-    const int NZ = 33, NP = 8;
-    std::vector<float> zc(size_t(NZ) * NP * NP, 0.0f);
+    // Phase of modes 4..N+1 as 2D Chebyshev series over the aperture square:
+    // Z_j(x, y) = sum_{p,q < NCH} E[j][p][q] T_p(x) T_q(y) exactly (a mode of
+    // radial order n is a polynomial of degree <= n in x and in y, and NCH
+    // is the plan's highest order plus one), with E by interpolation at the
+    // NCH x NCH Chebyshev nodes.  Coordinates are normalised to the aperture
+    // radius (P/4 samples), so the table does not depend on P.  Stored
+    // [j][p][q].
+    const int NZ = pl->N - 2, NP = pl->NCH;
+    // zero padded to the kernels' 33 (8 terms) or 63 (11 terms) modes
+    const int NZP = NP == 8 ? 33 : 63;
+    std::vector<float> zc(size_t(NZP) * NP * NP, 0.0f);
     for (int t = 0; t < NZ; ++t) {
-      double f[NP][NP];
+      double f[11][11];
       for (int k = 0; k < NP; ++k)
         for (int l = 0; l < NP; ++l) {
           const double x = std::cos(kPi * (k + 0.5) / NP), y = std::cos(kPi * (l + 0.5) / NP);

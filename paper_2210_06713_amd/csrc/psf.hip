@@ -86,30 +86,63 @@ __device__ __forceinline__ float2 pick(const float2 (&E)[32], const float2 (&O)[
 }
 
 // This lane's row coefficients d_p = sum_q C[p][q] T_q(y) of the pixel's 2D
-// Chebyshev phase series C (from LDS), y the row's normalised coordinate.
-__device__ __forceinline__ void row_series(const float *cb, float y, float (&d)[8]) {
-  float ty[8];
+// Chebyshev phase series C (NCH x NCH, from LDS), y the row's normalised
+// coordinate.
+template <int NCH>
+__device__ __forceinline__ void row_series(const float *cb, float y, float (&d)[NCH]) {
+  float ty[NCH];
   ty[0] = 1.f;
   ty[1] = y;
 #pragma unroll
-  for (int q = 2; q < 8; ++q) ty[q] = fmaf(2.f * y, ty[q - 1], -ty[q - 2]);
+  for (int q = 2; q < NCH; ++q) ty[q] = fmaf(2.f * y, ty[q - 1], -ty[q - 2]);
 #pragma unroll
-  for (int p = 0; p < 8; ++p) {
+  for (int p = 0; p < NCH; ++p) {
     float s = 0.f;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s = fmaf(cb[8 * p + q], ty[q], s);
+    for (int q = 0; q < NCH; ++q) s = fmaf(cb[NCH * p + q], ty[q], s);
     d[p] = s;
   }
 }
 
-template <int T>
+// Modes in a pixel's phase (Noll 4..N+1) for a series of NCH terms: at
+// most 33 for NCH = 8 (Noll 4..36), 63 for NCH = 11 (Noll 4..66).
+template <int NCH>
+constexpr int kMaxPhaseModes = NCH == 8 ? 33 : 63;
+
+// The pixel's phase as a 2D Chebyshev series, entry e of C (row-major p, q):
+// sum over the modes of a_j E[j][e], E the plan's table, zero padded to
+// kMaxPhaseModes<NCH> modes of NCH^2 entries (a_j = 0 beyond the plan's).
+template <int NCH>
+__device__ __forceinline__ float cheb_entry(const float (&a)[kMaxPhaseModes<NCH>], const float *zc, int e) {
+  float c = 0.f;
+#pragma unroll
+  for (int j = 0; j < kMaxPhaseModes<NCH>; ++j) c = fmaf(a[j], zc[j * NCH * NCH + e], c);
+  return c;
+}
+
+// This pixel's coefficients of the phase modes 4..N+1 (nm = N - 2 of them;
+// 33 for NCH = 8), zero beyond: the loads are unconditional (a clamped mode
+// index), so they all go out together.
+template <int NCH>
+__device__ __forceinline__ void phase_coeffs(const float *zp, size_t hw, int nm, float (&a)[kMaxPhaseModes<NCH>]) {
+#pragma unroll
+  for (int t = 0; t < kMaxPhaseModes<NCH>; ++t) {
+    const int tt = NCH == 8 ? t : min(t, nm - 1);
+    const float v = zp[size_t(tt + TSIM_PSF_MODE0) * hw];
+    a[t] = (NCH == 8 || t < nm) ? v : 0.f;
+  }
+}
+
+template <int T, int NCH>
 __global__ void __launch_bounds__(256)
-k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
+k_psf64(const float *__restrict__ zern, int hw, int nmodes, size_t p_base, int n_pix,
         const float *__restrict__ zc, float *__restrict__ psf) {
+  constexpr int NCC = NCH * NCH, NMAX = kMaxPhaseModes<NCH>;
+  const int nm = nmodes - 2;
   constexpr int R = (T - 1) / 2;  // crop radius, <= 16
   constexpr int LS = 33;          // LDS row stride (complex)
   __shared__ float2 s1[8][32 * LS];
-  __shared__ float cbuf[8][64];   // per pixel: 2D Chebyshev coefficients of the phase
+  __shared__ float cbuf[8][NCC];  // per pixel: 2D Chebyshev coefficients of the phase
   const int lane = threadIdx.x & 31;
   const int slot = threadIdx.x >> 5;  // half-wave within the block
   float2 *buf = s1[slot];
@@ -117,27 +150,30 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
   const bool active = p < n_pix;
   const int pc = active ? p : 0;
 
-  // Zernike coefficients of modes 4..36 of this pixel
-  float a[33];
+  // Zernike coefficients of modes 4..N+1 of this pixel
+  float a[NMAX];
   {
     const size_t pg = p_base + size_t(pc);  // pixel index into zern
     const size_t fr = pg / size_t(hw), yx = pg - fr * size_t(hw);
-    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
-#pragma unroll
-    for (int t = 0; t < 33; ++t) a[t] = zp[size_t(t + TSIM_PSF_MODE0) * hw];
+    const float *zp = zern + fr * nmodes * size_t(hw) + yx;
+    phase_coeffs<NCH>(zp, size_t(hw), nm, a);
   }
 
   // the pixel's phase as a 2D Chebyshev series C[p][q] = sum_j a_j E[j][p][q]
-  // (lane: entries 2 lane, 2 lane + 1), shared through LDS
-  {
+  // (lane: entries 2 lane, 2 lane + 1 for 8 terms; lane, lane + 32, ... for
+  // 11), shared through LDS
+  if constexpr (NCH == 8) {
     float c0 = 0.f, c1 = 0.f;
 #pragma unroll
-    for (int j = 0; j < 33; ++j) {
-      c0 = fmaf(a[j], zc[j * 64 + 2 * lane], c0);
-      c1 = fmaf(a[j], zc[j * 64 + 2 * lane + 1], c1);
+    for (int j = 0; j < NMAX; ++j) {
+      c0 = fmaf(a[j], zc[j * NCC + 2 * lane], c0);
+      c1 = fmaf(a[j], zc[j * NCC + 2 * lane + 1], c1);
     }
     cbuf[slot][2 * lane] = c0;
     cbuf[slot][2 * lane + 1] = c1;
+  } else {
+#pragma unroll
+    for (int e = lane; e < NCC; e += 32) cbuf[slot][e] = cheb_entry<NCH>(a, zc, e);
   }
   __syncthreads();
 
@@ -147,8 +183,8 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
     const int wr = lane;
     const int rp = wr - 16;
     // this row's phase as a Chebyshev series in x: phi(x) = sum_p d_p T_p(x)
-    float d[8];
-    row_series(cbuf[slot], float(rp) * 0.0625f, d);
+    float d[NCH];
+    row_series<NCH>(cbuf[slot], float(rp) * 0.0625f, d);
 #pragma unroll
     for (int n = 0; n < 32; ++n) {
       const int cp = (n < 16) ? n : n - 32;  // signed column offset
@@ -156,7 +192,7 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
       if (rp * rp + cp * cp < 256) {
         float phi = 0.f;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) phi = fmaf(d[p], kChebCol[n][p], phi);
+        for (int p = 0; p < NCH; ++p) phi = fmaf(d[p], kChebCol[n][p], phi);
         // exp(-i phi) with the hardware sine/cosine (input in revolutions)
         const float rev = phi * 0.15915494309189535f;
         v = make_float2(__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev));
@@ -245,32 +281,29 @@ k_psf64(const float *__restrict__ zern, int hw, size_t p_base, int n_pix,
 // FFT-64s run one after the other, then its 65 outputs overwrite it.
 // Stage 2: lane = frequency column kx in [-32, 32); the column kx = +32 is a
 // direct 64-term DFT (row ky = +32 of it: twiddles (-i)^r', a wave sum).
-template <int T>
+template <int T, int NCH>
 __global__ void __launch_bounds__(64)
-k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__restrict__ zc,
+k_psf128(const float *__restrict__ zern, int hw, int nmodes, size_t p_base, const float *__restrict__ zc,
          float *__restrict__ psf) {
+  constexpr int NCC = NCH * NCH, NMAX = kMaxPhaseModes<NCH>;
+  const int nm = nmodes - 2;
   constexpr int R = (T - 1) / 2;  // crop radius, <= 32
   constexpr int LS = 65;          // LDS row stride (complex)
   __shared__ float2 buf[64 * LS];
-  __shared__ float cbuf[64];      // 2D Chebyshev coefficients of the phase
+  __shared__ float cbuf[NCC];     // 2D Chebyshev coefficients of the phase
   const int lane = threadIdx.x;
   const size_t p = blockIdx.x;
 
-  float a[33];
+  float a[NMAX];
   {
     const size_t pg = p_base + p;
     const size_t fr = pg / size_t(hw), yx = pg - fr * size_t(hw);
-    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
-#pragma unroll
-    for (int t = 0; t < 33; ++t) a[t] = zp[size_t(t + TSIM_PSF_MODE0) * hw];
+    const float *zp = zern + fr * nmodes * size_t(hw) + yx;
+    phase_coeffs<NCH>(zp, size_t(hw), nm, a);
   }
 
-  {
-    float c = 0.f;
 #pragma unroll
-    for (int j = 0; j < 33; ++j) c = fmaf(a[j], zc[j * 64 + lane], c);
-    cbuf[lane] = c;
-  }
+  for (int e = lane; e < NCC; e += 64) cbuf[e] = cheb_entry<NCH>(a, zc, e);
   __syncthreads();
 
   float2 X[64];
@@ -278,8 +311,8 @@ k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__r
   {
     const int wr = lane, rp = wr - 32;
     float2 *row = buf + wr * LS;
-    float d[8];
-    row_series(cbuf, float(rp) * 0.03125f, d);
+    float d[NCH];
+    row_series<NCH>(cbuf, float(rp) * 0.03125f, d);
 #pragma unroll
     for (int n = 0; n < 64; ++n) {
       const int cp = (n < 32) ? n : n - 64;
@@ -287,7 +320,7 @@ k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__r
       if (rp * rp + cp * cp < 1024) {
         float phi = 0.f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) phi = fmaf(d[q], kChebCol64[n][q], phi);
+        for (int q = 0; q < NCH; ++q) phi = fmaf(d[q], kChebCol64[n][q], phi);
         const float rev = phi * 0.15915494309189535f;
         v = make_float2(__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev));
       }
@@ -387,24 +420,36 @@ k_psf128(const float *__restrict__ zern, int hw, size_t p_base, const float *__r
 int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_base, int n, float *psf,
                     hipStream_t s) {
   const float *zt = pl->d_zcheb;
+  const int N = pl->N;
+  const bool wide = pl->NCH == 11;   // more than 35 modes
   if (pl->P == 128) {
     TraceScope tr("k_psf128", s);
-    switch (pl->T) {
-      case 65: hipLaunchKernelGGL(k_psf128<65>, dim3(n), dim3(64), 0, s, zern, hw, p_base, zt, psf); break;
-      case 33: hipLaunchKernelGGL(k_psf128<33>, dim3(n), dim3(64), 0, s, zern, hw, p_base, zt, psf); break;
-      default: return TSIM_EUNSUPPORTED;
-    }
+    if (pl->T == 65 && !wide)
+      hipLaunchKernelGGL((k_psf128<65, 8>), dim3(n), dim3(64), 0, s, zern, hw, N, p_base, zt, psf);
+    else if (pl->T == 33 && !wide)
+      hipLaunchKernelGGL((k_psf128<33, 8>), dim3(n), dim3(64), 0, s, zern, hw, N, p_base, zt, psf);
+    else if (pl->T == 65)
+      hipLaunchKernelGGL((k_psf128<65, 11>), dim3(n), dim3(64), 0, s, zern, hw, N, p_base, zt, psf);
+    else if (pl->T == 33)
+      hipLaunchKernelGGL((k_psf128<33, 11>), dim3(n), dim3(64), 0, s, zern, hw, N, p_base, zt, psf);
+    else
+      return TSIM_EUNSUPPORTED;
     return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
   }
   if (pl->P != 64) return TSIM_EUNSUPPORTED;
   dim3 grid((n + 7) / 8);
   TraceScope tr("k_psf64", s);
+  if (wide) {
+    if (pl->T != 33) return TSIM_EUNSUPPORTED;
+    hipLaunchKernelGGL((k_psf64<33, 11>), grid, dim3(256), 0, s, zern, hw, N, p_base, n, zt, psf);
+    return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+  }
   switch (pl->T) {
-    case 33: hipLaunchKernelGGL(k_psf64<33>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
-    case 31: hipLaunchKernelGGL(k_psf64<31>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
-    case 21: hipLaunchKernelGGL(k_psf64<21>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
-    case 15: hipLaunchKernelGGL(k_psf64<15>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
-    case 9: hipLaunchKernelGGL(k_psf64<9>, grid, dim3(256), 0, s, zern, hw, p_base, n, zt, psf); break;
+    case 33: hipLaunchKernelGGL((k_psf64<33, 8>), grid, dim3(256), 0, s, zern, hw, N, p_base, n, zt, psf); break;
+    case 31: hipLaunchKernelGGL((k_psf64<31, 8>), grid, dim3(256), 0, s, zern, hw, N, p_base, n, zt, psf); break;
+    case 21: hipLaunchKernelGGL((k_psf64<21, 8>), grid, dim3(256), 0, s, zern, hw, N, p_base, n, zt, psf); break;
+    case 15: hipLaunchKernelGGL((k_psf64<15, 8>), grid, dim3(256), 0, s, zern, hw, N, p_base, n, zt, psf); break;
+    case 9: hipLaunchKernelGGL((k_psf64<9, 8>), grid, dim3(256), 0, s, zern, hw, N, p_base, n, zt, psf); break;
     default: return TSIM_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
@@ -425,12 +470,14 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
 // DFT order).  With TILT = false the tilt modes (Noll 2, 3: 2x and 2y on the
 // unit disc) enter the phase's Chebyshev series; TILT = true leaves them out
 // (the short-exposure OTF's tilt-corrected phase).
-template <bool TILT>
+template <bool TILT, int NCH>
 __global__ void __launch_bounds__(64)
-k_otf64(const float *__restrict__ zern, int hw, size_t n, const float *__restrict__ zc, float *__restrict__ part) {
-  constexpr int LS = 33;
+k_otf64(const float *__restrict__ zern, int hw, int nmodes, size_t n, const float *__restrict__ zc,
+        float *__restrict__ part) {
+  constexpr int LS = 33, NCC = NCH * NCH, NMAX = kMaxPhaseModes<NCH>;
+  const int nm = nmodes - 2;
   __shared__ float2 buf[2][32 * LS];
-  __shared__ float cbuf[64];
+  __shared__ float cbuf[NCC];
   const int lane = threadIdx.x;
   const int par = lane >> 5, m = lane & 31;
   float acc[64];
@@ -438,26 +485,33 @@ k_otf64(const float *__restrict__ zern, int hw, size_t n, const float *__restric
   for (int k = 0; k < 64; ++k) acc[k] = 0.f;
   for (size_t smp = blockIdx.x; smp < n; smp += gridDim.x) {
     const size_t fr = smp / size_t(hw), yx = smp - fr * size_t(hw);
-    const float *zp = zern + fr * TSIM_N_MODES * size_t(hw) + yx;
+    const float *zp = zern + fr * nmodes * size_t(hw) + yx;
     {
-      // Chebyshev coefficient `lane` of the phase: modes 4..36 from the
-      // plan's table; the tilts 2 a2 x (entry p = 1, q = 0) and 2 a3 y (p =
-      // 0, q = 1) unless removed
-      float c = 0.f;
+      // Chebyshev coefficients of the phase: modes 4..N+1 from the plan's
+      // table; the tilts 2 a2 x (entry p = 1, q = 0) and 2 a3 y (p = 0,
+      // q = 1) unless removed
 #pragma unroll
-      for (int j = 0; j < 33; ++j) c = fmaf(zp[size_t(j + TSIM_PSF_MODE0) * hw], zc[j * 64 + lane], c);
-      if (!TILT) {
-        if (lane == 8) c = fmaf(2.f, zp[0], c);
-        if (lane == 1) c = fmaf(2.f, zp[size_t(hw)], c);
+      for (int e = lane; e < NCC; e += 64) {
+        float c = 0.f;
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) {
+          const int jj = NCH == 8 ? j : min(j, nm - 1);
+          const float v = zp[size_t(jj + TSIM_PSF_MODE0) * hw];
+          c = fmaf((NCH == 8 || j < nm) ? v : 0.f, zc[j * NCC + e], c);
+        }
+        if (!TILT) {
+          if (e == NCH) c = fmaf(2.f, zp[0], c);
+          if (e == 1) c = fmaf(2.f, zp[size_t(hw)], c);
+        }
+        cbuf[e] = c;
       }
-      cbuf[lane] = c;
     }
     __syncthreads();
     {
       // ---- stage 1: row wr = m, parity par ----
       const int rp = m - 16;
-      float d[8];
-      row_series(cbuf, float(rp) * 0.0625f, d);
+      float d[NCH];
+      row_series<NCH>(cbuf, float(rp) * 0.0625f, d);
       float2 X[32];
 #pragma unroll
       for (int k = 0; k < 32; ++k) {
@@ -466,7 +520,7 @@ k_otf64(const float *__restrict__ zern, int hw, size_t n, const float *__restric
         if (rp * rp + cp * cp < 256) {
           float phi = 0.f;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) phi = fmaf(d[q], kChebCol[k][q], phi);
+          for (int q = 0; q < NCH; ++q) phi = fmaf(d[q], kChebCol[k][q], phi);
           const float rev = phi * 0.15915494309189535f;
           v = make_float2(__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev));
         }
@@ -509,7 +563,8 @@ k_otf64(const float *__restrict__ zern, int hw, size_t n, const float *__restric
 
 }  // namespace
 
-bool psf_size_supported(int P, int T) {
+bool psf_size_supported(int P, int T, int n_modes) {
+  if (n_modes != 35) return (P == 64 && T == 33) || (P == 128 && (T == 65 || T == 33));
   if (P == 128) return T == 65 || T == 33;
   if (P == 64) return T == 33 || T == 31 || T == 21 || T == 15 || T == 9;
   return false;
@@ -570,10 +625,22 @@ int launch_otf_sums(const tsim_plan *pl, int frames, const float *zern, int shor
   float *part = static_cast<float *>(ws);
   {
     TraceScope tr("k_otf64", s);
-    if (short_exposure)
-      hipLaunchKernelGGL(k_otf64<true>, dim3(unsigned(blocks)), dim3(64), 0, s, zern, hw, n, pl->d_zcheb, part);
-    else
-      hipLaunchKernelGGL(k_otf64<false>, dim3(unsigned(blocks)), dim3(64), 0, s, zern, hw, n, pl->d_zcheb, part);
+    const int N = pl->N;
+    if (pl->NCH == 8) {
+      if (short_exposure)
+        hipLaunchKernelGGL((k_otf64<true, 8>), dim3(unsigned(blocks)), dim3(64), 0, s, zern, hw, N, n, pl->d_zcheb,
+                           part);
+      else
+        hipLaunchKernelGGL((k_otf64<false, 8>), dim3(unsigned(blocks)), dim3(64), 0, s, zern, hw, N, n, pl->d_zcheb,
+                           part);
+    } else {
+      if (short_exposure)
+        hipLaunchKernelGGL((k_otf64<true, 11>), dim3(unsigned(blocks)), dim3(64), 0, s, zern, hw, N, n,
+                           pl->d_zcheb, part);
+      else
+        hipLaunchKernelGGL((k_otf64<false, 11>), dim3(unsigned(blocks)), dim3(64), 0, s, zern, hw, N, n,
+                           pl->d_zcheb, part);
+    }
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
   }
   return launch_partial_sum(part, blocks, 4096, dev_sums, s);

@@ -68,13 +68,13 @@ k_render_fp32(const float *__restrict__ img, const float *__restrict__ beta,
 
 __global__ void __launch_bounds__(256)
 k_warp(const float *__restrict__ img, const float *__restrict__ zern, float *__restrict__ out,
-       int H, int W, int C) {
+       int H, int W, int C, int nmodes) {
   const int f = blockIdx.z;
   const int y = blockIdx.y;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= W) return;
   const size_t plane = size_t(H) * W;
-  const float *zf = zern + size_t(f) * TSIM_N_MODES * plane;
+  const float *zf = zern + size_t(f) * nmodes * plane;
   const float k = -1.27323954473516268f;  // -4/pi pixels per radian of tilt
   const float tx = k * zf[size_t(y) * W + x];
   const float ty = k * zf[plane + size_t(y) * W + x];
@@ -150,6 +150,6 @@ int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *
                 hipStream_t s) {
   dim3 grid((pl->W + 255) / 256, pl->H, frames);
   TraceScope tr("k_warp", s);
-  hipLaunchKernelGGL(k_warp, grid, dim3(256), 0, s, img, zern, out, pl->H, pl->W, pl->C);
+  hipLaunchKernelGGL(k_warp, grid, dim3(256), 0, s, img, zern, out, pl->H, pl->W, pl->C, pl->N);
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }

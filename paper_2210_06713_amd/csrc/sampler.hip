@@ -11,8 +11,8 @@
 // draws' LDS positions are read and formed once.
 // Pass 2 (k_sampler_rows_mix): one block per output row y inverse-transforms
 // V[f][q][y][:] along kx for every field, keeps columns x < W, and mixes the
-// 35 unit-variance fields at each pixel with (D/r0)^{5/6} L before writing
-// the 35 coefficient planes (only L's structurally non-zero entries, each
+// N unit-variance fields at each pixel with (D/r0)^{5/6} L before writing
+// the N coefficient planes (N = 35 modes by default, Noll 2..N+1) (only L's structurally non-zero entries, each
 // output plane written once its last field is in).  Only rows y < H survive pass 1 and only columns
 // x < W pass 2 (crop of the top-left corner of the periodic grid).
 #include <algorithm>
@@ -136,7 +136,7 @@ template <int IPT>
 __global__ void __launch_bounds__(512)
 k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, float2 *__restrict__ V,
                int Gh, int Gw, int log2h, int H, int NC, uint32_t key0, uint32_t key1,
-               uint32_t frame_base, int nf) {
+               uint32_t frame_base, int nf, int nmodes) {
   extern __shared__ float2 lds[];  // [NC][Gh] in the lds_swz layout, slot-major; then the twiddles
   float2 *tws = lds + NC * Gh;
   load_twiddles(tws, tw, Gh, log2h);
@@ -153,7 +153,7 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
   const int grp = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
   const int s0 = grp * NC;          // first slot of this block
   const int ma = 2 * q, mb = 2 * q + 1;  // 0-based mode indices (Noll 2+2q, 3+2q)
-  const bool has_b = mb < TSIM_N_MODES;
+  const bool has_b = mb < nmodes;
   // (NC / 2) Gh = IPT x 512 draws, plus two in the self-mirror pair
   const int tail = (s0 == 0 && threadIdx.x < 2) ? IPT * 512 + threadIdx.x : -1;
   DrawItem it[IPT];
@@ -174,7 +174,7 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
     if (tail >= 0) draw_noise(lds, itt, q, frame, key0, key1);
     __syncthreads();
     lds_fft_dit(lds, Gh, log2h, NC, ysh, tws, 1.f);
-    float2 *Vout = V + (size_t(fl) * TSIM_FIELDS + q) * size_t(H) * Gw + s0;
+    float2 *Vout = V + (size_t(fl) * gridDim.y + q) * size_t(H) * Gw + s0;
     for (int e = threadIdx.x; e < ritems; e += blockDim.x) {
       const int c = (e >> ysh) & (NC - 1);
       const int y = (e & ym) | ((e >> (ysh + log2nc)) << ysh);
@@ -191,18 +191,24 @@ k_sampler_cols(const float *__restrict__ sqrtS, const float2 *__restrict__ tw, f
 // matrix in Noll order) is non-zero only inside the (|m|, parity) groups of
 // modes: mode k feeds output t iff both have the same |m| (and, for m != 0,
 // the same parity of the Noll index) and k <= t.  Field q carries modes
-// 2q and 2q + 1 (0-based, Noll 2 + 2q and 3 + 2q); fields are transformed in
-// the order below, chosen so that at most 9 outputs have received some but
-// not all of their terms at any point, and each output is written as soon as
-// its last field is mixed in: few accumulators stay live per pixel.
+// 2q and 2q + 1 (0-based, Noll 2 + 2q and 3 + 2q).  For the 35 modes of the
+// default plan the mix is fused into the row pass: fields are transformed
+// in the order below, chosen so that at most 9 outputs have received some
+// but not all of their terms at any point, and each output is written as
+// soon as its last field is mixed in: few accumulators stay live per pixel.
+// Plans with more modes write the unit fields and mix them afterwards, group
+// by group (k_mix_groups).
+template <int N>
 struct MixPlan {
-  bool nz[TSIM_N_MODES][TSIM_N_MODES];  // L[t][k] structurally non-zero
-  int first[TSIM_N_MODES];               // position in kFieldOrder of output t's first term
-  int first_k[TSIM_N_MODES];             // mode of that first term
-  int last[TSIM_N_MODES];                // position in kFieldOrder of output t's last field
+  static constexpr int NF = (N + 1) / 2;
+  bool nz[N][N];   // L[t][k] structurally non-zero
+  int order[NF];   // fields in transform order
+  int first[N];    // position in `order` of output t's first term
+  int first_k[N];  // mode of that first term
+  int last[N];     // position in `order` of output t's last field
 };
 
-constexpr int kFieldOrder[TSIM_FIELDS] = {10, 4, 16, 8, 15, 9, 1, 17, 14, 3, 7, 5, 2, 11, 0, 6, 13, 12};
+constexpr int kFieldOrder35[18] = {10, 4, 16, 8, 15, 9, 1, 17, 14, 3, 7, 5, 2, 11, 0, 6, 13, 12};
 
 constexpr int noll_abs_m(int j) {
   int n = 0;
@@ -216,17 +222,21 @@ constexpr int mix_group(int t) {  // t = 0-based mode index (Noll t + 2)
   return m == 0 ? 0 : 2 * m - 1 + (j & 1);
 }
 
-constexpr MixPlan make_mix_plan() {
-  MixPlan mp{};
-  for (int t = 0; t < TSIM_N_MODES; ++t) {
+template <int N>
+constexpr MixPlan<N> make_mix_plan() {
+  static_assert(N == 35, "the fused mix is built for the 35-mode plan");
+  constexpr int NF = (N + 1) / 2;
+  MixPlan<N> mp{};
+  for (int t = 0; t < N; ++t) {
     mp.first[t] = mp.first_k[t] = mp.last[t] = -1;
-    for (int k = 0; k < TSIM_N_MODES; ++k) mp.nz[t][k] = k <= t && mix_group(k) == mix_group(t);
+    for (int k = 0; k < N; ++k) mp.nz[t][k] = k <= t && mix_group(k) == mix_group(t);
   }
-  for (int i = 0; i < TSIM_FIELDS; ++i) {
-    const int q = kFieldOrder[i];
-    for (int t = 0; t < TSIM_N_MODES; ++t) {
+  for (int i = 0; i < NF; ++i) mp.order[i] = kFieldOrder35[i];
+  for (int i = 0; i < NF; ++i) {
+    const int q = mp.order[i];
+    for (int t = 0; t < N; ++t) {
       const bool a = mp.nz[t][2 * q];
-      const bool b = 2 * q + 1 < TSIM_N_MODES && mp.nz[t][2 * q + 1];
+      const bool b = 2 * q + 1 < N && mp.nz[t][2 * q + 1];
       if ((a || b) && mp.first[t] < 0) {
         mp.first[t] = i;
         mp.first_k[t] = a ? 2 * q : 2 * q + 1;
@@ -237,7 +247,10 @@ constexpr MixPlan make_mix_plan() {
   return mp;
 }
 
-constexpr MixPlan kMix = make_mix_plan();
+template <int N>
+struct Mix {
+  static constexpr MixPlan<N> plan = make_mix_plan<N>();
+};
 
 struct RowArgs {
   float2 *lds;      // RW lines of Gw samples in the lds_swz layout (line term 0 and 1)
@@ -251,9 +264,9 @@ struct RowArgs {
 
 // The block's RW rows of field position I: GPT = Gw / NT samples per thread
 // and row, read into registers (GPT > 0), or straight into LDS (GPT = 0).
-template <int I, int NT, int RW, int GPT>
+template <int N, int I, int NT, int RW, int GPT>
 __device__ __forceinline__ void read_field(const RowArgs &a, float2 (&pre)[RW][GPT > 0 ? GPT : 1]) {
-  constexpr int q = kFieldOrder[I];
+  constexpr int q = Mix<N>::plan.order[I];
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     const float2 *row = a.V + (size_t(q) * a.H + a.y0 + (r < a.nrows ? r : 0)) * size_t(a.Gw);
@@ -262,15 +275,16 @@ __device__ __forceinline__ void read_field(const RowArgs &a, float2 (&pre)[RW][G
   }
 }
 
-// Field at position I of kFieldOrder for the block's RW rows: inverse
+// Field at position I of the transform order for the block's RW rows: inverse
 // transform of the rows (one LDS pass over all RW lines), then the field's
 // terms of the mix; outputs whose last field this is are written.  With
 // GPT > 0 the field's samples arrive in registers, read while the previous
 // field was transformed, and the next field's are requested here.
-template <int I, int PX, int NT, int RW, int GPT>
-__device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_MODES][RW][PX],
+template <int N, int I, int PX, int NT, int RW, int GPT>
+__device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[N][RW][PX],
                                           float2 (&pre)[RW][GPT > 0 ? GPT : 1]) {
-  constexpr int q = kFieldOrder[I];
+  constexpr MixPlan<N> kMix = Mix<N>::plan;
+  constexpr int q = kMix.order[I];
   constexpr int ta = 2 * q, tb = 2 * q + 1;
   if constexpr (GPT > 0) {
 #pragma unroll
@@ -280,7 +294,7 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
         const int c = threadIdx.x + j * NT;
         a.lds[r * a.Gw + lds_swz(bitrev(uint32_t(slot_col(c, a.Gw)), a.log2w), r)] = pre[r][j];
       }
-    if constexpr (I + 1 < TSIM_FIELDS) read_field<I + 1, NT, RW, GPT>(a, pre);
+    if constexpr (I + 1 < MixPlan<N>::NF) read_field<N, I + 1, NT, RW, GPT>(a, pre);
   } else {
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
@@ -303,17 +317,17 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
     }
   __syncthreads();  // lds is overwritten by the next field
 #pragma unroll
-  for (int t = 0; t < TSIM_N_MODES; ++t) {
+  for (int t = 0; t < N; ++t) {
     if (kMix.nz[t][ta]) {
-      const float la = a.Lmat[t * TSIM_N_MODES + ta];
+      const float la = a.Lmat[t * N + ta];
       const bool init = kMix.first[t] == I && kMix.first_k[t] == ta;
 #pragma unroll
       for (int r = 0; r < RW; ++r)
 #pragma unroll
         for (int k = 0; k < PX; ++k) acc[t][r][k] = init ? la * ya[r][k] : fmaf(la, ya[r][k], acc[t][r][k]);
     }
-    if (tb < TSIM_N_MODES && kMix.nz[t][tb]) {
-      const float lb = a.Lmat[t * TSIM_N_MODES + tb];
+    if (tb < N && kMix.nz[t][tb]) {
+      const float lb = a.Lmat[t * N + tb];
       const bool init = kMix.first[t] == I && kMix.first_k[t] == tb;
 #pragma unroll
       for (int r = 0; r < RW; ++r)
@@ -321,7 +335,7 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
         for (int k = 0; k < PX; ++k) acc[t][r][k] = init ? lb * yb[r][k] : fmaf(lb, yb[r][k], acc[t][r][k]);
     }
     if (kMix.last[t] == I) {
-      // opaque plane size: keeps the compiler from forming all 35 plane
+      // opaque plane size: keeps the compiler from forming all N plane
       // addresses at kernel entry and holding them in registers
       size_t plane = size_t(a.H) * a.W;
       asm volatile("" : "+s"(plane));
@@ -339,24 +353,20 @@ __device__ __forceinline__ void mix_field(const RowArgs &a, float (&acc)[TSIM_N_
   }
 }
 
-template <int I, int PX, int NT, int RW, int GPT>
+template <int N, int I, int PX, int NT, int RW, int GPT>
 struct FieldSteps {
-  __device__ __forceinline__ static void run(const RowArgs &a, float (&acc)[TSIM_N_MODES][RW][PX],
+  __device__ __forceinline__ static void run(const RowArgs &a, float (&acc)[N][RW][PX],
                                              float2 (&pre)[RW][GPT > 0 ? GPT : 1]) {
-    mix_field<I, PX, NT, RW, GPT>(a, acc, pre);
-    FieldSteps<I + 1, PX, NT, RW, GPT>::run(a, acc, pre);
+    if constexpr (I < MixPlan<N>::NF) {
+      mix_field<N, I, PX, NT, RW, GPT>(a, acc, pre);
+      FieldSteps<N, I + 1, PX, NT, RW, GPT>::run(a, acc, pre);
+    }
   }
-};
-
-template <int PX, int NT, int RW, int GPT>
-struct FieldSteps<TSIM_FIELDS, PX, NT, RW, GPT> {
-  __device__ __forceinline__ static void run(const RowArgs &, float (&)[TSIM_N_MODES][RW][PX],
-                                             float2 (&)[RW][GPT > 0 ? GPT : 1]) {}
 };
 
 // One block per RW consecutive output rows (the last block may hold fewer).
 // GPT = Gw / NT (field samples per thread and row, read one field ahead) or 0.
-template <int PX, int NT, int RW, int GPT>
+template <int N, int PX, int NT, int RW, int GPT>
 __global__ void __launch_bounds__(NT)
 k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
                    const float *__restrict__ Lmat, float *__restrict__ zern, int Gw, int log2w,
@@ -366,11 +376,11 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
   const int fl = blockIdx.y;
   RowArgs a;
   a.lds = lds;
-  a.V = V + size_t(fl) * TSIM_FIELDS * H * size_t(Gw);
+  a.V = V + size_t(fl) * MixPlan<N>::NF * H * size_t(Gw);
   a.tws = lds + RW * Gw;
   load_twiddles(lds + RW * Gw, tw, Gw, log2w);
   a.Lmat = Lmat;
-  a.out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * size_t(H) * W + size_t(y0) * W;
+  a.out = zern + size_t(frame_out0 + fl) * N * size_t(H) * W + size_t(y0) * W;
   a.Gw = Gw;
   a.log2w = log2w;
   a.H = H;
@@ -378,10 +388,91 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
   a.y0 = y0;
   a.nrows = min(RW, H - y0);
   a.sc = scales.s[fl];
-  float acc[TSIM_N_MODES][RW][PX];  // each output starts at its first term
+  float acc[N][RW][PX];  // each output starts at its first term
   float2 pre[RW][GPT > 0 ? GPT : 1];
-  if constexpr (GPT > 0) read_field<0, NT, RW, GPT>(a, pre);
-  FieldSteps<0, PX, NT, RW, GPT>::run(a, acc, pre);
+  if constexpr (GPT > 0) read_field<N, 0, NT, RW, GPT>(a, pre);
+  FieldSteps<N, 0, PX, NT, RW, GPT>::run(a, acc, pre);
+}
+
+// Row pass without the mix (plans with more than 35 modes): one block per
+// RW output rows inverse-transforms every field's rows and writes its real
+// and imaginary parts, cropped to W columns, as the unit fields of modes
+// 2q and 2q + 1 (planes of zern, unscaled); k_mix_groups then mixes them.
+template <int PX, int NT, int RW>
+__global__ void __launch_bounds__(NT)
+k_sampler_rows_unit(const float2 *__restrict__ V, const float2 *__restrict__ tw, float *__restrict__ zern, int Gw,
+                    int log2w, int H, int W, int nmodes, int frame_out0) {
+  extern __shared__ float2 lds[];
+  const int y0 = blockIdx.x * RW;
+  const int fl = blockIdx.y;
+  const int nfields = (nmodes + 1) / 2;
+  const int nrows = min(RW, H - y0);
+  float2 *tws = lds + RW * Gw;
+  load_twiddles(tws, tw, Gw, log2w);
+  const float2 *Vf = V + size_t(fl) * nfields * H * size_t(Gw);
+  const size_t plane = size_t(H) * W;
+  float *out = zern + size_t(frame_out0 + fl) * nmodes * plane + size_t(y0) * W;
+  for (int q = 0; q < nfields; ++q) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const float2 *row = Vf + (size_t(q) * H + y0 + (r < nrows ? r : 0)) * size_t(Gw);
+      for (int c = threadIdx.x; c < Gw; c += NT)
+        lds[r * Gw + lds_swz(bitrev(uint32_t(slot_col(c, Gw)), log2w), r)] = row[c];
+    }
+    __syncthreads();
+    lds_fft_dit(lds, Gw, log2w, RW, 0, tws, 1.f);
+    const bool has_b = 2 * q + 1 < nmodes;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      if (r >= nrows) break;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        const int x = threadIdx.x + k * NT;
+        if (x < W) {
+          const float2 z = lds[r * Gw + lds_swz(x, r)];
+          out[size_t(2 * q) * plane + size_t(r) * W + x] = z.x;
+          if (has_b) out[size_t(2 * q + 1) * plane + size_t(r) * W + x] = z.y;
+        }
+      }
+    }
+    __syncthreads();  // lds is overwritten by the next field
+  }
+}
+
+// The mix of Eq. (9) in place on unit fields, a = (D/r0)^{5/6} L ybar, one
+// (|m|, parity) group of modes at a time (L is block-diagonal on the groups):
+// a group's members (at most kMaxGroup, listed in Noll order) are read at a
+// pixel, their lower-triangular block of L applied, the outputs written.
+// One thread per pixel, grid (ceil(H W / 256), frames).
+constexpr int kMaxGroup = 6;   // modes per group up to radial order 10
+constexpr int kMaxGroups = 21; // m = 0 and two parities for m = 1..10
+struct MixGroups {
+  int count;
+  int member[kMaxGroups][kMaxGroup];            // 0-based mode index, -1 beyond the group
+  float L[kMaxGroups][kMaxGroup][kMaxGroup];    // the group's block of L
+};
+
+__global__ void __launch_bounds__(256)
+k_mix_groups(float *__restrict__ zern, size_t plane, int nmodes, FrameScales scales, int frame_out0,
+             MixGroups g) {
+  const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= plane) return;
+  const int fl = blockIdx.y;
+  float *z = zern + size_t(frame_out0 + fl) * nmodes * plane + e;
+  const float sc = scales.s[fl];
+  for (int gi = 0; gi < g.count; ++gi) {
+    float y[kMaxGroup];
+#pragma unroll
+    for (int i = 0; i < kMaxGroup; ++i) y[i] = g.member[gi][i] >= 0 ? z[size_t(g.member[gi][i]) * plane] : 0.f;
+#pragma unroll
+    for (int i = 0; i < kMaxGroup; ++i) {
+      if (g.member[gi][i] < 0) break;
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k <= i; ++k) a = fmaf(g.L[gi][i][k], y[k], a);
+      z[size_t(g.member[gi][i]) * plane] = a * sc;
+    }
+  }
 }
 
 // Subharmonic waves of the tilt fields, added after the mix: the waves w2,
@@ -390,7 +481,7 @@ k_sampler_rows_mix(const float2 *__restrict__ V, const float2 *__restrict__ tw,
 // tilt groups (|m| = 1).  One thread per pixel, grid (ceil(W/256), H,
 // frames); the first 4 * levels threads draw the frame's wave amplitudes.
 __global__ void __launch_bounds__(256)
-k_subharmonic_add(float *__restrict__ zern, const float *__restrict__ Lmat, int H, int W,
+k_subharmonic_add(float *__restrict__ zern, const float *__restrict__ Lmat, int H, int W, int N,
                   FrameScales scales, SubhArgs sub, int frame_out0) {
   __shared__ float coef[kSubhMaxLevels * 16];  // [level][cell][A2, B2, A3, B3]
   const int fl = blockIdx.z;
@@ -423,13 +514,14 @@ k_subharmonic_add(float *__restrict__ zern, const float *__restrict__ Lmat, int 
   }
   const float sc = scales.s[fl];
   const size_t plane = size_t(H) * W;
-  float *out = zern + size_t(frame_out0 + fl) * TSIM_N_MODES * plane + size_t(y) * W + x;
-#pragma unroll
-  for (int t = 0; t < TSIM_N_MODES; ++t) {
-    if (kMix.nz[t][0] || kMix.nz[t][1]) {
+  float *out = zern + size_t(frame_out0 + fl) * N * plane + size_t(y) * W + x;
+  // L[t][0] and L[t][1] are exactly zero outside the two tilt groups
+  for (int t = 0; t < N; ++t) {
+    const float l0 = Lmat[t * N], l1 = Lmat[t * N + 1];
+    if (l0 != 0.f || l1 != 0.f) {
       float d = 0.f;
-      if (kMix.nz[t][0]) d = fmaf(Lmat[t * TSIM_N_MODES], w2, d);
-      if (kMix.nz[t][1]) d = fmaf(Lmat[t * TSIM_N_MODES + 1], w3, d);
+      if (l0 != 0.f) d = fmaf(l0, w2, d);
+      if (l1 != 0.f) d = fmaf(l1, w3, d);
       out[size_t(t) * plane] += sc * d;
     }
   }
@@ -477,7 +569,7 @@ int ilog2(int v) {
 
 int frames_per_chunk(const tsim_plan *pl, int frames) {
   // bound the pass-1 intermediate to ~2 GB and the launch's scale table
-  size_t per = size_t(TSIM_FIELDS) * pl->H * size_t(pl->Gw) * sizeof(float2);
+  size_t per = size_t(pl->NF) * pl->H * size_t(pl->Gw) * sizeof(float2);
   size_t cap = size_t(2) << 30;
   int n = int(std::max<size_t>(1, cap / per));
   n = std::min(n, kMaxFramesPerLaunch);
@@ -489,38 +581,112 @@ int frames_per_chunk(const tsim_plan *pl, int frames) {
 size_t sampler_ws_bytes(const tsim_plan *pl, int frames) {
   if (frames < 1) return 0;
   int n = frames_per_chunk(pl, frames);
-  return size_t(n) * TSIM_FIELDS * pl->H * size_t(pl->Gw) * sizeof(float2);
+  return size_t(n) * pl->NF * pl->H * size_t(pl->Gw) * sizeof(float2);
 }
 
 // pass 2 with the per-thread sample count Gw / NT as a compile-time constant
 // where it is 2, 4 or 8 (the samples of the next field are then read one
-// field ahead), without the look-ahead otherwise and for the 1024-thread
+// field ahead), without the look-ahead otherwise, for the 1024-thread
 // blocks (whose extra registers would halve the blocks resident per CU)
-template <int PX, int NT, int RW>
+template <int N, int PX, int NT, int RW>
 void launch_rows(dim3 grid, size_t lds, hipStream_t s, const float2 *V, const float2 *tw, const float *L,
                  float *zern, int Gw, int log2w, int H, int W, FrameScales sc, int f0) {
   if constexpr (NT > 256) {
-    hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 0>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w, H, W,
-                       sc, f0);
+    hipLaunchKernelGGL((k_sampler_rows_mix<N, PX, NT, RW, 0>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
+                       H, W, sc, f0);
   } else {
     switch (Gw / NT) {
       case 2:
-        hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 2>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
-                           H, W, sc, f0);
+        hipLaunchKernelGGL((k_sampler_rows_mix<N, PX, NT, RW, 2>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw,
+                           log2w, H, W, sc, f0);
         break;
       case 4:
-        hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 4>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
-                           H, W, sc, f0);
+        hipLaunchKernelGGL((k_sampler_rows_mix<N, PX, NT, RW, 4>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw,
+                           log2w, H, W, sc, f0);
         break;
       case 8:
-        hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 8>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
-                           H, W, sc, f0);
+        hipLaunchKernelGGL((k_sampler_rows_mix<N, PX, NT, RW, 8>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw,
+                           log2w, H, W, sc, f0);
         break;
       default:
-        hipLaunchKernelGGL((k_sampler_rows_mix<PX, NT, RW, 0>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw, log2w,
-                           H, W, sc, f0);
+        hipLaunchKernelGGL((k_sampler_rows_mix<N, PX, NT, RW, 0>), grid, dim3(NT), lds, s, V, tw, L, zern, Gw,
+                           log2w, H, W, sc, f0);
     }
   }
+}
+
+// pass 2 (with the mix for 35 modes; unit fields and k_mix_groups beyond)
+// and the subharmonic waves
+int launch_rows_n(const tsim_plan *pl, int nf, int f0, const float2 *V, float *zern, const FrameScales &sc,
+                  const SubhArgs &sub, hipStream_t s) {
+  const int Gw = pl->Gw, H = pl->H, W = pl->W, log2w = ilog2(Gw);
+  {
+    TraceScope tr("k_sampler_rows_mix", s);
+    // two rows per block (one LDS transform pass and one barrier set for both)
+    // up to 1024 columns; 1024-thread blocks over single rows beyond
+    const size_t lds2 = (2 * size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
+    const size_t lds1 = (size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
+    dim3 g2((H + 1) / 2, nf), g1r(H, nf);
+    if (pl->N == 35) {
+      if (W <= 256)
+        launch_rows<35, 1, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
+      else if (W <= 512)
+        launch_rows<35, 2, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
+      else if (W <= 1024)
+        launch_rows<35, 4, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
+      else
+        launch_rows<35, 4, 1024, 1>(g1r, lds1, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
+    } else {
+      const int N = pl->N;
+      if (W <= 256)
+        hipLaunchKernelGGL((k_sampler_rows_unit<1, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, zern, Gw, log2w,
+                           H, W, N, f0);
+      else if (W <= 512)
+        hipLaunchKernelGGL((k_sampler_rows_unit<2, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, zern, Gw, log2w,
+                           H, W, N, f0);
+      else if (W <= 1024)
+        hipLaunchKernelGGL((k_sampler_rows_unit<4, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, zern, Gw, log2w,
+                           H, W, N, f0);
+      else
+        hipLaunchKernelGGL((k_sampler_rows_unit<4, 1024, 1>), g1r, dim3(1024), lds1, s, V, pl->d_tw_w, zern, Gw,
+                           log2w, H, W, N, f0);
+    }
+  }
+  if (pl->N != 35) {
+    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+    // the groups of modes sharing (|m|, parity), members in Noll order
+    MixGroups g{};
+    int gid[kMaxModes];
+    for (int t = 0; t < pl->N; ++t) gid[t] = -1;
+    for (int t = 0; t < pl->N; ++t) {
+      if (gid[t] >= 0) continue;
+      if (g.count >= kMaxGroups) return TSIM_EUNSUPPORTED;
+      int n = 0;
+      for (int k = t; k < pl->N; ++k)
+        if (mix_group(k) == mix_group(t)) {
+          if (n >= kMaxGroup) return TSIM_EUNSUPPORTED;
+          gid[k] = g.count;
+          g.member[g.count][n++] = k;
+        }
+      for (int i = n; i < kMaxGroup; ++i) g.member[g.count][i] = -1;
+      for (int i = 0; i < n; ++i)
+        for (int k = 0; k < kMaxGroup; ++k)
+          g.L[g.count][i][k] =
+              k <= i && k < n ? float(pl->L[size_t(g.member[g.count][i]) * pl->N + g.member[g.count][k]]) : 0.f;
+      ++g.count;
+    }
+    const size_t plane = size_t(H) * W;
+    TraceScope tr("k_mix_groups", s);
+    hipLaunchKernelGGL(k_mix_groups, dim3(unsigned((plane + 255) / 256), nf), dim3(256), 0, s, zern, plane, pl->N, sc,
+                       f0, g);
+  }
+  if (sub.levels > 0) {
+    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+    TraceScope tr("k_subharmonic_add", s);
+    hipLaunchKernelGGL(k_subharmonic_add, dim3((W + 255) / 256, H, nf), dim3(256), 0, s, zern, pl->d_L, H, W, pl->N,
+                       sc, sub, f0);
+  }
+  return TSIM_OK;
 }
 
 int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
@@ -555,19 +721,19 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
   if (ipt != 2 && ipt != 4 && ipt != 8) return TSIM_EUNSUPPORTED;
   for (int f0 = 0; f0 < frames; f0 += chunk) {
     const int nf = std::min(chunk, frames - f0);
-    dim3 g1(Gw / NC, TSIM_FIELDS);
+    dim3 g1(Gw / NC, pl->NF);
     {
       TraceScope tr("k_sampler_cols", s);
       const uint32_t fb = uint32_t(frame0 + uint64_t(f0));
       if (ipt == 2)
         hipLaunchKernelGGL(k_sampler_cols<2>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
-                           H, NC, key0, key1, fb, nf);
+                           H, NC, key0, key1, fb, nf, pl->N);
       else if (ipt == 4)
         hipLaunchKernelGGL(k_sampler_cols<4>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
-                           H, NC, key0, key1, fb, nf);
+                           H, NC, key0, key1, fb, nf, pl->N);
       else
         hipLaunchKernelGGL(k_sampler_cols<8>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
-                           H, NC, key0, key1, fb, nf);
+                           H, NC, key0, key1, fb, nf, pl->N);
     }
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
     FrameScales sc;
@@ -585,29 +751,9 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
     sub.key0 = key0;
     sub.key1 = key1;
     sub.frame_base = uint32_t(frame0 + uint64_t(f0));
-    {
-      TraceScope tr("k_sampler_rows_mix", s);
-      // two rows per block (one LDS transform pass and one barrier set for both)
-      // up to 1024 columns; 1024-thread blocks over single rows beyond
-      const size_t lds2 = (2 * size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
-      const size_t lds1 = (size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
-      dim3 g2((H + 1) / 2, nf), g1r(H, nf);
-      if (W <= 256)
-        launch_rows<1, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-      else if (W <= 512)
-        launch_rows<2, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-      else if (W <= 1024)
-        launch_rows<4, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-      else
-        launch_rows<4, 1024, 1>(g1r, lds1, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-      if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
-    }
-    if (sub.levels > 0) {
-      TraceScope tr("k_subharmonic_add", s);
-      hipLaunchKernelGGL(k_subharmonic_add, dim3((W + 255) / 256, H, nf), dim3(256), 0, s, zern, pl->d_L, H, W,
-                         sc, sub, f0);
-      if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
-    }
+    const int st = launch_rows_n(pl, nf, f0, V, zern, sc, sub, s);
+    if (st != TSIM_OK) return st;
+    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
   }
   return TSIM_OK;
 }
@@ -617,7 +763,7 @@ int launch_sampler_ar(const tsim_plan *pl, int frames, const float *scale_host, 
                       float *zern, void *ws, hipStream_t s) {
   int st = launch_sampler(pl, frames, scale_host, seed, frame0, zern, ws, s);
   if (st != TSIM_OK) return st;
-  const size_t plane = size_t(TSIM_N_MODES) * pl->H * pl->W;
+  const size_t plane = size_t(pl->N) * pl->H * pl->W;
   const float c = sqrtf(fmaxf(0.f, 1.f - alpha * alpha));
   const unsigned blocks = unsigned(std::min<size_t>((plane + 255) / 256, size_t(1) << 20));
   for (int f0 = 0; f0 < frames; f0 += kMaxFramesPerLaunch) {

@@ -20,11 +20,11 @@ namespace {
 constexpr int kStatsThreads = 256;
 
 __global__ void __launch_bounds__(kStatsThreads)
-k_tilt_stats_rows(const float *__restrict__ zern, int H, int W, int L, float *__restrict__ part) {
+k_tilt_stats_rows(const float *__restrict__ zern, int H, int W, int L, int nmodes, float *__restrict__ part) {
   extern __shared__ float row[];  // [2][W] tilt rows
   const int y = blockIdx.x, f = blockIdx.y;
   const size_t plane = size_t(H) * W;
-  const float *a = zern + size_t(f) * TSIM_N_MODES * plane;  // Noll 2; Noll 3 at + plane
+  const float *a = zern + size_t(f) * nmodes * plane;  // Noll 2; Noll 3 at + plane
   for (int x = threadIdx.x; x < W; x += kStatsThreads) {
     row[x] = a[size_t(y) * W + x];
     row[W + x] = a[plane + size_t(y) * W + x];
@@ -141,7 +141,7 @@ int launch_tilt_stats(const tsim_plan *pl, int frames, const float *zern, int ma
   {
     TraceScope tr("k_tilt_stats_rows", s);
     const size_t lds = 2 * size_t(W) * sizeof(float);
-    hipLaunchKernelGGL(k_tilt_stats_rows, dim3(H, frames), dim3(kStatsThreads), lds, s, zern, H, W, L, part);
+    hipLaunchKernelGGL(k_tilt_stats_rows, dim3(H, frames), dim3(kStatsThreads), lds, s, zern, H, W, L, pl->N, part);
     if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
   }
   {

@@ -142,3 +142,42 @@ def test_subharmonic_tables_match_oracle(t, Gh, Gw, ds, fold, levels):
     # levels 0: the table is all zero and the spectra are the plain ones
     p0 = t.make_params(32, 32, 1, Gh, Gw, pixel_pitch_over_d=ds, alias_fold=fold)
     assert not t.host_tables(p0, 4).any()
+
+
+# ---- more than 35 modes (Sec. II-B: N can be raised at some cost) ----
+
+@pytest.mark.parametrize("n_modes", [44, 54, 65])
+def test_noll_cholesky_and_spectra_match_oracle_more_modes(t, n_modes):
+    """Plans of 44, 54 and 65 modes (complete radial orders up to 8, 9, 10):
+    A_0, L and the folded spectra of every mode equal the oracle's."""
+    jl = n_modes + 1
+    p = t.make_params(32, 32, 1, 64, 128, pixel_pitch_over_d=0.125, n_modes=n_modes)
+    A0 = t.host_tables(p, 0)
+    assert A0.shape == (n_modes, n_modes)
+    ref = ozern.noll_matrix(1.0, j_last=jl)
+    np.testing.assert_allclose(A0, ref, rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(t.host_tables(p, 1), ozern.cholesky_lower(ref), rtol=1e-10, atol=1e-14)
+    sq = t.host_tables(p, 2)
+    S = ospec.all_spectra(64, 128, 0.125, 2, j_last=jl)
+    for j in range(2, jl + 1):
+        quarter = np.sqrt(S[j - 2, :33, :65]).T
+        np.testing.assert_allclose(sq[j - 2], quarter, rtol=1e-11, atol=1e-14, err_msg=f"j={j}")
+
+
+@pytest.mark.parametrize("n_modes,kw,status", [
+    (36, {}, "EINVAL"), (50, {}, "EINVAL"), (66, {}, "EINVAL"),
+    (65, dict(psf_t=31), "EUNSUPPORTED"),            # exact PSFs with more modes: T = 33 (P = 64)
+    (44, dict(p2s_mode=1, basis_k=100), "EUNSUPPORTED"),   # the network takes 35 inputs
+])
+def test_mode_counts_checked_at_plan_creation(t, n_modes, kw, status):
+    p = t.make_params(32, 32, 1, 64, 64, n_modes=n_modes, **kw)
+    with pytest.raises(t.TsimError) as e:
+        t.host_tables(p, 0)
+    assert e.value.status == getattr(t, status)
+
+
+def test_mode_counts_accepted(t):
+    for n in (35, 44, 54, 65):
+        for P, T in ((64, 33), (128, 65), (128, 33)):
+            p = t.make_params(32, 32, 1, 64, 64, n_modes=n, pupil_n=P, psf_t=T)
+            assert t.host_tables(p, 3) == 0.125
