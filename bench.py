@@ -42,10 +42,12 @@ DR_CYCLE = (1.0, 2.0, 4.0)
 N_BASIS_PSF = 20000
 
 # the two single-frame-size workloads; `chunk` frames go through each call
+# "counters": the name the workload's rocprofv3 byte counts are filed under in
+# profiles/traffic.json (per launch, taken at the same launch shapes)
 S512 = dict(H=H, W=W, C=C, G=G, T=T, P=P, K=K, frames=FRAMES, chunk=FRAMES, drs=DR_CYCLE,
-            square=16)
+            square=16, counters="512x512x3_16frames")
 S4K = dict(H=2160, W=3840, C=3, G=4096, T=65, P=128, K=100, frames=30, chunk=6, drs=(3.0,),
-           square=64)
+           square=64, counters="3840x2160x3_6frames")
 
 
 def n_aperture(P):
@@ -99,7 +101,7 @@ def kernel_work(name, frames, s):
     return None
 
 
-def summarize(rep, steps, frames, s, traffic=True):
+def summarize(rep, steps, frames, s, traffic=False):
     """Per-kernel roofline entries from the tracer's {name: (launches, ms)}."""
     kernels = {}
     for name, (n, tot) in rep.items():
@@ -125,7 +127,7 @@ def summarize(rep, steps, frames, s, traffic=True):
     d = kernels[dom]
     roof = {"kernel": dom, "bound": d.get("bound"), "achieved": d.get("achieved"),
             "peak": d.get("peak"), "unit": d.get("unit"), "frac": d.get("frac"),
-            "traffic": measured_traffic(dom, d["launches_per_step"]) if traffic else None}
+            "traffic": measured_traffic(dom, s["counters"]) if traffic else None}
     return kernels, roof
 
 
@@ -143,14 +145,14 @@ def source_hash(kernel):
                           open(os.path.join(csrc, "common.cuh"), "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel, launches_per_step):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    the workload, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        d = json.load(open(path)).get(kernel)
+        d = json.load(open(path)).get(workload, {}).get("kernels", {}).get(kernel)
     except Exception:
         return None
     if not d or d.get("src_hash") != source_hash(kernel):
@@ -564,7 +566,7 @@ def large_frame(tsim, torch, np, synthetic, dev, args):
     f_plain = n
     st_plain = max(1, min(args.steps, 2))
     ms_p, rep_p, out_p = wl.run(tsim, plan, beta32, st_plain, 1, f_plain)
-    kern_p, roof_p = summarize(rep_p, st_plain, f_plain, s, traffic=False)
+    kern_p, roof_p = summarize(rep_p, st_plain, f_plain, s, traffic=True)
     del beta32
     plan.close()
     px = s["H"] * s["W"]
@@ -581,7 +583,7 @@ def large_frame(tsim, torch, np, synthetic, dev, args):
         net, info = train_network(tsim, torch, np, plan_l, args.train_steps)
         beta16 = torch.empty((n, s["H"], s["W"], kpad(s["K"])), dtype=torch.bfloat16, device=dev)
         ms_l, rep_l, out_l = wl.run(tsim, plan_l, beta16, args.steps, args.warmup, s["frames"])
-        kern_l, roof_l = summarize(rep_l, args.steps, s["frames"], s, traffic=False)
+        kern_l, roof_l = summarize(rep_l, args.steps, s["frames"], s, traffic=True)
         learned = {"value": round(s["frames"] * px / (ms_l * 1e-3) / 1e6, 3), "unit": "Mpixel/s",
                    "ms_per_step": round(ms_l, 3), "frames_per_step": s["frames"],
                    "steps": args.steps, "warmup": args.warmup,
@@ -639,7 +641,7 @@ def main():
     ms, rep, out_plain = wl.run(tsim, plan, beta32, args.steps, args.warmup, FRAMES)
     zern_first = wl.zern_first
     outs_first = {"plain_fp32": out_plain[:3].cpu().numpy()}
-    kernels, roofline = summarize(rep, args.steps, FRAMES, s)
+    kernels, roofline = summarize(rep, args.steps, FRAMES, s, traffic=True)
     value = FRAMES * H * W / (ms * 1e-3) / 1e6
     del beta32
 
@@ -652,7 +654,7 @@ def main():
         beta16 = torch.empty((FRAMES, H, W, kpad(K)), dtype=torch.bfloat16, device=dev)
         ms_l, rep_l, out_l = wl.run(tsim, plan_l, beta16, args.steps, args.warmup, FRAMES)
         outs_first["learned_bf16"] = out_l[:3].cpu().numpy()
-        kern_l, roof_l = summarize(rep_l, args.steps, FRAMES, s, traffic=False)
+        kern_l, roof_l = summarize(rep_l, args.steps, FRAMES, s, traffic=True)
         learned = {"value": round(FRAMES * H * W / (ms_l * 1e-3) / 1e6, 3), "unit": "Mpixel/s",
                    "ms_per_step": round(ms_l, 3), "dtype": "bf16 MFMA, fp32 accumulate",
                    "speedup_vs_plain_fp32": round(ms / ms_l, 2),

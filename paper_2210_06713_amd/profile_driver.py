@@ -1,20 +1,28 @@
 """Short, fixed workload for hardware-counter profiling of the hot path.
 
-    rocprofv3 --pmc FETCH_SIZE -d OUT -o run -- python paper_2210_06713_amd/profile_driver.py
-    rocprofv3 --pmc WRITE_SIZE -d OUT -o run -- python paper_2210_06713_amd/profile_driver.py
-    python paper_2210_06713_amd/profile_driver.py --summarize OUT_FETCH OUT_WRITE profiles/
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d F -o run -- python paper_2210_06713_amd/profile_driver.py
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d W -o run -- python paper_2210_06713_amd/profile_driver.py
+    python paper_2210_06713_amd/profile_driver.py --summarize F W profiles/ [--workload 4k]
+    rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS \
+        SQ_ACTIVE_INST_VMEM GRBM_GUI_ACTIVE --output-format csv -d Q -o run -- python ...profile_driver.py
+    python paper_2210_06713_amd/profile_driver.py --sq-summary Q OUT.md "command" "title"
     python paper_2210_06713_amd/profile_driver.py --stats-md STATS.csv OUT.md "command" "title"
 
 Runs ``--steps`` steps (default 2) of the 512 x 512 x 3, 16-frame workload
 (or, with ``--workload 4k``, of 6-frame chunks of the 3840 x 2160 x 3
 workload) in the plain FP32 form and in the learned BF16 form (network with
 seeded random weights: the kernels' time and traffic do not depend on the
-weight values), then one
-element-wise copy of 256 MiB (read 256 MiB, write 256 MiB) whose counter
-readings calibrate the per-kernel byte counts.  ``--summarize`` turns the two
-counter runs into ``traffic.json`` (bytes per launch for each kernel, with
-the hash of the kernel's source file and of the shared device header) and a
-Markdown summary.
+weight values), then one element-wise copy of 256 MiB (read 256 MiB, write
+256 MiB) whose counter readings calibrate the per-kernel byte counts.
+
+``--summarize`` turns the two byte-counter runs into the workload's entry of
+``traffic.json`` (bytes per launch for each kernel, with the hash of the
+kernel's source file and of the shared device header) and a Markdown table.
+``--sq-summary`` turns a run of shader-sequencer counters into per-kernel
+busy fractions: matrix-core busy = SQ_VALU_MFMA_BUSY_CYCLES / (cycles x 1024
+SIMDs), and vector-ALU, LDS and vector-memory issue = SQ_ACTIVE_INST_* (in
+quad cycles, per SIMD) x 4 / (cycles x 1024 SIMDs), with cycles = the
+kernel's GRBM_GUI_ACTIVE, which rocprofv3 sums over the eight XCDs.
 """
 import argparse
 import csv
@@ -43,6 +51,10 @@ WORKLOADS = {
     "512": (512, 512, 3, 1024, 33, 64, 100, 16, (1.0, 2.0, 4.0), 16),
     "4k": (2160, 3840, 3, 4096, 65, 128, 100, 6, (3.0,), 64),
 }
+# the name each workload's counter figures are filed under
+WORKLOAD_KEYS = {"512": "512x512x3_16frames", "4k": "3840x2160x3_6frames"}
+N_SIMD = 1024      # 256 compute units x 4 SIMDs
+N_XCD = 8
 
 
 def run(workload, steps):
@@ -117,7 +129,7 @@ def _per_kernel(rows, counter):
     return out
 
 
-def summarize(fetch_dir, write_dir, dst):
+def summarize(fetch_dir, write_dir, dst, workload="512"):
     fetch = _per_kernel(_rows(fetch_dir), "FETCH_SIZE")
     write = _per_kernel(_rows(write_dir), "WRITE_SIZE")
 
@@ -128,12 +140,10 @@ def summarize(fetch_dir, write_dir, dst):
         raise SystemExit("calibration copy not found")
 
     fr, wr = cal(fetch), cal(write)
-    res = {"calibration": {"bytes": CAL_BYTES, "fetch_factor": round(fr, 4), "write_factor": round(wr, 4)}}
+    entry = {"calibration": {"bytes": CAL_BYTES, "fetch_factor": round(fr, 4), "write_factor": round(wr, 4)},
+             "kernels": {}}
     lines = ["| kernel | dispatches | read MB/launch | write MB/launch | total MB/launch |",
              "|---|---:|---:|---:|---:|"]
-    def median(v):
-        v = sorted(v)
-        return v[len(v) // 2]
 
     for k in sorted(set(fetch) | set(write)):
         s = _short(k)
@@ -143,20 +153,78 @@ def summarize(fetch_dir, write_dir, dst):
         f = fetch.get(k, [0.0])
         w = write.get(k, [0.0])
         # median over dispatches: the one-off basis-build launch is not typical
-        rb = median(f) * 1024 * fr
-        wb = median(w) * 1024 * wr
-        csrc = os.path.join(ROOT, "paper_2210_06713_amd", "csrc")
-        # the kernel's file and the shared device header it includes
-        h = hashlib.sha256(open(os.path.join(csrc, src), "rb").read() +
-                           open(os.path.join(csrc, "common.cuh"), "rb").read()).hexdigest()[:16]
+        rb = _median(f) * 1024 * fr
+        wb = _median(w) * 1024 * wr
         name = k.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0].strip()
-        res[trace] = {"kernel": name, "dispatches": len(f), "read_bytes_per_launch": round(rb),
-                      "write_bytes_per_launch": round(wb), "bytes_per_launch": round(rb + wb),
-                      "src_hash": h}
+        entry["kernels"][trace] = {"kernel": name, "dispatches": len(f), "read_bytes_per_launch": round(rb),
+                                   "write_bytes_per_launch": round(wb), "bytes_per_launch": round(rb + wb),
+                                   "src_hash": source_hash(src)}
         lines.append(f"| {name} | {len(f)} | {rb / 1e6:.1f} | {wb / 1e6:.1f} | {(rb + wb) / 1e6:.1f} |")
     os.makedirs(dst, exist_ok=True)
-    json.dump(res, open(os.path.join(dst, "traffic.json"), "w"), indent=1)
+    path = os.path.join(dst, "traffic.json")
+    res = {}
+    if os.path.exists(path):
+        res = json.load(open(path))
+        if "calibration" in res:       # a single-workload file: start afresh
+            res = {}
+    res[WORKLOAD_KEYS[workload]] = entry
+    json.dump(res, open(path, "w"), indent=1, sort_keys=True)
     return res, lines, fr, wr
+
+
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def source_hash(src):
+    """Hash of a kernel's source file and of the shared device header."""
+    csrc = os.path.join(ROOT, "paper_2210_06713_amd", "csrc")
+    return hashlib.sha256(open(os.path.join(csrc, src), "rb").read() +
+                          open(os.path.join(csrc, "common.cuh"), "rb").read()).hexdigest()[:16]
+
+
+SQ_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VMEM")
+
+
+def sq_summary(qdir, dst, command, title):
+    """Per-kernel busy fractions from one run of shader-sequencer counters
+    (median over each kernel's dispatches)."""
+    per = {}
+    names = {}
+    for r in _rows(qdir):
+        key = r.get("Dispatch_Id")
+        d = per.setdefault(key, {})
+        c = r.get("Counter_Name")
+        d[c] = d.get(c, 0.0) + float(r["Counter_Value"])
+        names[key] = r.get("Kernel_Name")
+    by_kernel = {}
+    for key, d in per.items():
+        if "GRBM_GUI_ACTIVE" not in d or not all(c in d for c in SQ_COUNTERS):
+            continue
+        n = names[key].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0].strip()
+        cyc = d["GRBM_GUI_ACTIVE"] / N_XCD
+        if cyc <= 0:
+            continue
+        by_kernel.setdefault(n, []).append((cyc, 100.0 * d["SQ_VALU_MFMA_BUSY_CYCLES"] / (cyc * N_SIMD),
+                                            100.0 * 4 * d["SQ_ACTIVE_INST_VALU"] / (cyc * N_SIMD),
+                                            100.0 * 4 * d["SQ_ACTIVE_INST_LDS"] / (cyc * N_SIMD),
+                                            100.0 * 4 * d["SQ_ACTIVE_INST_VMEM"] / (cyc * N_SIMD)))
+    out = [f"# {title}", "", "Command (from the repository root, on one MI355X):", "", "```", command, "```", "",
+           "Per kernel, the median over its dispatches. cycles = GRBM_GUI_ACTIVE / 8 (rocprofv3 sums it",
+           "over the eight XCDs); matrix cores busy = SQ_VALU_MFMA_BUSY_CYCLES / (cycles x 1024 SIMDs);",
+           "VALU / LDS / VMEM issue = SQ_ACTIVE_INST_{VALU,LDS,VMEM} x 4 (quad cycles) / (cycles x 1024 SIMDs).",
+           "", "| kernel | dispatches | cycles (median) | matrix cores busy % | VALU issue % | LDS issue % | VMEM issue % |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for n in sorted(by_kernel):
+        v = by_kernel[n]
+        med = [_median([x[i] for x in v]) for i in range(5)]
+        label = n if len(n) <= 60 else n[:57] + "..."
+        out.append(f"| {label} | {len(v)} | {med[0]:.0f} | {med[1]:.1f} | {med[2]:.1f} | {med[3]:.1f} | "
+                   f"{med[4]:.1f} |")
+    with open(dst, "w") as f:
+        f.write("\n".join(out) + "\n")
+    return out
 
 
 def stats_markdown(csv_path, dst, command, title):
@@ -178,13 +246,16 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "DST"))
     ap.add_argument("--stats-md", nargs=4, metavar=("KERNEL_STATS_CSV", "DST_MD", "COMMAND", "TITLE"))
+    ap.add_argument("--sq-summary", nargs=4, metavar=("COUNTER_DIR", "DST_MD", "COMMAND", "TITLE"))
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="512")
     ap.add_argument("--steps", type=int, default=2)
     a = ap.parse_args()
     if a.stats_md:
         stats_markdown(*a.stats_md)
+    elif a.sq_summary:
+        print("\n".join(sq_summary(*a.sq_summary)))
     elif a.summarize:
-        res, lines, fr, wr = summarize(*a.summarize)
+        res, lines, fr, wr = summarize(*a.summarize, workload=a.workload)
         print("\n".join(lines))
         print(f"calibration: fetch x{fr:.4f}, write x{wr:.4f}")
     else:
