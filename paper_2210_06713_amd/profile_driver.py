@@ -167,8 +167,24 @@ def summarize(fetch_dir, write_dir, dst, workload="512"):
         res = json.load(open(path))
         if "calibration" in res:       # a single-workload file: start afresh
             res = {}
-    res[WORKLOAD_KEYS[workload]] = entry
+    key = WORKLOAD_KEYS[workload]
+    res[key] = entry
     json.dump(res, open(path, "w"), indent=1, sort_keys=True)
+    drv = "REPO/paper_2210_06713_amd/profile_driver.py"
+    md = [f"# HBM traffic per launch: {key} (plain FP32 and learned BF16 forms)", "",
+          "Commands (from the repository root, on one MI355X; one counter per run):", "", "```",
+          f"cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d FETCH -o run -- python -u {drv} "
+          f"--workload {workload}",
+          f"cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d WRITE -o run -- python -u {drv} "
+          f"--workload {workload}",
+          f"python {drv} --summarize FETCH WRITE REPO/profiles/ --workload {workload}", "```", "",
+          "The driver runs two steps of each form, then one element-wise copy of 256 MiB (read 256 MiB,",
+          f"write 256 MiB) whose readings give the calibration: FETCH_SIZE x{fr:.4f}, WRITE_SIZE x{wr:.4f}",
+          "(bytes = KiB reading x 1024 x factor). Each value is the median over the kernel's dispatches;",
+          "traffic.json holds the same figures with the hash of each kernel's source file and of the",
+          "shared device header, and bench.py reports roofline.traffic only while that hash matches.", ""]
+    with open(os.path.join(dst, f"hbm_traffic_{key}.md"), "w") as f:
+        f.write("\n".join(md + lines) + "\n")
     return res, lines, fr, wr
 
 
