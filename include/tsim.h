@@ -180,9 +180,10 @@ int tsim_sample_zernike(const tsim_plan *plan, int frames, const float *d_over_r
  * device array of the library, TSIM_NOALLOC_SCRATCH_BYTES (256 MiB) on each
  * GPU the library runs on, held until the process ends; its address is
  * looked up at plan creation.  Frames are processed in chunks that fit it.
- *   Limit: one frame's intermediate, 18 * H * Gw * 8 bytes, must fit the
- *   array (e.g. 768 x 1024 on a 2048-wide grid fits, 2160 x 3840 on 4096
- *   does not): larger plans return TSIM_EUNSUPPORTED before any launch.
+ *   Limit: one frame's intermediate, ceil(N / 2) * H * Gw * 8 bytes (18
+ *   fields for N = 35), must fit the array (e.g. 768 x 1024 on a 2048-wide
+ *   grid fits, 2160 x 3840 on 4096 does not): larger plans return
+ *   TSIM_EUNSUPPORTED before any launch.
  *   Every call on one GPU shares that GPU's array, so calls that overlap in
  *   time on one GPU (other threads, other streams without ordering) race;
  *   calls on one stream are ordered and safe.  The array's contents from
@@ -233,7 +234,7 @@ int tsim_structure_function(const tsim_plan *plan, int frames, const float *zern
 /* Long- and short-exposure optical transfer functions (the aperture
  * statistics of Sec. IV-B): one realisation's OTF is the autocorrelation of
  * the generalised pupil, H(xi) = sum_x G(x) conj(G(x - xi)) with
- * G = P exp(-j phi) and phi = sum_j a_j Z_j over Noll 2..36; the long-
+ * G = P exp(-j phi) and phi = sum_j a_j Z_j over the plan's modes, Noll 2..N+1; the long-
  * exposure OTF is its mean over realisations, the short-exposure OTF the
  * same with the tilt-corrected phase (the plane of best fit over the
  * aperture, i.e. the Zernike tilts Noll 2 and 3, removed).  Every pixel of
