@@ -77,7 +77,9 @@ def kernel_work(name, frames, s):
         dft = rows * 2 * fft + n * 2 * fft + (n + 1) * n * 8   # + the direct edge column
         return "alu", px * (phase + dft + 3 * t * t), "flop"
     if name == "k_project":
-        return "alu", px * 2 * t * t * k, "flop"
+        # read each pixel's T x T PSF, write its K weights (the contraction
+        # runs on the 16-bit matrix cores, as three FP16 products per term)
+        return "hbm", px * (t * t * 4 + k * 4), "B"
     if name == "k_render_fp32":
         return "alu", px * (2 * k * t * t + 2 * c * t * t), "flop"
     if name == "k_warp":

@@ -41,7 +41,8 @@ struct tsim_plan {
   float *d_basis = nullptr;    // [K][T*T] float32
   float *d_basis_t = nullptr;  // [T*T][KP] float32 (tap-major, zero padded)
   uint16_t *d_basis_bf = nullptr;  // [groups of 32 tap pairs][2][32][KP + 8] bfloat16, zero padded
-  float *d_basis_t128 = nullptr;   // [T*T][128] float32, zero padded (projection on matrix cores)
+  uint16_t *d_basis_h3 = nullptr;  // basis x 2^10 as FP16 (hi, lo) pairs in matrix-core fragment order:
+                                   // [ceil(T*T/32)][2][ceil(KP/32)][64][2][8] (projection)
   float *d_basis_k2 = nullptr;     // [roundup(T*T,32)][2][K2P] float32: psi[2s+g][tap] (FP32 matrix-core blur)
   uint16_t *d_mlp_w = nullptr;     // packed BF16 network weights (inference layout)
   float *d_mlp_f = nullptr;        // biases, input scales, output means (FP32)

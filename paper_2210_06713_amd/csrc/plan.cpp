@@ -246,6 +246,30 @@ double zernike(int j, double rho, double theta) {
                       : r * std::sqrt(2.0) * std::sin(m * theta);
 }
 
+// IEEE half precision of a double, nearest with ties to even (subnormals
+// kept, overflow to infinity), and the exact value of a half
+uint16_t f16_rn(double x) {
+  const uint16_t sign = std::signbit(x) ? 0x8000 : 0;
+  const double a = std::fabs(x);
+  if (a == 0.0) return sign;
+  int e;
+  (void)std::frexp(a, &e);                         // a = f 2^e, f in [0.5, 1)
+  const int q = std::max(e - 11, -24);             // weight of the last kept bit
+  const double v = std::ldexp(std::nearbyint(std::ldexp(a, -q)), q);  // ties to even
+  if (v >= 65520.0) return sign | 0x7c00;
+  if (v < std::ldexp(1.0, -14)) return sign | uint16_t(std::ldexp(v, 24));  // subnormal
+  int ev;
+  const double fr = std::frexp(v, &ev);            // v = fr 2^ev, fr in [0.5, 1)
+  const uint16_t man = uint16_t(uint32_t(std::ldexp(fr, 11)) & 0x3ffu);
+  return uint16_t(sign | uint16_t((ev + 14) << 10) | man);
+}
+
+double f16_value(uint16_t h) {
+  const int e = (h >> 10) & 0x1f, m = h & 0x3ff;
+  const double v = e == 0 ? std::ldexp(double(m), -24) : std::ldexp(double(1024 + m), e - 25);
+  return (h & 0x8000) ? -v : v;
+}
+
 template <class T>
 int upload(T **dst, const T *src, size_t n) {
   if (hipMalloc(dst, n * sizeof(T)) != hipSuccess) {
@@ -290,7 +314,7 @@ int validate(const tsim_params *p) {
 
 void free_plan(tsim_plan *pl) {
   if (!pl) return;
-  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zcheb, pl->d_basis, pl->d_basis_t128, pl->d_basis_k2,
+  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zcheb, pl->d_basis, pl->d_basis_h3, pl->d_basis_k2,
                   pl->d_basis_t, pl->d_basis_bf, pl->d_mlp_w, pl->d_mlp_f};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -558,10 +582,28 @@ int plan_create_impl(const tsim_params *p, tsim_plan **out) {
         }
       }
     if ((st = upload(&pl->d_basis_bf, bb.data(), bb.size())) != TSIM_OK) goto fail;
-    std::vector<float> b128(size_t(T2) * 128, 0.0f);
-    for (int t = 0; t < T2; ++t)
-      for (int k = 0; k < K; ++k) b128[size_t(t) * 128 + k] = float(pl->basis[size_t(k) * T2 + t]);
-    if ((st = upload(&pl->d_basis_t128, b128.data(), b128.size())) != TSIM_OK) goto fail;
+    // the projection's operand: psi x 2^10 split into FP16 (hi, lo), in
+    // fragment order [chunk of 32 taps][step][output tile][lane][hi, lo][8]:
+    // lane l holds output 32 tile + l % 32, taps 32 chunk + 16 step +
+    // 8 (l / 32) + 0..7; zero past K and T*T
+    {
+      const int NCHK = (T2 + 31) / 32, NTL = (KP + 31) / 32;
+      std::vector<uint16_t> h3(size_t(NCHK) * 2 * NTL * 64 * 2 * 8, 0);
+      for (int c = 0; c < NCHK; ++c)
+        for (int st2 = 0; st2 < 2; ++st2)
+          for (int j = 0; j < NTL; ++j)
+            for (int l = 0; l < 64; ++l)
+              for (int e = 0; e < 8; ++e) {
+                const int o = 32 * j + l % 32, t = 32 * c + 16 * st2 + 8 * (l / 32) + e;
+                const double x = (o < K && t < T2) ? std::ldexp(pl->basis[size_t(o) * T2 + t], 10) : 0.0;
+                const uint16_t hi = f16_rn(x);
+                const uint16_t lo = f16_rn(x - f16_value(hi));
+                const size_t at = ((((size_t(c) * 2 + st2) * NTL + j) * 64 + l) * 2) * 8 + e;
+                h3[at] = hi;
+                h3[at + 8] = lo;
+              }
+      if ((st = upload(&pl->d_basis_h3, h3.data(), h3.size())) != TSIM_OK) goto fail;
+    }
     // lane-contiguous layout for the FP32 matrix-core blur: [tap][g][s] = psi[2s + g][tap]
     const int K2 = (K + 1) / 2, K2P = (K2 + 3) / 4 * 4, TTP = (T2 + 31) / 32 * 32;
     std::vector<float> bk2(size_t(TTP) * 2 * K2P, 0.0f);

@@ -1,6 +1,17 @@
 // Exact projection of PSFs on the PCA basis (Eq. (7)): beta = Psi h per
-// pixel, a dense [pixels x T^2] x [T^2 x K] contraction on the FP32 matrix
-// cores.
+// pixel, a dense [pixels x T^2] x [T^2 x K] contraction.
+//
+// The FP32 matrix instructions of this chip run at the rate of its FP32
+// vector ALU, on which the PSF kernels already spend their time, so the
+// contraction runs on the 16-bit matrix cores instead, at FP32 accuracy:
+// every operand is split into two FP16 numbers, x = x_hi + x_lo with
+// x_hi = fp16(x) and x_lo = fp16(x - x_hi), and the product is
+// Psi_hi h_hi + Psi_hi h_lo + Psi_lo h_hi with FP32 accumulation.  The
+// dropped term Psi_lo h_lo and the rounding of the two parts are each below
+// 2^-22 of |Psi h|, about 1e-6 of every product; the products of FP16
+// numbers and their sums are exact FP32 operations.  Operands are scaled
+// into FP16's normal range first (h by 2^12, PSFs summing to 1; Psi by
+// 2^10, rows of unit norm) and the sums scaled back by 2^-22.
 #include <algorithm>
 
 #include "common.cuh"
@@ -8,114 +19,146 @@
 
 namespace {
 
-// beta[p][k] = sum_t h[p][t] psi[k][t] on the FP32 matrix cores
-// (v_mfma_f32_16x16x4f32).  Block: 128 pixels x 16 NT outputs, 4 waves;
-// wave w owns pixels [32w, 32w + 32) as two 16-row tiles and all NT 16-wide
-// output tiles, so padding K = 100 costs 12 columns (NT = 7) rather than 28.
-// 32-tap chunks of h and psi^T are staged through LDS (h rows padded against
-// bank conflicts), and the global loads of chunk c + 1 are in flight in
-// registers while the matrix cores work on chunk c.
-constexpr int PJ_PX = kProjectTile, PJ_TK = 32, PJ_N = 128;
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// OUT_BF16: beta rows of KB bfloat16 (K weights, zeros up to KB <= 16 PJ_NT),
-// the layout BF16 plans use; else rows of K floats.
-template <int PJ_NT, bool OUT_BF16>  // 16-wide output tiles: 7 for KB <= 112, 8 up to 128
+constexpr float kHScale = 4096.f;                    // 2^12
+constexpr float kOutScale = 1.f / (4096.f * 1024.f);  // 2^-22
+
+__device__ __forceinline__ f32x16 mfma_f16(const uint4 &a, const uint4 &b, const f32x16 &c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                0, 0);
+}
+
+// beta[p][k] = sum_t psi[k][t] h[p][t] on v_mfma_f32_32x32x16_f16, A = the
+// basis (rows = outputs), B = the PSFs (columns = pixels).  Block: 128 pixels,
+// 4 waves; wave w owns pixels [32 w, 32 w + 32) and NT 32-row output tiles.
+// Taps go in chunks of 32 (two 16-tap matrix-core steps).  Per chunk the
+// block stages its 128 pixels' 32 taps in LDS by coalesced row loads
+// (thread: 16 taps of pixel rows, consecutive threads consecutive taps) and
+// the chunk's basis fragments (hi and lo, in fragment order in the plan
+// table); the global loads of chunk c + 1 are in flight in registers while
+// the matrix cores work on chunk c.  A lane's B fragment is its pixel's taps
+// 8 (l / 32) + 0..7 of the step, split into FP16 hi and lo on the fly.
+constexpr int HS = 36;  // LDS row stride of the staged PSF taps (floats; 16-byte aligned groups of 8)
+
+template <int NT, bool OUT_BF16>
 __global__ void __launch_bounds__(256)
-k_project_mfma(const float *__restrict__ h, const float *__restrict__ psi_t128 /*[T2][128]*/,
-               void *__restrict__ beta, int n, int T2, int K, int KB) {
-  __shared__ float As[PJ_PX][PJ_TK + 1];
-  __shared__ __attribute__((aligned(16))) float Bs[PJ_TK][PJ_N];
+k_project_h3(const float *__restrict__ h, const uint4 *__restrict__ psi /*[chunks][2][NT][64][2] x 8 f16*/,
+             void *__restrict__ beta, int n, int T2, int K, int KB) {
+  constexpr int CH = 2 * NT * 64 * 2;  // uint4 per chunk
+  __shared__ uint4 ps[CH];
+  __shared__ __attribute__((aligned(16))) float hs[kProjectTile * HS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;   // MFMA row/column in the tile, k within the step
-  const int p0 = blockIdx.x * PJ_PX;
-  constexpr int NA = PJ_PX * PJ_TK / 256, NB = PJ_TK * PJ_N / 4 / 256;
-  float ra[NA];
-  float4 rb[NB];
-  auto gload = [&](int t0) {
+  const int p0 = blockIdx.x * kProjectTile;
+  const int nchunk = (T2 + 31) / 32;
+
+  // staging loads: element e = threadIdx.x + 256 i is pixel e / 32, tap e % 32
+  // of the chunk; pixels past n read pixel n - 1 and taps past T^2 the row's
+  // last tap, so every load is unconditional (the basis table is zero past
+  // T^2, and such pixels are not stored)
+  // (element offsets fit 32 bits: a P2S chunk holds at most about 5 GB of PSFs)
+  const int tt = threadIdx.x & 31;
+  uint32_t hrow[16];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = threadIdx.x + i * 256;
-      const int px = e >> 5, tt = e & 31;
-      const int gp = p0 + px, gt = t0 + tt;
-      ra[i] = (gp < n && gt < T2) ? h[size_t(gp) * T2 + gt] : 0.f;
-    }
+  for (int i = 0; i < 16; ++i) hrow[i] = uint32_t(min(p0 + (threadIdx.x >> 5) + 8 * i, n - 1)) * uint32_t(T2);
+  float hv[16];
+  auto hload = [&](int t0) {
+    const uint32_t t = uint32_t(min(t0 + tt, T2 - 1));
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = threadIdx.x + i * 256;
-      const int tt = e >> 5, c4 = e & 31;
-      const int gt = t0 + tt;
-      rb[i] = (gt < T2) ? *reinterpret_cast<const float4 *>(psi_t128 + size_t(gt) * PJ_N + 4 * c4)
-                        : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int i = 0; i < 16; ++i) hv[i] = h[hrow[i] + t];
   };
-  f32x4 acc[2][PJ_NT];
+  constexpr int PER = CH / 256;  // uint4 of a chunk's basis fragments per thread (= NT)
+  const uint4 *pp = psi + threadIdx.x;
+  uint4 pv0 = pp[0], pv1, pv2, pv3;
+  if constexpr (PER > 1) pv1 = pp[256];
+  if constexpr (PER > 2) pv2 = pp[512];
+  if constexpr (PER > 3) pv3 = pp[768];
+
+  f32x16 acc[NT];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < NT; ++j) acc[j] = f32x16{};
+  hload(0);
+  const float *hb = hs + (32 * w + (lane & 31)) * HS + 8 * (lane >> 5);
+  for (int c = 0; c < nchunk; ++c) {
+    ps[threadIdx.x] = pv0;
+    if constexpr (PER > 1) ps[threadIdx.x + 256] = pv1;
+    if constexpr (PER > 2) ps[threadIdx.x + 512] = pv2;
+    if constexpr (PER > 3) ps[threadIdx.x + 768] = pv3;
 #pragma unroll
-    for (int j = 0; j < PJ_NT; ++j) acc[i][j] = f32x4{};
-  gload(0);
-  for (int t0 = 0; t0 < T2; t0 += PJ_TK) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = threadIdx.x + i * 256;
-      As[e >> 5][e & 31] = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = threadIdx.x + i * 256;
-      *reinterpret_cast<float4 *>(&Bs[e >> 5][4 * (e & 31)]) = rb[i];
-    }
+    for (int i = 0; i < 16; ++i) hs[((threadIdx.x >> 5) + 8 * i) * HS + tt] = hv[i];
     __syncthreads();
-    if (t0 + PJ_TK < T2) gload(t0 + PJ_TK);
+    if (c + 1 < nchunk) {
+      hload(32 * (c + 1));
+      pp += CH;
+      pv0 = pp[0];
+      if constexpr (PER > 1) pv1 = pp[256];
+      if constexpr (PER > 2) pv2 = pp[512];
+      if constexpr (PER > 3) pv3 = pp[768];
+    }
 #pragma unroll
-    for (int s = 0; s < PJ_TK / 4; ++s) {
-      const int k = 4 * s + lk;
-      const float a0 = As[w * 32 + li][k], a1 = As[w * 32 + 16 + li][k];
+    for (int s = 0; s < 2; ++s) {
+      // this step's PSF values as FP16 pairs
+      const float4 u0 = *reinterpret_cast<const float4 *>(hb + 16 * s);
+      const float4 u1 = *reinterpret_cast<const float4 *>(hb + 16 * s + 4);
+      const f32x8 v = f32x8{u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w} * kHScale;
+      const f16x8 hi = __builtin_convertvector(v, f16x8);
+      const f16x8 lo = __builtin_convertvector(v - __builtin_convertvector(hi, f32x8), f16x8);
+      const uint4 bhi = __builtin_bit_cast(uint4, hi), blo = __builtin_bit_cast(uint4, lo);
+      uint4 ahi[NT], alo[NT];
 #pragma unroll
-      for (int j = 0; j < PJ_NT; ++j) {
-        const float b = Bs[k][16 * j + li];
-        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][j], 0, 0, 0);
-        acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][j], 0, 0, 0);
+      for (int j = 0; j < NT; ++j) {
+        ahi[j] = ps[((s * NT + j) * 64 + lane) * 2];
+        alo[j] = ps[((s * NT + j) * 64 + lane) * 2 + 1];
       }
+      // the three products of each tile, tiles interleaved so consecutive
+      // matrix-core instructions are independent
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[j] = mfma_f16(ahi[j], bhi, acc[j]);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[j] = mfma_f16(ahi[j], blo, acc[j]);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[j] = mfma_f16(alo[j], bhi, acc[j]);
     }
     __syncthreads();
   }
-  // C layout: lane holds column li of the tile, rows 4 lk + r
+  const int pix = p0 + 32 * w + (lane & 31);
+  if (pix >= n) return;
+  // D layout: lane holds column (pixel) lane % 32, rows 8 i + 4 (lane / 32) + r
 #pragma unroll
-  for (int j = 0; j < PJ_NT; ++j) {
-    const int k = 16 * j + li;
-    if (k >= (OUT_BF16 ? KB : K)) continue;
+  for (int j = 0; j < NT; ++j)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gp = p0 + w * 32 + 16 * i + 4 * lk + r;
-        if (gp >= n) continue;
-        if constexpr (OUT_BF16)
-          static_cast<__bf16 *>(beta)[size_t(gp) * KB + k] = __bf16(k < K ? acc[i][j][r] : 0.f);
-        else
-          static_cast<float *>(beta)[size_t(gp) * K + k] = acc[i][j][r];
+        const int k = 32 * j + 8 * i + 4 * (lane >> 5) + r;
+        const float v = acc[j][4 * i + r] * kOutScale;
+        if constexpr (OUT_BF16) {
+          if (k < KB) static_cast<__bf16 *>(beta)[size_t(pix) * KB + k] = __bf16(k < K ? v : 0.f);
+        } else {
+          if (k < K) static_cast<float *>(beta)[size_t(pix) * K + k] = v;
+        }
       }
-  }
 }
 
 }  // namespace
 
 int launch_project(const tsim_plan *pl, const float *h, int n, void *beta, int out_bf16, hipStream_t s) {
   const int T2 = pl->T * pl->T, KB = out_bf16 ? pl->KP : pl->K;
-  dim3 grid((n + PJ_PX - 1) / PJ_PX);
+  const int nt = (pl->KP + 31) / 32;  // the plan table's output tiles (KP >= KB)
+  dim3 grid((n + kProjectTile - 1) / kProjectTile);
   TraceScope tr("k_project", s);
-  if (KB <= 112) {
-    if (out_bf16)
-      hipLaunchKernelGGL((k_project_mfma<7, true>), grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K, KB);
-    else
-      hipLaunchKernelGGL((k_project_mfma<7, false>), grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K, KB);
-  } else {
-    if (out_bf16)
-      hipLaunchKernelGGL((k_project_mfma<8, true>), grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K, KB);
-    else
-      hipLaunchKernelGGL((k_project_mfma<8, false>), grid, dim3(256), 0, s, h, pl->d_basis_t128, beta, n, T2, pl->K, KB);
+  const uint4 *psi = reinterpret_cast<const uint4 *>(pl->d_basis_h3);
+#define TSIM_PJ(NT, BF) \
+  hipLaunchKernelGGL((k_project_h3<NT, BF>), grid, dim3(256), 0, s, h, psi, beta, n, T2, pl->K, KB)
+  switch (nt) {
+    case 1: if (out_bf16) TSIM_PJ(1, true); else TSIM_PJ(1, false); break;
+    case 2: if (out_bf16) TSIM_PJ(2, true); else TSIM_PJ(2, false); break;
+    case 3: if (out_bf16) TSIM_PJ(3, true); else TSIM_PJ(3, false); break;
+    case 4: if (out_bf16) TSIM_PJ(4, true); else TSIM_PJ(4, false); break;
+    default: return TSIM_EUNSUPPORTED;
   }
+#undef TSIM_PJ
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
