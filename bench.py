@@ -81,7 +81,9 @@ def kernel_work(name, frames, s):
         # runs on the 16-bit matrix cores, as three FP16 products per term)
         return "hbm", px * (t * t * 4 + k * 4), "B"
     if name == "k_render_fp32":
-        return "alu", px * (2 * k * t * t + 2 * c * t * t), "flop"
+        # the plain blur's products run on the 16-bit matrix cores, three
+        # FP16 products per FP32 term: executed flops against the FP16 peak
+        return "mfma", px * 3 * 2 * k * t * t, "flop"
     if name == "k_warp":
         return "hbm", px * (8 + 4 * c + 4 * c), "B"
     if name == "k_subharmonic_add":

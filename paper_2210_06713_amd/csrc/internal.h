@@ -43,7 +43,8 @@ struct tsim_plan {
   uint16_t *d_basis_bf = nullptr;  // [groups of 32 tap pairs][2][32][KP + 8] bfloat16, zero padded
   uint16_t *d_basis_h3 = nullptr;  // basis x 2^10 as FP16 (hi, lo) pairs in matrix-core fragment order:
                                    // [ceil(T*T/32)][2][ceil(KP/32)][64][2][8] (projection)
-  float *d_basis_k2 = nullptr;     // [roundup(T*T,32)][2][K2P] float32: psi[2s+g][tap] (FP32 matrix-core blur)
+  uint16_t *d_basis_h3r = nullptr;  // basis x 2^10 as FP16 (hi, lo) in fragment order for the plain blur:
+                                    // [ceil(T*T/32)][KP/16][2][64][8]
   uint16_t *d_mlp_w = nullptr;     // packed BF16 network weights (inference layout)
   float *d_mlp_f = nullptr;        // biases, input scales, output means (FP32)
   float mlp_s_out = 1.f;

@@ -314,7 +314,7 @@ int validate(const tsim_params *p) {
 
 void free_plan(tsim_plan *pl) {
   if (!pl) return;
-  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zcheb, pl->d_basis, pl->d_basis_h3, pl->d_basis_k2,
+  void *ptrs[] = {pl->d_sqrtS, pl->d_tw_h, pl->d_tw_w, pl->d_L, pl->d_zcheb, pl->d_basis, pl->d_basis_h3, pl->d_basis_h3r,
                   pl->d_basis_t, pl->d_basis_bf, pl->d_mlp_w, pl->d_mlp_f};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -604,16 +604,26 @@ int plan_create_impl(const tsim_params *p, tsim_plan **out) {
               }
       if ((st = upload(&pl->d_basis_h3, h3.data(), h3.size())) != TSIM_OK) goto fail;
     }
-    // lane-contiguous layout for the FP32 matrix-core blur: [tap][g][s] = psi[2s + g][tap]
-    const int K2 = (K + 1) / 2, K2P = (K2 + 3) / 4 * 4, TTP = (T2 + 31) / 32 * 32;
-    std::vector<float> bk2(size_t(TTP) * 2 * K2P, 0.0f);
-    for (int t = 0; t < T2; ++t)
-      for (int g = 0; g < 2; ++g)
-        for (int s2 = 0; s2 < K2; ++s2) {
-          const int k = 2 * s2 + g;
-          if (k < K) bk2[(size_t(t) * 2 + g) * K2P + s2] = float(pl->basis[size_t(k) * T2 + t]);
-        }
-    if ((st = upload(&pl->d_basis_k2, bk2.data(), bk2.size())) != TSIM_OK) goto fail;
+    // the plain blur's operand: psi x 2^10 split into FP16 (hi, lo), in
+    // fragment order [tap block of 32][k-step of 16][hi, lo][lane][8]: lane l
+    // holds tap 32 block + l % 32, coefficients 16 step + 8 (l / 32) + 0..7;
+    // zero past K and T*T
+    {
+      const int NTB = (T2 + 31) / 32, KSR = KP / 16;
+      std::vector<uint16_t> r3(size_t(NTB) * KSR * 2 * 64 * 8, 0);
+      for (int tb = 0; tb < NTB; ++tb)
+        for (int q = 0; q < KSR; ++q)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e) {
+              const int t = 32 * tb + l % 32, k = 16 * q + 8 * (l / 32) + e;
+              const double x = (t < T2 && k < K) ? std::ldexp(pl->basis[size_t(k) * T2 + t], 10) : 0.0;
+              const uint16_t hi = f16_rn(x);
+              const uint16_t lo = f16_rn(x - f16_value(hi));
+              r3[(((size_t(tb) * KSR + q) * 2 + 0) * 64 + l) * 8 + e] = hi;
+              r3[(((size_t(tb) * KSR + q) * 2 + 1) * 64 + l) * 8 + e] = lo;
+            }
+      if ((st = upload(&pl->d_basis_h3r, r3.data(), r3.size())) != TSIM_OK) goto fail;
+    }
   }
   // device address of the allocation-free sampler's scratch array, looked
   // up now (once per device) so that its calls do no set-up work

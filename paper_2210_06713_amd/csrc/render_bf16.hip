@@ -26,6 +26,8 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 
 // Fragments are kept as four 32-bit words and reinterpreted only at the
 // matrix-core call: copies of 8 x bf16 vectors between pipeline stages
@@ -323,26 +325,70 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
   }
 }
 
-// The plain form's blur on the FP32 matrix cores (v_mfma_f32_32x32x2f32),
-// same block/wave/lane layout as the BF16 kernel: htilde^T[32 taps][32 px] =
-// psi x beta^T over K2 = K/2 k-steps of two.  psi2 holds, for tap n and lane
-// half g, the values psi[2s + g][n] for s = 0..K2P-1 contiguously, so a lane
-// streams its k-values with 16-byte loads; beta is FP32 [px][K].
-template <int K2, int T>
+// The plain form's blur on the 16-bit matrix cores at FP32 accuracy
+// (v_mfma_f32_32x32x16_f16), with the block/wave/lane layout of the BF16
+// kernel: htilde^T[32 taps][32 px] = psi x beta^T per 32-tap block, then the
+// taps applied to the image tile with FP32 FMAs.  The FP32 matrix
+// instructions would run at the FP32 vector rate; instead every operand is
+// split into FP16 x = x_hi + x_lo (x_lo = fp16(x - x_hi)) and each 16-wide
+// k-step is three products, psi_hi beta_hi + psi_hi beta_lo +
+// psi_lo beta_hi, in three FP32 accumulators (the dropped psi_lo beta_lo
+// and the rounding of the parts are each below 2^-22 of |psi beta|).  beta
+// is scaled by 2^12 and psi by 2^10 into FP16's normal range; the sums are
+// scaled back by 2^-22 at the end.  A lane's beta (its pixel, constant over
+// the taps) is split once; psi_hi and psi_lo of each tap block come split
+// from the plan table in fragment order and are staged in LDS for the
+// block's four waves by asynchronous copies, two blocks ahead, in a ring of
+// three stages.
+constexpr float kRBetaScale = 4096.f;                   // 2^12
+constexpr float kROutScale = 1.f / (4096.f * 1024.f);   // 2^-22
+
+template <int KS, int T>
+struct H3Geom {
+  static constexpr int TH = 8, TW = 16, R = (T - 1) / 2;
+  static constexpr int SH = TH + T - 1, SW = TW + T - 1, PLANE = SH * SW;
+  static constexpr int NT = (T * T + 31) / 32;   // tap blocks
+  static constexpr int GB = KS * 2 * 1024;        // bytes of one block's fragments: [KS][hi, lo][64 lanes][16 B]
+  static constexpr int NCH = GB / 1024;           // 1 KB wave copies per block
+  static constexpr int NS = 3;                    // ring stages: blocks tb + 1 and tb + 2 in flight
+  static size_t lds(int C) { return size_t(C) * PLANE * sizeof(float) + NS * size_t(GB); }
+};
+
+__device__ __forceinline__ f32x16 mfma_f16(const uint4 &a, const uint4 &b, const f32x16 &c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                0, 0);
+}
+
+template <int KS, int T>
 __global__ void __launch_bounds__(256)
-k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
-              const float *__restrict__ psi2 /*[ntaps][2][K2P]*/, float *__restrict__ out, int H,
-              int W, int C, int K) {
-  constexpr int TH = 8, TW = 16;
-  constexpr int K2P = (K2 + 3) / 4 * 4;
-  constexpr int R = (T - 1) / 2;
-  constexpr int SH = TH + T - 1, SW = TW + T - 1, PLANE = SH * SW;
-  constexpr int NT = (T * T + 31) / 32;
-  extern __shared__ float tile[];
+k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
+            const uint16_t *__restrict__ psi /*[NT][KS][2][64][8] f16*/, float *__restrict__ out, int H, int W,
+            int C, int K) {
+  using G = H3Geom<KS, T>;
+  constexpr int TH = G::TH, TW = G::TW, R = G::R, SW = G::SW, PLANE = G::PLANE, NT = G::NT;
+  constexpr int GB = G::GB, NCH = G::NCH, CPW = (NCH + 3) / 4, NS = G::NS;
+  static_assert(CPW <= 15, "copies per wave fit the counted wait");
+  extern __shared__ __attribute__((aligned(16))) float tile[];  // [C][PLANE] image samples, then the psi ring
   __shared__ short offtab[NT * 32];
   const int f = blockIdx.z;
   const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
   const float *imf = img + size_t(f) * C * H * W;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  char *ring = reinterpret_cast<char *>(tile + C * PLANE);
+  // tap block tb goes to ring stage tb % 3; wave w copies pieces w, w + 4,
+  // ... (a wave past the last piece repeats it: same bytes to the same place)
+  const uint32_t ring_lds = uint32_t(reinterpret_cast<uintptr_t>(ring));
+  auto stage_in = [&](int tb) {
+    const char *src = reinterpret_cast<const char *>(psi) + size_t(tb) * GB;
+    const uint32_t dst = ring_lds + uint32_t((tb % NS) * GB);
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      const int piece = min(w + 4 * k, NCH - 1);
+      copy_to_lds(src + piece * 1024, dst + uint32_t(piece * 1024), lane);
+    }
+  };
+  stage_in(0);
+  if (NT > 1) stage_in(1);
   // tile loads in batches of eight per thread, all requested before any is
   // stored (a frame spans < 4 GiB)
   {
@@ -371,58 +417,104 @@ k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
     const int uy = e / T - R, ux = e % T - R;
     offtab[e] = (e < T * T) ? uy * SW + ux : 0;
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 5, pn = lane & 31;
   const int py = 2 * w + (pn >> 4), px = pn & 15;
   const int y = ty0 + py, x = tx0 + px;
   const bool ok = (y < H) && (x < W);
-  float b[K2];
+  // B operand: this pixel's beta, k-slice 16 q + 8 g + 0..7 of step q, as
+  // FP16 hi and lo
+  uint4 bhi[KS], blo[KS];
   {
     const float *bp = beta + ((size_t(f) * H + (ok ? y : 0)) * W + (ok ? x : 0)) * K;
 #pragma unroll
-    for (int s = 0; s < K2; ++s) b[s] = (ok && 2 * s + g < K) ? bp[2 * s + g] : 0.f;
+    for (int q = 0; q < KS; ++q) {
+      f32x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 16 * q + 8 * g + e;
+        v[e] = (ok && k < K) ? bp[k] : 0.f;
+      }
+      v *= kRBetaScale;
+      const f16x8 hi = __builtin_convertvector(v, f16x8);
+      const f16x8 lo = __builtin_convertvector(v - __builtin_convertvector(hi, f32x8), f16x8);
+      bhi[q] = __builtin_bit_cast(uint4, hi);
+      blo[q] = __builtin_bit_cast(uint4, lo);
+    }
   }
   const int pbase = (py + R) * SW + px + R;
-  const float *prow = psi2 + (size_t(pn) * 2 + g) * K2P;
-  const size_t tstride = size_t(32) * 2 * K2P;
   const int mrow = 4 * g;
-  __syncthreads();
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  f32x16 acc0 = {};
-  // psi of tap block t + 1 is loaded while block t goes through the matrix cores
-  float4 cur[K2P / 4], nxt[K2P / 4];
-  {
-    const float4 *pp = reinterpret_cast<const float4 *>(prow);
+  const char *frag = ring + lane * 16;
+  // products of tap block tb: x1 = psi_hi beta_hi, x2 = psi_hi beta_lo +
+  // psi_lo beta_hi.  This wave's copies complete in order, so block tb has
+  // landed once at most the CPW copies of block tb + 1 are in flight; past
+  // the barrier every wave's copies of it have, and every wave is done with
+  // stage (tb + 2) % 3 (read at step tb - 1).  Before the first block the
+  // barrier also completes the tile and the offset table.
+  auto products = [&](int tb, f32x16 &x1, f32x16 &x2) {
+    if (tb + 1 < NT)
+      __builtin_amdgcn_s_waitcnt((CPW & 15) | (7 << 4) | ((CPW >> 4) << 14));  // vmcnt(CPW) lgkmcnt(0)
+    else
+      __builtin_amdgcn_s_waitcnt(7 << 4);                                      // vmcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    if (tb + 2 < NT) stage_in(tb + 2);
+    const char *st = frag + (tb % NS) * GB;
+    uint4 ahi[KS], alo[KS];
 #pragma unroll
-    for (int q = 0; q < K2P / 4; ++q) cur[q] = pp[q];
-  }
-  for (int t = 0; t < NT; ++t) {
-    if (t + 1 < NT) {
-      const float4 *pp = reinterpret_cast<const float4 *>(prow + size_t(t + 1) * tstride);
-#pragma unroll
-      for (int q = 0; q < K2P / 4; ++q) nxt[q] = pp[q];
+    for (int q = 0; q < KS; ++q) {
+      ahi[q] = *reinterpret_cast<const uint4 *>(st + (2 * q) * 1024);
+      alo[q] = *reinterpret_cast<const uint4 *>(st + (2 * q + 1) * 1024);
     }
-    acc0 = f32x16{};
+    x1 = f32x16{};
+    x2 = f32x16{};
 #pragma unroll
-    for (int q = 0; q < K2P / 4; ++q) {
-      const float4 a = cur[q];
-      if (4 * q + 0 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b[4 * q + 0], acc0, 0, 0, 0);
-      if (4 * q + 1 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b[4 * q + 1], acc0, 0, 0, 0);
-      if (4 * q + 2 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b[4 * q + 2], acc0, 0, 0, 0);
-      if (4 * q + 3 < K2) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b[4 * q + 3], acc0, 0, 0, 0);
+    for (int q = 0; q < KS; ++q) {
+      x1 = mfma_f16(ahi[q], bhi[q], x1);
+      x2 = mfma_f16(ahi[q], blo[q], x2);
+      x2 = mfma_f16(alo[q], bhi[q], x2);
     }
-#pragma unroll
-    for (int q = 0; q < K2P / 4; ++q) cur[q] = nxt[q];
-    const short *ot = offtab + 32 * t + mrow;
+  };
+  // the taps of block tb applied to the image tile
+  auto apply = [&](int tb, const f32x16 &x1, const f32x16 &x2) {
+    const short *ot = offtab + 32 * tb + mrow;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int idx = pbase - ot[8 * (r >> 2) + (r & 3)];
-      const float v = acc0[r];
+      const float v = x1[r] + x2[r];
       s0 = fmaf(v, tile[idx], s0);
       if (C > 1) s1 = fmaf(v, tile[PLANE + idx], s1);
       if (C > 2) s2 = fmaf(v, tile[2 * PLANE + idx], s2);
       if (C > 3) s3 = fmaf(v, tile[3 * PLANE + idx], s3);
     }
+  };
+  // each matrix-core instruction of block tb is followed in the schedule by
+  // LDS reads and FMAs of block tb - 1's application
+  auto interleave = [&]() {
+#pragma unroll
+    for (int i = 0; i < 3 * KS; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+    }
+  };
+  f32x16 p1, p2, q1, q2;
+  products(0, p1, p2);
+  int tb = 1;
+  for (; tb + 1 < NT; tb += 2) {
+    products(tb, q1, q2);
+    apply(tb - 1, p1, p2);
+    interleave();
+    products(tb + 1, p1, p2);
+    apply(tb, q1, q2);
+    interleave();
+  }
+  if (tb < NT) {
+    products(tb, q1, q2);
+    apply(tb - 1, p1, p2);
+    interleave();
+    apply(tb, q1, q2);
+  } else {
+    apply(tb - 1, p1, p2);
   }
   s0 += __shfl_xor(s0, 32);
   s1 += __shfl_xor(s1, 32);
@@ -431,10 +523,10 @@ k_render_f32m(const float *__restrict__ img, const float *__restrict__ beta,
   if (lane < 32 && ok) {
     float *of = out + size_t(f) * C * H * W + size_t(y) * W + x;
     const size_t pl = size_t(H) * W;
-    of[0] = s0;
-    if (C > 1) of[pl] = s1;
-    if (C > 2) of[2 * pl] = s2;
-    if (C > 3) of[3 * pl] = s3;
+    of[0] = s0 * kROutScale;
+    if (C > 1) of[pl] = s1 * kROutScale;
+    if (C > 2) of[2 * pl] = s2 * kROutScale;
+    if (C > 3) of[3 * pl] = s3 * kROutScale;
   }
 }
 
@@ -541,23 +633,43 @@ int launch_ks(const tsim_plan *pl, int frames, const float *img, const uint16_t 
 
 }  // namespace
 
-int launch_render_f32_mfma(const tsim_plan *pl, int frames, const float *img, const float *beta,
-                           float *out, hipStream_t s) {
-  const int H = pl->H, W = pl->W, C = pl->C, T = pl->T;
-  if (!pl->d_basis_k2 || pl->K != 100 || (T != 33 && T != 65)) return TSIM_EUNSUPPORTED;
-  if (size_t(C) * H * W * sizeof(float) >= (size_t(1) << 32)) return TSIM_EUNSUPPORTED;
-  dim3 grid((W + 15) / 16, (H + 7) / 8, frames);
-  const size_t lds = size_t(C) * (8 + T - 1) * (16 + T - 1) * sizeof(float);
-  const int st = T == 33 ? prepare_lds(k_render_f32m<50, 33>, lds, T) : prepare_lds(k_render_f32m<50, 65>, lds, T);
+namespace {
+
+template <int KS, int T>
+int launch_h3(const tsim_plan *pl, int frames, const float *img, const float *beta, float *out, hipStream_t s) {
+  using G = H3Geom<KS, T>;
+  const int H = pl->H, W = pl->W, C = pl->C;
+  dim3 grid((W + G::TW - 1) / G::TW, (H + G::TH - 1) / G::TH, frames);
+  const size_t lds = G::lds(C);
+  const int st = prepare_lds(k_render_h3<KS, T>, lds, T);
   if (st != TSIM_OK) return st;
   TraceScope tr("k_render_fp32", s);
-  if (T == 33)
-    hipLaunchKernelGGL((k_render_f32m<50, 33>), grid, dim3(256), lds, s, img, beta, pl->d_basis_k2, out,
-                       H, W, C, pl->K);
-  else
-    hipLaunchKernelGGL((k_render_f32m<50, 65>), grid, dim3(256), lds, s, img, beta, pl->d_basis_k2, out,
-                       H, W, C, pl->K);
+  hipLaunchKernelGGL((k_render_h3<KS, T>), grid, dim3(256), lds, s, img, beta, pl->d_basis_h3r, out, H, W, C,
+                     pl->K);
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+template <int KS>
+int launch_h3_ks(const tsim_plan *pl, int frames, const float *img, const float *beta, float *out,
+                 hipStream_t s) {
+  if (pl->T == 33) return launch_h3<KS, 33>(pl, frames, img, beta, out, s);
+  if (pl->T == 65) return launch_h3<KS, 65>(pl, frames, img, beta, out, s);
+  return TSIM_EUNSUPPORTED;
+}
+
+}  // namespace
+
+int launch_render_f32_mfma(const tsim_plan *pl, int frames, const float *img, const float *beta,
+                           float *out, hipStream_t s) {
+  if (!pl->d_basis_h3r || pl->C > 4) return TSIM_EUNSUPPORTED;
+  if (size_t(pl->C) * pl->H * pl->W * sizeof(float) >= (size_t(1) << 32)) return TSIM_EUNSUPPORTED;
+  switch (pl->KP) {
+    case 32: return launch_h3_ks<2>(pl, frames, img, beta, out, s);
+    case 64: return launch_h3_ks<4>(pl, frames, img, beta, out, s);
+    case 112: return launch_h3_ks<7>(pl, frames, img, beta, out, s);
+    case 128: return launch_h3_ks<8>(pl, frames, img, beta, out, s);
+    default: return TSIM_EUNSUPPORTED;
+  }
 }
 
 int launch_render_bf16(const tsim_plan *pl, int frames, const float *img, const uint16_t *beta,
