@@ -68,11 +68,20 @@ k_render_fp32(const float *__restrict__ img, const float *__restrict__ beta,
 
 __global__ void __launch_bounds__(256)
 k_warp(const float *__restrict__ img, const float *__restrict__ zern, float *__restrict__ out,
-       int H, int W, int C, int nmodes) {
-  const int f = blockIdx.z;
-  const int y = blockIdx.y;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= W) return;
+       int H, int W, int C, int nmodes, int tiles_x, int tiles_y, int n_tiles) {
+  // Tiles of 64 x 4 pixels, so the source rows a tile reads (its own rows
+  // shifted by the local tilt) are shared within the block; workgroups go to
+  // the 8 XCDs in turn, so XCD k is given the contiguous band of tiles
+  // [k n / 8, (k + 1) n / 8) (rows of tiles, frame by frame) and neighbouring
+  // tiles read their common source rows through one L2.
+  const int band = (n_tiles + 7) / 8;
+  const int t = int(blockIdx.x % 8u) * band + int(blockIdx.x / 8u);
+  if (t >= n_tiles) return;
+  const int per_frame = tiles_x * tiles_y;
+  const int f = t / per_frame, tr = t - f * per_frame;
+  const int y = (tr / tiles_x) * 4 + int(threadIdx.x >> 6);
+  const int x = (tr % tiles_x) * 64 + int(threadIdx.x & 63);
+  if (x >= W || y >= H) return;
   const size_t plane = size_t(H) * W;
   const float *zf = zern + size_t(f) * nmodes * plane;
   const float k = -1.27323954473516268f;  // -4/pi pixels per radian of tilt
@@ -148,8 +157,12 @@ int launch_render_fp32(const tsim_plan *pl, int frames, const float *img, const 
 
 int launch_warp(const tsim_plan *pl, int frames, const float *img, const float *zern, float *out,
                 hipStream_t s) {
-  dim3 grid((pl->W + 255) / 256, pl->H, frames);
+  const int tiles_x = (pl->W + 63) / 64, tiles_y = (pl->H + 3) / 4;
+  const size_t n_tiles = size_t(tiles_x) * tiles_y * size_t(frames);
+  if (n_tiles > size_t(1) << 30) return TSIM_EUNSUPPORTED;
+  const unsigned blocks = unsigned((n_tiles + 7) / 8 * 8);
   TraceScope tr("k_warp", s);
-  hipLaunchKernelGGL(k_warp, grid, dim3(256), 0, s, img, zern, out, pl->H, pl->W, pl->C, pl->N);
+  hipLaunchKernelGGL(k_warp, dim3(blocks), dim3(256), 0, s, img, zern, out, pl->H, pl->W, pl->C, pl->N, tiles_x,
+                     tiles_y, int(n_tiles));
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
