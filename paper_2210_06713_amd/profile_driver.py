@@ -20,7 +20,7 @@ weight values), then one element-wise copy of 256 MiB (read 256 MiB, write
 kernel's source file and of the shared device header) and a Markdown table.
 ``--sq-summary`` turns a run of shader-sequencer counters into per-kernel
 busy fractions: matrix-core busy = SQ_VALU_MFMA_BUSY_CYCLES / (cycles x 1024
-SIMDs), and vector-ALU, LDS and vector-memory issue = SQ_ACTIVE_INST_* (in
+SIMDs), and vector-ALU and LDS issue = SQ_ACTIVE_INST_* (in
 quad cycles, per SIMD) x 4 / (cycles x 1024 SIMDs), with cycles = the
 kernel's GRBM_GUI_ACTIVE, which rocprofv3 sums over the eight XCDs.
 """
@@ -40,8 +40,8 @@ CAL_BYTES = 256 << 20
 SOURCES = {"k_sampler_cols": ("k_sampler_cols", "sampler.hip"),
            "k_sampler_rows_mix": ("k_sampler_rows_mix", "sampler.hip"),
            "k_psf64": ("k_psf64", "psf.hip"), "k_psf128": ("k_psf128", "psf.hip"),
-           "k_project_mfma": ("k_project", "project.hip"),
-           "k_render_f32m": ("k_render_fp32", "render_bf16.hip"),
+           "k_project_h3": ("k_project", "project.hip"),
+           "k_render_h3": ("k_render_fp32", "render_bf16.hip"),
            "k_render_bf16": ("k_render_bf16", "render_bf16.hip"),
            "k_mlp_infer": ("k_mlp_infer", "mlp.hip"), "k_warp": ("k_warp", "render.hip")}
 
@@ -229,15 +229,15 @@ def sq_summary(qdir, dst, command, title):
     out = [f"# {title}", "", "Command (from the repository root, on one MI355X):", "", "```", command, "```", "",
            "Per kernel, the median over its dispatches. cycles = GRBM_GUI_ACTIVE / 8 (rocprofv3 sums it",
            "over the eight XCDs); matrix cores busy = SQ_VALU_MFMA_BUSY_CYCLES / (cycles x 1024 SIMDs);",
-           "VALU / LDS / VMEM issue = SQ_ACTIVE_INST_{VALU,LDS,VMEM} x 4 (quad cycles) / (cycles x 1024 SIMDs).",
-           "", "| kernel | dispatches | cycles (median) | matrix cores busy % | VALU issue % | LDS issue % | VMEM issue % |",
-           "|---|---:|---:|---:|---:|---:|---:|"]
+           "VALU / LDS issue = SQ_ACTIVE_INST_{VALU,LDS} x 4 (quad cycles) / (cycles x 1024 SIMDs).",
+           "(SQ_ACTIVE_INST_VMEM reads zero for every kernel on this chip and is not shown.)",
+           "", "| kernel | dispatches | cycles (median) | matrix cores busy % | VALU issue % | LDS issue % |",
+           "|---|---:|---:|---:|---:|---:|"]
     for n in sorted(by_kernel):
         v = by_kernel[n]
         med = [_median([x[i] for x in v]) for i in range(5)]
         label = n if len(n) <= 60 else n[:57] + "..."
-        out.append(f"| {label} | {len(v)} | {med[0]:.0f} | {med[1]:.1f} | {med[2]:.1f} | {med[3]:.1f} | "
-                   f"{med[4]:.1f} |")
+        out.append(f"| {label} | {len(v)} | {med[0]:.0f} | {med[1]:.1f} | {med[2]:.1f} | {med[3]:.1f} |")
     with open(dst, "w") as f:
         f.write("\n".join(out) + "\n")
     return out
