@@ -400,6 +400,9 @@ class Workload:
         n = s["chunk"]
         ws = pl.workspace(n)
         drs = s["drs"]
+        # the sampler's launch forms, chosen by the library's autotuner on
+        # these buffers (the fields do not depend on the choice)
+        self.tuning = pl.autotune(n, self.zern[:n], ws)
 
         def chunk(i, c0):
             m = min(n, frames - c0)
@@ -643,6 +646,7 @@ def main():
     # ---- plain FP32 form (exact P2S) ----
     beta32 = torch.empty((FRAMES, H, W, K), dtype=torch.float32, device=dev)
     ms, rep, out_plain = wl.run(tsim, plan, beta32, args.steps, args.warmup, FRAMES)
+    wl_tuning = wl.tuning
     zern_first = wl.zern_first
     outs_first = {"plain_fp32": out_plain[:3].cpu().numpy()}
     kernels, roofline = summarize(rep, args.steps, FRAMES, s, traffic=True)
@@ -688,6 +692,7 @@ def main():
                                    "basis, FP32 basis blur + bilinear tilt warp (plain FP32 form)",
                        "frames_per_step": FRAMES, "H": H, "W": W, "C": C, "grid": G, "K": K,
                        "T": T, "pupil": P},
+            "sampler_forms": {"pass1_columns_per_block": wl_tuning[0], "pass2_form": wl_tuning[1]},
             "roofline": roofline, "kernels": kernels, "learned_bf16": learned,
             "subharmonic_sampler": subh, "large_4k": large, "setup_s": round(setup_s, 2)}
     if cpu is not None:

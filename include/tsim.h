@@ -195,6 +195,30 @@ int tsim_sample_zernike_noalloc(const tsim_plan *plan, int frames, const float *
                                 uint64_t seed, uint64_t frame0, float *zern,
                                 tsim_stream stream);
 
+/* Launch forms of the field sampler (the two passes of tsim_sample_zernike,
+ * Sec. III-A / III-C), chosen per plan.  Every form computes the same
+ * transforms and sums, so the fields do not depend on it; only the time does.
+ *   pass-1 columns: columns of the grid one block transforms (NC columns of
+ *     Gh points in LDS; (NC / 2) Gh must be 1024, 2048 or 4096 draws);
+ *   pass-2 form: 1 = two rows per 256-thread block (W <= 1024), 2 = the same
+ *     with twice the outputs per thread (W <= 512), 3 = one row per
+ *     1024-thread block.
+ * tsim_plan_autotune times each candidate of each pass on the caller's
+ * buffers (a warm-up, then the best of three timed runs, HIP events on the
+ * stream) and keeps the fastest in the plan; a candidate replaces the
+ * built-in form only when at least 3% faster.  It synchronises the stream,
+ * overwrites zern and ws, and changes the plan: call it before the plan is
+ * used on other threads.
+ *   frames : frames of the workload to time (at most one pass-1 chunk is used)
+ *   zern   : device [frames][N][H][W] float32 scratch, 256-byte aligned
+ *   ws     : device workspace of tsim_workspace_bytes(plan, frames) bytes
+ * tsim_plan_set_tuning forces a form (0 = the built-in choice; TSIM_EINVAL
+ * for a form the plan's shape does not allow); tsim_plan_tuning returns the
+ * forms in effect. */
+int tsim_plan_autotune(tsim_plan *plan, int frames, float *zern, void *ws, tsim_stream stream);
+int tsim_plan_set_tuning(tsim_plan *plan, int columns, int rows_form);
+int tsim_plan_tuning(const tsim_plan *plan, int *columns, int *rows_form);
+
 /* Spatial tilt statistics of coefficient planes (the spatial validation of
  * Sec. IV-B): for Noll 2 and 3, the tilt correlation (mean product) and the
  * differential tilt variance (mean squared difference) of all pixel pairs at

@@ -63,6 +63,9 @@ _lib_ws = _sig("tsim_workspace_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_siz
 _lib_table = _sig("tsim_plan_table", _i, [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t])
 _lib_sample = _sig("tsim_sample_zernike", _i,
                    [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64, _vp, _vp, _vp])
+_lib_autotune = _sig("tsim_plan_autotune", _i, [_vp, _i, _vp, _vp, _vp])
+_lib_set_tuning = _sig("tsim_plan_set_tuning", _i, [_vp, _i, _i])
+_lib_tuning = _sig("tsim_plan_tuning", _i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)])
 _lib_sample_noalloc = _sig("tsim_sample_zernike_noalloc", _i,
                            [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64, _vp, _vp])
 _lib_sample_ar = _sig("tsim_sample_zernike_ar", _i, [_vp, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64,
@@ -111,6 +114,7 @@ _lib_last_error = _sig("tsim_last_error", _i, [ctypes.c_char_p, ctypes.c_size_t]
 _lib_sync = _sig("tsim_sync", _i, [_vp])
 
 EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "tsim_plan_table",
+            "tsim_plan_autotune", "tsim_plan_set_tuning", "tsim_plan_tuning",
             "tsim_sample_zernike", "tsim_sample_zernike_ar", "tsim_p2s", "tsim_render", "tsim_warp", "tsim_psf_exact",
             "tsim_status_string", "tsim_host_tables", "tsim_basis_build", "tsim_trace_enable",
             "tsim_trace_count", "tsim_trace_get", "tsim_mlp_create", "tsim_mlp_destroy",
@@ -348,6 +352,26 @@ class Plan:
         _check(_lib_sample(self._h, frames, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                            int(seed), int(frame0), _ptr(zern), _ptr(ws), _stream(stream)),
                "tsim_sample_zernike")
+
+    def autotune(self, frames, zern, ws, stream=None):
+        """Times the sampler's launch forms on these buffers and keeps the
+        fastest (tsim_plan_autotune); returns (pass-1 columns, pass-2 form)."""
+        f, dev = self._zern(zern)
+        if f != frames or frames < 1:
+            raise ValueError("zern must hold `frames` frames")
+        self._ws(ws, frames, dev)
+        _check(_lib_autotune(self._h, frames, _ptr(zern), _ptr(ws), _stream(stream)), "tsim_plan_autotune")
+        return self.tuning()
+
+    def set_tuning(self, columns=0, rows_form=0):
+        """Forces the sampler's launch forms (0 = the built-in choice)."""
+        _check(_lib_set_tuning(self._h, int(columns), int(rows_form)), "tsim_plan_set_tuning")
+
+    def tuning(self):
+        """(pass-1 columns per block, pass-2 form) in effect."""
+        c, r = _i(), _i()
+        _check(_lib_tuning(self._h, ctypes.byref(c), ctypes.byref(r)), "tsim_plan_tuning")
+        return c.value, r.value
 
     def sample_zernike_noalloc(self, d_over_r0, seed, frame0, zern, stream=None):
         """tsim_sample_zernike without a workspace and without any allocation

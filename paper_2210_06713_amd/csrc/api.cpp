@@ -279,6 +279,96 @@ int tsim_batch_destroy(tsim_batch *batch) {
   return TSIM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Times each candidate launch form of the sampler's two passes on the
+// caller's buffers (one warm-up, best of three, HIP events on the stream)
+// and keeps the fastest in the plan; a candidate replaces the built-in form
+// only if it is at least 3% faster.
+int autotune_impl(tsim_plan *pl, int frames, float *zern, void *ws, hipStream_t s) {
+  if (!frames_ok(pl, frames) || !zern || !ws || !aligned(zern) || !aligned(ws)) return TSIM_EINVAL;
+  const int nf = sampler_chunk_frames(pl, frames);
+  TraceQuiet quiet;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return TSIM_EDEVICE;
+  }
+  int st = TSIM_OK;
+  auto time_pass = [&](int pass, float *ms) {
+    st = launch_sampler_pass(pl, pass, nf, zern, ws, s);
+    float best = 1e30f;
+    for (int r = 0; r < 3 && st == TSIM_OK; ++r) {
+      float t = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess) st = TSIM_EDEVICE;
+      if (st == TSIM_OK) st = launch_sampler_pass(pl, pass, nf, zern, ws, s);
+      if (st == TSIM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        st = TSIM_EDEVICE;
+      best = std::min(best, t);
+    }
+    *ms = best;
+  };
+  const int nc0 = pl->tune_nc, rows0 = pl->tune_rows;
+  int cand[4], n = sampler_pass1_forms(pl, cand);
+  int best_nc = cand[0];
+  float best_t = 0.f;
+  for (int i = 0; i < n && st == TSIM_OK; ++i) {
+    pl->tune_nc = cand[i];
+    float t = 0.f;
+    time_pass(1, &t);
+    if (i == 0 || t < 0.97f * best_t) {
+      best_t = t;
+      best_nc = cand[i];
+    }
+  }
+  pl->tune_nc = best_nc;
+  n = sampler_pass2_forms(pl, cand);
+  int best_rows = cand[0];
+  for (int i = 0; i < n && st == TSIM_OK; ++i) {
+    pl->tune_rows = cand[i];
+    float t = 0.f;
+    time_pass(2, &t);
+    if (i == 0 || t < 0.97f * best_t) {
+      best_t = t;
+      best_rows = cand[i];
+    }
+  }
+  pl->tune_rows = best_rows;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != TSIM_OK) {
+    pl->tune_nc = nc0;
+    pl->tune_rows = rows0;
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsim_plan_autotune(tsim_plan *plan, int frames, float *zern, void *ws, tsim_stream stream) {
+  return note_status("tsim_plan_autotune", autotune_impl(plan, frames, zern, ws, hs(stream)));
+}
+
+int tsim_plan_set_tuning(tsim_plan *plan, int columns, int rows_form) {
+  if (!plan || columns < 0 || rows_form < 0 || rows_form > 3 || !sampler_form_valid(plan, columns, rows_form))
+    return note_status("tsim_plan_set_tuning", TSIM_EINVAL);
+  plan->tune_nc = columns;
+  plan->tune_rows = rows_form;
+  return TSIM_OK;
+}
+
+int tsim_plan_tuning(const tsim_plan *plan, int *columns, int *rows_form) {
+  if (!plan || !columns || !rows_form) return note_status("tsim_plan_tuning", TSIM_EINVAL);
+  *columns = pass1_nc(plan);
+  *rows_form = pass2_form(plan);
+  return TSIM_OK;
+}
+
 int tsim_workspace_bytes(const tsim_plan *pl, int frames, size_t *bytes) {
   if (!bytes || !frames_ok(pl, frames)) return note_status("tsim_workspace_bytes", TSIM_EINVAL);
   size_t a = sampler_ws_bytes(pl, frames);

@@ -45,6 +45,11 @@ struct tsim_plan {
                                    // [ceil(T*T/32)][2][ceil(KP/32)][64][2][8] (projection)
   uint16_t *d_basis_h3r = nullptr;  // basis x 2^10 as FP16 (hi, lo) in fragment order for the plain blur:
                                     // [ceil(T*T/32)][KP/16][2][64][8]
+  // sampler launch forms (0 = the built-in choice): pass-1 columns per
+  // block, pass-2 form (1 = two rows per 256-thread block, 2 = the same
+  // with twice the columns per thread, 3 = one row per 1024-thread block);
+  // set by tsim_plan_autotune / tsim_plan_set_tuning
+  int tune_nc = 0, tune_rows = 0;
   uint16_t *d_mlp_w = nullptr;     // packed BF16 network weights (inference layout)
   float *d_mlp_f = nullptr;        // biases, input scales, output means (FP32)
   float mlp_s_out = 1.f;
@@ -79,6 +84,17 @@ class TraceQuiet {
 int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
                    uint64_t frame0, float *zern, void *ws, hipStream_t s);
 size_t sampler_ws_bytes(const tsim_plan *pl, int frames);
+// the sampler's candidate launch forms for the plan's shape (built-in
+// choice first); out arrays of at least 4 entries, returns the count
+int sampler_pass1_forms(const tsim_plan *pl, int *nc);
+int sampler_pass2_forms(const tsim_plan *pl, int *form);
+// one pass of the sampler alone with a given form, for timing (frames <=
+// one chunk, ws as for tsim_sample_zernike, zern of frames frames)
+int launch_sampler_pass(const tsim_plan *pl, int pass, int frames, float *zern, void *ws, hipStream_t s);
+bool sampler_form_valid(const tsim_plan *pl, int nc, int rows);
+int pass1_nc(const tsim_plan *pl);    // effective pass-1 columns per block
+int pass2_form(const tsim_plan *pl);  // effective pass-2 form (1, 2, 3)
+int sampler_chunk_frames(const tsim_plan *pl, int frames);  // frames per pass-1 launch
 int launch_sampler_ar(const tsim_plan *pl, int frames, const float *scale_host, float alpha,
                       const float *zern_prev, float scale_prev, uint64_t seed, uint64_t frame0,
                       float *zern, void *ws, hipStream_t s);

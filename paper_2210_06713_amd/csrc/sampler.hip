@@ -615,6 +615,33 @@ void launch_rows(dim3 grid, size_t lds, hipStream_t s, const float2 *V, const fl
   }
 }
 
+// The row pass's form: 1 = two rows per 256-thread block with the fewest
+// outputs per thread covering W (up to W = 1024), 2 = the same with twice
+// the outputs per thread (W <= 512), 3 = one row per 1024-thread block
+// (four outputs per thread, any W <= 4096).  Every form computes the same
+// transforms and sums; they differ only in how the work is spread.
+int pass2_default(const tsim_plan *pl) { return pl->W <= 1024 ? 1 : 3; }
+
+int pass2_form(const tsim_plan *pl) { return pl->tune_rows ? pl->tune_rows : pass2_default(pl); }
+
+bool pass2_valid(const tsim_plan *pl, int form) {
+  if (form == 1) return pl->W <= 1024;
+  if (form == 2) return pl->W <= 512;
+  return form == 3;
+}
+
+// Pass-1 columns per block: NC columns of Gh points in LDS, (NC / 2) Gh =
+// 512 IPT draws with IPT = 2, 4 or 8; the built-in choice fills 32 KB.
+int pass1_default(const tsim_plan *pl) { return std::min(std::max(2, std::min(kLdsFloat2 / pl->Gh, 32)), pl->Gw); }
+
+bool pass1_valid(const tsim_plan *pl, int nc) {
+  if (nc < 2 || nc > pl->Gw || (nc & (nc - 1)) != 0) return false;
+  const long ipt = long(nc / 2) * pl->Gh / 512;
+  return (ipt == 2 || ipt == 4 || ipt == 8) && (long(nc / 2) * pl->Gh) % 512 == 0;
+}
+
+int pass1_nc(const tsim_plan *pl) { return pl->tune_nc ? pl->tune_nc : pass1_default(pl); }
+
 // pass 2 (with the mix for 35 modes; unit fields and k_mix_groups beyond)
 // and the subharmonic waves
 int launch_rows_n(const tsim_plan *pl, int nf, int f0, const float2 *V, float *zern, const FrameScales &sc,
@@ -627,24 +654,30 @@ int launch_rows_n(const tsim_plan *pl, int nf, int f0, const float2 *V, float *z
     const size_t lds2 = (2 * size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
     const size_t lds1 = (size_t(Gw) + fft_twiddle_count(log2w)) * sizeof(float2);
     dim3 g2((H + 1) / 2, nf), g1r(H, nf);
+    // outputs per thread of the two-row form: the least that covers W, or
+    // twice that (form 2); the one-row form takes four per thread
+    int px = W <= 256 ? 1 : W <= 512 ? 2 : 4;
+    const int form = pass2_form(pl);
+    if (form == 2) px *= 2;
+    if (form == 3 || px > 4) px = 0;  // one row per 1024-thread block
     if (pl->N == 35) {
-      if (W <= 256)
+      if (px == 1)
         launch_rows<35, 1, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-      else if (W <= 512)
+      else if (px == 2)
         launch_rows<35, 2, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
-      else if (W <= 1024)
+      else if (px == 4)
         launch_rows<35, 4, 256, 2>(g2, lds2, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
       else
         launch_rows<35, 4, 1024, 1>(g1r, lds1, s, V, pl->d_tw_w, pl->d_L, zern, Gw, log2w, H, W, sc, f0);
     } else {
       const int N = pl->N;
-      if (W <= 256)
+      if (px == 1)
         hipLaunchKernelGGL((k_sampler_rows_unit<1, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, zern, Gw, log2w,
                            H, W, N, f0);
-      else if (W <= 512)
+      else if (px == 2)
         hipLaunchKernelGGL((k_sampler_rows_unit<2, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, zern, Gw, log2w,
                            H, W, N, f0);
-      else if (W <= 1024)
+      else if (px == 4)
         hipLaunchKernelGGL((k_sampler_rows_unit<4, 256, 2>), g2, dim3(256), lds2, s, V, pl->d_tw_w, zern, Gw, log2w,
                            H, W, N, f0);
       else
@@ -689,18 +722,18 @@ int launch_rows_n(const tsim_plan *pl, int nf, int f0, const float2 *V, float *z
   return TSIM_OK;
 }
 
-int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
-                   uint64_t frame0, float *zern, void *ws, hipStream_t s) {
-  const int Gh = pl->Gh, Gw = pl->Gw, H = pl->H, W = pl->W;
-  const int log2h = ilog2(Gh), log2w = ilog2(Gw);
-  int NC = std::max(2, std::min(kLdsFloat2 / Gh, 32));
-  NC = std::min(NC, Gw);
-  const uint32_t key0 = uint32_t(seed & 0xffffffffu), key1 = uint32_t(seed >> 32);
-  float2 *V = static_cast<float2 *>(ws);
-  const int chunk = frames_per_chunk(pl, frames);
+namespace {
+
+// pass 1 over nf frames (frame counters fb, fb + 1, ...) into V
+int launch_pass1(const tsim_plan *pl, int nf, uint32_t fb, uint32_t key0, uint32_t key1, float2 *V,
+                 hipStream_t s) {
+  const int Gh = pl->Gh, Gw = pl->Gw, H = pl->H;
+  const int log2h = ilog2(Gh);
+  const int NC = pass1_nc(pl);
+  if (!pass1_valid(pl, NC)) return TSIM_EUNSUPPORTED;
   // NC columns plus the twiddle table: 2 x 4096 + 1365 samples (75 KB) at
   // Gh = 4096, above the default 64 KB of dynamic LDS; the device limit is
-  // checked and raised once
+  // checked and raised once (only the 8-draw form reaches it)
   const size_t lds1 = (size_t(NC) * Gh + fft_twiddle_count(log2h)) * sizeof(float2);
   if (lds1 > 64 * 1024) {
     static size_t raised = 0;
@@ -718,44 +751,93 @@ int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uin
   }
   // draws per thread of a pass-1 block: (NC / 2) Gh / 512 = 2, 4 or 8
   const int ipt = (NC / 2) * Gh / 512;
-  if (ipt != 2 && ipt != 4 && ipt != 8) return TSIM_EUNSUPPORTED;
+  dim3 g1(Gw / NC, pl->NF);
+  TraceScope tr("k_sampler_cols", s);
+  if (ipt == 2)
+    hipLaunchKernelGGL(k_sampler_cols<2>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h, H, NC,
+                       key0, key1, fb, nf, pl->N);
+  else if (ipt == 4)
+    hipLaunchKernelGGL(k_sampler_cols<4>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h, H, NC,
+                       key0, key1, fb, nf, pl->N);
+  else
+    hipLaunchKernelGGL(k_sampler_cols<8>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h, H, NC,
+                       key0, key1, fb, nf, pl->N);
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+// pass 2 (and the subharmonic waves) of nf frames with scales scale[0..nf)
+// into zern frames f0 .. f0 + nf - 1 of the call
+int launch_pass2(const tsim_plan *pl, int nf, int f0, const float *scale, uint32_t fb, uint32_t key0,
+                 uint32_t key1, const float2 *V, float *zern, hipStream_t s) {
+  const int Gh = pl->Gh, Gw = pl->Gw;
+  FrameScales sc;
+  for (int i = 0; i < kMaxFramesPerLaunch; ++i) sc.s[i] = 0.f;
+  for (int i = 0; i < nf; ++i) sc.s[i] = scale[i];
+  SubhArgs sub{};
+  sub.levels = pl->p.subharmonic_levels;
+  for (int p = 0; p < kSubhMaxLevels; ++p) {
+    const double r = std::pow(3.0, p + 1);
+    sub.fx[p] = float(2.0 / (Gw * r));
+    sub.fy[p] = float(2.0 / (Gh * r));
+    for (int c = 0; c < 4; ++c)
+      for (int t = 0; t < 2; ++t) sub.amp[t][p][c] = float(pl->subh[(t * 4 + p) * 4 + c]);
+  }
+  sub.key0 = key0;
+  sub.key1 = key1;
+  sub.frame_base = fb;
+  const int st = launch_rows_n(pl, nf, f0, V, zern, sc, sub, s);
+  if (st != TSIM_OK) return st;
+  return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
+}
+
+}  // namespace
+
+int launch_sampler(const tsim_plan *pl, int frames, const float *scale_host, uint64_t seed,
+                   uint64_t frame0, float *zern, void *ws, hipStream_t s) {
+  const uint32_t key0 = uint32_t(seed & 0xffffffffu), key1 = uint32_t(seed >> 32);
+  float2 *V = static_cast<float2 *>(ws);
+  const int chunk = frames_per_chunk(pl, frames);
   for (int f0 = 0; f0 < frames; f0 += chunk) {
     const int nf = std::min(chunk, frames - f0);
-    dim3 g1(Gw / NC, pl->NF);
-    {
-      TraceScope tr("k_sampler_cols", s);
-      const uint32_t fb = uint32_t(frame0 + uint64_t(f0));
-      if (ipt == 2)
-        hipLaunchKernelGGL(k_sampler_cols<2>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
-                           H, NC, key0, key1, fb, nf, pl->N);
-      else if (ipt == 4)
-        hipLaunchKernelGGL(k_sampler_cols<4>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
-                           H, NC, key0, key1, fb, nf, pl->N);
-      else
-        hipLaunchKernelGGL(k_sampler_cols<8>, g1, dim3(512), lds1, s, pl->d_sqrtS, pl->d_tw_h, V, Gh, Gw, log2h,
-                           H, NC, key0, key1, fb, nf, pl->N);
-    }
-    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
-    FrameScales sc;
-    for (int i = 0; i < kMaxFramesPerLaunch; ++i) sc.s[i] = 0.f;
-    for (int i = 0; i < nf; ++i) sc.s[i] = scale_host[f0 + i];
-    SubhArgs sub{};
-    sub.levels = pl->p.subharmonic_levels;
-    for (int p = 0; p < kSubhMaxLevels; ++p) {
-      const double r = std::pow(3.0, p + 1);
-      sub.fx[p] = float(2.0 / (Gw * r));
-      sub.fy[p] = float(2.0 / (Gh * r));
-      for (int c = 0; c < 4; ++c)
-        for (int t = 0; t < 2; ++t) sub.amp[t][p][c] = float(pl->subh[(t * 4 + p) * 4 + c]);
-    }
-    sub.key0 = key0;
-    sub.key1 = key1;
-    sub.frame_base = uint32_t(frame0 + uint64_t(f0));
-    const int st = launch_rows_n(pl, nf, f0, V, zern, sc, sub, s);
+    const uint32_t fb = uint32_t(frame0 + uint64_t(f0));
+    int st = launch_pass1(pl, nf, fb, key0, key1, V, s);
     if (st != TSIM_OK) return st;
-    if (hipGetLastError() != hipSuccess) return TSIM_EDEVICE;
+    st = launch_pass2(pl, nf, f0, scale_host + f0, fb, key0, key1, V, zern, s);
+    if (st != TSIM_OK) return st;
   }
   return TSIM_OK;
+}
+
+int sampler_chunk_frames(const tsim_plan *pl, int frames) { return frames_per_chunk(pl, frames); }
+
+int sampler_pass1_forms(const tsim_plan *pl, int *nc) {
+  const int d = pass1_default(pl);
+  int n = 0;
+  for (int c : {d, d / 2, d * 2})
+    if (pass1_valid(pl, c)) nc[n++] = c;
+  return n;
+}
+
+int sampler_pass2_forms(const tsim_plan *pl, int *form) {
+  const int d = pass2_default(pl);
+  int n = 0;
+  form[n++] = d;
+  for (int f = 1; f <= 3; ++f)
+    if (f != d && pass2_valid(pl, f)) form[n++] = f;
+  return n;
+}
+
+bool sampler_form_valid(const tsim_plan *pl, int nc, int rows) {
+  return (nc == 0 || pass1_valid(pl, nc)) && (rows == 0 || pass2_valid(pl, rows));
+}
+
+int launch_sampler_pass(const tsim_plan *pl, int pass, int frames, float *zern, void *ws, hipStream_t s) {
+  if (frames < 1 || frames > frames_per_chunk(pl, frames)) return TSIM_EINVAL;
+  float scale[kMaxFramesPerLaunch];
+  for (int i = 0; i < frames; ++i) scale[i] = 1.f;
+  float2 *V = static_cast<float2 *>(ws);
+  return pass == 1 ? launch_pass1(pl, frames, 0, 0, 0, V, s)
+                   : launch_pass2(pl, frames, 0, scale, 0, 0, 0, V, zern, s);
 }
 
 int launch_sampler_ar(const tsim_plan *pl, int frames, const float *scale_host, float alpha,
