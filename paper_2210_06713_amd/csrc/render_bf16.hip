@@ -28,6 +28,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 // Fragments are kept as four 32-bit words and reinterpreted only at the
 // matrix-core call: copies of 8 x bf16 vectors between pipeline stages
@@ -359,17 +360,17 @@ __device__ __forceinline__ f32x16 mfma_f16(const uint4 &a, const uint4 &b, const
                                                 0, 0);
 }
 
-template <int KS, int T>
+template <int KS, int T, int C>
 __global__ void __launch_bounds__(256)
 k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
             const uint16_t *__restrict__ psi /*[NT][KS][2][64][8] f16*/, float *__restrict__ out, int H, int W,
-            int C, int K) {
+            int K) {
   using G = H3Geom<KS, T>;
   constexpr int TH = G::TH, TW = G::TW, R = G::R, SW = G::SW, PLANE = G::PLANE, NT = G::NT;
   constexpr int GB = G::GB, NCH = G::NCH, CPW = (NCH + 3) / 4, NS = G::NS;
   static_assert(CPW <= 15, "copies per wave fit the counted wait");
   extern __shared__ __attribute__((aligned(16))) float tile[];  // [C][PLANE] image samples, then the psi ring
-  __shared__ short offtab[NT * 32];
+  __shared__ __attribute__((aligned(16))) short offtab[NT * 32];
   const int f = blockIdx.z;
   const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
   const float *imf = img + size_t(f) * C * H * W;
@@ -443,7 +444,9 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
   }
   const int pbase = (py + R) * SW + px + R;
   const int mrow = 4 * g;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  float sc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) sc[c] = 0.f;
   const char *frag = ring + lane * 16;
   // products of tap block tb: x1 = psi_hi beta_hi, x2 = psi_hi beta_lo +
   // psi_lo beta_hi.  This wave's copies complete in order, so block tb has
@@ -474,17 +477,23 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
       x2 = mfma_f16(alo[q], bhi[q], x2);
     }
   };
-  // the taps of block tb applied to the image tile
+  // the taps of block tb applied to the image tile: the lane's 16 tap
+  // offsets in four 8-byte reads, then every sample read before its FMA
+  // (no branch in between, so the reads go out together)
   auto apply = [&](int tb, const f32x16 &x1, const f32x16 &x2) {
     const short *ot = offtab + 32 * tb + mrow;
+    int idx[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const s16x4 o = *reinterpret_cast<const s16x4 *>(ot + 8 * i);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) idx[4 * i + j] = pbase - o[j];
+    }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int idx = pbase - ot[8 * (r >> 2) + (r & 3)];
       const float v = x1[r] + x2[r];
-      s0 = fmaf(v, tile[idx], s0);
-      if (C > 1) s1 = fmaf(v, tile[PLANE + idx], s1);
-      if (C > 2) s2 = fmaf(v, tile[2 * PLANE + idx], s2);
-      if (C > 3) s3 = fmaf(v, tile[3 * PLANE + idx], s3);
+#pragma unroll
+      for (int c = 0; c < C; ++c) sc[c] = fmaf(v, tile[c * PLANE + idx[r]], sc[c]);
     }
   };
   // each matrix-core instruction of block tb is followed in the schedule by
@@ -516,17 +525,13 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
   } else {
     apply(tb - 1, p1, p2);
   }
-  s0 += __shfl_xor(s0, 32);
-  s1 += __shfl_xor(s1, 32);
-  s2 += __shfl_xor(s2, 32);
-  s3 += __shfl_xor(s3, 32);
+#pragma unroll
+  for (int c = 0; c < C; ++c) sc[c] += __shfl_xor(sc[c], 32);
   if (lane < 32 && ok) {
     float *of = out + size_t(f) * C * H * W + size_t(y) * W + x;
     const size_t pl = size_t(H) * W;
-    of[0] = s0 * kROutScale;
-    if (C > 1) of[pl] = s1 * kROutScale;
-    if (C > 2) of[2 * pl] = s2 * kROutScale;
-    if (C > 3) of[3 * pl] = s3 * kROutScale;
+#pragma unroll
+    for (int c = 0; c < C; ++c) of[c * pl] = sc[c] * kROutScale;
   }
 }
 
@@ -641,11 +646,25 @@ int launch_h3(const tsim_plan *pl, int frames, const float *img, const float *be
   const int H = pl->H, W = pl->W, C = pl->C;
   dim3 grid((W + G::TW - 1) / G::TW, (H + G::TH - 1) / G::TH, frames);
   const size_t lds = G::lds(C);
-  const int st = prepare_lds(k_render_h3<KS, T>, lds, T);
+  int st = TSIM_OK;
+  switch (C) {
+    case 1: st = prepare_lds(k_render_h3<KS, T, 1>, lds, T); break;
+    case 2: st = prepare_lds(k_render_h3<KS, T, 2>, lds, T); break;
+    case 3: st = prepare_lds(k_render_h3<KS, T, 3>, lds, T); break;
+    case 4: st = prepare_lds(k_render_h3<KS, T, 4>, lds, T); break;
+    default: return TSIM_EUNSUPPORTED;
+  }
   if (st != TSIM_OK) return st;
   TraceScope tr("k_render_fp32", s);
-  hipLaunchKernelGGL((k_render_h3<KS, T>), grid, dim3(256), lds, s, img, beta, pl->d_basis_h3r, out, H, W, C,
-                     pl->K);
+#define TSIM_H3(CC) \
+  hipLaunchKernelGGL((k_render_h3<KS, T, CC>), grid, dim3(256), lds, s, img, beta, pl->d_basis_h3r, out, H, W, pl->K)
+  switch (C) {
+    case 1: TSIM_H3(1); break;
+    case 2: TSIM_H3(2); break;
+    case 3: TSIM_H3(3); break;
+    default: TSIM_H3(4); break;
+  }
+#undef TSIM_H3
   return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
 }
 
