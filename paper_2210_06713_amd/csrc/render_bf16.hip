@@ -496,31 +496,22 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
       for (int c = 0; c < C; ++c) sc[c] = fmaf(v, tile[c * PLANE + idx[r]], sc[c]);
     }
   };
-  // each matrix-core instruction of block tb is followed in the schedule by
-  // LDS reads and FMAs of block tb - 1's application
-  auto interleave = [&]() {
-#pragma unroll
-    for (int i = 0; i < 3 * KS; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
-    }
-  };
+  // block tb's products are issued before block tb - 1's application, so
+  // the matrix cores work while the image samples are read and applied (the
+  // compiler's own schedule of the two measured faster than a forced
+  // one-by-one interleave)
   f32x16 p1, p2, q1, q2;
   products(0, p1, p2);
   int tb = 1;
   for (; tb + 1 < NT; tb += 2) {
     products(tb, q1, q2);
     apply(tb - 1, p1, p2);
-    interleave();
     products(tb + 1, p1, p2);
     apply(tb, q1, q2);
-    interleave();
   }
   if (tb < NT) {
     products(tb, q1, q2);
     apply(tb - 1, p1, p2);
-    interleave();
     apply(tb, q1, q2);
   } else {
     apply(tb - 1, p1, p2);
