@@ -428,6 +428,29 @@ class Workload:
         return ms, rep, self.out[:min(n, frames)].clone()
 
 
+def frame_call(tsim, torch, wl, pl, s, steps, frames):
+    """The same frames through the one-call path (tsim_frame) at the plan's
+    default group: the whole step is one call, and the fields, weights and
+    blurred frames of one group at a time live in its workspace."""
+    g = pl.frame_group()
+    ws = pl.frame_workspace(g)
+    drs = s["drs"]
+    img = wl.img[:1].expand(frames, -1, -1, -1).contiguous() if frames > wl.img.shape[0] else wl.img[:frames]
+    out = torch.empty_like(img)
+    d = [drs[f % len(drs)] for f in range(frames)]
+    pl.frame(d, 0, 0, img, out, ws, group=g)
+    ms, rep = time_then_trace(tsim, torch, lambda i: pl.frame(d, 0, (1 + i) * frames, img, out, ws, group=g),
+                              steps)
+    kern, _ = summarize(rep, steps, frames, s, traffic=False)
+    px = s["H"] * s["W"]
+    sep = frames * px * (35 * 4 + pl.KP * 2 + s["C"] * 4)
+    res = {"value": round(frames * px / (ms * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(ms, 3),
+           "frames_per_call": frames, "group": g, "workspace_mib": round(pl.frame_workspace_bytes(g) / 2**20, 1),
+           "fields_weights_blur_of_all_frames_mib": round(sep / 2**20, 1), "kernels": kern}
+    del ws, img, out
+    return res
+
+
 def train_network(tsim, torch, np, plan_l, train_steps):
     """The learned form's network: 2M exact (Zernike, weight) pairs from the
     plan's own PSF path, MSE training on the GPU, held-out PSF error."""
@@ -599,8 +622,10 @@ def large_frame(tsim, torch, np, synthetic, dev, args):
                    "image_psnr_db_vs_plain_fp32": psnr(out_l, out_p)}
         learned.update(info)
         learned.update(roofline=roof_l, kernels=kern_l)
+        del beta16
+        learned["frame_call"] = frame_call(tsim, torch, wl, plan_l, s, max(1, min(args.steps, 2)), s["frames"])
         out["learned_bf16"] = learned
-        del beta16, net
+        del net
         plan_l.close()
         out["ar_sequence"] = ar_sequence(tsim, torch, wl, s, args.steps)
     return out
@@ -670,6 +695,7 @@ def main():
         learned.update(info)
         learned.update(roofline=roof_l, kernels=kern_l)
         del beta16
+        learned["frame_call"] = frame_call(tsim, torch, wl, plan_l, s, args.steps, FRAMES)
         if not args.no_batched:
             learned["batched_graph"] = batched_graph(tsim, basis, net, args.steps)
         del net

@@ -381,6 +381,37 @@ int tsim_batch_create(const tsim_batch_item *items, int n_items, uint64_t seed,
 int tsim_batch_launch(const tsim_batch *batch, tsim_stream stream);
 int tsim_batch_destroy(tsim_batch *batch);
 
+/* The whole per-frame path of Sec. III-C and Eq. (8) in one call: Zernike
+ * fields (as tsim_sample_zernike), basis weights (as tsim_p2s, in the plan's
+ * form), the blur of Eq. (8) (as tsim_render) and the tilt warp (as
+ * tsim_warp), so that out[f] = warp(blur(img[f])).  Frames go through the
+ * four steps in groups of `group` frames (the last group may be smaller);
+ * a group's fields, weights and blurred frames live in `ws`, so the
+ * workspace is set by the group, not by `frames`, and the weights of the
+ * whole call never exist at once.  The result equals the four individual
+ * calls on the same frames bit for bit, for any group size (frame f's
+ * fields depend only on seed, frame0 + f and d_over_r0[f]).
+ *   group     : frames per group, 1..65535; tsim_frame_group gives the
+ *               largest group whose fields, weights and blurred frames fit
+ *               about 1 GiB (e.g. 7 frames of 512 x 512 x 3 in a BF16
+ *               plan with K = 100, one 3840 x 2160 frame)
+ *   d_over_r0 : host [frames], each > 0 and finite
+ *   img, out  : device [frames][C][H][W] float32, distinct, 256-byte aligned
+ *   zern_out  : device [frames][N][H][W] float32 to keep the fields, or NULL
+ *               (then they live in ws only)
+ *   ws        : device workspace of tsim_frame_workspace_bytes(plan, group)
+ *               bytes, 256-byte aligned, owned by the caller (once a
+ *               network is set on the plan, the size leaves out the exact
+ *               form's PSF buffer; query it after tsim_plan_set_mlp)
+ * Asynchronous on `stream`.  TSIM_EINVAL on a bad argument, TSIM_EARTEFACT
+ * without a basis, TSIM_EUNSUPPORTED for a shape the blur does not build;
+ * all checked before the first launch. */
+int tsim_frame_group(const tsim_plan *plan, int *group);
+int tsim_frame_workspace_bytes(const tsim_plan *plan, int group, size_t *bytes);
+int tsim_frame(const tsim_plan *plan, int frames, int group, const float *d_over_r0,
+               uint64_t seed, uint64_t frame0, const float *img, float *zern_out,
+               float *out, void *ws, tsim_stream stream);
+
 /* Exact PSFs of Eq. (2) for n Zernike vectors:
  *   zvec : device [n][N] float32 (N the plan's n_modes; modes 4..N+1 enter
  *          the phase);  psf : device [n][T*T] float32, unit sum. */

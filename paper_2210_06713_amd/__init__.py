@@ -112,6 +112,10 @@ _lib_batch_launch = _sig("tsim_batch_launch", _i, [_vp, _vp])
 _lib_batch_destroy = _sig("tsim_batch_destroy", _i, [_vp])
 _lib_last_error = _sig("tsim_last_error", _i, [ctypes.c_char_p, ctypes.c_size_t])
 _lib_sync = _sig("tsim_sync", _i, [_vp])
+_lib_frame_group = _sig("tsim_frame_group", _i, [_vp, ctypes.POINTER(_i)])
+_lib_frame_ws = _sig("tsim_frame_workspace_bytes", _i, [_vp, _i, ctypes.POINTER(ctypes.c_size_t)])
+_lib_frame = _sig("tsim_frame", _i, [_vp, _i, _i, ctypes.POINTER(ctypes.c_float), _u64, _u64, _vp, _vp, _vp,
+                                     _vp, _vp])
 
 EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "tsim_plan_table",
             "tsim_plan_autotune", "tsim_plan_set_tuning", "tsim_plan_tuning",
@@ -123,7 +127,8 @@ EXPORTED = ["tsim_plan_create", "tsim_plan_destroy", "tsim_workspace_bytes", "ts
             "tsim_mlp_fit_output", "tsim_mlp_predict", "tsim_tilt_stats_ws_bytes", "tsim_tilt_stats",
             "tsim_structure_function_ws_bytes", "tsim_structure_function", "tsim_p2s_form",
             "tsim_last_error", "tsim_sync", "tsim_sample_zernike_noalloc", "tsim_batch_create",
-            "tsim_batch_launch", "tsim_batch_destroy", "tsim_otf_ws_bytes", "tsim_otf"]
+            "tsim_batch_launch", "tsim_batch_destroy", "tsim_otf_ws_bytes", "tsim_otf", "tsim_frame_group",
+            "tsim_frame_workspace_bytes", "tsim_frame"]
 
 
 def last_error():
@@ -482,6 +487,39 @@ class Plan:
         self._frames_img(out, "out", frames, dev)
         _check(_lib_warp(self._h, frames, _ptr(img), _ptr(zern), _ptr(out), _stream(stream)),
                "tsim_warp")
+
+    # ---- the whole path in one call ----------------------------------
+    def frame_group(self):
+        g = _i()
+        _check(_lib_frame_group(self._h, ctypes.byref(g)), "tsim_frame_group")
+        return g.value
+
+    def frame_workspace_bytes(self, group):
+        n = ctypes.c_size_t()
+        _check(_lib_frame_ws(self._h, group, ctypes.byref(n)), "tsim_frame_workspace_bytes")
+        return n.value
+
+    def frame_workspace(self, group, device="cuda"):
+        """Allocate a device workspace (plumbing only) for tsim_frame."""
+        return torch.empty(self.frame_workspace_bytes(group), dtype=torch.uint8, device=device)
+
+    def frame(self, d_over_r0, seed, frame0, img, out, ws, group=None, zern_out=None, stream=None):
+        if img is None or img.dim() != 4:
+            raise ValueError("img: [frames, C, H, W] tensor expected")
+        frames, dev = img.shape[0], img.device
+        if group is None:
+            group = self.frame_group()
+        self._frames_img(img, "img", frames, dev)
+        self._frames_img(out, "out", frames, dev)
+        if zern_out is not None:
+            _expect(zern_out, "zern_out", (frames, self.N, self.H, self.W), torch.float32, dev)
+        _expect_bytes(ws, "ws", self.frame_workspace_bytes(group), dev)
+        if len(d_over_r0) != frames:
+            raise ValueError("d_over_r0: one value per frame expected")
+        d = (ctypes.c_float * frames)(*[float(v) for v in d_over_r0])
+        _check(_lib_frame(self._h, frames, group, d, int(seed), int(frame0), _ptr(img),
+                          _ptr(zern_out) if zern_out is not None else None, _ptr(out), _ptr(ws),
+                          _stream(stream)), "tsim_frame")
 
     def basis_build(self, n_psf=20000, seed=0, dr_lo=0.5, dr_hi=5.0):
         """PCA PSF basis (K x T*T float64) and its eigenvalues, computed by

@@ -1,5 +1,6 @@
 // Per-frame entry points of the C ABI: argument validation, then launches.
 // Every entry point records a failing status for tsim_last_error.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <new>
@@ -149,7 +150,7 @@ int otf_impl(const tsim_plan *pl, int frames, const float *zern, int short_expos
 // The form tsim_p2s runs: the network once one is set on a learned plan,
 // else the exact pupil-FFT path (also the learned form's fallback).
 int p2s_form(const tsim_plan *pl) {
-  return (pl->p.p2s_mode == TSIM_P2S_LEARNED && pl->d_mlp_w) ? TSIM_P2S_LEARNED : TSIM_P2S_EXACT;
+  return (pl->p.p2s_mode == TSIM_P2S_LEARNED && pl->d_mlp_w && pl->d_mlp_f) ? TSIM_P2S_LEARNED : TSIM_P2S_EXACT;
 }
 
 int p2s_impl(const tsim_plan *pl, int frames, const float *zern, void *beta, void *ws, hipStream_t s) {
@@ -193,6 +194,77 @@ int batch_item_calls(const tsim_batch_item &it, uint64_t seed, hipStream_t s) {
   if (st == TSIM_OK) st = render_impl(it.plan, it.frames, it.img, it.beta, it.blur, s);
   if (st == TSIM_OK) st = warp_impl(it.plan, it.frames, it.blur, it.zern, it.out, s);
   return st;
+}
+
+// ---- the whole path in one call, group by group of frames ----
+// A group's fields, weights and blurred frames live in the workspace, so its
+// size is set by the group, not by the number of frames of the call.
+constexpr size_t kFrameGroupBudget = size_t(1) << 30;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t beta_px_bytes(const tsim_plan *pl) {
+  return pl->p.precision == TSIM_BF16 ? size_t(pl->KP) * 2 : size_t(pl->K) * 4;
+}
+
+int frame_group_default(const tsim_plan *pl) {
+  const size_t per = size_t(pl->H) * pl->W * (size_t(pl->N) * 4 + beta_px_bytes(pl) + size_t(pl->C) * 4);
+  const size_t g = kFrameGroupBudget / per;
+  return int(std::max<size_t>(1, std::min<size_t>(g, 65535)));
+}
+
+// workspace layout of one group: fields | weights | blurred frames | step workspace
+struct FrameWs {
+  float *zern;
+  void *beta;
+  float *blur;
+  void *step;
+};
+
+size_t frame_ws_bytes(const tsim_plan *pl, int group, FrameWs *lay, void *base) {
+  const size_t hw = size_t(pl->H) * pl->W;
+  const size_t zb = align256(size_t(group) * pl->N * hw * 4);
+  const size_t bb = align256(size_t(group) * hw * beta_px_bytes(pl));
+  const size_t ib = align256(size_t(group) * pl->C * hw * 4);
+  // the exact form's PSF buffer only where P2S may take the exact form (a
+  // plan's network, once set, stays set)
+  const size_t pb = p2s_form(pl) == TSIM_P2S_LEARNED ? 0 : p2s_ws_bytes(pl, group);
+  const size_t sb = std::max(sampler_ws_bytes(pl, group), pb);
+  if (lay) {
+    char *c = static_cast<char *>(base);
+    lay->zern = reinterpret_cast<float *>(c);
+    lay->beta = c + zb;
+    lay->blur = reinterpret_cast<float *>(c + zb + bb);
+    lay->step = c + zb + bb + ib;
+  }
+  return zb + bb + ib + std::max<size_t>(sb, 256);
+}
+
+int frame_impl(const tsim_plan *pl, int frames, int group, const float *d_over_r0, uint64_t seed,
+               uint64_t frame0, const float *img, float *zern_out, float *out, void *ws, hipStream_t s) {
+  if (!frames_ok(pl, frames) || !frames_ok(pl, group) || !d_over_r0 || !img || !out || !ws)
+    return TSIM_EINVAL;
+  if (!aligned(img) || !aligned(out) || !aligned(ws) || (zern_out && !aligned(zern_out))) return TSIM_EINVAL;
+  if (img == out) return TSIM_EINVAL;
+  if (frame0 + uint64_t(frames) > (uint64_t(1) << 32)) return TSIM_EINVAL;
+  std::vector<float> scale;
+  if (!frame_scales(d_over_r0, frames, scale)) return TSIM_EINVAL;
+  if (!pl->d_basis) return TSIM_EARTEFACT;
+  if (pl->p.precision == TSIM_BF16 && !render_bf16_supported(pl->KP, pl->T, pl->C)) return TSIM_EUNSUPPORTED;
+  FrameWs w{};
+  frame_ws_bytes(pl, group, &w, ws);
+  const size_t hw = size_t(pl->H) * pl->W;
+  const size_t img_frame = size_t(pl->C) * hw, zern_frame = size_t(pl->N) * hw;
+  for (int g0 = 0; g0 < frames; g0 += group) {
+    const int n = std::min(group, frames - g0);
+    float *zern = zern_out ? zern_out + size_t(g0) * zern_frame : w.zern;
+    int st = sample_impl(pl, n, d_over_r0 + g0, seed, frame0 + uint64_t(g0), zern, w.step, s);
+    if (st == TSIM_OK) st = p2s_impl(pl, n, zern, w.beta, w.step, s);
+    if (st == TSIM_OK) st = render_impl(pl, n, img + size_t(g0) * img_frame, w.beta, w.blur, s);
+    if (st == TSIM_OK) st = warp_impl(pl, n, w.blur, zern, out + size_t(g0) * img_frame, s);
+    if (st != TSIM_OK) return st;
+  }
+  return TSIM_OK;
 }
 
 int batch_check(const tsim_batch_item &it) {
@@ -450,6 +522,24 @@ int tsim_warp(const tsim_plan *pl, int frames, const float *img, const float *ze
 int tsim_plan_set_mlp(tsim_plan *pl, const tsim_mlp *net) {
   if (!pl || !net) return note_status("tsim_plan_set_mlp", TSIM_EINVAL);
   return note_status("tsim_plan_set_mlp", plan_set_mlp_impl(pl, net));
+}
+
+int tsim_frame_group(const tsim_plan *pl, int *group) {
+  if (!pl || !group) return note_status("tsim_frame_group", TSIM_EINVAL);
+  *group = frame_group_default(pl);
+  return TSIM_OK;
+}
+
+int tsim_frame_workspace_bytes(const tsim_plan *pl, int group, size_t *bytes) {
+  if (!bytes || !frames_ok(pl, group)) return note_status("tsim_frame_workspace_bytes", TSIM_EINVAL);
+  *bytes = frame_ws_bytes(pl, group, nullptr, nullptr);
+  return TSIM_OK;
+}
+
+int tsim_frame(const tsim_plan *pl, int frames, int group, const float *d_over_r0, uint64_t seed,
+               uint64_t frame0, const float *img, float *zern_out, float *out, void *ws, tsim_stream stream) {
+  return note_status("tsim_frame", frame_impl(pl, frames, group, d_over_r0, seed, frame0, img, zern_out, out, ws,
+                                              hs(stream)));
 }
 
 int tsim_psf_exact(const tsim_plan *pl, int n, const float *zvec, float *psf, tsim_stream stream) {
