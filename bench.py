@@ -623,7 +623,9 @@ def large_frame(tsim, torch, np, synthetic, dev, args):
         learned.update(info)
         learned.update(roofline=roof_l, kernels=kern_l)
         del beta16
-        learned["frame_call"] = frame_call(tsim, torch, wl, plan_l, s, max(1, min(args.steps, 2)), s["frames"])
+        if not args.no_frame_call:
+            learned["frame_call"] = frame_call(tsim, torch, wl, plan_l, s, max(1, min(args.steps, 2)),
+                                               s["frames"])
         out["learned_bf16"] = learned
         del net
         plan_l.close()
@@ -641,6 +643,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=24000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-4k", action="store_true")
+    ap.add_argument("--no-frame-call", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); frames shard "
@@ -695,7 +698,8 @@ def main():
         learned.update(info)
         learned.update(roofline=roof_l, kernels=kern_l)
         del beta16
-        learned["frame_call"] = frame_call(tsim, torch, wl, plan_l, s, args.steps, FRAMES)
+        if not args.no_frame_call:
+            learned["frame_call"] = frame_call(tsim, torch, wl, plan_l, s, args.steps, FRAMES)
         if not args.no_batched:
             learned["batched_graph"] = batched_graph(tsim, basis, net, args.steps)
         del net
