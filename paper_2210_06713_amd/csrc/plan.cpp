@@ -585,9 +585,10 @@ int plan_create_impl(const tsim_params *p, tsim_plan **out) {
     // the projection's operand: psi x 2^10 split into FP16 (hi, lo), in
     // fragment order [chunk of 32 taps][step][output tile][lane][hi, lo][8]:
     // lane l holds output 32 tile + l % 32, taps 32 chunk + 16 step +
-    // 8 (l / 32) + 0..7; zero past K and T*T
+    // 8 (l / 32) + 0..7; zero past K and T*T, and to a whole number of
+    // 64-tap chunks (the kernel takes two of these chunks at a time)
     {
-      const int NCHK = (T2 + 31) / 32, NTL = (KP + 31) / 32;
+      const int NCHK = (T2 + 63) / 64 * 2, NTL = (KP + 31) / 32;
       std::vector<uint16_t> h3(size_t(NCHK) * 2 * NTL * 64 * 2 * 8, 0);
       for (int c = 0; c < NCHK; ++c)
         for (int st2 = 0; st2 < 2; ++st2)

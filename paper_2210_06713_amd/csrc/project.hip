@@ -34,47 +34,70 @@ __device__ __forceinline__ f32x16 mfma_f16(const uint4 &a, const uint4 &b, const
 // beta[p][k] = sum_t psi[k][t] h[p][t] on v_mfma_f32_32x32x16_f16, A = the
 // basis (rows = outputs), B = the PSFs (columns = pixels).  Block: 128 pixels,
 // 4 waves; wave w owns pixels [32 w, 32 w + 32) and NT 32-row output tiles.
-// Taps go in chunks of 32 (two 16-tap matrix-core steps).  Per chunk the
-// block stages its 128 pixels' 32 taps in LDS by coalesced row loads
-// (thread: 16 taps of pixel rows, consecutive threads consecutive taps) and
+// Taps go in chunks of 64 (four 16-tap matrix-core steps).  Per chunk the
+// block stages its 128 pixels' 64 taps in LDS by coalesced row loads
+// (thread: 32 taps of pixel rows, consecutive threads consecutive taps) and
 // the chunk's basis fragments (hi and lo, in fragment order in the plan
 // table); the global loads of chunk c + 1 are in flight in registers while
 // the matrix cores work on chunk c.  A lane's B fragment is its pixel's taps
 // 8 (l / 32) + 0..7 of the step, split into FP16 hi and lo on the fly.
-constexpr int HS = 36;  // LDS row stride of the staged PSF taps (floats; 16-byte aligned groups of 8)
+constexpr int CT = 64;       // taps per chunk
+constexpr int HS = CT + 4;   // LDS row stride of the staged PSF taps (floats; 16-byte aligned groups of 8)
 
 template <int NT, bool OUT_BF16>
 __global__ void __launch_bounds__(256)
-k_project_h3(const float *__restrict__ h, const uint4 *__restrict__ psi /*[chunks][2][NT][64][2] x 8 f16*/,
+k_project_h3(const float *__restrict__ h, const uint4 *__restrict__ psi /*[chunks][4][NT][64][2] x 8 f16*/,
              void *__restrict__ beta, int n, int T2, int K, int KB) {
-  constexpr int CH = 2 * NT * 64 * 2;  // uint4 per chunk
+  constexpr int SPC = CT / 16;          // matrix-core steps per chunk
+  constexpr int CH = SPC * NT * 64 * 2;  // uint4 per chunk
+  constexpr int PER = CH / 256;          // of them per thread
+  constexpr int HPT = kProjectTile * CT / 256;  // staged PSF values per thread
   __shared__ uint4 ps[CH];
   __shared__ __attribute__((aligned(16))) float hs[kProjectTile * HS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int p0 = blockIdx.x * kProjectTile;
-  const int nchunk = (T2 + 31) / 32;
+  const int nchunk = (T2 + CT - 1) / CT;
 
-  // staging loads: element e = threadIdx.x + 256 i is pixel e / 32, tap e % 32
-  // of the chunk; pixels past n read pixel n - 1 and taps past T^2 the row's
-  // last tap, so every load is unconditional (the basis table is zero past
-  // T^2, and such pixels are not stored)
+  // staging loads: element e = threadIdx.x + 256 i is pixel e / 64, tap
+  // e % 64 of the chunk; pixels past n read pixel n - 1 and taps past T^2
+  // the row's last tap, so every load is unconditional (the basis table is
+  // zero past T^2, and such pixels are not stored).  Rows of a full block
+  // are 4 pixels apart; only the last block clamps.
   // (element offsets fit 32 bits: a P2S chunk holds at most about 5 GB of PSFs)
-  const int tt = threadIdx.x & 31;
-  uint32_t hrow[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) hrow[i] = uint32_t(min(p0 + (threadIdx.x >> 5) + 8 * i, n - 1)) * uint32_t(T2);
-  float hv[16];
+  const int tt = threadIdx.x & (CT - 1), prow = threadIdx.x / CT;
+  const bool full = p0 + kProjectTile <= n;
+  const uint32_t rbase = uint32_t(p0 + prow) * uint32_t(T2), rstep = 4u * uint32_t(T2);
+  float hv[HPT];
   auto hload = [&](int t0) {
     const uint32_t t = uint32_t(min(t0 + tt, T2 - 1));
+    if (full) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) hv[i] = h[hrow[i] + t];
+      for (int i = 0; i < HPT; ++i) hv[i] = h[rbase + rstep * uint32_t(i) + t];
+    } else {
+#pragma unroll
+      for (int i = 0; i < HPT; ++i) hv[i] = h[uint32_t(min(p0 + prow + 4 * i, n - 1)) * uint32_t(T2) + t];
+    }
   };
-  constexpr int PER = CH / 256;  // uint4 of a chunk's basis fragments per thread (= NT)
+  // the chunk's basis fragments, PER (= 2 NT) per thread, as named values
+  // (an array of them ends up in scratch memory)
   const uint4 *pp = psi + threadIdx.x;
-  uint4 pv0 = pp[0], pv1, pv2, pv3;
-  if constexpr (PER > 1) pv1 = pp[256];
-  if constexpr (PER > 2) pv2 = pp[512];
-  if constexpr (PER > 3) pv3 = pp[768];
+  uint4 pv0, pv1, pv2, pv3, pv4, pv5, pv6, pv7;
+  auto pload = [&]() {
+    pv0 = pp[0];
+    pv1 = pp[256];
+    if constexpr (PER > 2) { pv2 = pp[512]; pv3 = pp[768]; }
+    if constexpr (PER > 4) { pv4 = pp[1024]; pv5 = pp[1280]; }
+    if constexpr (PER > 6) { pv6 = pp[1536]; pv7 = pp[1792]; }
+  };
+  auto pstore = [&]() {
+    ps[threadIdx.x] = pv0;
+    ps[threadIdx.x + 256] = pv1;
+    if constexpr (PER > 2) { ps[threadIdx.x + 512] = pv2; ps[threadIdx.x + 768] = pv3; }
+    if constexpr (PER > 4) { ps[threadIdx.x + 1024] = pv4; ps[threadIdx.x + 1280] = pv5; }
+    if constexpr (PER > 6) { ps[threadIdx.x + 1536] = pv6; ps[threadIdx.x + 1792] = pv7; }
+  };
+  static_assert(PER == 2 * NT && PER <= 8, "two basis fragments per thread and output tile");
+  pload();
 
   f32x16 acc[NT];
 #pragma unroll
@@ -82,23 +105,17 @@ k_project_h3(const float *__restrict__ h, const uint4 *__restrict__ psi /*[chunk
   hload(0);
   const float *hb = hs + (32 * w + (lane & 31)) * HS + 8 * (lane >> 5);
   for (int c = 0; c < nchunk; ++c) {
-    ps[threadIdx.x] = pv0;
-    if constexpr (PER > 1) ps[threadIdx.x + 256] = pv1;
-    if constexpr (PER > 2) ps[threadIdx.x + 512] = pv2;
-    if constexpr (PER > 3) ps[threadIdx.x + 768] = pv3;
+    pstore();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) hs[((threadIdx.x >> 5) + 8 * i) * HS + tt] = hv[i];
+    for (int i = 0; i < HPT; ++i) hs[(prow + 4 * i) * HS + tt] = hv[i];
     __syncthreads();
     if (c + 1 < nchunk) {
-      hload(32 * (c + 1));
+      hload(CT * (c + 1));
       pp += CH;
-      pv0 = pp[0];
-      if constexpr (PER > 1) pv1 = pp[256];
-      if constexpr (PER > 2) pv2 = pp[512];
-      if constexpr (PER > 3) pv3 = pp[768];
+      pload();
     }
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < SPC; ++s) {
       // this step's PSF values as FP16 pairs
       const float4 u0 = *reinterpret_cast<const float4 *>(hb + 16 * s);
       const float4 u1 = *reinterpret_cast<const float4 *>(hb + 16 * s + 4);
