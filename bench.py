@@ -428,11 +428,12 @@ class Workload:
         return ms, rep, self.out[:min(n, frames)].clone()
 
 
-def frame_call(tsim, torch, wl, pl, s, steps, frames):
-    """The same frames through the one-call path (tsim_frame) at the plan's
-    default group: the whole step is one call, and the fields, weights and
-    blurred frames of one group at a time live in its workspace."""
-    g = pl.frame_group()
+def frame_call(tsim, torch, wl, pl, s, steps, frames, group=None):
+    """The same frames through the one-call path (tsim_frame), at the plan's
+    default group unless one is given: the whole step is one call, and the
+    fields, weights and blurred frames of one group at a time live in its
+    workspace."""
+    g = pl.frame_group() if group is None else group
     ws = pl.frame_workspace(g)
     drs = s["drs"]
     img = wl.img[:1].expand(frames, -1, -1, -1).contiguous() if frames > wl.img.shape[0] else wl.img[:frames]
@@ -680,6 +681,9 @@ def main():
     kernels, roofline = summarize(rep, args.steps, FRAMES, s, traffic=True)
     value = FRAMES * H * W / (ms * 1e-3) / 1e6
     del beta32
+    # the same step as one tsim_frame call, in groups of one P2S chunk
+    frame_plain = None if args.no_frame_call else frame_call(tsim, torch, wl, plan, s, args.steps, FRAMES,
+                                                              group=(1 << 20) // (H * W))
 
     # ---- BF16 + learned form ----
     learned = None
@@ -723,7 +727,8 @@ def main():
                        "frames_per_step": FRAMES, "H": H, "W": W, "C": C, "grid": G, "K": K,
                        "T": T, "pupil": P},
             "sampler_forms": {"pass1_columns_per_block": wl_tuning[0], "pass2_form": wl_tuning[1]},
-            "roofline": roofline, "kernels": kernels, "learned_bf16": learned,
+            "roofline": roofline, "kernels": kernels, "frame_call_plain_fp32": frame_plain,
+            "learned_bf16": learned,
             "subharmonic_sampler": subh, "large_4k": large, "setup_s": round(setup_s, 2)}
     if cpu is not None:
         line["cpu_baseline"] = cpu

@@ -393,8 +393,9 @@ int tsim_batch_destroy(tsim_batch *batch);
  * fields depend only on seed, frame0 + f and d_over_r0[f]).
  *   group     : frames per group, 1..65535; tsim_frame_group gives the
  *               largest group whose fields, weights and blurred frames fit
- *               about 1 GiB (e.g. 7 frames of 512 x 512 x 3 in a BF16
- *               plan with K = 100, one 3840 x 2160 frame)
+ *               about 1 GiB (e.g. 10 frames of 512 x 512 x 3 in a BF16
+ *               plan with K = 100, 7 in an FP32 plan, one 3840 x 2160
+ *               frame)
  *   d_over_r0 : host [frames], each > 0 and finite
  *   img, out  : device [frames][C][H][W] float32, distinct, 256-byte aligned
  *   zern_out  : device [frames][N][H][W] float32 to keep the fields, or NULL
