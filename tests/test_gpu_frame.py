@@ -152,3 +152,33 @@ def test_frame_rejects_bad_arguments(t, basis):
     assert e.value.status == t.EARTEFACT
     nb.close()
     p.close()
+
+
+def test_frame_large_learned_frames_equal_calls(t, basis):
+    """Two 768 x 1024 x 3 frames on the 2048^2 grid (the batch workload's
+    largest size) in the learned form, one frame per group: equal to the
+    individual calls bit for bit."""
+    Hl, Wl, Fl = 768, 1024, 2
+    say(f"tsim_frame, learned BF16 form, {Fl} frames of {Hl}x{Wl}x3 on 2048^2, group 1")
+    p = t.Plan(Hl, Wl, 3, 2048, 2048, basis=basis, pixel_pitch_over_d=0.125, p2s_mode=t.P2S_LEARNED,
+               precision=t.BF16)
+    net = t.Mlp(p, batch=64, seed=8)
+    t.plan_set_mlp(p, net)
+    img = torch.tensor(np.repeat(synthetic.test_image(3, Hl, Wl, 16, 5)[None], Fl, 0), device="cuda")
+    dr = [1.5, 3.5]
+    zern = torch.empty((Fl, p.N, Hl, Wl), device="cuda")
+    beta = torch.empty((Fl, Hl, Wl, p.KP), dtype=torch.bfloat16, device="cuda")
+    blur = torch.empty_like(img)
+    ref = torch.empty_like(img)
+    ws = p.workspace(Fl)
+    p.sample_zernike(dr, SEED, 40, zern, ws)
+    p.p2s(zern, beta, ws)
+    p.render(img, beta, blur)
+    p.warp(blur, zern, ref)
+    del ws, beta, blur
+    out = torch.full_like(img, float("nan"))
+    p.frame(dr, SEED, 40, img, out, p.frame_workspace(1), group=1)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    net.close()
+    p.close()
