@@ -339,8 +339,8 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
 // scaled back by 2^-22 at the end.  A lane's beta (its pixel, constant over
 // the taps) is split once; psi_hi and psi_lo of each tap block come split
 // from the plan table in fragment order and are staged in LDS for the
-// block's four waves by asynchronous copies, two blocks ahead, in a ring of
-// three stages.
+// block's four waves by asynchronous copies, one block ahead, in a ring of
+// two stages.
 constexpr float kRBetaScale = 4096.f;                   // 2^12
 constexpr float kROutScale = 1.f / (4096.f * 1024.f);   // 2^-22
 
@@ -351,7 +351,7 @@ struct H3Geom {
   static constexpr int NT = (T * T + 31) / 32;   // tap blocks
   static constexpr int GB = KS * 2 * 1024;        // bytes of one block's fragments: [KS][hi, lo][64 lanes][16 B]
   static constexpr int NCH = GB / 1024;           // 1 KB wave copies per block
-  static constexpr int NS = 3;                    // ring stages: blocks tb + 1 and tb + 2 in flight
+  static constexpr int NS = 2;                    // ring stages: block tb + 1 in flight
   static size_t lds(int C) { return size_t(C) * PLANE * sizeof(float) + NS * size_t(GB); }
 };
 
@@ -389,7 +389,6 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
     }
   };
   stage_in(0);
-  if (NT > 1) stage_in(1);
   // tile loads in batches of eight per thread, all requested before any is
   // stored (a frame spans < 4 GiB)
   {
@@ -449,32 +448,26 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
   for (int c = 0; c < C; ++c) sc[c] = 0.f;
   const char *frag = ring + lane * 16;
   // products of tap block tb: x1 = psi_hi beta_hi, x2 = psi_hi beta_lo +
-  // psi_lo beta_hi.  This wave's copies complete in order, so block tb has
-  // landed once at most the CPW copies of block tb + 1 are in flight; past
-  // the barrier every wave's copies of it have, and every wave is done with
-  // stage (tb + 2) % 3 (read at step tb - 1).  Before the first block the
+  // psi_lo beta_hi.  This wave's only copies in flight are block tb's
+  // (issued at step tb - 1); past the barrier every wave's copies of it have
+  // landed, and every wave is done with stage (tb + 1) % 2 (read at step
+  // tb - 1), which the copies of block tb + 1 then fill.  The fragments are
+  // read from LDS next to their products.  Before the first block the
   // barrier also completes the tile and the offset table.
   auto products = [&](int tb, f32x16 &x1, f32x16 &x2) {
-    if (tb + 1 < NT)
-      __builtin_amdgcn_s_waitcnt((CPW & 15) | (7 << 4) | ((CPW >> 4) << 14));  // vmcnt(CPW) lgkmcnt(0)
-    else
-      __builtin_amdgcn_s_waitcnt(7 << 4);                                      // vmcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_waitcnt(7 << 4);  // vmcnt(0) lgkmcnt(0)
     __builtin_amdgcn_s_barrier();
-    if (tb + 2 < NT) stage_in(tb + 2);
+    if (tb + 1 < NT) stage_in(tb + 1);
     const char *st = frag + (tb % NS) * GB;
-    uint4 ahi[KS], alo[KS];
-#pragma unroll
-    for (int q = 0; q < KS; ++q) {
-      ahi[q] = *reinterpret_cast<const uint4 *>(st + (2 * q) * 1024);
-      alo[q] = *reinterpret_cast<const uint4 *>(st + (2 * q + 1) * 1024);
-    }
     x1 = f32x16{};
     x2 = f32x16{};
 #pragma unroll
     for (int q = 0; q < KS; ++q) {
-      x1 = mfma_f16(ahi[q], bhi[q], x1);
-      x2 = mfma_f16(ahi[q], blo[q], x2);
-      x2 = mfma_f16(alo[q], bhi[q], x2);
+      const uint4 ahi = *reinterpret_cast<const uint4 *>(st + (2 * q) * 1024);
+      const uint4 alo = *reinterpret_cast<const uint4 *>(st + (2 * q + 1) * 1024);
+      x1 = mfma_f16(ahi, bhi[q], x1);
+      x2 = mfma_f16(ahi, blo[q], x2);
+      x2 = mfma_f16(alo, bhi[q], x2);
     }
   };
   // the taps of block tb applied to the image tile: the lane's 16 tap
