@@ -273,44 +273,51 @@ k_psf64(const float *__restrict__ zern, int hw, int nmodes, size_t p_base, int n
 }
 
 // k_psf128 (pupil P = 128, aperture diameter 64 samples, crop T <= 65):
-// one wavefront owns one pixel.  The aperture fits the 64 x 64 window of
+// two wavefronts own one pixel.  The aperture fits the 64 x 64 window of
 // offsets [-32, 32) and the 65 x 65 lowest frequencies of the 128 x 128 DFT
 // are kept; a 128-point DFT of 64 samples at frequencies [-32, 32] splits
-// into the 64-point DFTs of x[c] (even) and x[c] exp(-2 pi i c/128) (odd).
-// Stage 1: lane = pupil row; the row is kept in LDS while its two register
-// FFT-64s run one after the other, then its 65 outputs overwrite it.
+// into the 64-point DFTs of x[c] (even frequencies) and
+// x[c] exp(-2 pi i c/128) (odd frequencies).  Wave 0 takes the even and
+// wave 1 the odd frequencies of both passes, so a lane holds one 64-point
+// transform at a time.
+// Stage 1: lane = pupil row; wave 1 forms its samples as
+// exp(-i (phi + 2 pi c/128)) from the phase directly.  The outputs go to an
+// LDS buffer of the 64 rows x 65 frequencies.
 // Stage 2: lane = frequency column kx in [-32, 32); the column kx = +32 is a
-// direct 64-term DFT (row ky = +32 of it: twiddles (-i)^r', a wave sum).
+// direct 64-term DFT (row ky = +32 of it: twiddles (-i)^r', a wave sum),
+// taken by wave 0.  The unit-sum normalisation adds the two waves' sums.
 template <int T, int NCH>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(128)
 k_psf128(const float *__restrict__ zern, int hw, int nmodes, size_t p_base, const float *__restrict__ zc,
          float *__restrict__ psf) {
   constexpr int NCC = NCH * NCH, NMAX = kMaxPhaseModes<NCH>;
   const int nm = nmodes - 2;
   constexpr int R = (T - 1) / 2;  // crop radius, <= 32
   constexpr int LS = 65;          // LDS row stride (complex)
+  constexpr int MR = R / 2;       // even ky = 2m, m in [-MR, MR]; odd ky = 2m + 1, m in [-MR, MR - 1]
+  static_assert(R % 2 == 0, "the crop radius splits into even and odd rows");
   __shared__ float2 buf[64 * LS];
   __shared__ float cbuf[NCC];     // 2D Chebyshev coefficients of the phase
-  const int lane = threadIdx.x;
+  __shared__ float part[2];       // the two waves' sums over the crop
+  const int lane = threadIdx.x & 63;
+  const int odd = threadIdx.x >> 6;  // 0: even frequencies, 1: odd
   const size_t p = blockIdx.x;
 
-  float a[NMAX];
   {
+    float a[NMAX];
     const size_t pg = p_base + p;
     const size_t fr = pg / size_t(hw), yx = pg - fr * size_t(hw);
     const float *zp = zern + fr * nmodes * size_t(hw) + yx;
     phase_coeffs<NCH>(zp, size_t(hw), nm, a);
-  }
-
 #pragma unroll
-  for (int e = lane; e < NCC; e += 64) cbuf[e] = cheb_entry<NCH>(a, zc, e);
+    for (int e = threadIdx.x; e < NCC; e += 128) cbuf[e] = cheb_entry<NCH>(a, zc, e);
+  }
   __syncthreads();
 
   float2 X[64];
   // ---- stage 1: lane = window row wr, pupil row offset r' = wr - 32 ----
   {
-    const int wr = lane, rp = wr - 32;
-    float2 *row = buf + wr * LS;
+    const int rp = lane - 32;
     float d[NCH];
     row_series<NCH>(cbuf, float(rp) * 0.03125f, d);
 #pragma unroll
@@ -321,35 +328,28 @@ k_psf128(const float *__restrict__ zern, int hw, int nmodes, size_t p_base, cons
         float phi = 0.f;
 #pragma unroll
         for (int q = 0; q < NCH; ++q) phi = fmaf(d[q], kChebCol64[n][q], phi);
-        const float rev = phi * 0.15915494309189535f;
+        const float rev = fmaf(phi, 0.15915494309189535f, odd ? float(cp) * 0.0078125f : 0.f);
         v = make_float2(__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev));
       }
       X[n] = v;
-      row[n] = v;
     }
     fft_fwd<64>(X);
-    float2 ev[33];  // even kx = 2m, m in [-16, 16]
+    // X1[r'][kx] for kx in [-32, 32] -> buf[wr][kx + 32]: kx = 2m + odd at X[m]
+    float2 *row = buf + lane * LS;
+    if (odd) {
 #pragma unroll
-    for (int m = -16; m <= 16; ++m) ev[m + 16] = X[m & 63];
+      for (int m = -16; m <= 15; ++m) row[2 * m + 1 + 32] = X[m & 63];
+    } else {
 #pragma unroll
-    for (int n = 0; n < 64; ++n) {
-      const int k = ((n < 32) ? n : n - 64) & 127;  // exp(-2 pi i c'/128)
-      X[n] = cmul(make_float2(kW128re[k], kW128im[k]), row[n]);
+      for (int m = -16; m <= 16; ++m) row[2 * m + 32] = X[m & 63];
     }
-    fft_fwd<64>(X);
-    // X1[r'][kx] for kx in [-32, 32] -> row[kx + 32]
-#pragma unroll
-    for (int kx = -32; kx <= 32; ++kx)
-      row[kx + 32] = (kx & 1) ? X[((kx - 1) >> 1) & 63] : ev[(kx >> 1) + 16];
   }
   __syncthreads();
 
   // ---- stage 2: lane = frequency column kx = lane - 32 ----
   const int kx = lane - 32;
-  float he[33], ho[32];  // |X|^2 at even ky = 2m (m in [-16, 16]) and odd ky = 2m + 1
   float hx = 0.f, hx32 = 0.f;  // column kx = +32: row ky = lane - 32, and row ky = +32
-  float total = 0.f;
-  if (R == 32) {
+  if (R == 32 && !odd) {
     float2 acc = make_float2(0.f, 0.f);
     const int ky = lane - 32;
     for (int wr = 0; wr < 64; ++wr) {
@@ -369,53 +369,43 @@ k_psf128(const float *__restrict__ zern, int hw, int nmodes, size_t p_base, cons
       t.y += __shfl_xor(t.y, off, 64);
     }
     hx32 = t.x * t.x + t.y * t.y;
-    total = hx + (lane == 0 ? hx32 : 0.f);
   }
-  {
-    const int col = lane;
 #pragma unroll
-    for (int n = 0; n < 64; ++n) {
-      const int rp = (n < 32) ? n : n - 64;
-      X[n] = buf[(rp + 32) * LS + col];
-    }
-    fft_fwd<64>(X);
-#pragma unroll
-    for (int m = -16; m <= 16; ++m) {
-      const float2 v = X[m & 63];
-      he[m + 16] = v.x * v.x + v.y * v.y;
-    }
-#pragma unroll
-    for (int n = 0; n < 64; ++n) {
-      const int rp = (n < 32) ? n : n - 64;
-      const int k = rp & 127;
-      X[n] = cmul(make_float2(kW128re[k], kW128im[k]), buf[(rp + 32) * LS + col]);
-    }
-    fft_fwd<64>(X);
-#pragma unroll
-    for (int m = -16; m <= 15; ++m) {
-      const float2 v = X[m & 63];
-      ho[m + 16] = v.x * v.x + v.y * v.y;
-    }
+  for (int n = 0; n < 64; ++n) {
+    const int r = (n < 32) ? n : n - 64;
+    const float2 v = buf[(r + 32) * LS + lane];
+    X[n] = odd ? cmul(make_float2(kW128re[r & 127], kW128im[r & 127]), v) : v;
   }
-  auto hval = [&](int ky) { return (ky & 1) ? ho[((ky - 1) >> 1) + 16] : he[(ky >> 1) + 16]; };
+  fft_fwd<64>(X);
+  // |X|^2 at ky = 2m + odd, m in [-MR, MR] (the last only for even ky)
+  float h[2 * MR + 1];
+#pragma unroll
+  for (int m = -MR; m <= MR; ++m) {
+    const float2 v = X[m & 63];
+    h[m + MR] = v.x * v.x + v.y * v.y;
+  }
+  float total = (R == 32 && !odd) ? hx + (lane == 0 ? hx32 : 0.f) : 0.f;
   if (kx >= -R && kx <= R) {
 #pragma unroll
-    for (int ky = -R; ky <= R; ++ky) total += hval(ky);
+    for (int m = -MR; m <= MR; ++m)
+      if (!odd || m < MR) total += h[m + MR];
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) total += __shfl_xor(total, off, 64);
-  const float inv = 1.0f / total;
+  if (lane == 0) part[odd] = total;
+  __syncthreads();
+  const float inv = 1.0f / (part[0] + part[1]);
   float *out = psf + p * T * T;
   if (kx >= -R && kx <= R) {
 #pragma unroll
-    for (int ky = -R; ky <= R; ++ky) out[(ky + R) * T + (kx + R)] = hval(ky) * inv;
+    for (int m = -MR; m <= MR; ++m)
+      if (!odd || m < MR) out[(2 * m + odd + R) * T + (kx + R)] = h[m + MR] * inv;
   }
-  if (R == 32) {
+  if (R == 32 && !odd) {
     out[(lane - 32 + R) * T + (32 + R)] = hx * inv;
     if (lane == 0) out[(32 + R) * T + (32 + R)] = hx32 * inv;
   }
 }
-
 
 int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_base, int n, float *psf,
                     hipStream_t s) {
@@ -425,13 +415,13 @@ int launch_psf_impl(const tsim_plan *pl, const float *zern, int hw, size_t p_bas
   if (pl->P == 128) {
     TraceScope tr("k_psf128", s);
     if (pl->T == 65 && !wide)
-      hipLaunchKernelGGL((k_psf128<65, 8>), dim3(n), dim3(64), 0, s, zern, hw, N, p_base, zt, psf);
+      hipLaunchKernelGGL((k_psf128<65, 8>), dim3(n), dim3(128), 0, s, zern, hw, N, p_base, zt, psf);
     else if (pl->T == 33 && !wide)
-      hipLaunchKernelGGL((k_psf128<33, 8>), dim3(n), dim3(64), 0, s, zern, hw, N, p_base, zt, psf);
+      hipLaunchKernelGGL((k_psf128<33, 8>), dim3(n), dim3(128), 0, s, zern, hw, N, p_base, zt, psf);
     else if (pl->T == 65)
-      hipLaunchKernelGGL((k_psf128<65, 11>), dim3(n), dim3(64), 0, s, zern, hw, N, p_base, zt, psf);
+      hipLaunchKernelGGL((k_psf128<65, 11>), dim3(n), dim3(128), 0, s, zern, hw, N, p_base, zt, psf);
     else if (pl->T == 33)
-      hipLaunchKernelGGL((k_psf128<33, 11>), dim3(n), dim3(64), 0, s, zern, hw, N, p_base, zt, psf);
+      hipLaunchKernelGGL((k_psf128<33, 11>), dim3(n), dim3(128), 0, s, zern, hw, N, p_base, zt, psf);
     else
       return TSIM_EUNSUPPORTED;
     return hipGetLastError() == hipSuccess ? TSIM_OK : TSIM_EDEVICE;
