@@ -344,9 +344,10 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
 constexpr float kRBetaScale = 4096.f;                   // 2^12
 constexpr float kROutScale = 1.f / (4096.f * 1024.f);   // 2^-22
 
-template <int KS, int T>
+template <int KS, int T, int TH_ = 8>
 struct H3Geom {
-  static constexpr int TH = 8, TW = 16, R = (T - 1) / 2;
+  static constexpr int TH = TH_, TW = 16, R = (T - 1) / 2;
+  static constexpr int NW = TH / 2, NTHR = 64 * NW;  // waves (two tile rows each), threads
   static constexpr int SH = TH + T - 1, SW = TW + T - 1, PLANE = SH * SW;
   static constexpr int NT = (T * T + 31) / 32;   // tap blocks
   static constexpr int GB = KS * 2 * 1024;        // bytes of one block's fragments: [KS][hi, lo][64 lanes][16 B]
@@ -360,14 +361,15 @@ __device__ __forceinline__ f32x16 mfma_f16(const uint4 &a, const uint4 &b, const
                                                 0, 0);
 }
 
-template <int KS, int T, int C>
-__global__ void __launch_bounds__(256)
+template <int KS, int T, int C, int TH_>
+__global__ void __launch_bounds__(32 * TH_)
 k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
             const uint16_t *__restrict__ psi /*[NT][KS][2][64][8] f16*/, float *__restrict__ out, int H, int W,
             int K) {
-  using G = H3Geom<KS, T>;
+  using G = H3Geom<KS, T, TH_>;
   constexpr int TH = G::TH, TW = G::TW, R = G::R, SW = G::SW, PLANE = G::PLANE, NT = G::NT;
-  constexpr int GB = G::GB, NCH = G::NCH, CPW = (NCH + 3) / 4, NS = G::NS;
+  constexpr int NW = G::NW, NTHR = G::NTHR;
+  constexpr int GB = G::GB, NCH = G::NCH, CPW = (NCH + NW - 1) / NW, NS = G::NS;
   static_assert(CPW <= 15, "copies per wave fit the counted wait");
   extern __shared__ __attribute__((aligned(16))) float tile[];  // [C][PLANE] image samples, then the psi ring
   __shared__ __attribute__((aligned(16))) short offtab[NT * 32];
@@ -376,7 +378,7 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
   const float *imf = img + size_t(f) * C * H * W;
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   char *ring = reinterpret_cast<char *>(tile + C * PLANE);
-  // tap block tb goes to ring stage tb % 3; wave w copies pieces w, w + 4,
+  // tap block tb goes to ring stage tb % 2; wave w copies pieces w, w + NW,
   // ... (a wave past the last piece repeats it: same bytes to the same place)
   const uint32_t ring_lds = uint32_t(reinterpret_cast<uintptr_t>(ring));
   auto stage_in = [&](int tb) {
@@ -384,7 +386,7 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
     const uint32_t dst = ring_lds + uint32_t((tb % NS) * GB);
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
-      const int piece = min(w + 4 * k, NCH - 1);
+      const int piece = min(w + NW * k, NCH - 1);
       copy_to_lds(src + piece * 1024, dst + uint32_t(piece * 1024), lane);
     }
   };
@@ -394,11 +396,11 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
   {
     const char *imb = reinterpret_cast<const char *>(imf);
     const int NE = C * PLANE;
-    for (int e0 = 0; e0 < NE; e0 += 8 * 256) {
+    for (int e0 = 0; e0 < NE; e0 += 8 * NTHR) {
       float v[8];
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
-        const int e = min(e0 + it * 256 + int(threadIdx.x), NE - 1);
+        const int e = min(e0 + it * NTHR + int(threadIdx.x), NE - 1);
         const int c = e / PLANE;
         const int rem = e - c * PLANE;
         const int sy = rem / SW, sx = rem - sy * SW;
@@ -408,12 +410,12 @@ k_render_h3(const float *__restrict__ img, const float *__restrict__ beta,
       }
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
-        const int e = e0 + it * 256 + int(threadIdx.x);
+        const int e = e0 + it * NTHR + int(threadIdx.x);
         if (e < NE) tile[e] = v[it];
       }
     }
   }
-  for (int e = threadIdx.x; e < NT * 32; e += 256) {
+  for (int e = threadIdx.x; e < NT * 32; e += NTHR) {
     const int uy = e / T - R, ux = e % T - R;
     offtab[e] = (e < T * T) ? uy * SW + ux : 0;
   }
@@ -624,24 +626,28 @@ int launch_ks(const tsim_plan *pl, int frames, const float *img, const uint16_t 
 
 namespace {
 
+// tiles of 8 rows (four waves) at T = 33; at T = 65 the tile is mostly
+// halo and one block fills a CU's LDS, so 16 rows (eight waves) per block
 template <int KS, int T>
 int launch_h3(const tsim_plan *pl, int frames, const float *img, const float *beta, float *out, hipStream_t s) {
-  using G = H3Geom<KS, T>;
+  constexpr int TH = T == 65 ? 16 : 8;
+  using G = H3Geom<KS, T, TH>;
   const int H = pl->H, W = pl->W, C = pl->C;
   dim3 grid((W + G::TW - 1) / G::TW, (H + G::TH - 1) / G::TH, frames);
   const size_t lds = G::lds(C);
   int st = TSIM_OK;
   switch (C) {
-    case 1: st = prepare_lds(k_render_h3<KS, T, 1>, lds, T); break;
-    case 2: st = prepare_lds(k_render_h3<KS, T, 2>, lds, T); break;
-    case 3: st = prepare_lds(k_render_h3<KS, T, 3>, lds, T); break;
-    case 4: st = prepare_lds(k_render_h3<KS, T, 4>, lds, T); break;
+    case 1: st = prepare_lds(k_render_h3<KS, T, 1, TH>, lds, T); break;
+    case 2: st = prepare_lds(k_render_h3<KS, T, 2, TH>, lds, T); break;
+    case 3: st = prepare_lds(k_render_h3<KS, T, 3, TH>, lds, T); break;
+    case 4: st = prepare_lds(k_render_h3<KS, T, 4, TH>, lds, T); break;
     default: return TSIM_EUNSUPPORTED;
   }
   if (st != TSIM_OK) return st;
   TraceScope tr("k_render_fp32", s);
-#define TSIM_H3(CC) \
-  hipLaunchKernelGGL((k_render_h3<KS, T, CC>), grid, dim3(256), lds, s, img, beta, pl->d_basis_h3r, out, H, W, pl->K)
+#define TSIM_H3(CC)                                                                                            \
+  hipLaunchKernelGGL((k_render_h3<KS, T, CC, TH>), grid, dim3(G::NTHR), lds, s, img, beta, pl->d_basis_h3r, out, \
+                     H, W, pl->K)
   switch (C) {
     case 1: TSIM_H3(1); break;
     case 2: TSIM_H3(2); break;
