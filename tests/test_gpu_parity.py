@@ -196,6 +196,30 @@ def test_p2s_exact_matches_oracle(t, basis33):
         assert err(got[f], ref) < TOL, f
 
 
+# the FP32-accurate blur's kernel forms: K = 20, 60, 120 (2, 4 and 8
+# matrix-core k-steps), C = 1, 2, 4, T = 33 (8-row tiles) and T = 65
+# (16-row tiles), ragged images; the basis is any K x T^2 matrix with unit
+# rows (Eq. (8) is linear in it)
+@pytest.mark.parametrize("T,C,K,H,W", [(33, 1, 20, 19, 37), (33, 2, 60, 24, 33), (33, 4, 120, 17, 48),
+                                       (65, 1, 120, 18, 21), (65, 2, 20, 33, 40), (65, 4, 60, 17, 35)])
+def test_render_fp32_kernel_shapes(t, T, C, K, H, W):
+    say(f"render fp32 T={T} C={C} K={K} {H}x{W}")
+    rng = np.random.default_rng(T * 1000 + C * 100 + K)
+    basis = rng.standard_normal((K, T * T))
+    basis /= np.linalg.norm(basis, axis=1, keepdims=True)
+    plan = t.Plan(H, W, C, 64, 64, basis=basis, psf_t=T, pupil_n=64 if T == 33 else 128)
+    img = synthetic.test_image(C, H, W, 4, seed=T + C)[None]
+    beta = (rng.standard_normal((1, H, W, K)) * 0.1).astype(np.float32)
+    out = torch.full((1, C, H, W), float("nan"), dtype=torch.float32, device="cuda")
+    plan.render(torch.tensor(img, device="cuda"), torch.tensor(beta, device="cuda"), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0]
+    for c in range(C):
+        ref = orender.render_basis(img[0, c].astype(np.float64), beta[0].astype(np.float64), basis, T)
+        assert err(got[c], ref) < TOL, c
+    plan.close()
+
+
 def test_render_matches_oracle(t, basis33):
     say("render fp32 C=3 40x72")
     H, W, C = 40, 72, 3
