@@ -339,8 +339,8 @@ k_render_bf16(const float *__restrict__ img, const uint16_t *__restrict__ beta,
 // scaled back by 2^-22 at the end.  A lane's beta (its pixel, constant over
 // the taps) is split once; psi_hi and psi_lo of each tap block come split
 // from the plan table in fragment order and are staged in LDS for the
-// block's four waves by asynchronous copies, one block ahead, in a ring of
-// two stages.
+// block's waves (two tile rows of 16 pixels each) by asynchronous copies,
+// one block ahead, in a ring of two stages.
 constexpr float kRBetaScale = 4096.f;                   // 2^12
 constexpr float kROutScale = 1.f / (4096.f * 1024.f);   // 2^-22
 
